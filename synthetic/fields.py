@@ -1,0 +1,149 @@
+"""Seeded synthetic scalar fields that stand in for the paper's datasets.
+
+The paper evaluates on CT/MRI scans and simulation volumes (Sec. 4.6,
+table ``tab:mc_benchmark_data``) that are not available here.  This module
+draws fields with the same character -- a noisy sphere distance field,
+Fourier-mode turbulence with a k^(-5/3) energy spectrum, Gaussian blobs and a
+channel-flow-like sheet -- from ``numpy.random.default_rng(seed)``.
+
+It holds none of the extraction method's arithmetic (no compression, no
+culling, no marching cubes); it is the one module that both the CPU oracle and
+the GPU path take their inputs from.
+
+Layout of every returned array: ``[nz][ny][nx]`` (x fastest); sample
+``(x, y, z)`` sits at position ``(x, y, z)`` in voxel units.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "sphere_sdf_noisy",
+    "sphere_sdf",
+    "plane_z",
+    "tilted_plane",
+    "turbulence",
+    "turbulence_modes",
+    "gaussian_blobs",
+    "batched_dims",
+    "percentile_iso",
+]
+
+
+def _grid(nx, ny, nz):
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    z = np.arange(nz, dtype=np.float64)
+    return x, y, z
+
+
+def sphere_sdf(n=64, radius=20.0, center=None, dtype=np.float32):
+    """f(p) = |p - c| - radius on an n^3 grid (c = grid centre by default)."""
+    nx = ny = nz = int(n)
+    c = (np.array([nx - 1, ny - 1, nz - 1], dtype=np.float64) / 2.0
+         if center is None else np.asarray(center, dtype=np.float64))
+    x, y, z = _grid(nx, ny, nz)
+    d2 = ((z - c[2])[:, None, None] ** 2 + (y - c[1])[None, :, None] ** 2
+          + (x - c[0])[None, None, :] ** 2)
+    return (np.sqrt(d2) - radius).astype(dtype)
+
+
+def sphere_sdf_noisy(n=64, radius=20.0, noise=0.5, seed=1, dtype=np.float32):
+    """Sphere distance field plus ``noise * N(0,1)`` per voxel (seeded)."""
+    f = sphere_sdf(n, radius, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    f = f + noise * rng.standard_normal(f.shape)
+    return f.astype(dtype)
+
+
+def plane_z(nx, ny, nz, z0, dtype=np.float32):
+    """f(p) = z - z0 (an axis-aligned plane)."""
+    z = np.arange(nz, dtype=np.float64) - z0
+    f = np.broadcast_to(z[:, None, None], (nz, ny, nx))
+    return np.ascontiguousarray(f).astype(dtype)
+
+
+def tilted_plane(nx, ny, nz, normal, d, dtype=np.float32):
+    """f(p) = normal . p - d (a linear field)."""
+    nrm = np.asarray(normal, dtype=np.float64)
+    x, y, z = _grid(nx, ny, nz)
+    f = (nrm[2] * z[:, None, None] + nrm[1] * y[None, :, None]
+         + nrm[0] * x[None, None, :] - d)
+    return f.astype(dtype)
+
+
+def turbulence_modes(seed, n_modes=256, kmin=1.0 / 512.0, kmax=1.0 / 16.0):
+    """Random Fourier modes: wave vectors k (cycles/voxel), amplitudes, phases.
+
+    |k| is uniform in [kmin, kmax] with a uniform direction on the sphere, so
+    the mode density is flat in |k|; amplitude |k|^(-5/6) then gives an
+    energy spectrum E(k) ~ a^2 ~ k^(-5/3).
+    """
+    rng = np.random.default_rng(seed)
+    kmag = rng.uniform(kmin, kmax, n_modes)
+    d = rng.standard_normal((n_modes, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    k = d * kmag[:, None]
+    phase = rng.uniform(0.0, 2.0 * np.pi, n_modes)
+    amp = kmag ** (-5.0 / 6.0)
+    return k, amp, phase
+
+
+def _mode_sum(nx, ny, nz, k, amp, phase, slab=32):
+    """sum_m amp_m cos(2 pi k_m . p + phase_m), evaluated separably.
+
+    cos(2 pi k.p + phi) = Re(e^{i phi} X(x) Y(y) Z(z)) with per-axis complex
+    exponentials, so each z-slab is one complex matrix product over modes.
+    """
+    x, y, z = _grid(nx, ny, nz)
+    X = np.exp(2j * np.pi * np.outer(k[:, 0], x))            # [M, nx]
+    Y = np.exp(2j * np.pi * np.outer(k[:, 1], y))            # [M, ny]
+    Z = np.exp(2j * np.pi * np.outer(k[:, 2], z))            # [M, nz]
+    c = amp * np.exp(1j * phase)                              # [M]
+    out = np.empty((nz, ny, nx), dtype=np.float64)
+    for z0 in range(0, nz, slab):
+        z1 = min(nz, z0 + slab)
+        # G[zz, y, m] = c_m Z[m, zz] Y[m, y]
+        G = (c[None, None, :] * Z[:, z0:z1].T[:, None, :]) * Y.T[None, :, :]
+        out[z0:z1] = np.real(G.reshape(-1, len(amp)) @ X).reshape(z1 - z0, ny, nx)
+    return out
+
+
+def turbulence(nx, ny=None, nz=None, seed=2, n_modes=256, dtype=np.float32,
+               kmin=1.0 / 512.0, kmax=1.0 / 16.0):
+    """Sum of random Fourier modes (k^-5/3 spectrum) normalised to mean 0, var 1."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    k, amp, phase = turbulence_modes(seed, n_modes, kmin, kmax)
+    f = _mode_sum(nx, ny, nz, k, amp, phase)
+    f -= f.mean()
+    f /= f.std()
+    return f.astype(dtype)
+
+
+def gaussian_blobs(n=256, n_blobs=16, seed=3, dtype=np.float32):
+    """sum_i A_i exp(-|p - c_i|^2 / (2 sigma_i^2)); c_i ~ U[0,n)^3,
+    sigma_i ~ U[8,24], A_i ~ U[0.5,1.5]."""
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(0.0, float(n), (n_blobs, 3))
+    sig = rng.uniform(8.0, 24.0, n_blobs)
+    amp = rng.uniform(0.5, 1.5, n_blobs)
+    x = np.arange(n, dtype=np.float64)
+    f = np.zeros((n, n, n), dtype=np.float64)
+    for i in range(n_blobs):
+        g = [np.exp(-((x - cen[i, a]) ** 2) / (2.0 * sig[i] ** 2)) for a in range(3)]
+        f += amp[i] * (g[2][:, None, None] * g[1][None, :, None] * g[0][None, None, :])
+    return f.astype(dtype)
+
+
+def batched_dims(n_volumes=48, seed=4, lo=32, hi=256):
+    """Per-volume (nx, ny, nz), each axis an independent integer in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    return [tuple(int(v) for v in row) for row in rng.integers(lo, hi + 1, size=(n_volumes, 3))]
+
+
+def percentile_iso(values, p):
+    """Isovalue at the p-th percentile (linear interpolation) of ``values``,
+    taken in float64 and rounded to float32."""
+    v = np.asarray(values, dtype=np.float64).ravel()
+    return np.float32(np.percentile(v, p, method="linear"))
