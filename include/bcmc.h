@@ -1,0 +1,175 @@
+/*
+ * bcmc -- block-compressed marching cubes on MI355X (gfx950).
+ *
+ * C ABI of libbcmc.so.  Implements the GPU-driven isosurface extraction from
+ * block-compressed volumes of Usher & Pascucci, "Interactive Visualization of
+ * Terascale Data in the Browser: Fact or Fiction?" (arXiv 2009.03254), Sec. 4:
+ * fixed-rate ZFP data uploaded once (Sec. 4 intro), active-block culling
+ * (Sec. 4.1), a GPU-driven LRU cache of decoded blocks (Sec. 4.2, Alg. 1) fed
+ * by on-demand block decoding (Sec. 4.2.1), and block-wise marching cubes
+ * with halo loads, per-block vertex counts and a triangle-soup output
+ * (Sec. 4.3-4.5).
+ *
+ * Conventions
+ *  - Volumes are nx*ny*nz samples, x fastest; blocks are 4x4x4 samples,
+ *    nbx = ceil(nx/4) etc., block id b = bx + nbx*(by + nby*bz) (the paper's
+ *    row-major block ids, Sec. 4.5); inside a block, sample (lx,ly,lz) is
+ *    element lx + 4*ly + 16*lz.  Dimensions need not be multiples of 4.
+ *  - A compressed volume is fixed-rate ZFP: block b occupies 64*rate bits =
+ *    `rate` little-endian u64 words starting at word b*rate.
+ *  - Pointers documented as "device" are HIP device pointers (e.g. from
+ *    torch); "host" pointers are ordinary memory.  `hip_stream` is a
+ *    hipStream_t (NULL = default stream); all GPU work is enqueued on it.
+ *  - Every function returns BCMC_OK (0) or a negative bcmc_status; on error
+ *    bcmc_last_error() describes it.  No C++ exception crosses the ABI.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef BCMC_H
+#define BCMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define BCMC_API __attribute__((visibility("default")))
+#else
+#define BCMC_API
+#endif
+
+typedef struct bcmc_volume bcmc_volume;
+
+typedef enum {
+    BCMC_OK = 0,
+    BCMC_E_INVALID = -1,   /* bad argument, size or state */
+    BCMC_E_NOMEM = -2,     /* a device allocation failed; nothing leaked */
+    BCMC_E_CACHE_CAP = -3, /* the active blocks do not fit the cache cap; cache reset */
+    BCMC_E_CAPACITY = -4,  /* the vertex buffer is too small; *n_triangles is set */
+    BCMC_E_HIP = -5,       /* a HIP runtime call failed */
+    BCMC_E_NONFINITE = -6  /* input (or decoded) data holds NaN or infinity */
+} bcmc_status;
+
+typedef enum { BCMC_F32 = 0, BCMC_F64 = 1 } bcmc_scalar;
+
+/* One triangle-soup vertex: position relative to the origin of its block
+ * (4*bx, 4*by, 4*bz) in voxel units, and that block's id.  16 bytes. */
+typedef struct {
+    float x, y, z;
+    uint32_t block;
+} bcmc_vertex;
+
+/* Statistics of the last bcmc_extract call (Sec. 4.6, tab:mc_benchmark_data
+ * and tab:mc_benchmark_table report the same quantities). */
+typedef struct {
+    uint64_t n_blocks;     /* blocks in the volume */
+    uint64_t n_active;     /* active blocks (Sec. 4.1) */
+    uint64_t n_new;        /* blocks decoded into the cache by this call */
+    uint64_t n_evicted;    /* blocks evicted by this call */
+    uint64_t n_occupied;   /* active blocks that emitted triangles (Sec. 4.4) */
+    uint64_t n_slots;      /* cache slots after this call */
+    uint64_t n_triangles;
+    uint64_t calls;        /* extract calls on this handle */
+    double hit_rate;       /* 1 - n_new / n_active (1 when nothing is active) */
+    double alg_bytes;      /* 8*N_b + n_new*(8*rate+256) + 256*n_active + 24*T */
+    double stage_ms[6];    /* with profiling on: cull+compact, cache update,
+                              decode, marching cubes, readback, total */
+} bcmc_stats;
+
+/* Upload a fixed-rate ZFP stream (Sec. 4: "uploading the compressed data to
+ * the GPU") and decode every block once to record its value range over the
+ * valid samples (Sec. 4.1: ranges precomputed at load).
+ *   stream, nbytes   compressed words; nbytes must equal N_b * 8 * rate.
+ *                    Copied: the caller keeps ownership.
+ *   stream_is_device 1 when `stream` is a device pointer, 0 for host memory.
+ *   type             BCMC_F32 (rate 1..32) or BCMC_F64 (rate 1..64); f64
+ *                    blocks are decoded in double and rounded to float.
+ * The cache starts empty and unbounded (see bcmc_set_cache_budget).
+ * Errors: BCMC_E_INVALID (sizes), BCMC_E_NONFINITE (a decoded value is not
+ * finite), BCMC_E_NOMEM, BCMC_E_HIP. */
+BCMC_API int bcmc_load_compressed(const void *stream, uint64_t nbytes, int stream_is_device,
+                         uint32_t nx, uint32_t ny, uint32_t nz, int type, uint32_t rate,
+                         void *hip_stream, bcmc_volume **out);
+
+/* A volume over already-decoded float blocks ([N_b][64], device, caller-owned
+ * and kept alive while the handle exists): every block is resident, slot =
+ * block id (no cache, no decoding).  Used by the differentiable extract. */
+BCMC_API int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uint32_t nz,
+                            void *hip_stream, bcmc_volume **out);
+
+/* Cache budget (Sec. 4.2: user-set initial number of slots, grown on demand).
+ * initial_bytes/256 slots exist at the start; growth adds
+ * max(n_new - n_avail, ceil(n_slots/2)) slots, never beyond max_bytes/256
+ * (max_bytes = 0: one slot per block).  Slot memory for the cap is reserved
+ * here so growth needs no host round-trip.  Empties the cache.
+ * Errors: BCMC_E_INVALID (max below initial, identity volume), BCMC_E_NOMEM. */
+BCMC_API int bcmc_set_cache_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes);
+
+/* Empty the cache (every slot empty, age 2^31), keeping the budget. */
+BCMC_API int bcmc_reset_cache(bcmc_volume *v, void *hip_stream);
+
+/* Extract the isosurface at `iso` (Sec. 4.1-4.5) into the caller's device
+ * buffer d_out of capacity_vertices bcmc_vertex records: a triangle soup,
+ * 3 vertices per triangle, in canonical order (blocks by id, cells by local
+ * index, triangles and vertices in table order).  A cell corner is inside
+ * when its value is < iso.  Synchronises hip_stream once to read the count.
+ * Errors: BCMC_E_CAPACITY when 3*T > capacity_vertices (*n_triangles = T,
+ * the first capacity_vertices records are written, the cache stays valid:
+ * enlarge and call again); BCMC_E_CACHE_CAP (cache reset); BCMC_E_HIP. */
+BCMC_API int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_vertices,
+                 uint64_t *n_triangles, void *hip_stream);
+
+/* Backward of the last bcmc_extract of a bcmc_volume_from_blocks handle
+ * (same iso), topology held fixed: from d_gV = dL/d(vertex position)
+ * ([3T][3] float, device) accumulates dL/d(field) into d_dfield ([N_b][64]
+ * float, device, overwritten) and dL/d(iso) into d_diso (one float, device,
+ * overwritten), through t = (iso - a)/(b - a).  Float atomics: the
+ * summation order is not fixed.
+ * Errors: BCMC_E_INVALID (not an identity handle, no extract, n_verts
+ * differs from the last extract). */
+BCMC_API int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_t n_verts,
+                  float *d_dfield, float *d_diso, void *hip_stream);
+
+BCMC_API int bcmc_get_stats(const bcmc_volume *v, bcmc_stats *out);
+/* 1 = record per-stage HIP events in bcmc_extract (bcmc_stats.stage_ms). */
+BCMC_API int bcmc_set_profiling(bcmc_volume *v, int on);
+BCMC_API void bcmc_free(bcmc_volume *v);
+/* Message of the last error on this thread (empty when none). */
+BCMC_API const char *bcmc_last_error(void);
+BCMC_API uint64_t bcmc_num_blocks(uint32_t nx, uint32_t ny, uint32_t nz);
+
+/* Fixed-rate ZFP compression of a device field ([nz][ny][nx], x fastest)
+ * into d_stream (N_b*rate u64 words, device, caller-owned).  Partial blocks
+ * replicate the last valid sample.  Errors: BCMC_E_INVALID,
+ * BCMC_E_NONFINITE. */
+BCMC_API int bcmc_encode(const void *d_field, int type, uint32_t nx, uint32_t ny, uint32_t nz,
+                uint32_t rate, uint64_t *d_stream, void *hip_stream);
+
+/* Decode every block of a compressed volume into d_blocks ([N_b][64] float,
+ * device, caller-owned) with the same decoder the cache uses. */
+BCMC_API int bcmc_decode_all(bcmc_volume *v, float *d_blocks, void *hip_stream);
+
+/* The generated marching cubes table: packed[c] holds the edge ids of case c
+ * (4 bits each, 15 = unused) and its triangle count in bits 60..63. */
+BCMC_API int bcmc_mc_table(uint64_t *packed256);
+
+/* ---- inspection of the last extract (host copies; synchronous) -------- */
+BCMC_API int bcmc_debug_ranges(const bcmc_volume *v, float *h_ranges /* [N_b][2] */);
+BCMC_API int bcmc_debug_active(const bcmc_volume *v, uint8_t *h_active /* [N_b] */,
+                      uint32_t *h_I_active /* [N_b] */, uint64_t *h_n_active);
+BCMC_API int bcmc_debug_new(const bcmc_volume *v, uint32_t *h_I_new /* [N_b] */, uint64_t *h_n_new);
+BCMC_API int bcmc_debug_cache_state(const bcmc_volume *v, int32_t *h_I_slot /* [N_b] */,
+                           int32_t *h_S_block /* [n_slots] */,
+                           uint32_t *h_S_age /* [n_slots] */, uint64_t *h_n_slots);
+BCMC_API int bcmc_debug_slot_data(const bcmc_volume *v, float *h_slots /* [n_slots][64] */);
+BCMC_API int bcmc_debug_block_counts(const bcmc_volume *v, uint32_t *h_cnt, uint64_t *h_off,
+                            uint64_t n /* <= n_active */);
+/* Cases of the 64 cells of every active block of the last extract (which
+ * must have used the same iso) into d_cases ([n_active][64], device). */
+BCMC_API int bcmc_debug_cases(bcmc_volume *v, float iso, uint8_t *d_cases, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BCMC_H */

@@ -1,0 +1,317 @@
+"""bcmc: GPU-driven isosurface extraction from block-compressed volumes on
+MI355X (gfx950) -- Usher & Pascucci, arXiv 2009.03254, Sec. 4.
+
+A thin Python binding of the C ABI in ``include/bcmc.h`` (libbcmc.so, built
+in-tree by ``paper_2009_03254_amd.build``).  It only marshals arguments: every
+step of the extraction runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current HIP stream.
+
+    import torch, paper_2009_03254_amd as bcmc
+    stream = bcmc.encode(field_cuda, rate=8)          # fixed-rate ZFP on the GPU
+    vol = bcmc.Volume(stream, field_cuda.shape[::-1], "f32", 8)
+    vol.set_cache_budget(initial_bytes=vol.n_blocks * 64)
+    verts, T = vol.extract(0.5)       # [3T, 4] int32 rows: x, y, z (float bits), block
+    xyz, blk = bcmc.split_vertices(verts)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import _capi
+from ._capi import BcmcError, lib  # noqa: F401
+
+__all__ = ["Volume", "FieldVolume", "ExtractFn", "encode", "mc_table", "num_blocks",
+           "split_vertices", "global_positions", "BcmcError", "lib"]
+
+F32, F64 = 0, 1
+_TYPES = {"f32": F32, "float32": F32, "f64": F64, "float64": F64}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def num_blocks(nx, ny, nz):
+    return int(lib().bcmc_num_blocks(nx, ny, nz))
+
+
+def mc_table():
+    """The library's generated marching cubes table as
+    (num_tris[256], tris[256,16] edge ids padded with -1)."""
+    packed = np.zeros(256, dtype=np.uint64)
+    _capi.check(lib().bcmc_mc_table(packed.ctypes.data_as(C.c_void_p)))
+    nt = (packed >> np.uint64(60)).astype(np.int32)
+    tri = np.full((256, 16), -1, dtype=np.int32)
+    for c in range(256):
+        w = int(packed[c])
+        for k in range(3 * int(nt[c])):
+            tri[c, k] = (w >> (4 * k)) & 15
+    return nt, tri
+
+
+def encode(field, rate, stream=None):
+    """Fixed-rate ZFP compression of a CUDA tensor [nz, ny, nx] (float32 or
+    float64) -> CUDA uint64 tensor of N_b*rate words."""
+    torch = _torch()
+    if not field.is_cuda:
+        raise ValueError("encode expects a CUDA tensor")
+    field = field.contiguous()
+    if field.dtype == torch.float32:
+        typ = F32
+    elif field.dtype == torch.float64:
+        typ = F64
+    else:
+        raise TypeError("field must be float32 or float64")
+    nz, ny, nx = field.shape
+    out = torch.empty(num_blocks(nx, ny, nz) * rate, dtype=torch.uint64, device=field.device)
+    _capi.check(lib().bcmc_encode(_dev_ptr(field), typ, nx, ny, nz, rate, _dev_ptr(out),
+                                  _stream_ptr(stream)))
+    return out
+
+
+def split_vertices(verts):
+    """[n, 4] int32 records -> (xyz float32 [n, 3] view, block int32 [n] view)."""
+    torch = _torch()
+    return verts.view(torch.float32)[:, :3], verts[:, 3]
+
+
+def global_positions(xyz, block, dims, dtype=None):
+    """Block-relative positions + block ids -> global voxel coordinates."""
+    torch = _torch()
+    nx, ny, nz = dims
+    nbx, nby = (nx + 3) // 4, (ny + 3) // 4
+    b = block.to(torch.int64)
+    org = torch.stack([b % nbx, (b // nbx) % nby, b // (nbx * nby)], dim=1) * 4
+    dt = dtype or xyz.dtype
+    return xyz.to(dt) + org.to(dt)
+
+
+class _Handle:
+    _h = None
+
+    def close(self):
+        if self._h:
+            lib().bcmc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        st = _capi.Stats()
+        _capi.check(lib().bcmc_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def set_profiling(self, on=True):
+        _capi.check(lib().bcmc_set_profiling(self._h, 1 if on else 0))
+
+    def _alloc_out(self, cap):
+        torch = _torch()
+        return torch.empty((max(cap, 1), 4), dtype=torch.int32, device="cuda")
+
+    def extract(self, iso, out=None, stream=None):
+        """Triangle soup at `iso`: ([3T, 4] int32 CUDA tensor, T).  `out` is
+        reused (and grown when too small)."""
+        cap = 0 if out is None else out.shape[0]
+        if out is None:
+            out = self._alloc_out(getattr(self, "_cap_hint", 1 << 16))
+            cap = out.shape[0]
+        T = C.c_uint64(0)
+        rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), cap, C.byref(T),
+                                _stream_ptr(stream))
+        if rc == _capi.E_CAPACITY:
+            need = 3 * T.value
+            self._cap_hint = need + need // 8 + 1024
+            out = self._alloc_out(self._cap_hint)
+            rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), out.shape[0],
+                                    C.byref(T), _stream_ptr(stream))
+        _capi.check(rc)
+        self._cap_hint = max(getattr(self, "_cap_hint", 0), 3 * T.value)
+        return out[: 3 * T.value], int(T.value)
+
+    def extract_into(self, iso, out, stream=None):
+        """Extract into a preallocated [cap, 4] int32 buffer; returns (rc, T)."""
+        T = C.c_uint64(0)
+        rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), out.shape[0],
+                                C.byref(T), _stream_ptr(stream))
+        return rc, int(T.value)
+
+    # ---- inspection ------------------------------------------------------
+    def ranges(self):
+        r = np.empty((self.n_blocks, 2), dtype=np.float32)
+        _capi.check(lib().bcmc_debug_ranges(self._h, r.ctypes.data_as(C.c_void_p)))
+        return r
+
+    def active(self):
+        a = np.empty(self.n_blocks, dtype=np.uint8)
+        ids = np.empty(self.n_blocks, dtype=np.uint32)
+        n = C.c_uint64(0)
+        _capi.check(lib().bcmc_debug_active(self._h, a.ctypes.data_as(C.c_void_p),
+                                            ids.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return a, ids[: n.value].copy()
+
+    def block_counts(self):
+        n = self.stats()["n_active"]
+        cnt = np.empty(max(n, 1), dtype=np.uint32)
+        off = np.empty(max(n, 1), dtype=np.uint64)
+        _capi.check(lib().bcmc_debug_block_counts(self._h, cnt.ctypes.data_as(C.c_void_p),
+                                                  off.ctypes.data_as(C.c_void_p), n))
+        return cnt[:n], off[:n]
+
+    def cases(self, iso, stream=None):
+        torch = _torch()
+        n = self.stats()["n_active"]
+        d = torch.zeros((max(n, 1), 64), dtype=torch.uint8, device="cuda")
+        _capi.check(lib().bcmc_debug_cases(self._h, C.c_float(iso), _dev_ptr(d),
+                                           _stream_ptr(stream)))
+        return d[:n]
+
+
+class Volume(_Handle):
+    """A fixed-rate ZFP compressed volume resident on the GPU, with its LRU
+    block cache (paper Sec. 4)."""
+
+    def __init__(self, stream_words, dims, dtype="f32", rate=8, stream=None):
+        torch = _torch()
+        nx, ny, nz = (int(d) for d in dims)
+        self.dims = (nx, ny, nz)
+        self.rate = int(rate)
+        self.type = _TYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.n_blocks = num_blocks(nx, ny, nz)
+        h = C.c_void_p()
+        if isinstance(stream_words, np.ndarray):
+            w = np.ascontiguousarray(stream_words, dtype=np.uint64)
+            rc = lib().bcmc_load_compressed(w.ctypes.data_as(C.c_void_p), w.nbytes, 0, nx, ny, nz,
+                                            self.type, self.rate, _stream_ptr(stream), C.byref(h))
+        else:
+            w = stream_words.contiguous()
+            dev = 1 if w.is_cuda else 0
+            rc = lib().bcmc_load_compressed(C.c_void_p(w.data_ptr()), w.numel() * w.element_size(),
+                                            dev, nx, ny, nz, self.type, self.rate,
+                                            _stream_ptr(stream), C.byref(h))
+        _capi.check(rc)
+        self._h = h
+
+    def set_cache_budget(self, initial_bytes=0, max_bytes=0):
+        _capi.check(lib().bcmc_set_cache_budget(self._h, int(initial_bytes), int(max_bytes)))
+
+    def reset_cache(self, stream=None):
+        _capi.check(lib().bcmc_reset_cache(self._h, _stream_ptr(stream)))
+
+    def decode_all(self, stream=None):
+        torch = _torch()
+        out = torch.empty((self.n_blocks, 64), dtype=torch.float32, device="cuda")
+        _capi.check(lib().bcmc_decode_all(self._h, _dev_ptr(out), _stream_ptr(stream)))
+        return out
+
+    def cache_state(self):
+        ns = C.c_uint64(0)
+        _capi.check(lib().bcmc_debug_cache_state(self._h, None, None, None, C.byref(ns)))
+        n = ns.value
+        I_slot = np.empty(self.n_blocks, dtype=np.int32)
+        S_block = np.empty(max(n, 1), dtype=np.int32)
+        S_age = np.empty(max(n, 1), dtype=np.uint32)
+        _capi.check(lib().bcmc_debug_cache_state(
+            self._h, I_slot.ctypes.data_as(C.c_void_p), S_block.ctypes.data_as(C.c_void_p),
+            S_age.ctypes.data_as(C.c_void_p), C.byref(ns)))
+        return I_slot, S_block[:n], S_age[:n]
+
+    def slot_data(self):
+        n = self.stats()["n_slots"]
+        out = np.empty((max(n, 1), 64), dtype=np.float32)
+        _capi.check(lib().bcmc_debug_slot_data(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out[:n]
+
+    def new_blocks(self):
+        ids = np.empty(self.n_blocks, dtype=np.uint32)
+        n = C.c_uint64(0)
+        _capi.check(lib().bcmc_debug_new(self._h, ids.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return ids[: n.value].copy()
+
+
+class FieldVolume(_Handle):
+    """A volume over decoded float blocks ([N_b, 64] CUDA float32 tensor, kept
+    referenced here): all blocks resident, no cache.  Differentiable."""
+
+    def __init__(self, blocks, dims, stream=None):
+        nx, ny, nz = (int(d) for d in dims)
+        self.dims = (nx, ny, nz)
+        self.n_blocks = num_blocks(nx, ny, nz)
+        if tuple(blocks.shape) != (self.n_blocks, 64) or not blocks.is_cuda:
+            raise ValueError("blocks must be a CUDA tensor of shape [N_b, 64]")
+        self.blocks = blocks.contiguous()
+        h = C.c_void_p()
+        _capi.check(lib().bcmc_volume_from_blocks(_dev_ptr(self.blocks), nx, ny, nz,
+                                                  _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def backward(self, iso, gV, stream=None):
+        torch = _torch()
+        gV = gV.contiguous().to(torch.float32)
+        dfield = torch.empty((self.n_blocks, 64), dtype=torch.float32, device="cuda")
+        diso = torch.empty((), dtype=torch.float32, device="cuda")
+        n = gV.shape[0]
+        _capi.check(lib().bcmc_backward(self._h, C.c_float(iso),
+                                        _dev_ptr(gV) if n else None, n, _dev_ptr(dfield),
+                                        _dev_ptr(diso), _stream_ptr(stream)))
+        return dfield, diso
+
+
+def _make_extract_fn():
+    torch = _torch()
+
+    class ExtractFn(torch.autograd.Function):
+        """verts_xyz, vblock = ExtractFn.apply(field_blocks, iso, dims).
+
+        field_blocks: [N_b, 64] float32 CUDA tensor (block layout); iso: 0-d
+        float tensor.  Returns block-relative vertex positions [3T, 3]
+        (differentiable) and block ids [3T] (int32).  Gradients flow to
+        field_blocks and iso through t = (iso - a)/(b - a), topology fixed."""
+
+        @staticmethod
+        def forward(ctx, field_blocks, iso, dims):
+            vol = FieldVolume(field_blocks.detach(), dims)
+            isof = float(iso)
+            verts, T = vol.extract(isof)
+            xyz, blk = split_vertices(verts)
+            ctx.vol, ctx.iso = vol, isof
+            ctx.iso_dtype = iso.dtype if torch.is_tensor(iso) else torch.float32
+            ctx.mark_non_differentiable(blk)
+            return xyz.clone(), blk.clone()
+
+        @staticmethod
+        def backward(ctx, g_xyz, g_blk):
+            dfield, diso = ctx.vol.backward(ctx.iso, g_xyz)
+            ctx.vol.close()
+            return dfield, diso.to(ctx.iso_dtype), None
+
+    return ExtractFn
+
+
+class _LazyFn:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _make_extract_fn()
+        return getattr(_LazyFn._fn, name)
+
+
+ExtractFn = _LazyFn()

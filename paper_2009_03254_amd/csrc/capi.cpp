@@ -1,0 +1,527 @@
+// C ABI of libbcmc: volume handles, buffers, and the stream-ordered
+// orchestration of one extract call (paper Sec. 4, Alg. 1).
+#include "../../include/bcmc.h"
+
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "common.h"
+
+using namespace bcmc;
+
+namespace bcmc {
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace bcmc
+
+struct bcmc_volume {
+    Geom g{};
+    int is_f64 = 0;
+    uint32_t rate = 0;
+    int identity = 0;              // slots are the caller's decoded blocks
+    const float *ext_blocks = nullptr;
+    DevState d;
+    StatusLayout sl{};
+    uint64_t init_slots = 0, max_slots = 0, n_slots = 0;  // host mirror
+    Counters *h_ctr = nullptr;     // pinned copy of the device counters
+    bcmc_stats stats{};
+    int profiling = 0;
+    hipEvent_t ev[6] = {};
+    int have_extract = 0;
+    float last_iso = 0.0f;
+};
+
+namespace {
+
+int invalid(const std::string &msg) {
+    set_error(msg);
+    return BCMC_E_INVALID;
+}
+
+template <typename T>
+int dev_alloc(T **p, uint64_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("hipMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed: " +
+                  hipGetErrorString(e));
+        return BCMC_E_NOMEM;
+    }
+    return BCMC_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+Geom make_geom(uint32_t nx, uint32_t ny, uint32_t nz) {
+    Geom g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.nbx = (nx + 3) / 4;
+    g.nby = (ny + 3) / 4;
+    g.nbz = (nz + 3) / 4;
+    g.nb = (uint64_t)g.nbx * g.nby * g.nbz;
+    return g;
+}
+
+int check_dims(uint32_t nx, uint32_t ny, uint32_t nz) {
+    if (nx < 2 || ny < 2 || nz < 2) return invalid("every dimension must be at least 2");
+    Geom g = make_geom(nx, ny, nz);
+    if (g.nb >= (1ull << 31)) return invalid("more than 2^31 - 1 blocks");
+    return BCMC_OK;
+}
+
+void free_cache(bcmc_volume *v) {
+    dev_free(v->d.S_block);
+    dev_free(v->d.S_age);
+    dev_free(v->d.slots);
+    for (int i = 0; i < 2; i++) {
+        dev_free(v->d.sort_key[i]);
+        dev_free(v->d.sort_val[i]);
+    }
+    dev_free(v->d.radix_hist);
+    dev_free(v->d.status);
+}
+
+void layout_status(bcmc_volume *v) {
+    StatusLayout &s = v->sl;
+    s.blk = 0;
+    s.slot = s.blk + (v->g.nb + BLK_TILE - 1) / BLK_TILE;
+    s.mc = s.slot + (v->max_slots + SLOT_TILE - 1) / SLOT_TILE;
+    s.scan = s.mc + (v->g.nb + MC_WAVES - 1) / MC_WAVES + 1;
+    uint64_t rtiles = (v->max_slots + RADIX_TILE - 1) / RADIX_TILE;
+    s.total = s.scan + (256 * rtiles + SCAN_TILE - 1) / SCAN_TILE + 1;
+}
+
+int alloc_common(bcmc_volume *v) {
+    int rc;
+    if ((rc = dev_alloc(&v->d.ranges, v->g.nb))) return rc;
+    if ((rc = dev_alloc(&v->d.active, v->g.nb + 16))) return rc;
+    if ((rc = dev_alloc(&v->d.I_active, v->g.nb))) return rc;
+    if ((rc = dev_alloc(&v->d.blk_cnt, v->g.nb))) return rc;
+    if ((rc = dev_alloc(&v->d.blk_off, v->g.nb))) return rc;
+    if ((rc = dev_alloc(&v->d.ctr, 1))) return rc;
+    if ((rc = dev_alloc(&v->d.mc_table, 256))) return rc;
+    if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
+    BCMC_HIP_TRY(hipMemcpy(v->d.mc_table, mc_table_host(), 256 * sizeof(uint64_t),
+                           hipMemcpyHostToDevice));
+    BCMC_HIP_TRY(hipHostMalloc((void **)&v->h_ctr, sizeof(Counters), hipHostMallocDefault));
+    memset(v->h_ctr, 0, sizeof(Counters));
+    v->stats.n_blocks = v->g.nb;
+    return BCMC_OK;
+}
+
+void destroy(bcmc_volume *v) {
+    if (!v) return;
+    free_cache(v);
+    dev_free(v->d.stream);
+    dev_free(v->d.ranges);
+    dev_free(v->d.active);
+    dev_free(v->d.I_active);
+    dev_free(v->d.I_new);
+    dev_free(v->d.I_slot);
+    dev_free(v->d.blk_cnt);
+    dev_free(v->d.blk_off);
+    dev_free(v->d.ctr);
+    dev_free(v->d.mc_table);
+    if (v->h_ctr) (void)hipHostFree(v->h_ctr);
+    for (auto &e : v->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete v;
+}
+
+int reset_cache_state(bcmc_volume *v, hipStream_t s) {
+    launch_fill_u32(reinterpret_cast<uint32_t *>(v->d.I_slot), 0xFFFFFFFFu, v->g.nb, s);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(v->d.S_block), 0xFFFFFFFFu, v->max_slots, s);
+    launch_fill_u32(v->d.S_age, HIGH_AGE, v->max_slots, s);
+    BCMC_HIP_TRY(hipGetLastError());
+    v->n_slots = v->init_slots;
+    v->have_extract = 0;
+    return BCMC_OK;
+}
+
+int set_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes, hipStream_t s) {
+    uint64_t init = initial_bytes / 256;
+    uint64_t maxs = max_bytes ? max_bytes / 256 : std::max<uint64_t>(init, v->g.nb);
+    if (maxs < init) return invalid("max_bytes is below initial_bytes");
+    if (maxs >= (1ull << 31)) return invalid("more than 2^31 - 1 cache slots");
+    BCMC_HIP_TRY(hipStreamSynchronize(s));
+    free_cache(v);
+    v->init_slots = init;
+    v->max_slots = maxs;
+    layout_status(v);
+    int rc;
+    if ((rc = dev_alloc(&v->d.S_block, maxs))) return rc;
+    if ((rc = dev_alloc(&v->d.S_age, maxs))) return rc;
+    if ((rc = dev_alloc(&v->d.slots, maxs * 64))) return rc;
+    for (int i = 0; i < 2; i++) {
+        if ((rc = dev_alloc(&v->d.sort_key[i], maxs))) return rc;
+        if ((rc = dev_alloc(&v->d.sort_val[i], maxs))) return rc;
+    }
+    if ((rc = dev_alloc(&v->d.radix_hist, 256 * ((maxs + RADIX_TILE - 1) / RADIX_TILE)))) return rc;
+    if ((rc = dev_alloc(&v->d.status, v->sl.total))) return rc;
+    BCMC_HIP_TRY(hipMemsetAsync(v->d.status, 0, v->sl.total * sizeof(uint64_t), s));
+    return reset_cache_state(v, s);
+}
+
+hipStream_t as_stream(void *p) { return reinterpret_cast<hipStream_t>(p); }
+
+int sync_counters(bcmc_volume *v, hipStream_t s) {
+    BCMC_HIP_TRY(hipMemcpyAsync(v->h_ctr, v->d.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    BCMC_HIP_TRY(hipStreamSynchronize(s));
+    return BCMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bcmc_last_error(void) { return g_last_error.c_str(); }
+
+uint64_t bcmc_num_blocks(uint32_t nx, uint32_t ny, uint32_t nz) { return make_geom(nx, ny, nz).nb; }
+
+int bcmc_mc_table(uint64_t *packed256) {
+    if (!packed256) return invalid("null table pointer");
+    if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
+    memcpy(packed256, mc_table_host(), 256 * sizeof(uint64_t));
+    return BCMC_OK;
+}
+
+int bcmc_load_compressed(const void *stream, uint64_t nbytes, int stream_is_device, uint32_t nx,
+                         uint32_t ny, uint32_t nz, int type, uint32_t rate, void *hip_stream,
+                         bcmc_volume **out) {
+    if (!out) return invalid("null output handle");
+    *out = nullptr;
+    if (!stream) return invalid("null stream");
+    int rc = check_dims(nx, ny, nz);
+    if (rc) return rc;
+    if (type != BCMC_F32 && type != BCMC_F64) return invalid("type must be BCMC_F32 or BCMC_F64");
+    if (rate < 1 || rate > (type == BCMC_F64 ? 64u : 32u)) return invalid("rate out of range");
+    Geom g = make_geom(nx, ny, nz);
+    if (nbytes != g.nb * 8ull * rate)
+        return invalid("stream size " + std::to_string(nbytes) + " != N_b*8*rate = " +
+                       std::to_string(g.nb * 8ull * rate));
+    hipStream_t s = as_stream(hip_stream);
+    bcmc_volume *v = new (std::nothrow) bcmc_volume();
+    if (!v) return BCMC_E_NOMEM;
+    v->g = g;
+    v->is_f64 = type == BCMC_F64;
+    v->rate = rate;
+    if ((rc = alloc_common(v)) || (rc = dev_alloc(&v->d.stream, g.nb * rate)) ||
+        (rc = dev_alloc(&v->d.I_new, g.nb)) || (rc = dev_alloc(&v->d.I_slot, g.nb))) {
+        destroy(v);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(v->d.stream, stream, nbytes,
+                                  stream_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(v->d.ctr, 0, sizeof(Counters), s);
+    if (e != hipSuccess) {
+        set_error(std::string("upload failed: ") + hipGetErrorString(e));
+        destroy(v);
+        return BCMC_E_HIP;
+    }
+    launch_decode_ranges(g, v->d.stream, v->is_f64, rate, v->d.ranges, nullptr, &v->d.ctr->err, s);
+    if ((rc = sync_counters(v, s))) {
+        destroy(v);
+        return rc;
+    }
+    if (v->h_ctr->err & ERR_NONFINITE) {
+        set_error("the stream decodes to non-finite values");
+        destroy(v);
+        return BCMC_E_NONFINITE;
+    }
+    if ((rc = set_budget(v, 0, 0, s))) {
+        destroy(v);
+        return rc;
+    }
+    *out = v;
+    return BCMC_OK;
+}
+
+int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uint32_t nz,
+                            void *hip_stream, bcmc_volume **out) {
+    if (!out) return invalid("null output handle");
+    *out = nullptr;
+    if (!d_blocks) return invalid("null blocks");
+    int rc = check_dims(nx, ny, nz);
+    if (rc) return rc;
+    hipStream_t s = as_stream(hip_stream);
+    bcmc_volume *v = new (std::nothrow) bcmc_volume();
+    if (!v) return BCMC_E_NOMEM;
+    v->g = make_geom(nx, ny, nz);
+    v->identity = 1;
+    v->ext_blocks = d_blocks;
+    v->max_slots = 0;
+    layout_status(v);
+    if ((rc = alloc_common(v)) || (rc = dev_alloc(&v->d.status, v->sl.total))) {
+        destroy(v);
+        return rc;
+    }
+    hipError_t e = hipMemsetAsync(v->d.ctr, 0, sizeof(Counters), s);
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        destroy(v);
+        return BCMC_E_HIP;
+    }
+    launch_ranges_from_blocks(v->g, d_blocks, v->d.ranges, &v->d.ctr->err, s);
+    if ((rc = sync_counters(v, s))) {
+        destroy(v);
+        return rc;
+    }
+    if (v->h_ctr->err & ERR_NONFINITE) {
+        set_error("the blocks hold non-finite values");
+        destroy(v);
+        return BCMC_E_NONFINITE;
+    }
+    v->n_slots = v->g.nb;
+    *out = v;
+    return BCMC_OK;
+}
+
+int bcmc_set_cache_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes) {
+    if (!v) return invalid("null handle");
+    if (v->identity) return invalid("identity volumes have no cache");
+    return set_budget(v, initial_bytes, max_bytes, nullptr);
+}
+
+int bcmc_reset_cache(bcmc_volume *v, void *hip_stream) {
+    if (!v) return invalid("null handle");
+    if (v->identity) return BCMC_OK;
+    return reset_cache_state(v, as_stream(hip_stream));
+}
+
+int bcmc_set_profiling(bcmc_volume *v, int on) {
+    if (!v) return invalid("null handle");
+    if (on && !v->ev[0])
+        for (auto &e : v->ev) BCMC_HIP_TRY(hipEventCreate(&e));
+    v->profiling = on;
+    return BCMC_OK;
+}
+
+int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_vertices,
+                 uint64_t *n_triangles, void *hip_stream) {
+    if (!v || !n_triangles) return invalid("null argument");
+    if (!d_out && capacity_vertices) return invalid("null output buffer with nonzero capacity");
+    if (iso != iso) return invalid("iso is NaN");
+    hipStream_t s = as_stream(hip_stream);
+    const bool prof = v->profiling;
+    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[0], s));
+    launch_cull(v->g, v->d, v->sl, iso, v->n_slots, s);
+    launch_compact_blocks(v->g, v->d, v->sl, v->identity, s);
+    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[1], s));
+    if (!v->identity) {
+        launch_slot_pass(v->d, v->sl, v->n_slots, s);
+        launch_plan_grow(v->d, v->max_slots, v->max_slots - v->n_slots, s);
+        launch_radix(v->d, v->sl, v->max_slots, s);
+        if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[2], s));
+        launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, s);
+    } else if (prof) {
+        BCMC_HIP_TRY(hipEventRecord(v->ev[2], s));
+    }
+    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[3], s));
+    const float *slots = v->identity ? v->ext_blocks : v->d.slots;
+    launch_mc(v->g, v->d, v->sl, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices,
+              (v->g.nb + MC_WAVES - 1) / MC_WAVES, s);
+    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[4], s));
+    BCMC_HIP_TRY(hipGetLastError());
+    int rc = sync_counters(v, s);
+    if (rc) return rc;
+    const Counters &c = *v->h_ctr;
+    v->stats.calls++;
+    if (c.err & ERR_INTERNAL) {
+        reset_cache_state(v, s);
+        set_error("internal consistency check failed in the cache update; cache reset");
+        return BCMC_E_HIP;
+    }
+    if (c.err & ERR_CACHE_CAP) {
+        reset_cache_state(v, s);
+        v->stats.n_active = c.n_act;
+        v->stats.n_new = v->stats.n_evicted = v->stats.n_occupied = v->stats.n_triangles = 0;
+        v->stats.n_slots = v->n_slots;
+        set_error("the active blocks (" + std::to_string(c.n_act) +
+                  ") do not fit the cache cap of " + std::to_string(v->max_slots) + " slots");
+        return BCMC_E_CACHE_CAP;
+    }
+    if (!v->identity && c.n_new) v->n_slots = c.n_slots;
+    const uint64_t T = c.total_verts / 3;
+    *n_triangles = T;
+    bcmc_stats &st = v->stats;
+    st.n_active = c.n_act;
+    st.n_new = v->identity ? 0 : c.n_new;
+    st.n_evicted = c.n_evicted;
+    st.n_occupied = c.n_occ;
+    st.n_slots = v->n_slots;
+    st.n_triangles = T;
+    st.hit_rate = c.n_act ? 1.0 - (double)st.n_new / (double)c.n_act : 1.0;
+    st.alg_bytes = 8.0 * v->g.nb + (double)st.n_new * (8.0 * v->rate + 256.0) +
+                   256.0 * (double)c.n_act + 24.0 * (double)T;
+    if (prof) {
+        float ms[4];
+        for (int i = 0; i < 4; i++) (void)hipEventElapsedTime(&ms[i], v->ev[i], v->ev[i + 1]);
+        st.stage_ms[0] = ms[0];
+        st.stage_ms[1] = ms[1];
+        st.stage_ms[2] = ms[2];
+        st.stage_ms[3] = ms[3];
+        float tot = 0;
+        (void)hipEventElapsedTime(&tot, v->ev[0], v->ev[4]);
+        st.stage_ms[4] = 0;
+        st.stage_ms[5] = tot;
+    }
+    v->have_extract = 1;
+    v->last_iso = iso;
+    if (c.total_verts > capacity_vertices) {
+        set_error("vertex buffer too small: need " + std::to_string(c.total_verts) + " vertices");
+        return BCMC_E_CAPACITY;
+    }
+    return BCMC_OK;
+}
+
+int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_t n_verts, float *d_dfield,
+                  float *d_diso, void *hip_stream) {
+    if (!v || !d_dfield || !d_diso) return invalid("null argument");
+    if (!v->identity) return invalid("backward needs a bcmc_volume_from_blocks handle");
+    if (!v->have_extract || iso != v->last_iso) return invalid("no extract at this iso to differentiate");
+    if (n_verts != v->h_ctr->total_verts) return invalid("n_verts differs from the last extract");
+    if (n_verts && !d_gV) return invalid("null gradient");
+    hipStream_t s = as_stream(hip_stream);
+    BCMC_HIP_TRY(hipMemsetAsync(d_dfield, 0, v->g.nb * 64 * sizeof(float), s));
+    BCMC_HIP_TRY(hipMemsetAsync(d_diso, 0, sizeof(float), s));
+    if (n_verts)
+        launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, d_dfield, d_diso, v->g.nb, s);
+    BCMC_HIP_TRY(hipGetLastError());
+    return BCMC_OK;
+}
+
+int bcmc_get_stats(const bcmc_volume *v, bcmc_stats *out) {
+    if (!v || !out) return invalid("null argument");
+    *out = v->stats;
+    return BCMC_OK;
+}
+
+void bcmc_free(bcmc_volume *v) {
+    if (!v) return;
+    (void)hipDeviceSynchronize();
+    destroy(v);
+}
+
+int bcmc_encode(const void *d_field, int type, uint32_t nx, uint32_t ny, uint32_t nz, uint32_t rate,
+                uint64_t *d_stream, void *hip_stream) {
+    if (!d_field || !d_stream) return invalid("null pointer");
+    int rc = check_dims(nx, ny, nz);
+    if (rc) return rc;
+    if (type != BCMC_F32 && type != BCMC_F64) return invalid("type must be BCMC_F32 or BCMC_F64");
+    if (rate < 1 || rate > (type == BCMC_F64 ? 64u : 32u)) return invalid("rate out of range");
+    hipStream_t s = as_stream(hip_stream);
+    unsigned int *err = nullptr;
+    if ((rc = dev_alloc(&err, 1))) return rc;
+    BCMC_HIP_TRY(hipMemsetAsync(err, 0, sizeof(unsigned int), s));
+    launch_encode(make_geom(nx, ny, nz), d_field, type == BCMC_F64, rate, d_stream, err, s);
+    unsigned int h = 0;
+    hipError_t e = hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(err);
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        return BCMC_E_HIP;
+    }
+    if (h & ERR_NONFINITE) {
+        set_error("the field holds non-finite values");
+        return BCMC_E_NONFINITE;
+    }
+    return BCMC_OK;
+}
+
+int bcmc_decode_all(bcmc_volume *v, float *d_blocks, void *hip_stream) {
+    if (!v || !d_blocks) return invalid("null argument");
+    if (v->identity) return invalid("identity volumes hold no compressed stream");
+    launch_decode_ranges(v->g, v->d.stream, v->is_f64, v->rate, v->d.ranges, d_blocks,
+                         &v->d.ctr->err, as_stream(hip_stream));
+    BCMC_HIP_TRY(hipGetLastError());
+    return BCMC_OK;
+}
+
+int bcmc_debug_ranges(const bcmc_volume *v, float *h_ranges) {
+    if (!v || !h_ranges) return invalid("null argument");
+    BCMC_HIP_TRY(hipDeviceSynchronize());
+    BCMC_HIP_TRY(hipMemcpy(h_ranges, v->d.ranges, v->g.nb * sizeof(float2), hipMemcpyDeviceToHost));
+    return BCMC_OK;
+}
+
+int bcmc_debug_active(const bcmc_volume *v, uint8_t *h_active, uint32_t *h_I_active,
+                      uint64_t *h_n_active) {
+    if (!v) return invalid("null handle");
+    if (!v->have_extract) return invalid("no extract yet");
+    BCMC_HIP_TRY(hipDeviceSynchronize());
+    uint64_t n = v->h_ctr->n_act;
+    if (h_n_active) *h_n_active = n;
+    if (h_active) BCMC_HIP_TRY(hipMemcpy(h_active, v->d.active, v->g.nb, hipMemcpyDeviceToHost));
+    if (h_I_active && n)
+        BCMC_HIP_TRY(hipMemcpy(h_I_active, v->d.I_active, n * 4, hipMemcpyDeviceToHost));
+    return BCMC_OK;
+}
+
+int bcmc_debug_new(const bcmc_volume *v, uint32_t *h_I_new, uint64_t *h_n_new) {
+    if (!v) return invalid("null handle");
+    if (!v->have_extract || v->identity) return invalid("no cached extract yet");
+    BCMC_HIP_TRY(hipDeviceSynchronize());
+    uint64_t n = v->h_ctr->n_new;
+    if (h_n_new) *h_n_new = n;
+    if (h_I_new && n) BCMC_HIP_TRY(hipMemcpy(h_I_new, v->d.I_new, n * 4, hipMemcpyDeviceToHost));
+    return BCMC_OK;
+}
+
+int bcmc_debug_cache_state(const bcmc_volume *v, int32_t *h_I_slot, int32_t *h_S_block,
+                           uint32_t *h_S_age, uint64_t *h_n_slots) {
+    if (!v) return invalid("null handle");
+    if (v->identity) return invalid("identity volumes have no cache");
+    BCMC_HIP_TRY(hipDeviceSynchronize());
+    if (h_n_slots) *h_n_slots = v->n_slots;
+    if (h_I_slot) BCMC_HIP_TRY(hipMemcpy(h_I_slot, v->d.I_slot, v->g.nb * 4, hipMemcpyDeviceToHost));
+    if (h_S_block && v->n_slots)
+        BCMC_HIP_TRY(hipMemcpy(h_S_block, v->d.S_block, v->n_slots * 4, hipMemcpyDeviceToHost));
+    if (h_S_age && v->n_slots)
+        BCMC_HIP_TRY(hipMemcpy(h_S_age, v->d.S_age, v->n_slots * 4, hipMemcpyDeviceToHost));
+    return BCMC_OK;
+}
+
+int bcmc_debug_slot_data(const bcmc_volume *v, float *h_slots) {
+    if (!v || !h_slots) return invalid("null argument");
+    if (v->identity) return invalid("identity volumes have no cache");
+    BCMC_HIP_TRY(hipDeviceSynchronize());
+    if (v->n_slots)
+        BCMC_HIP_TRY(hipMemcpy(h_slots, v->d.slots, v->n_slots * 256, hipMemcpyDeviceToHost));
+    return BCMC_OK;
+}
+
+int bcmc_debug_block_counts(const bcmc_volume *v, uint32_t *h_cnt, uint64_t *h_off, uint64_t n) {
+    if (!v) return invalid("null handle");
+    if (!v->have_extract) return invalid("no extract yet");
+    if (n > v->h_ctr->n_act) return invalid("n exceeds the active block count");
+    BCMC_HIP_TRY(hipDeviceSynchronize());
+    if (h_cnt && n) BCMC_HIP_TRY(hipMemcpy(h_cnt, v->d.blk_cnt, n * 4, hipMemcpyDeviceToHost));
+    if (h_off && n) BCMC_HIP_TRY(hipMemcpy(h_off, v->d.blk_off, n * 8, hipMemcpyDeviceToHost));
+    return BCMC_OK;
+}
+
+int bcmc_debug_cases(bcmc_volume *v, float iso, uint8_t *d_cases, void *hip_stream) {
+    if (!v || !d_cases) return invalid("null argument");
+    if (!v->have_extract || iso != v->last_iso) return invalid("no extract at this iso");
+    const float *slots = v->identity ? v->ext_blocks : v->d.slots;
+    launch_debug_cases(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_cases, v->g.nb,
+                       as_stream(hip_stream));
+    BCMC_HIP_TRY(hipGetLastError());
+    return BCMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal definitions shared by the HIP sources of libbcmc (not part of the
+// C ABI).  gfx950 only: wave64, one process per GPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace bcmc {
+
+// ---- constants ----------------------------------------------------------
+constexpr uint32_t HIGH_AGE = 0x80000000u;  // age of a slot created empty
+constexpr int BLK_TILE = 4096;               // blocks per compaction tile
+constexpr int SLOT_TILE = 4096;              // slots per compaction tile
+constexpr int RADIX_TILE = 1024;             // elements per radix tile (1 wave)
+constexpr int SCAN_TILE = 4096;              // u32 per look-back scan tile
+constexpr int MC_WAVES = 4;                  // blocks (one per wave) per MC tile
+
+// look-back status words: 2 flag bits on top, value below
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_PRE = 2ull << 62;
+constexpr uint64_t LB_VAL = (1ull << 62) - 1;
+
+enum : uint32_t { ERR_CACHE_CAP = 1u, ERR_NONFINITE = 2u, ERR_INTERNAL = 4u };
+
+// Device-resident scalars of one extract call.  Written only by kernels of
+// that call, read back once by the host at its end.
+struct Counters {
+    unsigned long long n_act;        // active blocks
+    unsigned long long n_new;        // active blocks not in the cache
+    unsigned long long n_avail;      // available slots (after growth)
+    unsigned long long n_slots;      // slots in use by the cache (after growth)
+    unsigned long long n_slots_old;  // slots before growth
+    unsigned long long n_avail_old;  // available slots before growth
+    unsigned long long n_grow;       // slots added this call
+    unsigned long long n_evicted;    // blocks evicted this call
+    unsigned long long n_occ;        // active blocks that emit triangles
+    unsigned long long total_verts;  // 3 * triangles
+    unsigned int err;                // ERR_* bits
+    unsigned int key_or, key_and;    // OR / AND of the sort keys of available slots
+    unsigned int pass_mask;          // radix digits that vary (bit p = digit p)
+    unsigned int tile_ctr[8];        // dynamic tile counters of look-back kernels
+};
+enum { TC_BLK = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */ };
+
+// Geometry of a volume in blocks.
+struct Geom {
+    uint32_t nx, ny, nz;
+    uint32_t nbx, nby, nbz;
+    uint64_t nb;
+};
+
+// Device buffers of a volume (all owned by the volume).
+struct DevState {
+    uint64_t *stream = nullptr;     // fixed-rate ZFP words, block b at b*rate
+    float2 *ranges = nullptr;       // per block (min, max) of decoded valid samples
+    uint8_t *active = nullptr;      // M_active
+    uint32_t *I_active = nullptr;   // ascending active block ids
+    uint32_t *I_new = nullptr;      // ascending new block ids
+    int32_t *I_slot = nullptr;      // per block: slot or -1
+    // cache (max_slots entries)
+    int32_t *S_block = nullptr;
+    uint32_t *S_age = nullptr;
+    float *slots = nullptr;         // [max_slots][64] decoded blocks
+    uint32_t *sort_key[2] = {nullptr, nullptr};  // ~age of available slots
+    uint32_t *sort_val[2] = {nullptr, nullptr};  // slot ids
+    uint32_t *radix_hist = nullptr;              // 256 * radix tiles
+    // MC
+    uint32_t *blk_cnt = nullptr;    // per active block vertex count
+    uint64_t *blk_off = nullptr;    // per active block first vertex
+    uint64_t *status = nullptr;     // look-back status words (all kernels)
+    Counters *ctr = nullptr;
+    uint64_t *mc_table = nullptr;   // 256 packed cases
+};
+
+// Offsets of each kernel's region inside DevState::status.
+struct StatusLayout {
+    uint64_t blk, slot, mc, scan, total;
+};
+
+// ---- launchers (extract.hip) -------------------------------------------
+void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
+                 uint64_t n_slots_host, hipStream_t s);
+void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
+                           int identity_cache, hipStream_t s);
+void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
+                      hipStream_t s);
+void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound, hipStream_t s);
+void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, hipStream_t s);
+void launch_mc(const Geom &g, const DevState &d, const StatusLayout &sl, const float *slots,
+               const int32_t *I_slot, int identity_cache, float iso, void *out,
+               uint64_t cap_verts, uint64_t max_tiles, hipStream_t s);
+void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
+                        const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
+                        uint64_t max_act, hipStream_t s);
+void launch_backward(const Geom &g, const DevState &d, const float *slots, float iso,
+                     const float *gV, float *dfield, float *diso, uint64_t max_act,
+                     hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_iota_i32(int32_t *p, uint64_t n, hipStream_t s);
+
+// ---- launchers (zfp.hip) -----------------------------------------------
+void launch_decode_ranges(const Geom &g, const uint64_t *stream, int is_f64, uint32_t rate,
+                          float2 *ranges, float *blocks_out, unsigned int *err, hipStream_t s);
+void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *ranges,
+                               unsigned int *err, hipStream_t s);
+void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new,
+                          hipStream_t s);
+void launch_encode(const Geom &g, const void *field, int is_f64, uint32_t rate,
+                   uint64_t *stream, unsigned int *err, hipStream_t s);
+
+// ---- host-side tables (tables.cpp) --------------------------------------
+// Packed marching cubes table: bits 4k..4k+3 = k-th edge id (15 = unused),
+// bits 60..63 = number of triangles.
+const uint64_t *mc_table_host();
+int mc_table_status();  // 0 when the generator succeeded
+
+// ---- error reporting (capi.cpp) -----------------------------------------
+void set_error(const std::string &msg);
+
+}  // namespace bcmc
+
+#define BCMC_HIP_TRY(expr)                                                  \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            bcmc::set_error(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return BCMC_E_HIP;                                              \
+        }                                                                   \
+    } while (0)

@@ -1,0 +1,821 @@
+// Extraction kernels for gfx950 (paper Sec. 4): active-block culling (4.1),
+// the GPU-driven LRU cache update (4.2, Alg. 1), and block-wise marching cubes
+// (4.3-4.5).  Every count the host does not know is read from device memory,
+// so the whole sequence is enqueued without host round-trips.
+//
+// Shared idioms:
+//   * wave64 primitives: ballot / mbcnt compaction, shuffle scans;
+//   * single-pass scans with decoupled look-back (Merrill & Garland 2016):
+//     each tile publishes its aggregate, then its inclusive prefix, in a
+//     64-bit status word (2 flag bits + value); tiles are taken from an atomic
+//     counter in order, so a tile only ever waits on tiles already running.
+#include <stdint.h>
+
+#include "common.h"
+
+namespace bcmc {
+namespace {
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back, run by one whole wave: publishes `agg` for tile t and
+// returns the exclusive prefix of the tile.  64 predecessors are inspected
+// per step: the window is summed up to (and including) the nearest tile
+// that already holds an inclusive prefix.
+__device__ uint64_t lookback(uint64_t *status, uint64_t t, uint64_t agg) {
+    const int l = lane();
+    if (t == 0) {
+        if (l == 0) lb_store(&status[0], LB_PRE | agg);
+        return 0;
+    }
+    if (l == 0) lb_store(&status[t], LB_AGG | agg);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)t - 1;
+    for (;;) {
+        int64_t idx = j - l;
+        uint64_t w = idx >= 0 ? lb_load(&status[idx]) : LB_PRE;
+        uint64_t flag = w & ~LB_VAL;
+        uint64_t pre = __ballot(flag == LB_PRE);
+        uint64_t notready = __ballot(flag == 0);
+        int first = pre ? (int)__builtin_ctzll(pre) : 64;
+        uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (notready & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t v = (l <= first) ? (w & LB_VAL) : 0;
+        excl += wave_sum(v);
+        if (first < 64) break;
+        j -= 64;
+    }
+    if (l == 0) lb_store(&status[t], LB_PRE | (excl + agg));
+    return excl;
+}
+
+// Workgroup (256 threads = 4 waves) exclusive scan of one value per thread
+// followed by the look-back; returns the thread's global exclusive prefix and
+// the tile total through *total (inclusive prefix of the tile in *incl_end).
+__device__ uint64_t tile_scan_lookback(uint64_t v, uint64_t *status, uint64_t t,
+                                       uint64_t *incl_end) {
+    __shared__ uint64_t s_w[4];
+    __shared__ uint64_t s_excl;
+    const int w = threadIdx.x >> 6;
+    uint64_t incl = wave_incl_scan(v);
+    if (lane() == 63) s_w[w] = incl;
+    __syncthreads();
+    uint64_t woff = 0, agg = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (i < w) woff += s_w[i];
+        agg += s_w[i];
+    }
+    if (w == 0) {
+        uint64_t e = lookback(status, t, agg);
+        if (lane() == 0) s_excl = e;
+    }
+    __syncthreads();
+    uint64_t e = s_excl;
+    *incl_end = e + agg;
+    __syncthreads();  // s_w / s_excl are reused by the next tile
+    return e + woff + incl - v;
+}
+
+__device__ __forceinline__ uint32_t take_tile(unsigned int *ctr) {
+    __shared__ uint32_t s_tile;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
+    __syncthreads();
+    uint32_t t = s_tile;
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 4.1: active blocks.  Block b is active when its range, or its range
+// united with the range of one of its 26 neighbours, contains iso
+// (lo < iso <= hi).  With LO / HI the min / max over the 3x3x3 neighbourhood
+// that is:  (lo_b < iso <= HI)  or  (LO < iso <= hi_b).
+// Also resets the call's counters and clears the look-back status words.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
+                                             uint8_t *__restrict__ active, Counters *ctr,
+                                             uint64_t n_slots_host, uint64_t *status,
+                                             uint64_t status_words) {
+    const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+    if (gid == 0) {
+        Counters c{};
+        c.n_slots = n_slots_host;
+        c.n_slots_old = n_slots_host;
+        c.key_or = 0u;
+        c.key_and = ~0u;
+        *ctr = c;
+    }
+    for (uint64_t w = gid; w < status_words; w += gsz) status[w] = 0;
+    for (uint64_t b = gid; b < g.nb; b += gsz) {
+        uint32_t bx = (uint32_t)(b % g.nbx);
+        uint64_t r = b / g.nbx;
+        uint32_t by = (uint32_t)(r % g.nby), bz = (uint32_t)(r / g.nby);
+        float2 own = ranges[b];
+        float LO = own.x, HI = own.y;
+        for (int dz = -1; dz <= 1; dz++) {
+            int z = (int)bz + dz;
+            if (z < 0 || z >= (int)g.nbz) continue;
+            for (int dy = -1; dy <= 1; dy++) {
+                int y = (int)by + dy;
+                if (y < 0 || y >= (int)g.nby) continue;
+                const float2 *row = ranges + ((uint64_t)z * g.nby + y) * g.nbx;
+                for (int dx = -1; dx <= 1; dx++) {
+                    int x = (int)bx + dx;
+                    if (x < 0 || x >= (int)g.nbx) continue;
+                    float2 q = row[x];
+                    LO = fminf(LO, q.x);
+                    HI = fmaxf(HI, q.y);
+                }
+            }
+        }
+        bool act = (own.x < iso && iso <= HI) || (LO < iso && iso <= own.y);
+        active[b] = act ? 1 : 0;
+    }
+}
+
+// I_active (StreamCompactIDs of M_active) and I_new (active blocks without a
+// slot, Alg. 1 MarkNewBlocks) in one look-back pass over the blocks.  Counts
+// are packed as (active << 31 | new) so one status word carries both.
+__global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *__restrict__ active,
+                                                       const int32_t *__restrict__ I_slot,
+                                                       int identity, uint32_t *__restrict__ I_active,
+                                                       uint32_t *__restrict__ I_new, Counters *ctr,
+                                                       uint64_t *status) {
+    const uint64_t n_tiles = (g.nb + BLK_TILE - 1) / BLK_TILE;
+    const uint32_t t = take_tile(&ctr->tile_ctr[TC_BLK]);
+    if (t >= n_tiles) return;
+    const uint64_t base = (uint64_t)t * BLK_TILE + threadIdx.x * 16u;
+    uint32_t actb = 0, newb = 0;
+    if (base + 16 <= g.nb) {
+        uint4 q = *reinterpret_cast<const uint4 *>(active + base);
+        uint32_t wds[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            if ((wds[j >> 2] >> (8 * (j & 3))) & 0xFFu) actb |= 1u << j;
+    } else {
+        for (int j = 0; j < 16; j++)
+            if (base + j < g.nb && active[base + j]) actb |= 1u << j;
+    }
+    if (!identity) {
+        for (uint32_t m = actb; m; m &= m - 1) {
+            int j = __builtin_ctz(m);
+            if (I_slot[base + j] < 0) newb |= 1u << j;
+        }
+    }
+    uint64_t v = ((uint64_t)__popc(actb) << 31) | (uint64_t)__popc(newb);
+    uint64_t incl_end;
+    uint64_t e = tile_scan_lookback(v, status, t, &incl_end);
+    uint64_t oa = e >> 31, on = e & 0x7FFFFFFFull;
+    for (uint32_t m = actb; m; m &= m - 1) I_active[oa++] = (uint32_t)(base + __builtin_ctz(m));
+    for (uint32_t m = newb; m; m &= m - 1) I_new[on++] = (uint32_t)(base + __builtin_ctz(m));
+    if (t == n_tiles - 1 && threadIdx.x == 0) {
+        ctr->n_act = incl_end >> 31;
+        ctr->n_new = incl_end & 0x7FFFFFFFull;
+    }
+}
+
+// Alg. 1 IncrementSlotAge + the slot half of MarkNewBlocks, then
+// StreamCompactIDs of the available slots (I_avail) and StreamCompact of their
+// ages (K_age, stored as ~age so that ascending key = descending age).
+__global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ active,
+                                                  const int32_t *__restrict__ S_block,
+                                                  uint32_t *__restrict__ S_age, uint64_t n_slots,
+                                                  uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals, Counters *ctr,
+                                                  uint64_t *status) {
+    const uint64_t n_tiles = (n_slots + SLOT_TILE - 1) / SLOT_TILE;
+    const uint32_t t = take_tile(&ctr->tile_ctr[TC_SLOT]);
+    if (t >= n_tiles) return;
+    const bool need_list = ctr->n_new != 0;
+    const uint64_t base = (uint64_t)t * SLOT_TILE + threadIdx.x * 16u;
+    uint32_t availb = 0;
+    uint32_t age[16];
+    uint32_t kor = 0, kand = ~0u;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        uint64_t s = base + j;
+        age[j] = 0;
+        if (s < n_slots) {
+            int32_t b = S_block[s];
+            bool act = b >= 0 && active[b];
+            uint32_t a = S_age[s];
+            a = act ? 0u : (a == 0xFFFFFFFFu ? a : a + 1u);
+            S_age[s] = a;
+            age[j] = a;
+            if (!act) {
+                availb |= 1u << j;
+                kor |= ~a;
+                kand &= ~a;
+            }
+        }
+    }
+    if (!need_list) return;
+    uint64_t incl_end;
+    uint64_t e = tile_scan_lookback((uint64_t)__popc(availb), status, t, &incl_end);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+        if ((availb >> j) & 1u) {
+            keys[e] = ~age[j];
+            vals[e] = (uint32_t)(base + j);
+            e++;
+        }
+    // OR / AND of the keys: which radix digits vary
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        kor |= __shfl_xor(kor, d, 64);
+        kand &= __shfl_xor(kand, d, 64);
+    }
+    if (lane() == 0) {
+        atomicOr(&ctr->key_or, kor);
+        atomicAnd(&ctr->key_and, kand);
+    }
+    if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_avail_old = incl_end;
+}
+
+// Alg. 1 "exit if n_new = 0" / "grow if n_new > n_avail": every workgroup
+// derives the same plan from values no kernel of this launch writes; block 0
+// publishes it and all threads initialise the appended slots (empty,
+// available, age HIGH_AGE) and append them to the available list.
+__global__ __launch_bounds__(256) void k_plan_grow(Counters *ctr, uint64_t max_slots,
+                                                  int32_t *__restrict__ S_block,
+                                                  uint32_t *__restrict__ S_age,
+                                                  uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals) {
+    const uint64_t n_new = ctr->n_new;
+    if (ctr->err || n_new == 0) return;
+    const uint64_t na = ctr->n_avail_old, ns = ctr->n_slots_old;
+    uint64_t grow = 0;
+    if (n_new > na) {
+        grow = n_new - na;
+        uint64_t half = (ns + 1) / 2;
+        if (half > grow) grow = half;
+        if (ns + grow > max_slots) grow = max_slots - ns;
+    }
+    const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (na + grow < n_new) {
+        if (gid == 0) ctr->err |= ERR_CACHE_CAP;
+        return;
+    }
+    if (gid == 0) {
+        uint32_t kor = ctr->key_or, kand = ctr->key_and;
+        if (grow) {
+            kor |= ~HIGH_AGE;
+            kand &= ~HIGH_AGE;
+        }
+        uint32_t vary = kor ^ kand;
+        uint32_t mask = 0;
+        for (int p = 0; p < 4; p++)
+            if ((vary >> (8 * p)) & 0xFFu) mask |= 1u << p;
+        ctr->pass_mask = mask;
+        ctr->n_grow = grow;
+        ctr->n_slots = ns + grow;
+        ctr->n_avail = na + grow;
+    }
+    for (uint64_t i = gid; i < grow; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t s = ns + i;
+        S_block[s] = -1;
+        S_age[s] = HIGH_AGE;
+        keys[na + i] = ~HIGH_AGE;
+        vals[na + i] = (uint32_t)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 SortByKey: stable LSD radix sort of the available slots by ~age
+// (8-bit digits).  Digits on which every key agrees are skipped: a pass over
+// such a digit is the identity.  Tiles of 1024 elements are owned by single
+// waves, striped as element = tile*1024 + round*64 + lane.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool radix_pass_live(const Counters *ctr, int p) {
+    return !ctr->err && ctr->n_new != 0 && ((ctr->pass_mask >> p) & 1u);
+}
+__device__ __forceinline__ int radix_in_buf(const Counters *ctr, int p) {
+    return __popc(ctr->pass_mask & ((1u << p) - 1u)) & 1;
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(Counters *ctr, int p,
+                                                   const uint32_t *__restrict__ keys0,
+                                                   const uint32_t *__restrict__ keys1,
+                                                   uint32_t *__restrict__ hist, uint64_t *status) {
+    if (!radix_pass_live(ctr, p)) return;
+    const uint32_t *keys = radix_in_buf(ctr, p) ? keys1 : keys0;
+    const uint64_t n = ctr->n_avail;
+    const uint64_t n_tiles = (n + RADIX_TILE - 1) / RADIX_TILE;
+    const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
+    // clear the scan's status words and tile counter for this pass
+    const uint64_t scan_tiles = (256 * n_tiles + SCAN_TILE - 1) / SCAN_TILE;
+    for (uint64_t w = gid; w < scan_tiles; w += gsz) status[w] = 0;
+    if (gid == 0) ctr->tile_ctr[TC_SCAN0 + p] = 0;
+    __shared__ uint32_t h[4][256];
+    const int w = threadIdx.x >> 6;
+    const int shift = 8 * p;
+    const uint64_t waves = (uint64_t)gridDim.x * 4;
+    for (uint64_t tb = blockIdx.x * 4ull; tb < n_tiles; tb += waves) {
+        uint64_t tile = tb + w;
+        for (int i = lane(); i < 256; i += 64) h[w][i] = 0;
+        __syncthreads();
+        if (tile < n_tiles) {
+            for (int r = 0; r < RADIX_TILE / 64; r++) {
+                uint64_t idx = tile * RADIX_TILE + r * 64 + lane();
+                if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 0xFFu], 1u);
+            }
+        }
+        __syncthreads();
+        if (tile < n_tiles)
+            for (int d = lane(); d < 256; d += 64) hist[(uint64_t)d * n_tiles + tile] = h[w][d];
+        __syncthreads();
+    }
+}
+
+// In-place exclusive scan of the digit-major histogram (256 * n_tiles u32).
+__global__ __launch_bounds__(256) void k_radix_scan(Counters *ctr, int p, uint32_t *hist,
+                                                   uint64_t *status) {
+    if (!radix_pass_live(ctr, p)) return;
+    const uint64_t n_tiles = (ctr->n_avail + RADIX_TILE - 1) / RADIX_TILE;
+    const uint64_t len = 256 * n_tiles;
+    const uint64_t scan_tiles = (len + SCAN_TILE - 1) / SCAN_TILE;
+    for (;;) {
+        const uint32_t t = take_tile(&ctr->tile_ctr[TC_SCAN0 + p]);
+        if (t >= scan_tiles) return;
+        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * 16u;
+        uint32_t x[16];
+        uint64_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            x[j] = base + j < len ? hist[base + j] : 0u;
+            sum += x[j];
+        }
+        uint64_t incl_end;
+        uint64_t e = tile_scan_lookback(sum, status, t, &incl_end);
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            if (base + j < len) hist[base + j] = (uint32_t)e;
+            e += x[j];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(Counters *ctr, int p,
+                                                      uint32_t *keys0, uint32_t *keys1,
+                                                      uint32_t *vals0, uint32_t *vals1,
+                                                      const uint32_t *__restrict__ hist) {
+    if (!radix_pass_live(ctr, p)) return;
+    const int in = radix_in_buf(ctr, p);
+    const uint32_t *__restrict__ kin = in ? keys1 : keys0;
+    const uint32_t *__restrict__ vin = in ? vals1 : vals0;
+    uint32_t *__restrict__ kout = in ? keys0 : keys1;
+    uint32_t *__restrict__ vout = in ? vals0 : vals1;
+    const uint64_t n = ctr->n_avail;
+    const uint64_t n_tiles = (n + RADIX_TILE - 1) / RADIX_TILE;
+    __shared__ uint32_t off[4][256];
+    const int w = threadIdx.x >> 6;
+    const int l = lane();
+    const int shift = 8 * p;
+    const uint64_t lt = (1ull << l) - 1ull;
+    const uint64_t waves = (uint64_t)gridDim.x * 4;
+    for (uint64_t tile = blockIdx.x * 4ull + w; tile < n_tiles; tile += waves) {
+        for (int d = l; d < 256; d += 64) off[w][d] = hist[(uint64_t)d * n_tiles + tile];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int r = 0; r < RADIX_TILE / 64; r++) {
+            uint64_t idx = tile * RADIX_TILE + r * 64 + l;
+            bool valid = idx < n;
+            uint32_t key = valid ? kin[idx] : 0u;
+            uint32_t val = valid ? vin[idx] : 0u;
+            uint32_t d = (key >> shift) & 0xFFu;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; bit++) {
+                uint64_t m = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? m : ~m;
+            }
+            uint32_t base = off[w][d];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid) {
+                uint32_t pos = base + (uint32_t)__popcll(peers & lt);
+                if (pos < n) {
+                    kout[pos] = key;
+                    vout[pos] = val;
+                } else {
+                    atomicOr(&ctr->err, ERR_INTERNAL);
+                }
+                if ((peers & lt) == 0) off[w][d] = base + (uint32_t)__popcll(peers);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Marching cubes over the active blocks (Sec. 4.3-4.5).  One wave64 owns one
+// 4^3 block: lane = dual cell.  The block and its +x/+y/+z halo (5^3
+// samples) are staged in LDS from the cache slots of the block and its 7
+// positive neighbours.  If an in-volume positive neighbour is inactive, every
+// sample the block's cells read lies on one side of iso (the culling rule is
+// exact), so the block emits nothing and is skipped.
+// Count, block scan and emission are fused: a 4-block tile takes its output
+// offset by decoupled look-back, then writes its triangle soup lane-per-vertex.
+// ---------------------------------------------------------------------------
+struct Halo {
+    int ok;                 // block may emit (all in-volume + neighbours active)
+    int bad;                // a needed block has no slot (internal error)
+    uint32_t bx, by, bz;
+    uint32_t nslot[8];      // slots of the block (0) and its + neighbours (mask dx|dy<<1|dz<<2)
+};
+
+__device__ __forceinline__ void halo_setup(const Geom &g, uint32_t b, const uint8_t *__restrict__ active,
+                                           const int32_t *__restrict__ I_slot, int identity, Halo &h) {
+    h.bx = b % g.nbx;
+    uint32_t r = b / g.nbx;
+    h.by = r % g.nby;
+    h.bz = r / g.nby;
+    h.ok = 1;
+    h.bad = 0;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        uint32_t x = h.bx + (m & 1), y = h.by + ((m >> 1) & 1), z = h.bz + (m >> 2);
+        h.nslot[m] = 0;
+        if (x < g.nbx && y < g.nby && z < g.nbz) {
+            uint32_t nb = x + g.nbx * (y + g.nby * z);
+            if (m && !active[nb]) {
+                h.ok = 0;
+            } else if (identity) {
+                h.nslot[m] = nb;
+            } else {
+                int32_t s = I_slot[nb];
+                if (s < 0) h.bad = 1;
+                h.nslot[m] = s < 0 ? 0u : (uint32_t)s;
+            }
+        }
+    }
+    if (h.bad) h.ok = 0;
+}
+
+// LDS index of sample (x,y,z) of the 5^3 tile
+__device__ __forceinline__ int tix(int x, int y, int z) { return x + 5 * y + 25 * z; }
+
+// Stage the 125 samples: lane -> own sample, lanes 0..60 -> one halo sample.
+__device__ __forceinline__ void stage_tile(const Geom &g, const Halo &h, const float *__restrict__ slots,
+                                           float *tile) {
+    const int l = lane();
+    const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    tile[tix(lx, ly, lz)] = slots[(uint64_t)h.nslot[0] * 64 + l];
+    if (l < 61) {
+        int x, y, z;
+        if (l < 16) { x = 4; y = l & 3; z = l >> 2; }
+        else if (l < 32) { x = l & 3; y = 4; z = (l >> 2) & 3; }
+        else if (l < 48) { x = l & 3; y = (l >> 2) & 3; z = 4; }
+        else if (l < 52) { x = 4; y = 4; z = l - 48; }
+        else if (l < 56) { x = 4; y = l - 52; z = 4; }
+        else if (l < 60) { x = l - 56; y = 4; z = 4; }
+        else { x = 4; y = 4; z = 4; }
+        int m = (x >> 2) | ((y >> 2) << 1) | ((z >> 2) << 2);
+        bool inside = (h.bx + (x >> 2) < g.nbx) && (h.by + (y >> 2) < g.nby) && (h.bz + (z >> 2) < g.nbz);
+        float v = 0.0f;
+        if (inside) v = slots[(uint64_t)h.nslot[m] * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)];
+        tile[tix(x, y, z)] = v;
+    }
+}
+
+// Case of the lane's cell (corner k at +(k&1, k>>1&1, k>>2&1); bit k set when
+// the corner value is below iso) or -1 when the cell lies outside the volume.
+__device__ __forceinline__ int cell_case(const Geom &g, const Halo &h, const float *tile, float iso) {
+    const int l = lane();
+    const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    if (!h.ok) return -1;
+    if (4 * h.bx + lx + 1 >= g.nx || 4 * h.by + ly + 1 >= g.ny || 4 * h.bz + lz + 1 >= g.nz) return -1;
+    int cs = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (tile[tix(lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2))] < iso) cs |= 1 << k;
+    return cs;
+}
+
+// Edge e of a cell: its lower endpoint offset and axis.
+__device__ __forceinline__ void edge_geom(int e, int &ox, int &oy, int &oz, int &axis) {
+    axis = e >> 2;
+    int b0 = e & 1, b1 = (e >> 1) & 1;
+    ox = axis == 0 ? 0 : b0;
+    oy = axis == 1 ? 0 : (axis == 0 ? b0 : b1);
+    oz = axis == 2 ? 0 : b1;
+}
+
+struct McShared {
+    uint64_t tab[256];
+    float tile[MC_WAVES][128];
+    uint32_t pref[MC_WAVES][64];
+    uint8_t cs[MC_WAVES][64];
+    uint8_t map[MC_WAVES][64 * 15];
+    uint32_t wtot[MC_WAVES];
+    uint64_t excl;
+};
+
+__global__ __launch_bounds__(256) void k_mc(Geom g, const uint32_t *__restrict__ I_active,
+                                           const uint8_t *__restrict__ active,
+                                           const int32_t *__restrict__ I_slot, int identity,
+                                           const float *__restrict__ slots,
+                                           const uint64_t *__restrict__ mc_table, float iso,
+                                           uint4 *__restrict__ out, uint64_t cap,
+                                           uint32_t *__restrict__ blk_cnt,
+                                           uint64_t *__restrict__ blk_off, Counters *ctr,
+                                           uint64_t *status) {
+    __shared__ McShared sh;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
+    const uint64_t n_act = ctr->n_act;
+    if (ctr->err) return;
+    const uint64_t n_tiles = (n_act + MC_WAVES - 1) / MC_WAVES;
+    const int w = threadIdx.x >> 6, l = lane();
+    float *tile = sh.tile[w];
+    for (;;) {
+        const uint32_t t = take_tile(&ctr->tile_ctr[TC_MC]);
+        if (t >= n_tiles) break;
+        const uint64_t i = (uint64_t)t * MC_WAVES + w;
+        const bool have = i < n_act;
+        const uint32_t b = have ? I_active[i] : 0u;
+        Halo h;
+        halo_setup(g, b, active, I_slot, identity, h);
+        if (h.bad && have && l == 0) atomicOr(&ctr->err, ERR_INTERNAL);
+        h.ok = h.ok && have;
+        if (h.ok) stage_tile(g, h, slots, tile);
+        __syncthreads();
+        const int cs = cell_case(g, h, tile, iso);
+        const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
+        const uint32_t incl = wave_incl_scan(nv);
+        const uint32_t total = __shfl(incl, 63, 64);
+        sh.pref[w][l] = incl - nv;
+        sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
+        for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
+        if (l == 0) sh.wtot[w] = total;
+        __syncthreads();
+        uint64_t woff = 0, agg = 0;
+#pragma unroll
+        for (int k = 0; k < MC_WAVES; k++) {
+            if (k < w) woff += sh.wtot[k];
+            agg += sh.wtot[k];
+        }
+        if (w == 0) {
+            uint64_t e = lookback(status, t, agg);
+            if (l == 0) sh.excl = e;
+        }
+        __syncthreads();
+        const uint64_t base = sh.excl + woff;
+        if (t == n_tiles - 1 && threadIdx.x == 0) ctr->total_verts = sh.excl + agg;
+        if (have && l == 0) {
+            blk_cnt[i] = total;
+            blk_off[i] = base;
+            if (total) atomicAdd(&ctr->n_occ, 1ull);
+        }
+        // emission: lane per vertex, canonical order (cell, triangle, vertex)
+        for (uint32_t j = l; j < total; j += 64) {
+            const int c = sh.map[w][j];
+            const int k = (int)(j - sh.pref[w][c]);
+            const int ccs = sh.cs[w][c];
+            const int e = (int)((sh.tab[ccs] >> (4 * k)) & 15u);
+            int ox, oy, oz, axis;
+            edge_geom(e, ox, oy, oz, axis);
+            const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
+            const float a = tile[tix(x0, y0, z0)];
+            const float bv = tile[tix(x0 + (axis == 0), y0 + (axis == 1), z0 + (axis == 2))];
+            const float tt = (iso - a) / (bv - a);
+            float px = (float)x0, py = (float)y0, pz = (float)z0;
+            if (axis == 0) px += tt;
+            else if (axis == 1) py += tt;
+            else pz += tt;
+            const uint64_t o = base + j;
+            if (o < cap)
+                out[o] = make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+        }
+        __syncthreads();
+    }
+}
+
+// Cases of every cell of every active block (0 for cells outside the volume
+// or in blocks that cannot emit), [n_act][64].
+__global__ __launch_bounds__(256) void k_debug_cases(Geom g, const uint32_t *__restrict__ I_active,
+                                                    const uint8_t *__restrict__ active,
+                                                    const int32_t *__restrict__ I_slot, int identity,
+                                                    const float *__restrict__ slots, float iso,
+                                                    uint8_t *__restrict__ cases,
+                                                    const Counters *ctr) {
+    __shared__ float tiles[4][128];
+    const uint64_t n_act = ctr->n_act;
+    if (ctr->err) return;
+    const int w = threadIdx.x >> 6;
+    for (uint64_t i0 = blockIdx.x * 4ull; i0 < n_act; i0 += gridDim.x * 4ull) {
+        const uint64_t i = i0 + w;
+        const bool have = i < n_act;
+        Halo h;
+        halo_setup(g, have ? I_active[i] : 0u, active, I_slot, identity, h);
+        h.ok = h.ok && have;
+        if (h.ok) stage_tile(g, h, slots, tiles[w]);
+        __syncthreads();
+        int cs = cell_case(g, h, tiles[w], iso);
+        if (have) cases[i * 64 + lane()] = (uint8_t)(cs < 0 ? 0 : cs);
+        __syncthreads();
+    }
+}
+
+// Backward of the vertex positions through t = (iso - a)/(b - a), topology
+// fixed: for a vertex on an edge along axis e with dL/dv = gV,
+//   dL/dt = gV[e];  dL/da += dL/dt (t-1)/(b-a);  dL/db += dL/dt (-t)/(b-a);
+//   dL/diso += dL/dt / (b-a).
+// Recomputes the forward's per-block layout (same cells, same order) and
+// scatters into the block-layout field gradient.
+__global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__restrict__ I_active,
+                                                 const uint8_t *__restrict__ active,
+                                                 const float *__restrict__ slots,
+                                                 const uint64_t *__restrict__ mc_table, float iso,
+                                                 const uint64_t *__restrict__ blk_off,
+                                                 const float *__restrict__ gV,
+                                                 float *__restrict__ dfield, float *diso,
+                                                 const Counters *ctr) {
+    __shared__ McShared sh;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
+    __syncthreads();
+    const uint64_t n_act = ctr->n_act;
+    const int w = threadIdx.x >> 6, l = lane();
+    float *tile = sh.tile[w];
+    float giso = 0.0f;
+    for (uint64_t i0 = blockIdx.x * (uint64_t)MC_WAVES; i0 < n_act; i0 += gridDim.x * (uint64_t)MC_WAVES) {
+        const uint64_t i = i0 + w;
+        const bool have = i < n_act;
+        const uint32_t b = have ? I_active[i] : 0u;
+        Halo h;
+        halo_setup(g, b, active, nullptr, 1, h);
+        h.ok = h.ok && have;
+        if (h.ok) stage_tile(g, h, slots, tile);
+        __syncthreads();
+        const int cs = cell_case(g, h, tile, iso);
+        const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
+        const uint32_t incl = wave_incl_scan(nv);
+        const uint32_t total = __shfl(incl, 63, 64);
+        sh.pref[w][l] = incl - nv;
+        sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
+        for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
+        __syncthreads();
+        const uint64_t base = have ? blk_off[i] : 0;
+        for (uint32_t j = l; j < total; j += 64) {
+            const int c = sh.map[w][j];
+            const int k = (int)(j - sh.pref[w][c]);
+            const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * k)) & 15u);
+            int ox, oy, oz, axis;
+            edge_geom(e, ox, oy, oz, axis);
+            const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
+            const int x1 = x0 + (axis == 0), y1 = y0 + (axis == 1), z1 = z0 + (axis == 2);
+            const float a = tile[tix(x0, y0, z0)];
+            const float bv = tile[tix(x1, y1, z1)];
+            const float inv = 1.0f / (bv - a);
+            const float tt = (iso - a) * inv;
+            const float gt = gV[3 * (base + j) + axis];
+            // sample (x,y,z) of the 5^3 tile -> block id and local index
+            const uint32_t na = (h.bx + (x0 >> 2)) + g.nbx * ((h.by + (y0 >> 2)) + g.nby * (h.bz + (z0 >> 2)));
+            const uint32_t nb = (h.bx + (x1 >> 2)) + g.nbx * ((h.by + (y1 >> 2)) + g.nby * (h.bz + (z1 >> 2)));
+            atomicAdd(&dfield[(uint64_t)na * 64 + (x0 & 3) + 4 * (y0 & 3) + 16 * (z0 & 3)], gt * (tt - 1.0f) * inv);
+            atomicAdd(&dfield[(uint64_t)nb * 64 + (x1 & 3) + 4 * (y1 & 3) + 16 * (z1 & 3)], -gt * tt * inv);
+            giso += gt * inv;
+        }
+        __syncthreads();
+    }
+    giso = wave_sum(giso);
+    if (l == 0 && giso != 0.0f) atomicAdd(diso, giso);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_iota_i32(int32_t *p, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+unsigned grid_cap(uint64_t n_threads, unsigned cap) {
+    uint64_t gsz = (n_threads + 255) / 256;
+    if (gsz < 1) gsz = 1;
+    return (unsigned)(gsz < cap ? gsz : cap);
+}
+
+}  // namespace
+
+void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
+                 uint64_t n_slots_host, hipStream_t s) {
+    uint64_t work = g.nb > sl.total ? g.nb : sl.total;
+    k_cull<<<grid_cap(work, 16384), 256, 0, s>>>(g, d.ranges, iso, d.active, d.ctr, n_slots_host,
+                                                 d.status, sl.total);
+}
+
+void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
+                           int identity_cache, hipStream_t s) {
+    unsigned tiles = (unsigned)((g.nb + BLK_TILE - 1) / BLK_TILE);
+    k_compact_blocks<<<tiles, 256, 0, s>>>(g, d.active, d.I_slot, identity_cache, d.I_active,
+                                           d.I_new, d.ctr, d.status + sl.blk);
+}
+
+void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
+                      hipStream_t s) {
+    if (n_slots_host == 0) return;
+    unsigned tiles = (unsigned)((n_slots_host + SLOT_TILE - 1) / SLOT_TILE);
+    k_slot_pass<<<tiles, 256, 0, s>>>(d.active, d.S_block, d.S_age, n_slots_host, d.sort_key[0],
+                                      d.sort_val[0], d.ctr, d.status + sl.slot);
+}
+
+void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound, hipStream_t s) {
+    k_plan_grow<<<grid_cap(grow_bound, 2048), 256, 0, s>>>(d.ctr, max_slots, d.S_block, d.S_age,
+                                                          d.sort_key[0], d.sort_val[0]);
+}
+
+void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, hipStream_t s) {
+    uint64_t tiles = (max_elems + RADIX_TILE - 1) / RADIX_TILE;
+    unsigned grid = (unsigned)((tiles + 3) / 4 < 2048 ? (tiles + 3) / 4 : 2048);
+    if (grid == 0) grid = 1;
+    uint64_t scan_tiles = (256 * tiles + SCAN_TILE - 1) / SCAN_TILE;
+    unsigned sgrid = (unsigned)(scan_tiles < 2048 ? scan_tiles : 2048);
+    if (sgrid == 0) sgrid = 1;
+    for (int p = 0; p < 4; p++) {
+        k_radix_hist<<<grid, 256, 0, s>>>(d.ctr, p, d.sort_key[0], d.sort_key[1], d.radix_hist,
+                                          d.status + sl.scan);
+        k_radix_scan<<<sgrid, 256, 0, s>>>(d.ctr, p, d.radix_hist, d.status + sl.scan);
+        k_radix_scatter<<<grid, 256, 0, s>>>(d.ctr, p, d.sort_key[0], d.sort_key[1], d.sort_val[0],
+                                             d.sort_val[1], d.radix_hist);
+    }
+}
+
+void launch_mc(const Geom &g, const DevState &d, const StatusLayout &sl, const float *slots,
+               const int32_t *I_slot, int identity_cache, float iso, void *out,
+               uint64_t cap_verts, uint64_t max_tiles, hipStream_t s) {
+    unsigned grid = (unsigned)(max_tiles < 2048 ? max_tiles : 2048);
+    if (grid == 0) grid = 1;
+    k_mc<<<grid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, slots, d.mc_table,
+                              iso, reinterpret_cast<uint4 *>(out), cap_verts, d.blk_cnt, d.blk_off,
+                              d.ctr, d.status + sl.mc);
+}
+
+void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
+                        const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
+                        uint64_t max_act, hipStream_t s) {
+    unsigned grid = grid_cap(max_act * 64, 4096);
+    k_debug_cases<<<grid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, slots, iso,
+                                       cases, d.ctr);
+}
+
+void launch_backward(const Geom &g, const DevState &d, const float *slots, float iso,
+                     const float *gV, float *dfield, float *diso, uint64_t max_act,
+                     hipStream_t s) {
+    unsigned grid = grid_cap(max_act * 64, 2048);
+    k_backward<<<grid, 256, 0, s>>>(g, d.I_active, d.active, slots, d.mc_table, iso, d.blk_off, gV,
+                                    dfield, diso, d.ctr);
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n) k_fill_u32<<<grid_cap(n, 8192), 256, 0, s>>>(p, v, n);
+}
+
+void launch_iota_i32(int32_t *p, uint64_t n, hipStream_t s) {
+    if (n) k_iota_i32<<<grid_cap(n, 8192), 256, 0, s>>>(p, n);
+}
+
+}  // namespace bcmc

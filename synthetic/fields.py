@@ -27,6 +27,8 @@ __all__ = [
     "gaussian_blobs",
     "batched_dims",
     "percentile_iso",
+    "turbulence_torch",
+    "percentile_iso_torch",
 ]
 
 
@@ -147,3 +149,48 @@ def percentile_iso(values, p):
     taken in float64 and rounded to float32."""
     v = np.asarray(values, dtype=np.float64).ravel()
     return np.float32(np.percentile(v, p, method="linear"))
+
+
+def turbulence_torch(nx, ny=None, nz=None, seed=2, n_modes=256, device="cuda",
+                     kmin=1.0 / 512.0, kmax=1.0 / 16.0, slab=64):
+    """Same field as ``turbulence`` (same seeded modes), summed on ``device``
+    with torch in float64; returns a float32 tensor [nz, ny, nx].  The result
+    matches the numpy version up to the rounding of the mode sum."""
+    import torch
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    k, amp, phase = turbulence_modes(seed, n_modes, kmin, kmax)
+    kt = torch.tensor(k, dtype=torch.float64, device=device)
+    c = torch.tensor(amp * np.exp(1j * phase), dtype=torch.complex128, device=device)
+
+    def axis(n, col):
+        x = torch.arange(n, dtype=torch.float64, device=device)
+        return torch.exp(2j * np.pi * torch.outer(kt[:, col], x))      # [M, n]
+
+    X, Y, Z = axis(nx, 0), axis(ny, 1), axis(nz, 2)
+    out = torch.empty((nz, ny, nx), dtype=torch.float64, device=device)
+    for z0 in range(0, nz, slab):
+        z1 = min(nz, z0 + slab)
+        G = (c[None, None, :] * Z[:, z0:z1].T[:, None, :]) * Y.T[None, :, :]
+        out[z0:z1] = torch.real(G.reshape(-1, n_modes) @ X).reshape(z1 - z0, ny, nx)
+    out -= out.mean()
+    out /= out.std(unbiased=False)
+    return out.to(torch.float32)
+
+
+def percentile_iso_torch(values, p):
+    """``percentile_iso`` for a (possibly huge) torch tensor: sort on the
+    device, then numpy's linear interpolation in float64 between the two
+    neighbouring order statistics."""
+    import torch
+    v = values.reshape(-1)
+    n = v.numel()
+    h = (n - 1) * (p / 100.0)
+    lo = int(np.floor(h))
+    hi = min(lo + 1, n - 1)
+    s = torch.sort(v.to(torch.float32)).values
+    a, b = float(s[lo].item()), float(s[hi].item())
+    del s
+    t = h - lo
+    # numpy's linear interpolation, including its form for t >= 1/2
+    return np.float32(b - (b - a) * (1.0 - t) if t >= 0.5 else a + (b - a) * t)

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  Bit-exact for encoded/decoded values, ranges, active
+blocks, cache state, cases, cell lists, counts and block ids; vertices within
+1e-5 voxel of the FP64 oracle (and bit-exact against its FP32 mode)."""
+import numpy as np
+import pytest
+
+from synthetic import fields
+from tests.gpu_common import say, to_cuda, torch_cuda, verts_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bc():
+    torch_cuda()
+    import paper_2009_03254_amd as bcmc
+    bcmc.lib()
+    return bcmc
+
+
+ENC_CASES = [
+    ("sphere64", lambda: fields.sphere_sdf_noisy(64, 20.0, 0.5, seed=1), 16),
+    ("turb_ragged_r8", lambda: fields.turbulence(37, 29, 23, seed=21, n_modes=64), 8),
+    ("turb_ragged_r1", lambda: fields.turbulence(13, 9, 6, seed=22, n_modes=16), 1),
+    ("turb_r2", lambda: fields.turbulence(24, 24, 24, seed=23, n_modes=32), 2),
+    ("turb_r32", lambda: fields.turbulence(16, 12, 8, seed=24, n_modes=16), 32),
+    ("f64_r2", lambda: fields.turbulence(21, 18, 10, seed=25, n_modes=32, dtype=np.float64), 2),
+    ("f64_r8", lambda: fields.turbulence(16, 16, 16, seed=26, n_modes=32, dtype=np.float64), 8),
+    ("f64_r64", lambda: fields.turbulence(8, 8, 8, seed=27, n_modes=8, dtype=np.float64), 64),
+]
+
+
+def _special_field():
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((16, 16, 16)).astype(np.float32)
+    f[0:4, 0:4, 0:4] = 0.0                       # all-zero block
+    f[0:4, 0:4, 4:8] = 1.5                       # constant block
+    f[0:4, 4:8, 0:4] = 1e-40                     # subnormal block
+    f[4:8, 0:4, 0:4] = 3e38                      # huge block
+    f[4:8, 4:8, 4:8] *= 1e-30                    # tiny block
+    return f
+
+
+@pytest.mark.parametrize("name,make,rate", ENC_CASES + [("special_r8", _special_field, 8)])
+def test_encode_decode_bitexact(bc, orc, name, make, rate):
+    say(f"[encode/decode] {name} rate={rate}")
+    f = make()
+    nz, ny, nx = f.shape
+    is64 = f.dtype == np.float64
+    ref = orc.zfp_encode(f, rate)
+    got = bc.encode(to_cuda(f), rate).cpu().numpy()
+    assert np.array_equal(got, ref), "GPU encoder differs from the oracle encoder"
+    vol = bc.Volume(ref, (nx, ny, nz), "f64" if is64 else "f32", rate)
+    dec = vol.decode_all().cpu().numpy()
+    oref = orc.zfp_decode(ref, (nx, ny, nz), rate, is64)
+    assert np.array_equal(dec.view(np.uint32), oref.view(np.uint32))
+    assert np.array_equal(vol.ranges(), orc.block_ranges(oref, (nx, ny, nz)))
+    vol.close()
+
+
+def _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=True):
+    import torch
+    r = orc.mc_extract(D, dims, iso, want=("verts", "vblock", "cell_keys", "cases"))
+    out = torch.empty((3 * r["T"] + 7, 4), dtype=torch.int32, device="cuda")
+    rc, T = vol.extract_into(float(iso), out)
+    assert rc == 0, bc.lib().bcmc_last_error()
+    verts = out[: 3 * T]
+    assert T == r["T"], (T, r["T"])
+    xyz, blk = verts_np(verts)
+    assert np.array_equal(blk, r["vblock"])
+    err = np.abs(xyz.astype(np.float64) - r["verts"]).max() if T else 0.0
+    assert err <= 1e-5, err
+    v32, vb32 = orc.mc_extract_f32(D, dims, iso)
+    assert np.array_equal(xyz.view(np.uint32), v32.view(np.uint32))
+    # active blocks == the oracle's culling
+    act, ids = vol.active()
+    ract = orc.active_blocks(orc.block_ranges(D, dims), dims, iso)
+    assert np.array_equal(act, ract)
+    assert np.array_equal(ids, np.nonzero(ract)[0].astype(np.uint32))
+    if check_cells:
+        cases = vol.cases(iso).cpu().numpy()
+        nt, _ = bc.mc_table()
+        nontriv = nt[cases] > 0
+        keys = (ids.astype(np.uint64)[:, None] * 64 + np.arange(64, dtype=np.uint64))[nontriv]
+        assert np.array_equal(keys, r["cell_keys"])
+        assert np.array_equal(cases[nontriv], r["cases"])
+        # brute-force triangle count over the whole field
+        assert T == orc.brute_count_blocks(D, dims, iso)
+    # per-block counts and offsets are an exclusive scan
+    cnt, off = vol.block_counts()
+    ref_cnt = orc.block_vertex_counts(D, dims, iso, ids)
+    assert np.array_equal(cnt, ref_cnt)
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(cnt.astype(np.uint64))[:-1]]).astype(np.uint64)) if len(cnt) else True
+    return T
+
+
+def test_config1_sphere_cold(bc, orc):
+    say("[extract] 64^3 noisy sphere, rate 16, iso 0, cold cache")
+    f = fields.sphere_sdf_noisy(64, 20.0, 0.5, seed=1)
+    s = orc.zfp_encode(f, 16)
+    D = orc.zfp_decode(s, (64, 64, 64), 16)
+    vol = bc.Volume(s, (64, 64, 64), "f32", 16)
+    T = _extract_and_compare(bc, orc, vol, D, (64, 64, 64), np.float32(0.0))
+    assert T > 10000
+    st = vol.stats()
+    assert st["n_new"] == st["n_active"] and st["hit_rate"] == 0.0
+    # warm repeat: nothing new, identical output
+    T2 = _extract_and_compare(bc, orc, vol, D, (64, 64, 64), np.float32(0.0), check_cells=False)
+    st = vol.stats()
+    assert T2 == T and st["n_new"] == 0 and st["hit_rate"] == 1.0
+
+
+@pytest.mark.parametrize("dims,rate,seed", [((70, 61, 53), 8, 31), ((33, 47, 29), 4, 32),
+                                            ((130, 66, 40), 2, 33)])
+def test_turbulence_ragged_isovalues(bc, orc, dims, rate, seed):
+    nx, ny, nz = dims
+    say(f"[extract] turbulence {dims} rate {rate}")
+    f = fields.turbulence(nx, ny, nz, seed=seed, n_modes=64)
+    s = orc.zfp_encode(f, rate)
+    D = orc.zfp_decode(s, dims, rate)
+    vol = bc.Volume(s, dims, "f32", rate)
+    for p in (50, 90, 10, 50):
+        iso = fields.percentile_iso(orc.blocks_to_field(D, dims), p)
+        _extract_and_compare(bc, orc, vol, D, dims, iso)
+
+
+def test_lru_cache_matches_simulator(bc, orc):
+    dims = (72, 64, 56)
+    say(f"[cache] LRU parity {dims}")
+    f = fields.turbulence(*dims, seed=41, n_modes=64)
+    s = orc.zfp_encode(f, 8)
+    D = orc.zfp_decode(s, dims, 8)
+    nb = orc.num_blocks(*dims)
+    vol = bc.Volume(s, dims, "f32", 8)
+    init = nb // 10
+    vol.set_cache_budget(initial_bytes=init * 256, max_bytes=nb * 256)
+    sim = orc.LRU(nb, init, nb)
+    rg = orc.block_ranges(D, dims)
+    field = orc.blocks_to_field(D, dims)
+    isos = [fields.percentile_iso(field, p) for p in (50, 55, 90, 10, 50, 52, 52, 95, 30)]
+    import torch
+    cap = 3 * max(orc.mc_count(D, dims, iso) for iso in isos) + 16
+    out = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
+    for k, iso in enumerate(isos):
+        rc, T = vol.extract_into(float(iso), out)
+        assert rc == 0, bc.lib().bcmc_last_error()
+        act = orc.active_blocks(rg, dims, iso)
+        rc, I_new, ev = sim.update(act)
+        assert rc == 0
+        st = vol.stats()
+        say(f"  call {k}: iso={iso:.4f} n_act={st['n_active']} n_new={st['n_new']} slots={st['n_slots']}")
+        assert st["n_new"] == len(I_new) and st["n_evicted"] == ev
+        if len(I_new):
+            assert np.array_equal(vol.new_blocks(), I_new)
+        I_slot, S_block, S_age = vol.cache_state()
+        sI, sB, sA = sim.state()
+        assert st["n_slots"] == sim.n_slots
+        assert np.array_equal(I_slot, sI)
+        assert np.array_equal(S_block, sB)
+        assert np.array_equal(S_age, sA)
+        # slot contents are the decoded blocks
+        data = vol.slot_data()
+        used = S_block >= 0
+        assert np.array_equal(data[used].view(np.uint32), D[S_block[used]].view(np.uint32))
+        assert T == orc.mc_count(D, dims, iso)
+
+
+def test_cache_cap_error_and_capacity_retry(bc, orc):
+    dims = (40, 40, 40)
+    f = fields.turbulence(*dims, seed=51, n_modes=32)
+    s = orc.zfp_encode(f, 8)
+    D = orc.zfp_decode(s, dims, 8)
+    iso = fields.percentile_iso(orc.blocks_to_field(D, dims), 50)
+    vol = bc.Volume(s, dims, "f32", 8)
+    vol.set_cache_budget(initial_bytes=10 * 256, max_bytes=20 * 256)
+    import torch
+    out = torch.empty((16, 4), dtype=torch.int32, device="cuda")
+    rc, T = vol.extract_into(float(iso), out)
+    assert rc == bc._capi.E_CACHE_CAP
+    I_slot, S_block, _ = vol.cache_state()
+    assert (I_slot == -1).all() and vol.stats()["n_slots"] == 10
+    vol.set_cache_budget(0, 0)
+    rc, T = vol.extract_into(float(iso), out)
+    assert rc == bc._capi.E_CAPACITY and T == orc.mc_count(D, dims, iso)
+    verts, T2 = vol.extract(float(iso))      # grows the buffer and retries (warm)
+    assert T2 == T and vol.stats()["n_new"] == 0
+
+
+def test_invalid_arguments(bc, orc):
+    s = np.zeros(orc.num_blocks(8, 8, 8) * 4, np.uint64)
+    with pytest.raises(bc.BcmcError):
+        bc.Volume(s[:-1], (8, 8, 8), "f32", 4)
+    with pytest.raises(bc.BcmcError):
+        bc.Volume(s, (8, 8, 8), "f32", 40)
+    vol = bc.Volume(s, (8, 8, 8), "f32", 4)   # all-zero stream: valid, no surface
+    v, T = vol.extract(0.5)
+    assert T == 0
+
+
+def test_mc_single_cells_all_cases(bc, orc):
+    """Every one of the 256 cube cases on a 2x2x2 volume: the GPU emits
+    exactly the table's triangles at the corner configuration."""
+    nt, tri = bc.mc_table()
+    for cs in range(256):
+        f = np.array([[[(-1.0 if (cs >> (x + 2 * y + 4 * z)) & 1 else 1.0) for x in range(2)]
+                       for y in range(2)] for z in range(2)], dtype=np.float32)
+        B = orc.field_to_blocks(f)
+        vol = bc.FieldVolume(to_cuda(B), (2, 2, 2))
+        verts, T = vol.extract(0.0)
+        assert T == nt[cs], cs
+        if T:
+            r = orc.mc_extract(B, (2, 2, 2), 0.0, want=("verts", "vblock"))
+            xyz, blk = verts_np(verts)
+            assert np.abs(xyz - r["verts"]).max() < 1e-6
+        vol.close()
