@@ -158,25 +158,33 @@ def main():
         calls.append({
             "call": name, "ms": round(ms, 4), "triangles": st["n_triangles"],
             "n_active": st["n_active"], "n_new": st["n_new"], "n_slots": st["n_slots"],
-            "n_occupied": st["n_occupied"], "hit_rate": round(st["hit_rate"], 4),
+            "n_occupied": st["n_occupied"], "n_candidates": st["n_candidates"],
+            "hit_rate": round(st["hit_rate"], 4),
             "alg_gbs": round(st["alg_bytes"] / (ms * 1e-3) / 1e9, 2),
             "stage_ms": [round(float(np.median([r[2]["stage_ms"][i] for r in rs])), 4)
-                         for i in range(6)],
+                         for i in range(8)],
         })
 
-    # dominant kernel: marching cubes (stage 3) or block decode (stage 2),
-    # algorithmic bytes per launch / its HIP-event duration
-    mc_ms = sum(r[2]["stage_ms"][3] for r in records)
-    dec_ms = sum(r[2]["stage_ms"][2] for r in records)
-    mc_bytes = sum(256.0 * r[2]["n_active"] + 24.0 * r[2]["n_triangles"] for r in records)
-    dec_bytes = sum(r[2]["n_new"] * (8.0 * RATE + 256.0) for r in records)
-    if mc_ms >= dec_ms:
-        kern, kbytes, kms, nlaunch = "k_mc", mc_bytes, mc_ms, len(records)
-    else:
-        kern = "k_assign_decode"
-        kbytes, kms = dec_bytes, dec_ms
-        nlaunch = sum(1 for r in records if r[2]["n_new"] > 0)
-    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    # per-kernel algorithmic bytes / HIP-event durations over the timed region
+    # (stage_ms: 2 = assign+decode, 3 = MC count, 4 = block scan, 5 = MC emit)
+    def kstats(stage, bytes_fn, live_fn):
+        ms = sum(r[2]["stage_ms"][stage] for r in records)
+        nbytes = sum(bytes_fn(r[2]) for r in records)
+        launches = sum(1 for r in records if live_fn(r[2]))
+        return {"total_ms": ms, "bytes": nbytes, "launches": max(launches, 1),
+                "avg_ms": ms / max(launches, 1),
+                "gbs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
+
+    kern = {
+        "k_assign_decode": kstats(2, lambda st: st["n_new"] * (8.0 * RATE + 256.0),
+                                  lambda st: st["n_new"] > 0),
+        "k_mc_count": kstats(3, lambda st: 256.0 * st["n_candidates"], lambda st: True),
+        "k_scan_counts": kstats(4, lambda st: 12.0 * st["n_active"], lambda st: True),
+        "k_mc_emit": kstats(5, lambda st: 256.0 * st["n_occupied"] + 24.0 * st["n_triangles"],
+                            lambda st: True),
+    }
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    kd = kern[dom]
     alg_total = sum(r[2]["alg_bytes"] for r in records)
 
     ms_per_step = elapsed / args.steps * 1e3
@@ -203,11 +211,15 @@ def main():
         "hbm_gbs_alg": round(alg_total / elapsed / 1e9, 2),
         "hbm_frac_alg": round(alg_total / elapsed / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {
-            "bound": "hbm", "kernel": kern, "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_launch_ms": round(kms / max(nlaunch, 1), 5),
-            "alg_bytes_per_launch": round(kbytes / max(nlaunch, 1)),
+            "bound": "hbm", "kernel": dom, "achieved": round(kd["gbs"], 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_launch_ms": round(kd["avg_ms"], 5),
+            "alg_bytes_per_launch": round(kd["bytes"] / kd["launches"]),
         },
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_gbs": round(v["gbs"], 1),
+                        "share_of_gpu_time": round(v["total_ms"] / max(
+                            sum(r[2]["stage_ms"][7] for r in records), 1e-9), 3)}
+                    for k, v in kern.items()},
         "calls": calls,
     }
     if not args.no_cpu_baseline:

@@ -68,13 +68,18 @@ typedef struct {
     uint64_t n_new;        /* blocks decoded into the cache by this call */
     uint64_t n_evicted;    /* blocks evicted by this call */
     uint64_t n_occupied;   /* active blocks that emitted triangles (Sec. 4.4) */
+    uint64_t n_candidates; /* active blocks whose 2x2x2 group straddles iso (staged) */
     uint64_t n_slots;      /* cache slots after this call */
     uint64_t n_triangles;
     uint64_t calls;        /* extract calls on this handle */
     double hit_rate;       /* 1 - n_new / n_active (1 when nothing is active) */
     double alg_bytes;      /* 8*N_b + n_new*(8*rate+256) + 256*n_active + 24*T */
-    double stage_ms[6];    /* with profiling on: cull+compact, cache update,
-                              decode, marching cubes, readback, total */
+    double stage_ms[8];    /* with profiling on (HIP events on the stream):
+                              [0] cull + active/new compaction,
+                              [1] cache update (slot pass, growth, age sort),
+                              [2] assign + decode of new blocks,
+                              [3] marching cubes count pass, [4] block scan,
+                              [5] emission pass, [6] unused, [7] total */
 } bcmc_stats;
 
 /* Upload a fixed-rate ZFP stream (Sec. 4: "uploading the compressed data to
@@ -156,6 +161,8 @@ BCMC_API int bcmc_mc_table(uint64_t *packed256);
 
 /* ---- inspection of the last extract (host copies; synchronous) -------- */
 BCMC_API int bcmc_debug_ranges(const bcmc_volume *v, float *h_ranges /* [N_b][2] */);
+/* h_active[b]: bit 0 = active (M_active), bit 1 = may emit (the value hull
+ * of b and its +x/+y/+z neighbours contains iso). */
 BCMC_API int bcmc_debug_active(const bcmc_volume *v, uint8_t *h_active /* [N_b] */,
                       uint32_t *h_I_active /* [N_b] */, uint64_t *h_n_active);
 BCMC_API int bcmc_debug_new(const bcmc_volume *v, uint32_t *h_I_new /* [N_b] */, uint64_t *h_n_new);

@@ -159,13 +159,17 @@ class _Handle:
         _capi.check(lib().bcmc_debug_ranges(self._h, r.ctypes.data_as(C.c_void_p)))
         return r
 
-    def active(self):
+    def active(self, with_flags=False):
+        """(M_active as 0/1 per block, I_active); with_flags adds the per-block
+        "can emit" flags of the last extract."""
         a = np.empty(self.n_blocks, dtype=np.uint8)
         ids = np.empty(self.n_blocks, dtype=np.uint32)
         n = C.c_uint64(0)
         _capi.check(lib().bcmc_debug_active(self._h, a.ctypes.data_as(C.c_void_p),
                                             ids.ctypes.data_as(C.c_void_p), C.byref(n)))
-        return a, ids[: n.value].copy()
+        if with_flags:
+            return a & 1, ids[: n.value].copy(), (a >> 1) & 1
+        return a & 1, ids[: n.value].copy()
 
     def block_counts(self):
         n = self.stats()["n_active"]

@@ -30,7 +30,7 @@ struct bcmc_volume {
     Counters *h_ctr = nullptr;     // pinned copy of the device counters
     bcmc_stats stats{};
     int profiling = 0;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[8] = {};
     int have_extract = 0;
     float last_iso = 0.0f;
 };
@@ -99,7 +99,7 @@ void layout_status(bcmc_volume *v) {
     s.blk = 0;
     s.slot = s.blk + (v->g.nb + BLK_TILE - 1) / BLK_TILE;
     s.mc = s.slot + (v->max_slots + SLOT_TILE - 1) / SLOT_TILE;
-    s.scan = s.mc + (v->g.nb + MC_WAVES - 1) / MC_WAVES + 1;
+    s.scan = s.mc + (v->g.nb + SCAN_TILE - 1) / SCAN_TILE + 1;
     uint64_t rtiles = (v->max_slots + RADIX_TILE - 1) / RADIX_TILE;
     s.total = s.scan + (256 * rtiles + SCAN_TILE - 1) / SCAN_TILE + 1;
 }
@@ -316,24 +316,26 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     if (iso != iso) return invalid("iso is NaN");
     hipStream_t s = as_stream(hip_stream);
     const bool prof = v->profiling;
-    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[0], s));
+    auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(v->ev[i], s) : hipSuccess; };
+    BCMC_HIP_TRY(mark(0));
     launch_cull(v->g, v->d, v->sl, iso, v->n_slots, s);
     launch_compact_blocks(v->g, v->d, v->sl, v->identity, s);
-    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[1], s));
+    BCMC_HIP_TRY(mark(1));
     if (!v->identity) {
         launch_slot_pass(v->d, v->sl, v->n_slots, s);
         launch_plan_grow(v->d, v->max_slots, v->max_slots - v->n_slots, s);
         launch_radix(v->d, v->sl, v->max_slots, s);
-        if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[2], s));
-        launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, s);
-    } else if (prof) {
-        BCMC_HIP_TRY(hipEventRecord(v->ev[2], s));
     }
-    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[3], s));
+    BCMC_HIP_TRY(mark(2));
+    if (!v->identity) launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, s);
+    BCMC_HIP_TRY(mark(3));
     const float *slots = v->identity ? v->ext_blocks : v->d.slots;
-    launch_mc(v->g, v->d, v->sl, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices,
-              (v->g.nb + MC_WAVES - 1) / MC_WAVES, s);
-    if (prof) BCMC_HIP_TRY(hipEventRecord(v->ev[4], s));
+    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, s);
+    BCMC_HIP_TRY(mark(4));
+    launch_scan_counts(v->g, v->d, v->sl, s);
+    BCMC_HIP_TRY(mark(5));
+    launch_mc_emit(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices, s);
+    BCMC_HIP_TRY(mark(6));
     BCMC_HIP_TRY(hipGetLastError());
     int rc = sync_counters(v, s);
     if (rc) return rc;
@@ -348,6 +350,7 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
         reset_cache_state(v, s);
         v->stats.n_active = c.n_act;
         v->stats.n_new = v->stats.n_evicted = v->stats.n_occupied = v->stats.n_triangles = 0;
+        v->stats.n_candidates = 0;
         v->stats.n_slots = v->n_slots;
         set_error("the active blocks (" + std::to_string(c.n_act) +
                   ") do not fit the cache cap of " + std::to_string(v->max_slots) + " slots");
@@ -361,22 +364,22 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     st.n_new = v->identity ? 0 : c.n_new;
     st.n_evicted = c.n_evicted;
     st.n_occupied = c.n_occ;
+    st.n_candidates = c.n_cand;
     st.n_slots = v->n_slots;
     st.n_triangles = T;
     st.hit_rate = c.n_act ? 1.0 - (double)st.n_new / (double)c.n_act : 1.0;
     st.alg_bytes = 8.0 * v->g.nb + (double)st.n_new * (8.0 * v->rate + 256.0) +
                    256.0 * (double)c.n_act + 24.0 * (double)T;
+    for (int i = 0; i < 8; i++) st.stage_ms[i] = 0.0;
     if (prof) {
-        float ms[4];
-        for (int i = 0; i < 4; i++) (void)hipEventElapsedTime(&ms[i], v->ev[i], v->ev[i + 1]);
-        st.stage_ms[0] = ms[0];
-        st.stage_ms[1] = ms[1];
-        st.stage_ms[2] = ms[2];
-        st.stage_ms[3] = ms[3];
+        for (int i = 0; i < 6; i++) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, v->ev[i], v->ev[i + 1]);
+            st.stage_ms[i] = ms;
+        }
         float tot = 0;
-        (void)hipEventElapsedTime(&tot, v->ev[0], v->ev[4]);
-        st.stage_ms[4] = 0;
-        st.stage_ms[5] = tot;
+        (void)hipEventElapsedTime(&tot, v->ev[0], v->ev[6]);
+        st.stage_ms[7] = tot;
     }
     v->have_extract = 1;
     v->last_iso = iso;

@@ -36,6 +36,7 @@ struct Counters {
     unsigned long long n_grow;       // slots added this call
     unsigned long long n_evicted;    // blocks evicted this call
     unsigned long long n_occ;        // active blocks that emit triangles
+    unsigned long long n_cand;       // active blocks that may emit (staged by the count pass)
     unsigned long long total_verts;  // 3 * triangles
     unsigned int err;                // ERR_* bits
     unsigned int key_or, key_and;    // OR / AND of the sort keys of available slots
@@ -88,9 +89,11 @@ void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slot
                       hipStream_t s);
 void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound, hipStream_t s);
 void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, hipStream_t s);
-void launch_mc(const Geom &g, const DevState &d, const StatusLayout &sl, const float *slots,
-               const int32_t *I_slot, int identity_cache, float iso, void *out,
-               uint64_t cap_verts, uint64_t max_tiles, hipStream_t s);
+void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
+                     int identity_cache, float iso, hipStream_t s);
+void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s);
+void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
+                    int identity_cache, float iso, void *out, uint64_t cap_verts, hipStream_t s);
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
                         const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
                         uint64_t max_act, hipStream_t s);

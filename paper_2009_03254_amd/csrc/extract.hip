@@ -146,7 +146,8 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
         uint64_t r = b / g.nbx;
         uint32_t by = (uint32_t)(r % g.nby), bz = (uint32_t)(r / g.nby);
         float2 own = ranges[b];
-        float LO = own.x, HI = own.y;
+        float LO = own.x, HI = own.y;    // over the 3x3x3 neighbourhood
+        float PLO = own.x, PHI = own.y;  // over the block and its + neighbours
         for (int dz = -1; dz <= 1; dz++) {
             int z = (int)bz + dz;
             if (z < 0 || z >= (int)g.nbz) continue;
@@ -160,11 +161,18 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
                     float2 q = row[x];
                     LO = fminf(LO, q.x);
                     HI = fmaxf(HI, q.y);
+                    if (dx >= 0 && dy >= 0 && dz >= 0) {
+                        PLO = fminf(PLO, q.x);
+                        PHI = fmaxf(PHI, q.y);
+                    }
                 }
             }
         }
         bool act = (own.x < iso && iso <= HI) || (LO < iso && iso <= own.y);
-        active[b] = act ? 1 : 0;
+        // "can emit": the hull of the 2x2x2 group headed by b contains iso
+        // (implies act, as that group contains b)
+        bool can_emit = PLO < iso && iso <= PHI;
+        active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u);
     }
 }
 
@@ -448,29 +456,35 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Counters *ctr, int p,
 }
 
 // ---------------------------------------------------------------------------
-// Marching cubes over the active blocks (Sec. 4.3-4.5).  One wave64 owns one
-// 4^3 block: lane = dual cell.  The block and its +x/+y/+z halo (5^3
-// samples) are staged in LDS from the cache slots of the block and its 7
-// positive neighbours.  If an in-volume positive neighbour is inactive, every
-// sample the block's cells read lies on one side of iso (the culling rule is
-// exact), so the block emits nothing and is skipped.
-// Count, block scan and emission are fused: a 4-block tile takes its output
-// offset by decoupled look-back, then writes its triangle soup lane-per-vertex.
+// Marching cubes over the active blocks (Sec. 4.3-4.5), as the paper's three
+// steps: a count pass (per-block vertex count, Sec. 4.4), a device-wide
+// exclusive scan of the block counts, and an emission pass (Sec. 4.5).
+// One wave64 owns one 4^3 block: lane = dual cell.  The block and its
+// +x/+y/+z halo (5^3 samples) are staged in LDS from the cache slots of the
+// block and its 7 positive neighbours.  Only blocks flagged "can emit" by the
+// cull (the value hull of the block and its positive neighbours contains
+// iso) are staged; every other block emits nothing, because a cell's eight
+// samples all lie in the block of its lowest corner and that block's positive
+// neighbours.
 // ---------------------------------------------------------------------------
 struct Halo {
-    int ok;                 // block may emit (all in-volume + neighbours active)
     int bad;                // a needed block has no slot (internal error)
     uint32_t bx, by, bz;
     uint32_t nslot[8];      // slots of the block (0) and its + neighbours (mask dx|dy<<1|dz<<2)
 };
 
-__device__ __forceinline__ void halo_setup(const Geom &g, uint32_t b, const uint8_t *__restrict__ active,
-                                           const int32_t *__restrict__ I_slot, int identity, Halo &h) {
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void halo_setup(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
+                                           int identity, Halo &h) {
     h.bx = b % g.nbx;
     uint32_t r = b / g.nbx;
     h.by = r % g.nby;
     h.bz = r / g.nby;
-    h.ok = 1;
     h.bad = 0;
 #pragma unroll
     for (int m = 0; m < 8; m++) {
@@ -478,9 +492,7 @@ __device__ __forceinline__ void halo_setup(const Geom &g, uint32_t b, const uint
         h.nslot[m] = 0;
         if (x < g.nbx && y < g.nby && z < g.nbz) {
             uint32_t nb = x + g.nbx * (y + g.nby * z);
-            if (m && !active[nb]) {
-                h.ok = 0;
-            } else if (identity) {
+            if (identity) {
                 h.nslot[m] = nb;
             } else {
                 int32_t s = I_slot[nb];
@@ -489,7 +501,6 @@ __device__ __forceinline__ void halo_setup(const Geom &g, uint32_t b, const uint
             }
         }
     }
-    if (h.bad) h.ok = 0;
 }
 
 // LDS index of sample (x,y,z) of the 5^3 tile
@@ -523,7 +534,6 @@ __device__ __forceinline__ void stage_tile(const Geom &g, const Halo &h, const f
 __device__ __forceinline__ int cell_case(const Geom &g, const Halo &h, const float *tile, float iso) {
     const int l = lane();
     const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
-    if (!h.ok) return -1;
     if (4 * h.bx + lx + 1 >= g.nx || 4 * h.by + ly + 1 >= g.ny || 4 * h.bz + lz + 1 >= g.nz) return -1;
     int cs = 0;
 #pragma unroll
@@ -547,71 +557,131 @@ struct McShared {
     uint32_t pref[MC_WAVES][64];
     uint8_t cs[MC_WAVES][64];
     uint8_t map[MC_WAVES][64 * 15];
-    uint32_t wtot[MC_WAVES];
-    uint64_t excl;
 };
 
-__global__ __launch_bounds__(256) void k_mc(Geom g, const uint32_t *__restrict__ I_active,
-                                           const uint8_t *__restrict__ active,
-                                           const int32_t *__restrict__ I_slot, int identity,
-                                           const float *__restrict__ slots,
-                                           const uint64_t *__restrict__ mc_table, float iso,
-                                           uint4 *__restrict__ out, uint64_t cap,
-                                           uint32_t *__restrict__ blk_cnt,
-                                           uint64_t *__restrict__ blk_off, Counters *ctr,
-                                           uint64_t *status) {
-    __shared__ McShared sh;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
-    const uint64_t n_act = ctr->n_act;
+// Stage block b, classify its cells and lay out its vertices in LDS:
+// pref = exclusive prefix of per-cell vertex counts, map[v] = cell of
+// vertex v.  Returns the block's vertex count (-1 on an internal error).
+__device__ __forceinline__ int block_layout(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
+                                            int identity, const float *__restrict__ slots, float iso,
+                                            McShared &sh, int w, Halo &h) {
+    const int l = lane();
+    halo_setup(g, b, I_slot, identity, h);
+    if (h.bad) return -1;
+    stage_tile(g, h, slots, sh.tile[w]);
+    wave_lds_sync();
+    const int cs = cell_case(g, h, sh.tile[w], iso);
+    const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
+    const uint32_t incl = wave_incl_scan(nv);
+    sh.pref[w][l] = incl - nv;
+    sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
+    for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
+    wave_lds_sync();
+    return (int)__shfl(incl, 63, 64);
+}
+
+// Count pass: vertex count of every active block (0 unless it can emit).
+__global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__restrict__ I_active,
+                                                 const uint8_t *__restrict__ active,
+                                                 const int32_t *__restrict__ I_slot, int identity,
+                                                 const float *__restrict__ slots,
+                                                 const uint64_t *__restrict__ mc_table, float iso,
+                                                 uint32_t *__restrict__ blk_cnt, Counters *ctr) {
+    __shared__ uint64_t tab[256];
+    __shared__ float tiles[MC_WAVES][128];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) tab[i] = mc_table[i];
+    __syncthreads();
     if (ctr->err) return;
-    const uint64_t n_tiles = (n_act + MC_WAVES - 1) / MC_WAVES;
+    const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    float *tile = sh.tile[w];
+    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
+    uint32_t occ = 0, cand = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
+        const uint32_t b = I_active[i];
+        uint32_t total = 0;
+        if (active[b] & 2u) {
+            cand++;
+            Halo h;
+            halo_setup(g, b, I_slot, identity, h);
+            if (h.bad) {
+                if (l == 0) atomicOr(&ctr->err, ERR_INTERNAL);
+            } else {
+                stage_tile(g, h, slots, tiles[w]);
+                wave_lds_sync();
+                const int cs = cell_case(g, h, tiles[w], iso);
+                total = wave_sum(cs < 0 ? 0u : 3u * (uint32_t)(tab[cs] >> 60));
+                wave_lds_sync();
+            }
+        }
+        if (l == 0) blk_cnt[i] = total;
+        occ += total != 0;
+    }
+    if (l == 0 && (occ | cand)) {
+        atomicAdd(&ctr->n_occ, (unsigned long long)occ);
+        atomicAdd(&ctr->n_cand, (unsigned long long)cand);
+    }
+}
+
+// Exclusive scan of the block vertex counts into 64-bit offsets; the last
+// tile records the total (Sec. 4.4: the per-block offsets and the output
+// size come from one prefix sum over the blocks).
+__global__ __launch_bounds__(256) void k_scan_counts(const uint32_t *__restrict__ cnt,
+                                                    uint64_t *__restrict__ off, Counters *ctr,
+                                                    uint64_t *status) {
+    if (ctr->err) return;
+    const uint64_t n = ctr->n_act;
+    const uint64_t n_tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     for (;;) {
         const uint32_t t = take_tile(&ctr->tile_ctr[TC_MC]);
-        if (t >= n_tiles) break;
-        const uint64_t i = (uint64_t)t * MC_WAVES + w;
-        const bool have = i < n_act;
-        const uint32_t b = have ? I_active[i] : 0u;
-        Halo h;
-        halo_setup(g, b, active, I_slot, identity, h);
-        if (h.bad && have && l == 0) atomicOr(&ctr->err, ERR_INTERNAL);
-        h.ok = h.ok && have;
-        if (h.ok) stage_tile(g, h, slots, tile);
-        __syncthreads();
-        const int cs = cell_case(g, h, tile, iso);
-        const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
-        const uint32_t incl = wave_incl_scan(nv);
-        const uint32_t total = __shfl(incl, 63, 64);
-        sh.pref[w][l] = incl - nv;
-        sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
-        for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
-        if (l == 0) sh.wtot[w] = total;
-        __syncthreads();
-        uint64_t woff = 0, agg = 0;
+        if (t >= n_tiles) return;
+        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * 16u;
+        uint32_t x[16];
+        uint64_t sum = 0;
 #pragma unroll
-        for (int k = 0; k < MC_WAVES; k++) {
-            if (k < w) woff += sh.wtot[k];
-            agg += sh.wtot[k];
+        for (int j = 0; j < 16; j++) {
+            x[j] = base + j < n ? cnt[base + j] : 0u;
+            sum += x[j];
         }
-        if (w == 0) {
-            uint64_t e = lookback(status, t, agg);
-            if (l == 0) sh.excl = e;
+        uint64_t incl_end;
+        uint64_t e = tile_scan_lookback(sum, status, t, &incl_end);
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            if (base + j < n) off[base + j] = e;
+            e += x[j];
         }
-        __syncthreads();
-        const uint64_t base = sh.excl + woff;
-        if (t == n_tiles - 1 && threadIdx.x == 0) ctr->total_verts = sh.excl + agg;
-        if (have && l == 0) {
-            blk_cnt[i] = total;
-            blk_off[i] = base;
-            if (total) atomicAdd(&ctr->n_occ, 1ull);
-        }
-        // emission: lane per vertex, canonical order (cell, triangle, vertex)
-        for (uint32_t j = l; j < total; j += 64) {
+        if (t == n_tiles - 1 && threadIdx.x == 0) ctr->total_verts = incl_end;
+    }
+}
+
+// Emission pass (Sec. 4.5): restage each occupied block, take the in-block
+// prefix of its per-cell vertex counts and write the triangle soup lane per
+// vertex at the block's offset, in canonical order (cell, triangle, vertex).
+__global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
+                                                const int32_t *__restrict__ I_slot, int identity,
+                                                const float *__restrict__ slots,
+                                                const uint64_t *__restrict__ mc_table, float iso,
+                                                const uint32_t *__restrict__ blk_cnt,
+                                                const uint64_t *__restrict__ blk_off,
+                                                uint4 *__restrict__ out, uint64_t cap,
+                                                Counters *ctr) {
+    __shared__ McShared sh;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
+    __syncthreads();
+    if (ctr->err) return;
+    const uint64_t n_act = ctr->n_act;
+    const int w = threadIdx.x >> 6, l = lane();
+    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
+    const float *tile = sh.tile[w];
+    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
+        if (blk_cnt[i] == 0) continue;
+        const uint32_t b = I_active[i];
+        const uint64_t base = blk_off[i];
+        Halo h;
+        const int total = block_layout(g, b, I_slot, identity, slots, iso, sh, w, h);
+        for (int j = l; j < total; j += 64) {
             const int c = sh.map[w][j];
-            const int k = (int)(j - sh.pref[w][c]);
-            const int ccs = sh.cs[w][c];
-            const int e = (int)((sh.tab[ccs] >> (4 * k)) & 15u);
+            const int k = j - (int)sh.pref[w][c];
+            const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * k)) & 15u);
             int ox, oy, oz, axis;
             edge_geom(e, ox, oy, oz, axis);
             const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
@@ -622,11 +692,11 @@ __global__ __launch_bounds__(256) void k_mc(Geom g, const uint32_t *__restrict__
             if (axis == 0) px += tt;
             else if (axis == 1) py += tt;
             else pz += tt;
-            const uint64_t o = base + j;
+            const uint64_t o = base + (uint64_t)j;
             if (o < cap)
                 out[o] = make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -638,21 +708,25 @@ __global__ __launch_bounds__(256) void k_debug_cases(Geom g, const uint32_t *__r
                                                     const float *__restrict__ slots, float iso,
                                                     uint8_t *__restrict__ cases,
                                                     const Counters *ctr) {
-    __shared__ float tiles[4][128];
-    const uint64_t n_act = ctr->n_act;
+    __shared__ float tiles[MC_WAVES][128];
     if (ctr->err) return;
+    const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6;
-    for (uint64_t i0 = blockIdx.x * 4ull; i0 < n_act; i0 += gridDim.x * 4ull) {
-        const uint64_t i = i0 + w;
-        const bool have = i < n_act;
-        Halo h;
-        halo_setup(g, have ? I_active[i] : 0u, active, I_slot, identity, h);
-        h.ok = h.ok && have;
-        if (h.ok) stage_tile(g, h, slots, tiles[w]);
-        __syncthreads();
-        int cs = cell_case(g, h, tiles[w], iso);
-        if (have) cases[i * 64 + lane()] = (uint8_t)(cs < 0 ? 0 : cs);
-        __syncthreads();
+    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
+    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
+        const uint32_t b = I_active[i];
+        int cs = -1;
+        if (active[b] & 2u) {
+            Halo h;
+            halo_setup(g, b, I_slot, identity, h);
+            if (!h.bad) {
+                stage_tile(g, h, slots, tiles[w]);
+                wave_lds_sync();
+                cs = cell_case(g, h, tiles[w], iso);
+                wave_lds_sync();
+            }
+        }
+        cases[i * 64 + lane()] = (uint8_t)(cs < 0 ? 0 : cs);
     }
 }
 
@@ -663,9 +737,9 @@ __global__ __launch_bounds__(256) void k_debug_cases(Geom g, const uint32_t *__r
 // Recomputes the forward's per-block layout (same cells, same order) and
 // scatters into the block-layout field gradient.
 __global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__restrict__ I_active,
-                                                 const uint8_t *__restrict__ active,
                                                  const float *__restrict__ slots,
                                                  const uint64_t *__restrict__ mc_table, float iso,
+                                                 const uint32_t *__restrict__ blk_cnt,
                                                  const uint64_t *__restrict__ blk_off,
                                                  const float *__restrict__ gV,
                                                  float *__restrict__ dfield, float *diso,
@@ -675,29 +749,18 @@ __global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__rest
     __syncthreads();
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    float *tile = sh.tile[w];
+    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
+    const float *tile = sh.tile[w];
     float giso = 0.0f;
-    for (uint64_t i0 = blockIdx.x * (uint64_t)MC_WAVES; i0 < n_act; i0 += gridDim.x * (uint64_t)MC_WAVES) {
-        const uint64_t i = i0 + w;
-        const bool have = i < n_act;
-        const uint32_t b = have ? I_active[i] : 0u;
+    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
+        if (blk_cnt[i] == 0) continue;
+        const uint32_t b = I_active[i];
+        const uint64_t base = blk_off[i];
         Halo h;
-        halo_setup(g, b, active, nullptr, 1, h);
-        h.ok = h.ok && have;
-        if (h.ok) stage_tile(g, h, slots, tile);
-        __syncthreads();
-        const int cs = cell_case(g, h, tile, iso);
-        const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
-        const uint32_t incl = wave_incl_scan(nv);
-        const uint32_t total = __shfl(incl, 63, 64);
-        sh.pref[w][l] = incl - nv;
-        sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
-        for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
-        __syncthreads();
-        const uint64_t base = have ? blk_off[i] : 0;
-        for (uint32_t j = l; j < total; j += 64) {
+        const int total = block_layout(g, b, nullptr, 1, slots, iso, sh, w, h);
+        for (int j = l; j < total; j += 64) {
             const int c = sh.map[w][j];
-            const int k = (int)(j - sh.pref[w][c]);
+            const int k = j - (int)sh.pref[w][c];
             const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * k)) & 15u);
             int ox, oy, oz, axis;
             edge_geom(e, ox, oy, oz, axis);
@@ -715,7 +778,7 @@ __global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__rest
             atomicAdd(&dfield[(uint64_t)nb * 64 + (x1 & 3) + 4 * (y1 & 3) + 16 * (z1 & 3)], -gt * tt * inv);
             giso += gt * inv;
         }
-        __syncthreads();
+        wave_lds_sync();
     }
     giso = wave_sum(giso);
     if (l == 0 && giso != 0.0f) atomicAdd(diso, giso);
@@ -784,30 +847,42 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
     }
 }
 
-void launch_mc(const Geom &g, const DevState &d, const StatusLayout &sl, const float *slots,
-               const int32_t *I_slot, int identity_cache, float iso, void *out,
-               uint64_t cap_verts, uint64_t max_tiles, hipStream_t s) {
-    unsigned grid = (unsigned)(max_tiles < 2048 ? max_tiles : 2048);
-    if (grid == 0) grid = 1;
-    k_mc<<<grid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, slots, d.mc_table,
-                              iso, reinterpret_cast<uint4 *>(out), cap_verts, d.blk_cnt, d.blk_off,
-                              d.ctr, d.status + sl.mc);
+static unsigned mc_grid(uint64_t max_blocks) {
+    uint64_t g = (max_blocks + MC_WAVES - 1) / MC_WAVES;
+    return (unsigned)(g < 2048 ? (g ? g : 1) : 2048);
+}
+
+void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
+                     int identity_cache, float iso, hipStream_t s) {
+    k_mc_count<<<mc_grid(g.nb), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
+                                              slots, d.mc_table, iso, d.blk_cnt, d.ctr);
+}
+
+void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s) {
+    uint64_t tiles = (g.nb + SCAN_TILE - 1) / SCAN_TILE;
+    unsigned grid = (unsigned)(tiles < 1024 ? (tiles ? tiles : 1) : 1024);
+    k_scan_counts<<<grid, 256, 0, s>>>(d.blk_cnt, d.blk_off, d.ctr, d.status + sl.mc);
+}
+
+void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
+                    int identity_cache, float iso, void *out, uint64_t cap_verts, hipStream_t s) {
+    k_mc_emit<<<mc_grid(g.nb), 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots,
+                                             d.mc_table, iso, d.blk_cnt, d.blk_off,
+                                             reinterpret_cast<uint4 *>(out), cap_verts, d.ctr);
 }
 
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
                         const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
                         uint64_t max_act, hipStream_t s) {
-    unsigned grid = grid_cap(max_act * 64, 4096);
-    k_debug_cases<<<grid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, slots, iso,
-                                       cases, d.ctr);
+    k_debug_cases<<<mc_grid(max_act), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
+                                                    slots, iso, cases, d.ctr);
 }
 
 void launch_backward(const Geom &g, const DevState &d, const float *slots, float iso,
                      const float *gV, float *dfield, float *diso, uint64_t max_act,
                      hipStream_t s) {
-    unsigned grid = grid_cap(max_act * 64, 2048);
-    k_backward<<<grid, 256, 0, s>>>(g, d.I_active, d.active, slots, d.mc_table, iso, d.blk_off, gV,
-                                    dfield, diso, d.ctr);
+    k_backward<<<mc_grid(max_act), 256, 0, s>>>(g, d.I_active, slots, d.mc_table, iso, d.blk_cnt,
+                                                 d.blk_off, gV, dfield, diso, d.ctr);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {

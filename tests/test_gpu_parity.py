@@ -74,10 +74,14 @@ def _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=True):
     v32, vb32 = orc.mc_extract_f32(D, dims, iso)
     assert np.array_equal(xyz.view(np.uint32), v32.view(np.uint32))
     # active blocks == the oracle's culling
-    act, ids = vol.active()
+    act, ids, can_emit = vol.active(with_flags=True)
     ract = orc.active_blocks(orc.block_ranges(D, dims), dims, iso)
     assert np.array_equal(act, ract)
     assert np.array_equal(ids, np.nonzero(ract)[0].astype(np.uint32))
+    # "may emit" implies active, and every block owning a non-trivial cell has it
+    assert not (can_emit & (1 - act)).any()
+    owners = np.unique((r["cell_keys"] // 64).astype(np.int64))
+    assert can_emit[owners].all()
     if check_cells:
         cases = vol.cases(iso).cpu().numpy()
         nt, _ = bc.mc_table()
