@@ -41,9 +41,10 @@ struct Counters {
     unsigned int err;                // ERR_* bits
     unsigned int key_or, key_and;    // OR / AND of the sort keys of available slots
     unsigned int pass_mask;          // radix digits that vary (bit p = digit p)
-    unsigned int tile_ctr[8];        // dynamic tile counters of look-back kernels
+    unsigned int tile_ctr[12];       // dynamic work counters (tiles / batches)
 };
-enum { TC_BLK = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */ };
+enum { TC_BLK = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */,
+       TC_MCCOUNT = 7, TC_MCEMIT = 8 };
 
 // Geometry of a volume in blocks.
 struct Geom {

@@ -11,6 +11,8 @@
 //     counter in order, so a tile only ever waits on tiles already running.
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace bcmc {
@@ -580,6 +582,130 @@ __device__ __forceinline__ int block_layout(const Geom &g, uint32_t b, const int
     return (int)__shfl(incl, 63, 64);
 }
 
+// ---- batched staging ------------------------------------------------------
+// A wave takes 64 consecutive active blocks at a time (one per lane): each lane
+// resolves the cache slots of its block and the block's 7 positive neighbours
+// (the "octet"), then the wave stages MC_SB of the selected blocks per memory
+// round trip (2 loads per lane per block, all in flight together) and works
+// through them from LDS.  Slots of out-of-volume neighbours are 0: what is
+// loaded from there only feeds cells outside the volume, which are never used.
+constexpr int MC_SB = 8;
+
+struct LaneGeom {            // per-lane constants of the 5^3 staging
+    int own_t;               // tile index of the lane's own sample
+    int halo_t;              // tile index of the lane's halo sample (lanes < 61)
+    int halo_m;              // which + neighbour holds it (dx | dy<<1 | dz<<2)
+    int halo_l;              // its index inside that neighbour
+};
+
+__device__ __forceinline__ LaneGeom lane_geom() {
+    const int l = lane();
+    LaneGeom q;
+    q.own_t = tix(l & 3, (l >> 2) & 3, l >> 4);
+    int x = 0, y = 0, z = 0;
+    if (l < 16) { x = 4; y = l & 3; z = l >> 2; }
+    else if (l < 32) { x = l & 3; y = 4; z = (l >> 2) & 3; }
+    else if (l < 48) { x = l & 3; y = (l >> 2) & 3; z = 4; }
+    else if (l < 52) { x = 4; y = 4; z = l - 48; }
+    else if (l < 56) { x = 4; y = l - 52; z = 4; }
+    else if (l < 60) { x = l - 56; y = 4; z = 4; }
+    else { x = 4; y = 4; z = 4; }
+    q.halo_t = tix(x, y, z);
+    q.halo_m = (x >> 2) | ((y >> 2) << 1) | ((z >> 2) << 2);
+    q.halo_l = (x & 3) + 4 * (y & 3) + 16 * (z & 3);
+    return q;
+}
+
+// Slots of block b and its 7 positive neighbours; false if one is missing.
+// The 8 lookups are issued unconditionally (an out-of-volume neighbour reads
+// block b's own entry) so that they are in flight together.
+__device__ __forceinline__ bool octet(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
+                                      int identity, uint32_t so[8]) {
+    const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
+    uint32_t nb[8];
+    bool in[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        const uint32_t x = bx + (m & 1), y = by + ((m >> 1) & 1), z = bz + (m >> 2);
+        in[m] = x < g.nbx && y < g.nby && z < g.nbz;
+        nb[m] = in[m] ? x + g.nbx * (y + g.nby * z) : b;
+    }
+    if (identity) {
+#pragma unroll
+        for (int m = 0; m < 8; m++) so[m] = in[m] ? nb[m] : 0u;
+        return true;
+    }
+    int32_t sl[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) sl[m] = I_slot[nb[m]];
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        ok = ok && (!in[m] || sl[m] >= 0);
+        so[m] = (in[m] && sl[m] >= 0) ? (uint32_t)sl[m] : 0u;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+// Stage up to MC_SB blocks (lanes jl[k] of the batch) into tiles[k].  Every
+// slot is loaded unconditionally (unused k repeat block jl[0]) so all
+// 2*MC_SB loads of a lane are in flight before the first LDS write.
+__device__ __forceinline__ void stage_batch(const LaneGeom &q, const float *__restrict__ slots,
+                                            const uint32_t so[8], const int *jl,
+                                            float (*tiles)[128]) {
+    const int l = lane();
+    float ov[MC_SB], hv[MC_SB];
+#pragma unroll
+    for (int k = 0; k < MC_SB; k++) {
+        uint32_t s_own = bcast(so[0], jl[k]);
+        uint32_t s_h = s_own;
+#pragma unroll
+        for (int m = 1; m < 8; m++) {
+            uint32_t sm = bcast(so[m], jl[k]);
+            s_h = (q.halo_m == m) ? sm : s_h;
+        }
+        ov[k] = slots[(uint64_t)s_own * 64 + l];
+        hv[k] = slots[(uint64_t)s_h * 64 + q.halo_l];
+    }
+#pragma unroll
+    for (int k = 0; k < MC_SB; k++) {
+        tiles[k][q.own_t] = ov[k];
+        if (l < 61) tiles[k][q.halo_t] = hv[k];
+    }
+}
+
+// Case of the lane's cell in block (bx,by,bz) staged in `tile`, -1 outside.
+__device__ __forceinline__ int tile_case(const Geom &g, uint32_t bx, uint32_t by, uint32_t bz,
+                                         const float *tile, float iso) {
+    const int l = lane();
+    const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    if (4 * bx + lx + 1 >= g.nx || 4 * by + ly + 1 >= g.ny || 4 * bz + lz + 1 >= g.nz) return -1;
+    int cs = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (tile[tix(lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2))] < iso) cs |= 1 << k;
+    return cs;
+}
+
+// Contiguous share [lo, hi) of n items for the calling wave.  Workgroups are
+// dispatched round-robin over the 8 XCDs (blockIdx % 8); the mapping gives
+// the workgroups of one XCD one contiguous eighth of the range, so blocks
+// whose halos overlap are staged through the same L2.  gridDim.x must be a
+// multiple of 8.
+__device__ __forceinline__ void xcd_wave_range(uint64_t n, uint64_t &lo, uint64_t &hi) {
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    const uint32_t logical = (g % 8u) * (G / 8u) + g / 8u;
+    const uint64_t waves = (uint64_t)G * MC_WAVES;
+    const uint64_t wv = (uint64_t)logical * MC_WAVES + (threadIdx.x >> 6);
+    const uint64_t chunk = (n + waves - 1) / waves;
+    lo = wv * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+}
+
 // Count pass: vertex count of every active block (0 unless it can emit).
 __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__restrict__ I_active,
                                                  const uint8_t *__restrict__ active,
@@ -587,34 +713,55 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
                                                  const float *__restrict__ slots,
                                                  const uint64_t *__restrict__ mc_table, float iso,
                                                  uint32_t *__restrict__ blk_cnt, Counters *ctr) {
-    __shared__ uint64_t tab[256];
-    __shared__ float tiles[MC_WAVES][128];
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) tab[i] = mc_table[i];
+    __shared__ uint8_t ntri[256];
+    __shared__ float tiles[MC_WAVES][MC_SB][128];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) ntri[i] = (uint8_t)(3u * (uint32_t)(mc_table[i] >> 60));
     __syncthreads();
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
+    const LaneGeom q = lane_geom();
     uint32_t occ = 0, cand = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
-        const uint32_t b = I_active[i];
-        uint32_t total = 0;
-        if (active[b] & 2u) {
-            cand++;
-            Halo h;
-            halo_setup(g, b, I_slot, identity, h);
-            if (h.bad) {
-                if (l == 0) atomicOr(&ctr->err, ERR_INTERNAL);
-            } else {
-                stage_tile(g, h, slots, tiles[w]);
-                wave_lds_sync();
-                const int cs = cell_case(g, h, tiles[w], iso);
-                total = wave_sum(cs < 0 ? 0u : 3u * (uint32_t)(tab[cs] >> 60));
-                wave_lds_sync();
+    uint64_t lo, hi;
+    xcd_wave_range(n_act, lo, hi);
+    for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
+        const uint64_t idx = i0 + l;
+        const bool valid = idx < hi;
+        const uint32_t b = valid ? I_active[idx] : 0u;
+        bool want = valid && (active[b] & 2u);
+        uint32_t so[8];
+        bool ok = octet(g, b, I_slot, identity, so) || !want;
+        if (!ok) atomicOr(&ctr->err, ERR_INTERNAL);
+        uint64_t todo = __ballot(want && ok);
+        cand += __popcll(todo);
+        uint32_t mycnt = 0;
+        while (todo) {
+            int jl[MC_SB], nsb = 0;
+#pragma unroll
+            for (int k = 0; k < MC_SB; k++) {
+                jl[k] = k ? jl[0] : 0;
+                if (todo) {
+                    jl[k] = (int)__builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    nsb++;
+                }
             }
+            stage_batch(q, slots, so, jl, tiles[w]);
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < MC_SB; k++) {
+                if (k < nsb) {
+                    const uint32_t bj = bcast(b, jl[k]);
+                    const uint32_t bx = bj % g.nbx, r = bj / g.nbx, by = r % g.nby, bz = r / g.nby;
+                    const int cs = tile_case(g, bx, by, bz, tiles[w][k], iso);
+                    const uint32_t total = wave_sum(cs < 0 ? 0u : (uint32_t)ntri[cs]);
+                    if (l == jl[k]) mycnt = total;
+                    occ += total != 0;
+                }
+            }
+            wave_lds_sync();
         }
-        if (l == 0) blk_cnt[i] = total;
-        occ += total != 0;
+        if (valid) blk_cnt[idx] = mycnt;
     }
     if (l == 0 && (occ | cand)) {
         atomicAdd(&ctr->n_occ, (unsigned long long)occ);
@@ -653,6 +800,14 @@ __global__ __launch_bounds__(256) void k_scan_counts(const uint32_t *__restrict_
     }
 }
 
+struct EmitShared {
+    uint64_t tab[256];
+    float tiles[MC_WAVES][MC_SB][128];
+    uint32_t pref[MC_WAVES][64];
+    uint8_t cs[MC_WAVES][64];
+    uint8_t map[MC_WAVES][64 * 15];
+};
+
 // Emission pass (Sec. 4.5): restage each occupied block, take the in-block
 // prefix of its per-cell vertex counts and write the triangle soup lane per
 // vertex at the block's offset, in canonical order (cell, triangle, vertex).
@@ -664,39 +819,73 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
                                                 const uint64_t *__restrict__ blk_off,
                                                 uint4 *__restrict__ out, uint64_t cap,
                                                 Counters *ctr) {
-    __shared__ McShared sh;
+    __shared__ EmitShared sh;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
     __syncthreads();
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
-    const float *tile = sh.tile[w];
-    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
-        if (blk_cnt[i] == 0) continue;
-        const uint32_t b = I_active[i];
-        const uint64_t base = blk_off[i];
-        Halo h;
-        const int total = block_layout(g, b, I_slot, identity, slots, iso, sh, w, h);
-        for (int j = l; j < total; j += 64) {
-            const int c = sh.map[w][j];
-            const int k = j - (int)sh.pref[w][c];
-            const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * k)) & 15u);
-            int ox, oy, oz, axis;
-            edge_geom(e, ox, oy, oz, axis);
-            const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
-            const float a = tile[tix(x0, y0, z0)];
-            const float bv = tile[tix(x0 + (axis == 0), y0 + (axis == 1), z0 + (axis == 2))];
-            const float tt = (iso - a) / (bv - a);
-            float px = (float)x0, py = (float)y0, pz = (float)z0;
-            if (axis == 0) px += tt;
-            else if (axis == 1) py += tt;
-            else pz += tt;
-            const uint64_t o = base + (uint64_t)j;
-            if (o < cap)
-                out[o] = make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+    const LaneGeom q = lane_geom();
+    uint64_t lo, hi;
+    xcd_wave_range(n_act, lo, hi);
+    for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
+        const uint64_t idx = i0 + l;
+        const bool valid = idx < hi;
+        const uint32_t cnt = valid ? blk_cnt[idx] : 0u;
+        const uint32_t b = cnt ? I_active[idx] : 0u;
+        const uint64_t boff = cnt ? blk_off[idx] : 0ull;
+        uint32_t so[8];
+        octet(g, b, I_slot, identity, so);
+        uint64_t todo = __ballot(cnt != 0);
+        while (todo) {
+            int jl[MC_SB], nsb = 0;
+#pragma unroll
+            for (int k = 0; k < MC_SB; k++) {
+                jl[k] = k ? jl[0] : 0;
+                if (todo) {
+                    jl[k] = (int)__builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    nsb++;
+                }
+            }
+            stage_batch(q, slots, so, jl, sh.tiles[w]);
+            wave_lds_sync();
+            for (int k = 0; k < nsb; k++) {
+                const uint32_t bj = bcast(b, jl[k]);
+                const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
+                                      bcast((uint32_t)boff, jl[k]);
+                const uint32_t bx = bj % g.nbx, r = bj / g.nbx, by = r % g.nby, bz = r / g.nby;
+                const float *tile = sh.tiles[w][k];
+                const int cs = tile_case(g, bx, by, bz, tile, iso);
+                const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
+                const uint32_t incl = wave_incl_scan(nv);
+                const int total = (int)__shfl(incl, 63, 64);
+                sh.pref[w][l] = incl - nv;
+                sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
+                for (uint32_t v = 0; v < nv; v++) sh.map[w][incl - nv + v] = (uint8_t)l;
+                wave_lds_sync();
+                for (int j = l; j < total; j += 64) {
+                    const int c = sh.map[w][j];
+                    const int kk = j - (int)sh.pref[w][c];
+                    const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * kk)) & 15u);
+                    int ox, oy, oz, axis;
+                    edge_geom(e, ox, oy, oz, axis);
+                    const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
+                    const float a = tile[tix(x0, y0, z0)];
+                    const float bv = tile[tix(x0 + (axis == 0), y0 + (axis == 1), z0 + (axis == 2))];
+                    const float tt = (iso - a) / (bv - a);
+                    float px = (float)x0, py = (float)y0, pz = (float)z0;
+                    if (axis == 0) px += tt;
+                    else if (axis == 1) py += tt;
+                    else pz += tt;
+                    const uint64_t o = base + (uint64_t)j;
+                    if (o < cap)
+                        out[o] = make_uint4(__float_as_uint(px), __float_as_uint(py),
+                                            __float_as_uint(pz), bj);
+                }
+                wave_lds_sync();
+            }
         }
-        wave_lds_sync();
     }
 }
 
@@ -847,14 +1036,37 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
     }
 }
 
+// Workgroups of a persistent kernel that are all resident at once (the
+// static per-wave shares assume no second round), in whole XCD rounds.
+template <typename K>
+static unsigned resident_grid(K kernel, uint64_t max_blocks) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    uint64_t g = (uint64_t)per_cu * cus;
+    uint64_t need = (max_blocks + MC_WAVES - 1) / MC_WAVES;
+    if (need < g) g = need;
+    g = g / 8 * 8;
+    return (unsigned)(g < 8 ? 8 : g);
+}
 static unsigned mc_grid(uint64_t max_blocks) {
     uint64_t g = (max_blocks + MC_WAVES - 1) / MC_WAVES;
-    return (unsigned)(g < 2048 ? (g ? g : 1) : 2048);
+    g = g < 2048 ? g : 2048;
+    return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
 }
 
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                      int identity_cache, float iso, hipStream_t s) {
-    k_mc_count<<<mc_grid(g.nb), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
+    static unsigned grid = 0;
+    if (!grid) grid = resident_grid(k_mc_count, ~0ull >> 4);
+    k_mc_count<<<std::min<unsigned>(grid, mc_grid(g.nb)), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
                                               slots, d.mc_table, iso, d.blk_cnt, d.ctr);
 }
 
@@ -866,7 +1078,9 @@ void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                     int identity_cache, float iso, void *out, uint64_t cap_verts, hipStream_t s) {
-    k_mc_emit<<<mc_grid(g.nb), 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots,
+    static unsigned grid = 0;
+    if (!grid) grid = resident_grid(k_mc_emit, ~0ull >> 4);
+    k_mc_emit<<<std::min<unsigned>(grid, mc_grid(g.nb)), 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots,
                                              d.mc_table, iso, d.blk_cnt, d.blk_off,
                                              reinterpret_cast<uint4 *>(out), cap_verts, d.ctr);
 }
