@@ -59,6 +59,73 @@ def cpu_baseline(stream_np, n, nz_sample, iso):
     }
 
 
+def differentiable_bench(steps, warmup):
+    """256^3 Gaussian blobs (16 blobs, seed 3), iso 0.5: forward extract and
+    forward + backward of L = sum_j (|v_j - c| - 64)^2 (c = grid centre)
+    through torch.autograd, against the plain extract of the same field
+    compressed at rate 16 with a warm cache.  Medians of `steps` runs."""
+    import numpy as np
+    import torch
+
+    import paper_2009_03254_amd as bcmc
+    from synthetic import fields
+
+    n = 256
+    dims = (n, n, n)
+    f = torch.from_numpy(fields.gaussian_blobs(n, 16, seed=3)).cuda()
+    blocks = bcmc.blocks_from_field(f)
+    words = bcmc.encode(f, 16)
+    vol = bcmc.Volume(words, dims, "f32", 16)
+    iso = 0.5
+    c = torch.full((3,), (n - 1) / 2.0, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        ts = []
+        for k in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            if k >= warmup:
+                ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) * 1e3, r
+
+    out = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    _, T = vol.extract_into(iso, out)
+    out = torch.empty((3 * T + 64, 4), dtype=torch.int32, device="cuda")
+    plain_ms, _ = timed(lambda: vol.extract_into(iso, out))
+    bl = blocks.clone().requires_grad_(True)
+    iso_t = torch.tensor(iso, device="cuda", requires_grad=True)
+
+    def fwd():
+        with torch.no_grad():
+            return bcmc.ExtractFn.apply(bl, iso_t, dims)
+
+    def fwd_bwd():
+        bl.grad = None
+        iso_t.grad = None
+        xyz, blk = bcmc.ExtractFn.apply(bl, iso_t, dims)
+        g = bcmc.global_positions(xyz, blk, dims, dtype=torch.float64)
+        loss = ((g - c).norm(dim=1) - 64.0).pow(2).sum()
+        loss.backward()
+        return loss
+
+    fwd_ms, _ = timed(fwd)
+    fb_ms, _ = timed(fwd_bwd)
+    vol.close()
+    return {
+        "workload": "gaussian blobs 256^3 f32 (16 blobs, seed 3), iso 0.5, "
+                    "L = sum (|v - c| - 64)^2 over all soup vertices",
+        "triangles": T,
+        "plain_extract_ms": round(plain_ms, 4),
+        "fwd_ms": round(fwd_ms, 4),
+        "fwd_bwd_ms": round(fb_ms, 4),
+        "fwd_bwd_vs_plain": round(fb_ms / plain_ms, 3),
+        "note": "plain = compressed (rate 16) volume, warm cache; fwd/bwd on the decoded "
+                "field through torch.autograd (loss in float64 torch ops included)",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +135,8 @@ def main():
     ap.add_argument("--cpu-sample-z", type=int, default=160,
                     help="z-planes of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-differentiable", action="store_true",
+                    help="skip the fwd / fwd+bwd measurement of the differentiable form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-profile-events", action="store_true",
@@ -104,11 +173,12 @@ def main():
     log(f"[bench] N_b={nb} iso50={float(iso50):.6f} iso90={float(iso90):.6f}")
 
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        # 1 GiB read + 1 GiB written by the library's plain copy kernel
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        a.fill_(1.0)
         torch.cuda.synchronize()
-        b.copy_(a)
+        bcmc._capi.check(bcmc.lib().bcmc_copy_calibration(
+            b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
         del a, b
 
@@ -222,6 +292,9 @@ def main():
                     for k, v in kern.items()},
         "calls": calls,
     }
+    if not args.no_differentiable:
+        log("[bench] differentiable form (256^3 blobs)")
+        result["differentiable"] = differentiable_bench(max(args.steps, 5), 2)
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_sample_z} z-planes")
         stream_np = words.cpu().numpy()

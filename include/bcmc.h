@@ -103,6 +103,12 @@ BCMC_API int bcmc_load_compressed(const void *stream, uint64_t nbytes, int strea
 BCMC_API int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uint32_t nz,
                             void *hip_stream, bcmc_volume **out);
 
+/* Point a bcmc_volume_from_blocks handle at new decoded blocks (same dims;
+ * device, caller-owned) and recompute the block ranges on hip_stream without
+ * synchronising.  Non-finite values are not detected here.
+ * Errors: BCMC_E_INVALID (not an identity handle). */
+BCMC_API int bcmc_rebind_blocks(bcmc_volume *v, const float *d_blocks, void *hip_stream);
+
 /* Cache budget (Sec. 4.2: user-set initial number of slots, grown on demand).
  * initial_bytes/256 slots exist at the start; growth adds
  * max(n_new - n_avail, ceil(n_slots/2)) slots, never beyond max_bytes/256
@@ -158,6 +164,12 @@ BCMC_API int bcmc_decode_all(bcmc_volume *v, float *d_blocks, void *hip_stream);
 /* The generated marching cubes table: packed[c] holds the edge ids of case c
  * (4 bits each, 15 = unused) and its triangle count in bits 60..63. */
 BCMC_API int bcmc_mc_table(uint64_t *packed256);
+
+/* Measurement helper: a plain device-to-device copy of nbytes (a multiple of
+ * 16) by the library's own streaming kernel, as a known-size reference when
+ * reading hardware traffic counters.  Not part of the extraction. */
+BCMC_API int bcmc_copy_calibration(void *d_dst, const void *d_src, uint64_t nbytes,
+                                   void *hip_stream);
 
 /* ---- inspection of the last extract (host copies; synchronous) -------- */
 BCMC_API int bcmc_debug_ranges(const bcmc_volume *v, float *h_ranges /* [N_b][2] */);

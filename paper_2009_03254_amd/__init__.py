@@ -24,7 +24,7 @@ from . import _capi
 from ._capi import BcmcError, lib  # noqa: F401
 
 __all__ = ["Volume", "FieldVolume", "ExtractFn", "encode", "mc_table", "num_blocks",
-           "split_vertices", "global_positions", "BcmcError", "lib"]
+           "blocks_from_field", "split_vertices", "global_positions", "BcmcError", "lib"]
 
 F32, F64 = 0, 1
 _TYPES = {"f32": F32, "float32": F32, "f64": F64, "float64": F64}
@@ -81,6 +81,21 @@ def encode(field, rate, stream=None):
     _capi.check(lib().bcmc_encode(_dev_ptr(field), typ, nx, ny, nz, rate, _dev_ptr(out),
                                   _stream_ptr(stream)))
     return out
+
+
+def blocks_from_field(field):
+    """[nz, ny, nx] CUDA tensor -> [N_b, 64] block layout (block id
+    bx + nbx*(by + nby*bz), sample lx + 4*ly + 16*lz), partial blocks padded
+    by replicating the last sample (a pure layout change)."""
+    torch = _torch()
+    nz, ny, nx = field.shape
+    pz, py, px = (-nz) % 4, (-ny) % 4, (-nx) % 4
+    f = field
+    if px or py or pz:
+        f = torch.nn.functional.pad(f[None, None], (0, px, 0, py, 0, pz), mode="replicate")[0, 0]
+    nbz, nby, nbx = f.shape[0] // 4, f.shape[1] // 4, f.shape[2] // 4
+    f = f.reshape(nbz, 4, nby, 4, nbx, 4).permute(0, 2, 4, 1, 3, 5)
+    return f.reshape(-1, 64).contiguous()
 
 
 def split_vertices(verts):
@@ -266,6 +281,13 @@ class FieldVolume(_Handle):
                                                   _stream_ptr(stream), C.byref(h)))
         self._h = h
 
+    def rebind(self, blocks, stream=None):
+        """Use new decoded blocks (same dims); ranges are recomputed on the GPU."""
+        if tuple(blocks.shape) != (self.n_blocks, 64) or not blocks.is_cuda:
+            raise ValueError("blocks must be a CUDA tensor of shape [N_b, 64]")
+        self.blocks = blocks.contiguous()
+        _capi.check(lib().bcmc_rebind_blocks(self._h, _dev_ptr(self.blocks), _stream_ptr(stream)))
+
     def backward(self, iso, gV, stream=None):
         torch = _torch()
         gV = gV.contiguous().to(torch.float32)
@@ -276,6 +298,24 @@ class FieldVolume(_Handle):
                                         _dev_ptr(gV) if n else None, n, _dev_ptr(dfield),
                                         _dev_ptr(diso), _stream_ptr(stream)))
         return dfield, diso
+
+
+_POOL = {}
+
+
+def _acquire_field_volume(blocks, dims):
+    """A FieldVolume for `dims` bound to `blocks`, reused across calls (a
+    handle holds the state of one forward until its backward is done)."""
+    free = _POOL.setdefault(tuple(dims), [])
+    if free:
+        vol = free.pop()
+        vol.rebind(blocks)
+        return vol
+    return FieldVolume(blocks, dims)
+
+
+def _release_field_volume(vol):
+    _POOL.setdefault(vol.dims, []).append(vol)
 
 
 def _make_extract_fn():
@@ -291,7 +331,7 @@ def _make_extract_fn():
 
         @staticmethod
         def forward(ctx, field_blocks, iso, dims):
-            vol = FieldVolume(field_blocks.detach(), dims)
+            vol = _acquire_field_volume(field_blocks.detach(), dims)
             isof = float(iso)
             verts, T = vol.extract(isof)
             xyz, blk = split_vertices(verts)
@@ -303,7 +343,8 @@ def _make_extract_fn():
         @staticmethod
         def backward(ctx, g_xyz, g_blk):
             dfield, diso = ctx.vol.backward(ctx.iso, g_xyz)
-            ctx.vol.close()
+            _release_field_volume(ctx.vol)
+            ctx.vol = None
             return dfield, diso.to(ctx.iso_dtype), None
 
     return ExtractFn

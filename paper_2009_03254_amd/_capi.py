@@ -40,6 +40,7 @@ SIGNATURES = {
     "bcmc_load_compressed": (_int, [_P, _u64, _int, _u32, _u32, _u32, _int, _u32, _P, _P]),
     "bcmc_volume_from_blocks": (_int, [_P, _u32, _u32, _u32, _P, _P]),
     "bcmc_set_cache_budget": (_int, [_P, _u64, _u64]),
+    "bcmc_rebind_blocks": (_int, [_P, _P, _P]),
     "bcmc_reset_cache": (_int, [_P, _P]),
     "bcmc_extract": (_int, [_P, _f32, _P, _u64, _P, _P]),
     "bcmc_backward": (_int, [_P, _f32, _P, _u64, _P, _P, _P]),
@@ -51,6 +52,7 @@ SIGNATURES = {
     "bcmc_encode": (_int, [_P, _int, _u32, _u32, _u32, _u32, _P, _P]),
     "bcmc_decode_all": (_int, [_P, _P, _P]),
     "bcmc_mc_table": (_int, [_P]),
+    "bcmc_copy_calibration": (_int, [_P, _P, _u64, _P]),
     "bcmc_debug_ranges": (_int, [_P, _P]),
     "bcmc_debug_active": (_int, [_P, _P, _P, _P]),
     "bcmc_debug_new": (_int, [_P, _P, _P]),

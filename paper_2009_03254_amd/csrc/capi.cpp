@@ -289,6 +289,16 @@ int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uin
     return BCMC_OK;
 }
 
+int bcmc_rebind_blocks(bcmc_volume *v, const float *d_blocks, void *hip_stream) {
+    if (!v || !d_blocks) return invalid("null argument");
+    if (!v->identity) return invalid("only bcmc_volume_from_blocks handles can be rebound");
+    v->ext_blocks = d_blocks;
+    v->have_extract = 0;
+    launch_ranges_from_blocks(v->g, d_blocks, v->d.ranges, &v->d.ctr->err, as_stream(hip_stream));
+    BCMC_HIP_TRY(hipGetLastError());
+    return BCMC_OK;
+}
+
 int bcmc_set_cache_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes) {
     if (!v) return invalid("null handle");
     if (v->identity) return invalid("identity volumes have no cache");
@@ -450,6 +460,13 @@ int bcmc_decode_all(bcmc_volume *v, float *d_blocks, void *hip_stream) {
     if (v->identity) return invalid("identity volumes hold no compressed stream");
     launch_decode_ranges(v->g, v->d.stream, v->is_f64, v->rate, v->d.ranges, d_blocks,
                          &v->d.ctr->err, as_stream(hip_stream));
+    BCMC_HIP_TRY(hipGetLastError());
+    return BCMC_OK;
+}
+
+int bcmc_copy_calibration(void *d_dst, const void *d_src, uint64_t nbytes, void *hip_stream) {
+    if (!d_dst || !d_src || (nbytes & 15)) return invalid("need device pointers and a multiple of 16 bytes");
+    launch_copy_calibration(d_dst, d_src, nbytes / 16, as_stream(hip_stream));
     BCMC_HIP_TRY(hipGetLastError());
     return BCMC_OK;
 }

@@ -973,6 +973,15 @@ __global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__rest
     if (l == 0 && giso != 0.0f) atomicAdd(diso, giso);
 }
 
+// Plain streaming copy (16 B per lane per iteration): a known-size reference
+// for reading memory-traffic counters.
+__global__ __launch_bounds__(256) void k_copy_calibration(uint4 *__restrict__ dst,
+                                                         const uint4 *__restrict__ src, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -1097,6 +1106,11 @@ void launch_backward(const Geom &g, const DevState &d, const float *slots, float
                      hipStream_t s) {
     k_backward<<<mc_grid(max_act), 256, 0, s>>>(g, d.I_active, slots, d.mc_table, iso, d.blk_cnt,
                                                  d.blk_off, gV, dfield, diso, d.ctr);
+}
+
+void launch_copy_calibration(void *dst, const void *src, uint64_t n16, hipStream_t s) {
+    if (n16) k_copy_calibration<<<grid_cap(n16, 16384), 256, 0, s>>>(
+        reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n16);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {
