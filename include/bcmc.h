@@ -171,6 +171,59 @@ BCMC_API int bcmc_mc_table(uint64_t *packed256);
 BCMC_API int bcmc_copy_calibration(void *d_dst, const void *d_src, uint64_t nbytes,
                                    void *hip_stream);
 
+/* ---- batched extraction: many volumes x isovalues in one launch ------- */
+/* A batch of jobs j = (volume job_vol[j], isovalue job_iso[j]) over
+ * compressed volumes that share one scalar type (the volumes must outlive
+ * the batch; their own caches are not used).  bcmc_batch_run extracts every
+ * job in ONE persistent cooperative kernel (phases separated by grid
+ * barriers), replayed from a hipGraph when the runtime allows it.  Job j's
+ * soup equals, byte for byte, bcmc_extract of its volume at its isovalue,
+ * and the jobs' soups are concatenated in job order.  The batch keeps one
+ * decoded-block store: a block needed by any job of its volume is decoded
+ * once and stays resident (nothing is evicted; 256 B per block reserved). */
+typedef struct bcmc_batch bcmc_batch;
+typedef struct {
+    uint64_t n_volumes, n_jobs;
+    uint64_t n_blocks;        /* blocks of all volumes */
+    uint64_t n_job_blocks;    /* sum over jobs of their volume's blocks */
+    uint64_t n_resident;      /* decoded blocks in the batch store */
+    uint64_t n_new;           /* decoded by the last run */
+    uint64_t n_pairs;         /* (job, block) pairs of the last run that may emit */
+    uint64_t n_vertices;      /* vertices of the last run (all jobs) */
+    uint32_t stage_blocks;    /* schedule: blocks staged per memory round trip (4 or 8) */
+    uint32_t grid;            /* schedule: workgroups of the persistent launch */
+    uint32_t workgroups_per_cu;
+    int32_t graph;            /* 1: the last run replayed a hipGraph */
+    int32_t graph_unsupported;/* 1: capturing the cooperative launch failed */
+    float last_ms;            /* GPU time of the last run (HIP events) */
+} bcmc_batch_info;
+
+BCMC_API int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t *job_vol,
+                               const float *job_iso, uint32_t n_jobs, void *hip_stream,
+                               bcmc_batch **out);
+/* New isovalues (host array of n_jobs floats); the captured graph reads them
+ * from device memory, so no re-capture is needed. */
+BCMC_API int bcmc_batch_set_isos(bcmc_batch *b, const float *job_iso, void *hip_stream);
+/* Empty the batch's decoded-block store. */
+BCMC_API int bcmc_batch_reset(bcmc_batch *b, void *hip_stream);
+/* 1 (default): capture the launch in a hipGraph and replay it; 0: launch directly. */
+BCMC_API int bcmc_batch_set_graph(bcmc_batch *b, int on);
+/* Run every job into d_out (capacity_vertices bcmc_vertex records, device);
+ * h_job_off (host, n_jobs + 1 entries) receives each job's first vertex and
+ * the total.  Synchronises once.  BCMC_E_CAPACITY when the total exceeds the
+ * capacity (offsets are set; enlarge and run again). */
+BCMC_API int bcmc_batch_run(bcmc_batch *b, void *d_out, uint64_t capacity_vertices,
+                            uint64_t *h_job_off, void *hip_stream);
+/* Autotune the schedule (blocks staged per round trip, workgroups per CU)
+ * by timing cold + warm runs of this batch; the best is kept and appended
+ * to cache_path (one JSON object per line, keyed by arch, scalar type and
+ * batch shape; NULL: $BCMC_AUTOTUNE_CACHE, or nothing).  Batches created
+ * later with a matching key start from the stored schedule.  Empties the
+ * batch store. */
+BCMC_API int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream);
+BCMC_API int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out);
+BCMC_API void bcmc_batch_free(bcmc_batch *b);
+
 /* ---- inspection of the last extract (host copies; synchronous) -------- */
 BCMC_API int bcmc_debug_ranges(const bcmc_volume *v, float *h_ranges /* [N_b][2] */);
 /* h_active[b]: bit 0 = active (M_active), bit 1 = may emit (the value hull

@@ -23,7 +23,7 @@ import numpy as np
 from . import _capi
 from ._capi import BcmcError, lib  # noqa: F401
 
-__all__ = ["Volume", "FieldVolume", "ExtractFn", "encode", "mc_table", "num_blocks",
+__all__ = ["Volume", "FieldVolume", "Batch", "ExtractFn", "encode", "mc_table", "num_blocks",
            "blocks_from_field", "split_vertices", "global_positions", "BcmcError", "lib"]
 
 F32, F64 = 0, 1
@@ -298,6 +298,75 @@ class FieldVolume(_Handle):
                                         _dev_ptr(gV) if n else None, n, _dev_ptr(dfield),
                                         _dev_ptr(diso), _stream_ptr(stream)))
         return dfield, diso
+
+
+class Batch:
+    """Many volumes x isovalues extracted in one persistent launch (hipGraph
+    replay).  jobs: list of (volume_index, isovalue)."""
+
+    def __init__(self, volumes, jobs, stream=None):
+        self.volumes = list(volumes)       # keep the volumes alive
+        self.n_jobs = len(jobs)
+        jv = np.ascontiguousarray([j[0] for j in jobs], dtype=np.uint32)
+        ji = np.ascontiguousarray([j[1] for j in jobs], dtype=np.float32)
+        arr = (C.c_void_p * len(self.volumes))(*[v._h for v in self.volumes])
+        h = C.c_void_p()
+        _capi.check(lib().bcmc_batch_create(arr, len(self.volumes), jv.ctypes.data_as(C.c_void_p),
+                                            ji.ctypes.data_as(C.c_void_p), self.n_jobs,
+                                            _stream_ptr(stream), C.byref(h)))
+        self._h = h
+        self._out = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bcmc_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_isos(self, isos, stream=None):
+        a = np.ascontiguousarray(isos, dtype=np.float32)
+        assert a.shape == (self.n_jobs,)
+        _capi.check(lib().bcmc_batch_set_isos(self._h, a.ctypes.data_as(C.c_void_p), _stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        _capi.check(lib().bcmc_batch_reset(self._h, _stream_ptr(stream)))
+
+    def set_graph(self, on=True):
+        _capi.check(lib().bcmc_batch_set_graph(self._h, 1 if on else 0))
+
+    def tune(self, cache_path=None, stream=None):
+        _capi.check(lib().bcmc_batch_tune(self._h, cache_path.encode() if cache_path else None,
+                                          _stream_ptr(stream)))
+
+    def info(self):
+        st = _capi.BatchInfo()
+        _capi.check(lib().bcmc_batch_get_info(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def run_into(self, out, stream=None):
+        """Run into a preallocated [cap, 4] int32 buffer: (rc, job offsets [n_jobs+1])."""
+        offs = np.zeros(self.n_jobs + 1, dtype=np.uint64)
+        rc = lib().bcmc_batch_run(self._h, _dev_ptr(out), out.shape[0],
+                                  offs.ctypes.data_as(C.c_void_p), _stream_ptr(stream))
+        return rc, offs
+
+    def run(self, stream=None):
+        """(vertices [V, 4] int32 CUDA tensor of all jobs, job offsets)."""
+        torch = _torch()
+        if self._out is None:
+            self._out = torch.empty((1 << 16, 4), dtype=torch.int32, device="cuda")
+        rc, offs = self.run_into(self._out, stream)
+        if rc == _capi.E_CAPACITY:
+            need = int(offs[-1])
+            self._out = torch.empty((need + need // 8 + 1024, 4), dtype=torch.int32, device="cuda")
+            rc, offs = self.run_into(self._out, stream)
+        _capi.check(rc)
+        return self._out[: int(offs[-1])], offs
 
 
 _POOL = {}

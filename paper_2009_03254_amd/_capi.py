@@ -34,6 +34,18 @@ class Stats(C.Structure):
         return d
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("n_volumes", C.c_uint64), ("n_jobs", C.c_uint64), ("n_blocks", C.c_uint64),
+                ("n_job_blocks", C.c_uint64), ("n_resident", C.c_uint64), ("n_new", C.c_uint64),
+                ("n_pairs", C.c_uint64), ("n_vertices", C.c_uint64),
+                ("stage_blocks", C.c_uint32), ("grid", C.c_uint32),
+                ("workgroups_per_cu", C.c_uint32), ("graph", C.c_int32),
+                ("graph_unsupported", C.c_int32), ("last_ms", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P, _u32, _u64, _i32, _f32, _int = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_float, C.c_int
 
 SIGNATURES = {
@@ -53,6 +65,14 @@ SIGNATURES = {
     "bcmc_decode_all": (_int, [_P, _P, _P]),
     "bcmc_mc_table": (_int, [_P]),
     "bcmc_copy_calibration": (_int, [_P, _P, _u64, _P]),
+    "bcmc_batch_create": (_int, [_P, _u32, _P, _P, _u32, _P, _P]),
+    "bcmc_batch_set_isos": (_int, [_P, _P, _P]),
+    "bcmc_batch_reset": (_int, [_P, _P]),
+    "bcmc_batch_set_graph": (_int, [_P, _int]),
+    "bcmc_batch_run": (_int, [_P, _P, _u64, _P, _P]),
+    "bcmc_batch_tune": (_int, [_P, C.c_char_p, _P]),
+    "bcmc_batch_get_info": (_int, [_P, _P]),
+    "bcmc_batch_free": (None, [_P]),
     "bcmc_debug_ranges": (_int, [_P, _P]),
     "bcmc_debug_active": (_int, [_P, _P, _P, _P]),
     "bcmc_debug_new": (_int, [_P, _P, _P]),

@@ -35,6 +35,15 @@ struct bcmc_volume {
     float last_iso = 0.0f;
 };
 
+namespace bcmc {
+const uint64_t *volume_stream(const bcmc_volume *v) { return v->d.stream; }
+const float2 *volume_ranges(const bcmc_volume *v) { return v->d.ranges; }
+Geom volume_geom(const bcmc_volume *v) { return v->g; }
+uint32_t volume_rate(const bcmc_volume *v) { return v->rate; }
+int volume_is_f64(const bcmc_volume *v) { return v->is_f64; }
+int volume_is_identity(const bcmc_volume *v) { return v->identity; }
+}  // namespace bcmc
+
 namespace {
 
 int invalid(const std::string &msg) {

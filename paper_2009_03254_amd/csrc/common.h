@@ -22,7 +22,7 @@ constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_PRE = 2ull << 62;
 constexpr uint64_t LB_VAL = (1ull << 62) - 1;
 
-enum : uint32_t { ERR_CACHE_CAP = 1u, ERR_NONFINITE = 2u, ERR_INTERNAL = 4u };
+enum : uint32_t { ERR_CACHE_CAP = 1u, ERR_NONFINITE = 2u, ERR_INTERNAL = 4u, ERR_TIMEOUT = 8u };
 
 // Device-resident scalars of one extract call.  Written only by kernels of
 // that call, read back once by the host at its end.

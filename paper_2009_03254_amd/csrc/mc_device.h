@@ -1,0 +1,423 @@
+// Device-side building blocks shared by the extraction kernels: wave64
+// primitives, decoupled look-back, and the 5^3 LDS staging of a block with
+// its +x/+y/+z halo.  Internal linkage in every includer.
+#pragma once
+
+#include <stdint.h>
+
+#include "common.h"
+
+namespace bcmc {
+namespace {
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back, run by one whole wave: publishes `agg` for tile t and
+// returns the exclusive prefix of the tile.  64 predecessors are inspected
+// per step: the window is summed up to (and including) the nearest tile
+// that already holds an inclusive prefix.
+__device__ uint64_t lookback(uint64_t *status, uint64_t t, uint64_t agg) {
+    const int l = lane();
+    if (t == 0) {
+        if (l == 0) lb_store(&status[0], LB_PRE | agg);
+        return 0;
+    }
+    if (l == 0) lb_store(&status[t], LB_AGG | agg);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)t - 1;
+    for (;;) {
+        int64_t idx = j - l;
+        uint64_t w = idx >= 0 ? lb_load(&status[idx]) : LB_PRE;
+        uint64_t flag = w & ~LB_VAL;
+        uint64_t pre = __ballot(flag == LB_PRE);
+        uint64_t notready = __ballot(flag == 0);
+        int first = pre ? (int)__builtin_ctzll(pre) : 64;
+        uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (notready & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t v = (l <= first) ? (w & LB_VAL) : 0;
+        excl += wave_sum(v);
+        if (first < 64) break;
+        j -= 64;
+    }
+    if (l == 0) lb_store(&status[t], LB_PRE | (excl + agg));
+    return excl;
+}
+
+// Workgroup (256 threads = 4 waves) exclusive scan of one value per thread
+// followed by the look-back; returns the thread's global exclusive prefix and
+// the tile total through *total (inclusive prefix of the tile in *incl_end).
+__device__ uint64_t tile_scan_lookback(uint64_t v, uint64_t *status, uint64_t t,
+                                       uint64_t *incl_end) {
+    __shared__ uint64_t s_w[4];
+    __shared__ uint64_t s_excl;
+    const int w = threadIdx.x >> 6;
+    uint64_t incl = wave_incl_scan(v);
+    if (lane() == 63) s_w[w] = incl;
+    __syncthreads();
+    uint64_t woff = 0, agg = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (i < w) woff += s_w[i];
+        agg += s_w[i];
+    }
+    if (w == 0) {
+        uint64_t e = lookback(status, t, agg);
+        if (lane() == 0) s_excl = e;
+    }
+    __syncthreads();
+    uint64_t e = s_excl;
+    *incl_end = e + agg;
+    __syncthreads();  // s_w / s_excl are reused by the next tile
+    return e + woff + incl - v;
+}
+
+__device__ __forceinline__ uint32_t take_tile(unsigned int *ctr) {
+    __shared__ uint32_t s_tile;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
+    __syncthreads();
+    uint32_t t = s_tile;
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Marching cubes over the active blocks (Sec. 4.3-4.5), as the paper's three
+// steps: a count pass (per-block vertex count, Sec. 4.4), a device-wide
+// exclusive scan of the block counts, and an emission pass (Sec. 4.5).
+// One wave64 owns one 4^3 block: lane = dual cell.  The block and its
+// +x/+y/+z halo (5^3 samples) are staged in LDS from the cache slots of the
+// block and its 7 positive neighbours.  Only blocks flagged "can emit" by the
+// cull (the value hull of the block and its positive neighbours contains
+// iso) are staged; every other block emits nothing, because a cell's eight
+// samples all lie in the block of its lowest corner and that block's positive
+// neighbours.
+// ---------------------------------------------------------------------------
+struct Halo {
+    int bad;                // a needed block has no slot (internal error)
+    uint32_t bx, by, bz;
+    uint32_t nslot[8];      // slots of the block (0) and its + neighbours (mask dx|dy<<1|dz<<2)
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void halo_setup(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
+                                           int identity, Halo &h) {
+    h.bx = b % g.nbx;
+    uint32_t r = b / g.nbx;
+    h.by = r % g.nby;
+    h.bz = r / g.nby;
+    h.bad = 0;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        uint32_t x = h.bx + (m & 1), y = h.by + ((m >> 1) & 1), z = h.bz + (m >> 2);
+        h.nslot[m] = 0;
+        if (x < g.nbx && y < g.nby && z < g.nbz) {
+            uint32_t nb = x + g.nbx * (y + g.nby * z);
+            if (identity) {
+                h.nslot[m] = nb;
+            } else {
+                int32_t s = I_slot[nb];
+                if (s < 0) h.bad = 1;
+                h.nslot[m] = s < 0 ? 0u : (uint32_t)s;
+            }
+        }
+    }
+}
+
+// LDS index of sample (x,y,z) of the 5^3 tile
+__device__ __forceinline__ int tix(int x, int y, int z) { return x + 5 * y + 25 * z; }
+
+// Stage the 125 samples: lane -> own sample, lanes 0..60 -> one halo sample.
+__device__ __forceinline__ void stage_tile(const Geom &g, const Halo &h, const float *__restrict__ slots,
+                                           float *tile) {
+    const int l = lane();
+    const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    tile[tix(lx, ly, lz)] = slots[(uint64_t)h.nslot[0] * 64 + l];
+    if (l < 61) {
+        int x, y, z;
+        if (l < 16) { x = 4; y = l & 3; z = l >> 2; }
+        else if (l < 32) { x = l & 3; y = 4; z = (l >> 2) & 3; }
+        else if (l < 48) { x = l & 3; y = (l >> 2) & 3; z = 4; }
+        else if (l < 52) { x = 4; y = 4; z = l - 48; }
+        else if (l < 56) { x = 4; y = l - 52; z = 4; }
+        else if (l < 60) { x = l - 56; y = 4; z = 4; }
+        else { x = 4; y = 4; z = 4; }
+        int m = (x >> 2) | ((y >> 2) << 1) | ((z >> 2) << 2);
+        bool inside = (h.bx + (x >> 2) < g.nbx) && (h.by + (y >> 2) < g.nby) && (h.bz + (z >> 2) < g.nbz);
+        float v = 0.0f;
+        if (inside) v = slots[(uint64_t)h.nslot[m] * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3)];
+        tile[tix(x, y, z)] = v;
+    }
+}
+
+// Case of the lane's cell (corner k at +(k&1, k>>1&1, k>>2&1); bit k set when
+// the corner value is below iso) or -1 when the cell lies outside the volume.
+__device__ __forceinline__ int cell_case(const Geom &g, const Halo &h, const float *tile, float iso) {
+    const int l = lane();
+    const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    if (4 * h.bx + lx + 1 >= g.nx || 4 * h.by + ly + 1 >= g.ny || 4 * h.bz + lz + 1 >= g.nz) return -1;
+    int cs = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (tile[tix(lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2))] < iso) cs |= 1 << k;
+    return cs;
+}
+
+// Edge e of a cell: its lower endpoint offset and axis.
+__device__ __forceinline__ void edge_geom(int e, int &ox, int &oy, int &oz, int &axis) {
+    axis = e >> 2;
+    int b0 = e & 1, b1 = (e >> 1) & 1;
+    ox = axis == 0 ? 0 : b0;
+    oy = axis == 1 ? 0 : (axis == 0 ? b0 : b1);
+    oz = axis == 2 ? 0 : b1;
+}
+
+struct McShared {
+    uint64_t tab[256];
+    float tile[MC_WAVES][128];
+    uint32_t pref[MC_WAVES][64];
+    uint8_t cs[MC_WAVES][64];
+    uint8_t map[MC_WAVES][64 * 15];
+};
+
+// Stage block b, classify its cells and lay out its vertices in LDS:
+// pref = exclusive prefix of per-cell vertex counts, map[v] = cell of
+// vertex v.  Returns the block's vertex count (-1 on an internal error).
+__device__ __forceinline__ int block_layout(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
+                                            int identity, const float *__restrict__ slots, float iso,
+                                            McShared &sh, int w, Halo &h) {
+    const int l = lane();
+    halo_setup(g, b, I_slot, identity, h);
+    if (h.bad) return -1;
+    stage_tile(g, h, slots, sh.tile[w]);
+    wave_lds_sync();
+    const int cs = cell_case(g, h, sh.tile[w], iso);
+    const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
+    const uint32_t incl = wave_incl_scan(nv);
+    sh.pref[w][l] = incl - nv;
+    sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
+    for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
+    wave_lds_sync();
+    return (int)__shfl(incl, 63, 64);
+}
+
+// ---- batched staging ------------------------------------------------------
+// A wave takes 64 consecutive active blocks at a time (one per lane): each lane
+// resolves the cache slots of its block and the block's 7 positive neighbours
+// (the "octet"), then the wave stages MC_SB of the selected blocks per memory
+// round trip (2 loads per lane per block, all in flight together) and works
+// through them from LDS.  Slots of out-of-volume neighbours are 0: what is
+// loaded from there only feeds cells outside the volume, which are never used.
+constexpr int MC_SB = 8;
+
+struct LaneGeom {            // per-lane constants of the 5^3 staging
+    int own_t;               // tile index of the lane's own sample
+    int halo_t;              // tile index of the lane's halo sample (lanes < 61)
+    int halo_m;              // which + neighbour holds it (dx | dy<<1 | dz<<2)
+    int halo_l;              // its index inside that neighbour
+};
+
+__device__ __forceinline__ LaneGeom lane_geom() {
+    const int l = lane();
+    LaneGeom q;
+    q.own_t = tix(l & 3, (l >> 2) & 3, l >> 4);
+    int x = 0, y = 0, z = 0;
+    if (l < 16) { x = 4; y = l & 3; z = l >> 2; }
+    else if (l < 32) { x = l & 3; y = 4; z = (l >> 2) & 3; }
+    else if (l < 48) { x = l & 3; y = (l >> 2) & 3; z = 4; }
+    else if (l < 52) { x = 4; y = 4; z = l - 48; }
+    else if (l < 56) { x = 4; y = l - 52; z = 4; }
+    else if (l < 60) { x = l - 56; y = 4; z = 4; }
+    else { x = 4; y = 4; z = 4; }
+    q.halo_t = tix(x, y, z);
+    q.halo_m = (x >> 2) | ((y >> 2) << 1) | ((z >> 2) << 2);
+    q.halo_l = (x & 3) + 4 * (y & 3) + 16 * (z & 3);
+    return q;
+}
+
+// Slots of block b and its 7 positive neighbours; false if one is missing.
+// The 8 lookups are issued unconditionally (an out-of-volume neighbour reads
+// block b's own entry) so that they are in flight together.
+__device__ __forceinline__ bool octet(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
+                                      int identity, uint32_t so[8]) {
+    const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
+    uint32_t nb[8];
+    bool in[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        const uint32_t x = bx + (m & 1), y = by + ((m >> 1) & 1), z = bz + (m >> 2);
+        in[m] = x < g.nbx && y < g.nby && z < g.nbz;
+        nb[m] = in[m] ? x + g.nbx * (y + g.nby * z) : b;
+    }
+    if (identity) {
+#pragma unroll
+        for (int m = 0; m < 8; m++) so[m] = in[m] ? nb[m] : 0u;
+        return true;
+    }
+    int32_t sl[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) sl[m] = I_slot[nb[m]];
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        ok = ok && (!in[m] || sl[m] >= 0);
+        so[m] = (in[m] && sl[m] >= 0) ? (uint32_t)sl[m] : 0u;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+// Stage up to SB blocks (lanes jl[k] of the batch) into tiles[k].  Every
+// slot is loaded unconditionally (unused k repeat block jl[0]) so all 2*SB
+// loads of a lane are in flight before the first LDS write.
+template <int SB>
+__device__ __forceinline__ void stage_batch_n(const LaneGeom &q, const float *__restrict__ slots,
+                                              const uint32_t so[8], const int *jl,
+                                              float (*tiles)[128]) {
+    const int l = lane();
+    float ov[SB], hv[SB];
+#pragma unroll
+    for (int k = 0; k < SB; k++) {
+        uint32_t s_own = bcast(so[0], jl[k]);
+        uint32_t s_h = s_own;
+#pragma unroll
+        for (int m = 1; m < 8; m++) {
+            uint32_t sm = bcast(so[m], jl[k]);
+            s_h = (q.halo_m == m) ? sm : s_h;
+        }
+        ov[k] = slots[(uint64_t)s_own * 64 + l];
+        hv[k] = slots[(uint64_t)s_h * 64 + q.halo_l];
+    }
+#pragma unroll
+    for (int k = 0; k < SB; k++) {
+        tiles[k][q.own_t] = ov[k];
+        if (l < 61) tiles[k][q.halo_t] = hv[k];
+    }
+}
+
+__device__ __forceinline__ void stage_batch(const LaneGeom &q, const float *__restrict__ slots,
+                                            const uint32_t so[8], const int *jl,
+                                            float (*tiles)[128]) {
+    stage_batch_n<MC_SB>(q, slots, so, jl, tiles);
+}
+
+// Case of the lane's cell in block (bx,by,bz) staged in `tile`, -1 outside.
+__device__ __forceinline__ int tile_case(const Geom &g, uint32_t bx, uint32_t by, uint32_t bz,
+                                         const float *tile, float iso) {
+    const int l = lane();
+    const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
+    if (4 * bx + lx + 1 >= g.nx || 4 * by + ly + 1 >= g.ny || 4 * bz + lz + 1 >= g.nz) return -1;
+    int cs = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (tile[tix(lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2))] < iso) cs |= 1 << k;
+    return cs;
+}
+
+// Contiguous share [lo, hi) of n items for the calling wave.  Workgroups are
+// dispatched round-robin over the 8 XCDs (blockIdx % 8); the mapping gives
+// the workgroups of one XCD one contiguous eighth of the range, so blocks
+// whose halos overlap are staged through the same L2.  gridDim.x must be a
+// multiple of 8.
+__device__ __forceinline__ void xcd_wave_range(uint64_t n, uint64_t &lo, uint64_t &hi) {
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    const uint32_t logical = (g % 8u) * (G / 8u) + g / 8u;
+    const uint64_t waves = (uint64_t)G * MC_WAVES;
+    const uint64_t wv = (uint64_t)logical * MC_WAVES + (threadIdx.x >> 6);
+    const uint64_t chunk = (n + waves - 1) / waves;
+    lo = wv * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+}
+
+struct EmitShared {
+    uint64_t tab[256];
+    float tiles[MC_WAVES][MC_SB][128];
+    uint32_t pref[MC_WAVES][64];
+    uint8_t cs[MC_WAVES][64];
+    uint8_t map[MC_WAVES][64 * 15];
+};
+
+}  // namespace
+}  // namespace bcmc
+
+namespace bcmc {
+namespace {
+
+// Emission of one staged block (Sec. 4.5): cases, in-block exclusive scan of
+// the per-cell vertex counts, then lane per vertex in canonical order (cell,
+// triangle, vertex), written from `base` on (records past `cap` dropped).
+__device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, const float *tile, float iso,
+                                           EmitShared &sh, int w, uint64_t base,
+                                           uint4 *__restrict__ out, uint64_t cap) {
+    const int l = lane();
+    const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
+    const int cs = tile_case(g, bx, by, bz, tile, iso);
+    const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
+    const uint32_t incl = wave_incl_scan(nv);
+    const int total = (int)__shfl(incl, 63, 64);
+    sh.pref[w][l] = incl - nv;
+    sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
+    for (uint32_t v = 0; v < nv; v++) sh.map[w][incl - nv + v] = (uint8_t)l;
+    wave_lds_sync();
+    for (int j = l; j < total; j += 64) {
+        const int c = sh.map[w][j];
+        const int kk = j - (int)sh.pref[w][c];
+        const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * kk)) & 15u);
+        int ox, oy, oz, axis;
+        edge_geom(e, ox, oy, oz, axis);
+        const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
+        const float a = tile[tix(x0, y0, z0)];
+        const float bv = tile[tix(x0 + (axis == 0), y0 + (axis == 1), z0 + (axis == 2))];
+        const float tt = (iso - a) / (bv - a);
+        float px = (float)x0, py = (float)y0, pz = (float)z0;
+        if (axis == 0) px += tt;
+        else if (axis == 1) py += tt;
+        else pz += tt;
+        const uint64_t o = base + (uint64_t)j;
+        if (o < cap) out[o] = make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+    }
+    wave_lds_sync();
+}
+
+}  // namespace
+}  // namespace bcmc

@@ -1,0 +1,125 @@
+"""GPU parity of the batched extraction: every job's slice of the batched
+output equals, byte for byte, the single-volume extract of its volume at its
+isovalue (and the oracle's counts / FP32 vertices), across cold and warm runs,
+isovalue updates, graph replay on and off, autotuned schedules, and f64."""
+import numpy as np
+import pytest
+
+from synthetic import fields
+from tests.gpu_common import say, torch_cuda, verts_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _make(orc, dims_list, rate, f64=False, seed0=500):
+    streams, decoded = [], []
+    for k, (nx, ny, nz) in enumerate(dims_list):
+        f = fields.turbulence(nx, ny, nz, seed=seed0 + k, n_modes=32,
+                              dtype=np.float64 if f64 else np.float32)
+        s = orc.zfp_encode(f, rate)
+        streams.append(s)
+        decoded.append(orc.zfp_decode(s, (nx, ny, nz), rate, f64))
+    return streams, decoded
+
+
+def _plain(bc, vol, iso):
+    import torch
+    out = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    rc, T = vol.extract_into(float(iso), out)
+    out = torch.empty((3 * T + 8, 4), dtype=torch.int32, device="cuda")
+    rc, T = vol.extract_into(float(iso), out)
+    assert rc == 0
+    return out[: 3 * T].cpu().numpy()
+
+
+def _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain_vols):
+    import torch
+    need = sum(3 * orc.mc_count(decoded[vi], dims_list[vi], iso) for vi, iso in jobs)
+    out = torch.empty((need + 16, 4), dtype=torch.int32, device="cuda")
+    rc, offs = batch.run_into(out)
+    assert rc == 0, bc.lib().bcmc_last_error()
+    assert int(offs[-1]) == need
+    v = out[:need].cpu().numpy()
+    assert offs[0] == 0 and np.all(np.diff(offs.astype(np.int64)) >= 0)
+    for j, (vi, iso) in enumerate(jobs):
+        got = v[int(offs[j]):int(offs[j + 1])]
+        ref = _plain(bc, plain_vols[vi], iso)
+        assert got.shape == ref.shape, (j, got.shape, ref.shape)
+        assert np.array_equal(got, ref), j
+        T = orc.mc_count(decoded[vi], dims_list[vi], iso)
+        assert got.shape[0] == 3 * T
+        if T:
+            v32, vb = orc.mc_extract_f32(decoded[vi], dims_list[vi], iso)
+            assert np.array_equal(got[:, :3].view(np.float32).view(np.uint32), v32.view(np.uint32))
+            assert np.array_equal(got[:, 3].view(np.uint32), vb)
+    return offs
+
+
+def test_batch_equals_plain_extract(orc):
+    torch_cuda()
+    import paper_2009_03254_amd as bc
+    rng = np.random.default_rng(7)
+    dims_list = [tuple(int(x) for x in rng.integers(18, 60, 3)) for _ in range(7)]
+    say(f"[batch] dims {dims_list}")
+    streams, decoded = _make(orc, dims_list, 8)
+    vols = [bc.Volume(s, d, "f32", 8) for s, d in zip(streams, dims_list)]
+    plain = [bc.Volume(s, d, "f32", 8) for s, d in zip(streams, dims_list)]
+    isos = {vi: [fields.percentile_iso(orc.blocks_to_field(decoded[vi], dims_list[vi]), p)
+                 for p in (20, 50, 80)] for vi in range(len(vols))}
+    jobs = [(vi, isos[vi][k]) for k in range(3) for vi in range(len(vols))]   # interleaved
+    batch = bc.Batch(vols, jobs)
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
+    info = batch.info()
+    assert info["n_new"] > 0 and info["n_resident"] == info["n_new"]
+    say(f"  cold: {info}")
+    # warm: nothing new, same output
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
+    assert batch.info()["n_new"] == 0
+    # new isovalues through device memory (graph replay without re-capture)
+    jobs2 = [(vi, isos[vi][(k + 1) % 3] * 0.5) for k in range(3) for vi in range(len(vols))]
+    batch.set_isos([j[1] for j in jobs2])
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs2, plain)
+    # direct cooperative launch (no graph) gives the same bytes
+    batch.set_graph(False)
+    batch.reset()
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs2, plain)
+    assert batch.info()["graph"] == 0
+    batch.set_graph(True)
+    # autotuned schedule, then the same result again
+    batch.tune()
+    info = batch.info()
+    say(f"  tuned: stage_blocks={info['stage_blocks']} grid={info['grid']} graph={info['graph']} "
+        f"unsupported={info['graph_unsupported']}")
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs2, plain)
+    batch.close()
+
+
+def test_batch_f64_and_empty_jobs(orc):
+    torch_cuda()
+    import paper_2009_03254_amd as bc
+    dims_list = [(21, 18, 13), (9, 30, 17)]
+    streams, decoded = _make(orc, dims_list, 2, f64=True, seed0=900)
+    vols = [bc.Volume(s, d, "f64", 2) for s, d in zip(streams, dims_list)]
+    plain = [bc.Volume(s, d, "f64", 2) for s, d in zip(streams, dims_list)]
+    jobs = [(1, 0.1), (0, 50.0), (0, -0.2), (1, -50.0), (0, 0.3)]    # two jobs without surface
+    batch = bc.Batch(vols, jobs)
+    offs = _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
+    assert offs[2] == offs[1] and offs[4] == offs[3]
+    batch.close()
+
+
+def test_batch_capacity_retry(orc):
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bc
+    dims_list = [(40, 33, 27)]
+    streams, decoded = _make(orc, dims_list, 8, seed0=950)
+    vols = [bc.Volume(streams[0], dims_list[0], "f32", 8)]
+    batch = bc.Batch(vols, [(0, 0.0), (0, 0.5)])
+    out = torch.empty((8, 4), dtype=torch.int32, device="cuda")
+    rc, offs = batch.run_into(out)
+    assert rc == bc._capi.E_CAPACITY
+    T = orc.mc_count(decoded[0], dims_list[0], 0.0) + orc.mc_count(decoded[0], dims_list[0], 0.5)
+    assert offs[-1] == 3 * T
+    verts, offs2 = batch.run()
+    assert np.array_equal(offs, offs2)
+    batch.close()
