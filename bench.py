@@ -31,8 +31,35 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
 RATE = 8
 
 
+# Sources of the single-volume kernels, hashed to tell whether the committed
+# traffic counters were taken on the kernels as they are now.
+KERNEL_SOURCES = ("common.h", "mc_device.h", "zfp_device.h", "extract.hip", "zfp.hip")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "path_turbulence512_rate8_hbm_counters.md")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when there is
+    none or the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2009_03254_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    m = re.search(rf"^traffic {re.escape(kernel)} bytes_per_dispatch=(\d+) sources_sha256=(\w+)$",
+                  text, re.M)
+    if not m or m.group(2) != h.hexdigest():
+        return None
+    return int(m.group(1))
 
 
 def cpu_baseline(stream_np, n, nz_sample, iso):
@@ -399,7 +426,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(kd["gbs"], 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_launch_ms": round(kd["avg_ms"], 5),
+            "traffic": measured_traffic(dom), "avg_launch_ms": round(kd["avg_ms"], 5),
             "alg_bytes_per_launch": round(kd["bytes"] / kd["launches"]),
         },
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_gbs": round(v["gbs"], 1),
