@@ -31,15 +31,28 @@ __device__ __forceinline__ void block_xyz(const Geom &g, uint64_t b, uint32_t &b
 
 // Decode every block once: value range over the valid samples (Sec. 4.1),
 // non-finite detection, and optionally the decoded blocks themselves.
-template <bool F64>
+template <bool F64, bool STAGED>
 __global__ __launch_bounds__(256) void k_decode_ranges(Geom g, const uint64_t *__restrict__ stream,
                                                       int rate, float2 *__restrict__ ranges,
                                                       float *__restrict__ blocks,
                                                       unsigned int *err) {
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < g.nb;
-         b += (uint64_t)gridDim.x * blockDim.x) {
+    extern __shared__ uint64_t stage_lds[];
+    constexpr bool staged = STAGED;
+    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGE_STRIDE * rate);
+    // whole waves iterate together (the staging is a wave-wide copy)
+    for (uint64_t b0 = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); b0 < g.nb;
+         b0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = b0 + __lane_id();
+        const bool valid = b < g.nb;
         float v[64];
-        decode_block<F64>(stream + b * rate, rate, v);
+        if (staged) {
+            stage_words(stream, rate, b, valid, st);
+            if (valid) decode_block_staged<F64>(st, rate, v);
+        } else if (valid) {
+            decode_block<F64>(stream + b * rate, rate, v);
+        }
+        if (staged) __builtin_amdgcn_wave_barrier();   // st is rewritten by the next round
+        if (!valid) continue;
         uint32_t bx, by, bz;
         block_xyz(g, b, bx, by, bz);
         uint32_t vx = min(4u, g.nx - 4 * bx), vy = min(4u, g.ny - 4 * by), vz = min(4u, g.nz - 4 * bz);
@@ -59,7 +72,7 @@ __global__ __launch_bounds__(256) void k_decode_ranges(Geom g, const uint64_t *_
         if (blocks) {
             float4 *o = reinterpret_cast<float4 *>(blocks + b * 64);
 #pragma unroll
-            for (int i = 0; i < 16; i++) o[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+            for (int q = 0; q < 16; q++) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
         }
     }
 }
@@ -98,7 +111,7 @@ __global__ __launch_bounds__(256) void k_ranges_from_blocks(Geom g, const float 
 // Alg. 1 AssignSlots fused with DecompressBlocks: new block I_new[i] takes the
 // i-th slot of the age-sorted available list, evicting its previous owner,
 // and is decoded straight into that slot.
-template <bool F64>
+template <bool F64, bool STAGED>
 __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
                                                       const uint32_t *__restrict__ sorted0,
                                                       const uint32_t *__restrict__ sorted1,
@@ -112,25 +125,40 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
     if (n_new == 0) return;
     // the radix passes ping-pong; the result is in buffer (#passes run) & 1
     const uint32_t *sorted = (__popc(ctr->pass_mask) & 1) ? sorted1 : sorted0;
+    extern __shared__ uint64_t stage_lds[];
+    constexpr bool staged = STAGED;
+    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGE_STRIDE * rate);
     uint32_t evicted = 0;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_new;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t b = I_new[i];
-        uint32_t s = sorted[i];
-        if (b >= n_blocks || s >= n_slots) {  // never expected: report, do not touch memory
+    // whole waves iterate together (the staging is a wave-wide copy)
+    for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); i0 < n_new;
+         i0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = i0 + __lane_id();
+        bool valid = i < n_new;
+        const uint32_t b = valid ? I_new[i] : 0u;
+        const uint32_t s = valid ? sorted[i] : 0u;
+        if (valid && (b >= n_blocks || s >= n_slots)) {  // never expected: report, do not touch memory
             atomicOr(&ctr->err, ERR_INTERNAL);
-            continue;
+            valid = false;
         }
-        int32_t old = S_block[s];
-        if (old >= 0) {
-            I_slot[old] = -1;
-            evicted++;
+        if (valid) {
+            int32_t old = S_block[s];
+            if (old >= 0) {
+                I_slot[old] = -1;
+                evicted++;
+            }
+            S_block[s] = (int32_t)b;
+            I_slot[b] = (int32_t)s;
+            S_age[s] = 0;
         }
-        S_block[s] = (int32_t)b;
-        I_slot[b] = (int32_t)s;
-        S_age[s] = 0;
         float v[64];
-        decode_block<F64>(stream + (uint64_t)b * rate, rate, v);
+        if (staged) {
+            stage_words(stream, rate, b, valid, st);
+            if (valid) decode_block_staged<F64>(st, rate, v);
+            __builtin_amdgcn_wave_barrier();   // st is rewritten by the next round
+        } else if (valid) {
+            decode_block<F64>(stream + (uint64_t)b * rate, rate, v);
+        }
+        if (!valid) continue;
         float4 *o = reinterpret_cast<float4 *>(slots + (uint64_t)s * 64);
 #pragma unroll
         for (int q = 0; q < 16; q++) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
@@ -167,13 +195,21 @@ unsigned grid_for(uint64_t n, unsigned cap) {
 
 }  // namespace
 
+// Instantiates a decode kernel for (type, staged) and launches it with the
+// staging LDS the rate needs.
+#define BCMC_DECODE_LAUNCH(KERNEL, grid, rate, s, ...)                                      \
+    do {                                                                                    \
+        const unsigned lds_ = stage_lds_bytes((int)(rate));                                 \
+        if (is_f64 && lds_) KERNEL<true, true><<<grid, 256, lds_, s>>>(__VA_ARGS__);         \
+        else if (is_f64) KERNEL<true, false><<<grid, 256, 0, s>>>(__VA_ARGS__);              \
+        else if (lds_) KERNEL<false, true><<<grid, 256, lds_, s>>>(__VA_ARGS__);             \
+        else KERNEL<false, false><<<grid, 256, 0, s>>>(__VA_ARGS__);                         \
+    } while (0)
+
 void launch_decode_ranges(const Geom &g, const uint64_t *stream, int is_f64, uint32_t rate,
                           float2 *ranges, float *blocks_out, unsigned int *err, hipStream_t s) {
     unsigned grid = grid_for(g.nb, 8192);
-    if (is_f64)
-        k_decode_ranges<true><<<grid, 256, 0, s>>>(g, stream, (int)rate, ranges, blocks_out, err);
-    else
-        k_decode_ranges<false><<<grid, 256, 0, s>>>(g, stream, (int)rate, ranges, blocks_out, err);
+    BCMC_DECODE_LAUNCH(k_decode_ranges, grid, rate, s, g, stream, (int)rate, ranges, blocks_out, err);
 }
 
 void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *ranges,
@@ -184,14 +220,8 @@ void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *range
 void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new,
                           hipStream_t s) {
     unsigned grid = grid_for(max_new, 2048);
-    if (is_f64)
-        k_assign_decode<true><<<grid, 256, 0, s>>>(d.ctr, d.I_new, d.sort_val[0], d.sort_val[1],
-                                                   d.S_block, d.I_slot, d.S_age, d.stream,
-                                                   (int)rate, d.slots, max_new);
-    else
-        k_assign_decode<false><<<grid, 256, 0, s>>>(d.ctr, d.I_new, d.sort_val[0], d.sort_val[1],
-                                                    d.S_block, d.I_slot, d.S_age, d.stream,
-                                                    (int)rate, d.slots, max_new);
+    BCMC_DECODE_LAUNCH(k_assign_decode, grid, rate, s, d.ctr, d.I_new, d.sort_val[0], d.sort_val[1],
+                       d.S_block, d.I_slot, d.S_age, d.stream, (int)rate, d.slots, max_new);
 }
 
 void launch_encode(const Geom &g, const void *field, int is_f64, uint32_t rate, uint64_t *stream,

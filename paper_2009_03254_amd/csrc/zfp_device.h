@@ -93,14 +93,18 @@ __device__ __forceinline__ void inv_zyx(Int *v) {
 }
 
 // ---- bit reader over one block's words ------------------------------------
+// Word w of the block sits at p[w * STRIDE]: STRIDE = 1 reads the stream in
+// global memory, STRIDE = STAGE_STRIDE reads a wave's LDS staging area
+// (stage_words below).
+template <int STRIDE>
 struct BitReader {
     const uint64_t *__restrict__ p;
     uint64_t cur;  // unread bits, LSB first; bits above cnt are zero
     int cnt;
 
     __device__ __forceinline__ void refill() {
-        cur = __builtin_nontemporal_load(p);
-        p++;
+        cur = *p;
+        p += STRIDE;
         cnt = 64;
     }
     __device__ __forceinline__ void skip(int n) {  // n <= cnt
@@ -120,8 +124,8 @@ struct BitReader {
             skip(n);
             return v;
         }
-        uint64_t w = __builtin_nontemporal_load(p);
-        p++;
+        uint64_t w = *p;
+        p += STRIDE;
         int take = n - cnt;  // 1..64, cnt < 64
         uint64_t v = cur | (w << cnt);
         if (n < 64) v &= (1ull << n) - 1;
@@ -131,14 +135,15 @@ struct BitReader {
     }
 };
 
-// Decode one block (words of 64*rate bits) into 64 floats in block order.
-template <bool F64>
-__device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words, int rate,
-                                             float *out) {
+// Decode one block (64*rate bits read through `br`) into 64 floats in block
+// order.  The bits of bit plane k are deposited only into the coefficients
+// below n (the number of significant coefficients after the plane), in
+// groups of 8: higher coefficients have no bit in the plane.
+template <bool F64, class BR>
+__device__ __forceinline__ void decode_block_from(BR br, int rate, float *out) {
     using T = Prec<F64>;
     using UInt = typename T::UInt;
     using Int = typename T::Int;
-    BitReader br{words, 0, 0};
     if (!br.bit()) {
 #pragma unroll
         for (int i = 0; i < 64; i++) out[i] = 0.0f;
@@ -182,16 +187,13 @@ __device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words,
             x |= 1ull << n;
             n++;
         }
-        if (x) {
-            if (F64) {
+        const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
 #pragma unroll
-                for (int i = 0; i < 64; i++) c[i] |= (UInt)((x >> i) & 1u) << k;
-            } else {
-                uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+        for (int g = 0; g < 8; g++) {
+            if (n > 8 * g) {
+                const uint32_t wv = g < 4 ? lo : hi;
 #pragma unroll
-                for (int i = 0; i < 32; i++) c[i] |= ((lo >> i) & 1u) << k;
-#pragma unroll
-                for (int i = 0; i < 32; i++) c[32 + i] |= ((hi >> i) & 1u) << k;
+                for (int i = 8 * g; i < 8 * g + 8; i++) c[i] |= (UInt)((wv >> (i & 31)) & 1u) << k;
             }
         }
     }
@@ -208,6 +210,62 @@ __device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words,
 #pragma unroll
         for (int i = 0; i < 64; i++) out[i] = (float)(int32_t)v[i] * s;
     }
+}
+
+// Decode one block straight from the stream in global memory.
+template <bool F64>
+__device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words, int rate,
+                                             float *out) {
+    decode_block_from<F64>(BitReader<1>{words, 0, 0}, rate, out);
+}
+
+// ---- wave-level staging of the compressed words ----------------------------
+// The 64 lanes of a wave each decode one block.  Before decoding, the wave
+// copies the words of its blocks into LDS, word w of lane l's block at
+// st[w * STAGE_STRIDE + l] (the odd row pitch keeps the transposing writes
+// free of bank conflicts).  When the wave's blocks are consecutive (lane l
+// holds block b0 + l, the usual case: new blocks are listed in ascending
+// order) the copy reads one contiguous run of the stream, 512 bytes per
+// instruction; otherwise each lane copies its own block's words.
+constexpr int STAGE_STRIDE = 65;
+constexpr int STAGE_MAX_RATE = 16;   // larger rates decode from global memory
+
+__device__ __forceinline__ void stage_words(const uint64_t *__restrict__ stream, int rate, uint64_t b,
+                                            bool valid, uint64_t *st) {
+    const int l = (int)__lane_id();
+    const uint64_t vmask = __ballot(valid);
+    const uint64_t b0 = __shfl(b, 0, 64);
+    const bool prefix = (vmask & (vmask + 1)) == 0;   // valid lanes are 0..nv-1
+    const bool consecutive = prefix && (vmask & 1) &&
+                             __ballot(valid && b == b0 + (uint64_t)l) == vmask;
+    if (consecutive) {
+        const uint32_t total = (uint32_t)__popcll(vmask) * (uint32_t)rate;
+        // i / rate as (i * ceil(2^32 / rate)) >> 32: exact for i < 2^32 / rate
+        const uint64_t magic = ((1ull << 32) + (uint64_t)rate - 1) / (uint64_t)rate;
+        const uint64_t *src = stream + b0 * (uint64_t)rate;
+        for (uint32_t i = (uint32_t)l; i < total; i += 64) {
+            const uint32_t ln = (uint32_t)(((uint64_t)i * magic) >> 32), wd = i - ln * (uint32_t)rate;
+            st[wd * STAGE_STRIDE + ln] = src[i];
+        }
+    } else if (valid) {
+        const uint64_t *src = stream + b * (uint64_t)rate;
+        for (int wd = 0; wd < rate; wd++) st[wd * STAGE_STRIDE + l] = src[wd];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Decode lane l's block from the staging area written by stage_words.
+template <bool F64>
+__device__ __forceinline__ void decode_block_staged(const uint64_t *st, int rate, float *out) {
+    decode_block_from<F64>(BitReader<STAGE_STRIDE>{st + __lane_id(), 0, 0}, rate, out);
+}
+
+// Bytes of dynamic LDS a 256-thread workgroup needs for staging at `rate`
+// (0: the rate is decoded from global memory).
+__host__ __device__ inline unsigned stage_lds_bytes(int rate) {
+    return rate <= STAGE_MAX_RATE ? 4u * STAGE_STRIDE * (unsigned)rate * 8u : 0u;
 }
 
 // ---- bit writer ------------------------------------------------------------
