@@ -262,6 +262,77 @@ def batch_bench(steps, warmup):
     }
 
 
+def large_bench(steps, warmup):
+    """5120 x 3840 x 768 float64 channel-flow-like field (tanh mean profile +
+    0.1 relative Fourier turbulence, seed 5), generated and ZFP-encoded at
+    rate 2 slab by slab on the GPU (3.8 GB compressed), iso 0.5, cache capped
+    at 64 GiB of decoded float32: cold extract (cache emptied) and warm
+    repeat, medians of `steps` runs, with per-stage HIP-event times."""
+    import numpy as np
+    import torch
+
+    import paper_2009_03254_amd as bcmc
+    from synthetic import fields
+
+    rate = 2
+    nx, ny, nz = fields.CHANNEL_FLOW_DIMS
+    nb = bcmc.num_blocks(nx, ny, nz)
+    words = torch.empty(nb * rate, dtype=torch.uint64, device="cuda")
+    per_layer = (nx // 4) * (ny // 4)
+    t0 = time.perf_counter()
+    for z0 in range(0, nz, 32):
+        f = fields.channel_flow_slab(z0, min(nz, z0 + 32))
+        w = bcmc.encode(f, rate)
+        first = (z0 // 4) * per_layer * rate
+        words[first: first + w.numel()] = w
+        del f, w
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    vol = bcmc.Volume(words, (nx, ny, nz), "f64", rate)
+    del words
+    torch.cuda.empty_cache()
+    vol.set_cache_budget(initial_bytes=0, max_bytes=64 << 30)
+    probe = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    _, T = vol.extract_into(0.5, probe)
+    out = torch.empty((3 * T + 64, 4), dtype=torch.int32, device="cuda")
+    vol.set_profiling(True)
+
+    def run(cold):
+        recs = []
+        for k in range(warmup + steps):
+            if cold:
+                vol.reset_cache()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, T2 = vol.extract_into(0.5, out)
+            dt = time.perf_counter() - t
+            if rc != 0 or T2 != T:
+                raise bcmc.BcmcError(rc, bcmc.lib().bcmc_last_error().decode())
+            if k >= warmup:
+                recs.append((dt, vol.stats()))
+        ms = float(np.median([r[0] for r in recs])) * 1e3
+        st = recs[-1][1]
+        return {"ms": round(ms, 4), "triangles_per_s": round(T / (ms * 1e-3)),
+                "alg_gbs": round(st["alg_bytes"] / (ms * 1e-3) / 1e9, 2),
+                "n_active": st["n_active"], "n_new": st["n_new"], "n_occupied": st["n_occupied"],
+                "stage_ms": [round(float(np.median([r[1]["stage_ms"][i] for r in recs])), 4)
+                             for i in range(8)]}
+
+    cold = run(True)
+    warm = run(False)
+    vol.set_profiling(False)
+    vol.close()
+    cull_ms = warm["stage_ms"][0]
+    return {
+        "workload": f"channel flow {nx}x{ny}x{nz} f64 (tanh profile + 0.1 Fourier turbulence, "
+                    "seed 5), ZFP rate 2, iso 0.5, cache cap 64 GiB",
+        "n_blocks": nb, "triangles": T, "generate_encode_s": round(gen_s, 2),
+        "cold": cold, "warm": warm,
+        "cull_range_gbs": round(8.0 * nb / (cull_ms * 1e-3) / 1e9, 1) if cull_ms > 0 else None,
+        "note": "cull_range_gbs = the 8-byte range table over the cull + compaction stage time",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +346,10 @@ def main():
                     help="skip the fwd / fwd+bwd measurement of the differentiable form")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched (48 volumes x 4 isovalues) measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 5120x3840x768 float64 measurement")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the 5120x3840x768 float64 measurement and print its JSON")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched measurement and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -299,6 +374,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.batched_only:
         print(json.dumps({"batched": batch_bench(max(args.steps, 5), args.warmup)}), flush=True)
+        return
+    if args.large_only:
+        print(json.dumps({"large_f64": large_bench(max(args.steps, 3), 1)}), flush=True)
         return
     log(f"[bench] generating {n}^3 turbulence on the GPU")
     field = fields.turbulence_torch(n, seed=2, device=dev)
@@ -438,6 +516,10 @@ def main():
     if not args.no_differentiable:
         log("[bench] differentiable form (256^3 blobs)")
         result["differentiable"] = differentiable_bench(max(args.steps, 5), 2)
+    if not args.no_large:
+        vol.close()
+        log("[bench] large float64 volume (5120x3840x768, rate 2)")
+        result["large_f64"] = large_bench(max(args.steps // 2, 3), 1)
     if not args.no_batched:
         log("[bench] batched form (48 volumes x 4 isovalues)")
         result["batched"] = batch_bench(max(args.steps, 5), 2)

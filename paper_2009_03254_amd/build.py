@@ -29,9 +29,29 @@ FLAGS = [
 ]
 
 
+GEN = os.path.join(BUILD, "gen")
+
+
+def _generate():
+    """Build and run gen_ntri (host only): writes _build/gen/mc_ntri.h, the
+    bit-sliced triangle count of the marching-cubes table."""
+    os.makedirs(GEN, exist_ok=True)
+    exe = os.path.join(GEN, "gen_ntri")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O2", "-std=c++17", "-x", "hip",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "gen_ntri.cpp"),
+           os.path.join(CSRC, "tables.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building gen_ntri failed:\n{r.stdout}{r.stderr}")
+    r = subprocess.run([exe, os.path.join(GEN, "mc_ntri.h")], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"gen_ntri failed:\n{r.stdout}{r.stderr}")
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-I", os.path.join(ROOT, "include"), "-c",
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "-I", os.path.join(ROOT, "include"), "-I", GEN, "-c",
            os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(line for line in (r.stdout + r.stderr).splitlines()
@@ -45,6 +65,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
+    _generate()
     with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

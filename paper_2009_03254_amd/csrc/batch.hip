@@ -318,8 +318,8 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
             const uint32_t j = find_base(p.job_jbase, p.n_jobs, e);
             const BatchVol &vol = p.vols[p.job_vol[j]];
             const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
-            uint32_t so[8];
-            octet(vol.g, b, p.I_slot + vol.gbase, 0, so);
+            uint32_t so[8], lbx, lby, lbz;
+            octet(vol.g, b, p.I_slot + vol.gbase, 0, so, lbx, lby, lbz);
             uint64_t todo = __ballot(valid);
             uint32_t mycnt = 0;
             while (todo) {
@@ -340,8 +340,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
                     if (k < nsb) {
                         const uint32_t vj = bcast(p.job_vol[j], jl[k]);
                         const Geom &g = p.vols[vj].g;
-                        const uint32_t bj = bcast(b, jl[k]);
-                        const uint32_t bx = bj % g.nbx, r = bj / g.nbx, by = r % g.nby, bz = r / g.nby;
+                        const uint32_t bx = bcast(lbx, jl[k]), by = bcast(lby, jl[k]), bz = bcast(lbz, jl[k]);
                         const float iso = __uint_as_float(bcast(__float_as_uint(p.job_iso[j]), jl[k]));
                         const int cs = tile_case(g, bx, by, bz, sh.emit.tiles[w][k], iso);
                         const uint32_t total = wave_sum(cs < 0 ? 0u : sh.ntri[cs]);
@@ -398,8 +397,8 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
             const BatchVol &vol = p.vols[p.job_vol[j]];
             const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
             const uint64_t boff = cnt ? p.off[idx] : 0ull;
-            uint32_t so[8];
-            octet(vol.g, b, p.I_slot + vol.gbase, 0, so);
+            uint32_t so[8], lbx, lby, lbz;
+            octet(vol.g, b, p.I_slot + vol.gbase, 0, so, lbx, lby, lbz);
             uint64_t todo = __ballot(cnt != 0);
             while (todo) {
                 int jl[SB], nsb = 0;
@@ -421,7 +420,8 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
                     const float iso = __uint_as_float(bcast(__float_as_uint(p.job_iso[j]), jl[k]));
                     const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
                                           bcast((uint32_t)boff, jl[k]);
-                    emit_block(g, bj, sh.emit.tiles[w][k], iso, sh.emit, w, base,
+                    emit_block(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
+                               sh.emit.tiles[w][k], iso, sh.emit, w, base,
                                reinterpret_cast<uint4 *>(p.out), p.cap);
                 }
             }

@@ -95,6 +95,7 @@ void free_cache(bcmc_volume *v) {
     dev_free(v->d.S_block);
     dev_free(v->d.S_age);
     dev_free(v->d.slots);
+    dev_free(v->d.masks);
     for (int i = 0; i < 2; i++) {
         dev_free(v->d.sort_key[i]);
         dev_free(v->d.sort_val[i]);
@@ -120,6 +121,8 @@ int alloc_common(bcmc_volume *v) {
     if ((rc = dev_alloc(&v->d.I_active, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_cnt, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_off, v->g.nb))) return rc;
+    if ((rc = dev_alloc(&v->d.part_cand, (v->g.nb + BLK_TILE - 1) / BLK_TILE))) return rc;
+    if ((rc = dev_alloc(&v->d.part_occ, (v->g.nb + SCAN_TILE - 1) / SCAN_TILE))) return rc;
     if ((rc = dev_alloc(&v->d.ctr, 1))) return rc;
     if ((rc = dev_alloc(&v->d.mc_table, 256))) return rc;
     if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
@@ -142,6 +145,8 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.I_slot);
     dev_free(v->d.blk_cnt);
     dev_free(v->d.blk_off);
+    dev_free(v->d.part_cand);
+    dev_free(v->d.part_occ);
     dev_free(v->d.ctr);
     dev_free(v->d.mc_table);
     if (v->h_ctr) (void)hipHostFree(v->h_ctr);
@@ -174,6 +179,7 @@ int set_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes, hipSt
     if ((rc = dev_alloc(&v->d.S_block, maxs))) return rc;
     if ((rc = dev_alloc(&v->d.S_age, maxs))) return rc;
     if ((rc = dev_alloc(&v->d.slots, maxs * 64))) return rc;
+    if ((rc = dev_alloc(&v->d.masks, maxs))) return rc;
     for (int i = 0; i < 2; i++) {
         if ((rc = dev_alloc(&v->d.sort_key[i], maxs))) return rc;
         if ((rc = dev_alloc(&v->d.sort_val[i], maxs))) return rc;
@@ -273,7 +279,8 @@ int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uin
     v->ext_blocks = d_blocks;
     v->max_slots = 0;
     layout_status(v);
-    if ((rc = alloc_common(v)) || (rc = dev_alloc(&v->d.status, v->sl.total))) {
+    if ((rc = alloc_common(v)) || (rc = dev_alloc(&v->d.status, v->sl.total)) ||
+        (rc = dev_alloc(&v->d.masks, v->g.nb))) {
         destroy(v);
         return rc;
     }

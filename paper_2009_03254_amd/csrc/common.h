@@ -12,9 +12,9 @@ namespace bcmc {
 // ---- constants ----------------------------------------------------------
 constexpr uint32_t HIGH_AGE = 0x80000000u;  // age of a slot created empty
 constexpr int BLK_TILE = 4096;               // blocks per compaction tile
-constexpr int SLOT_TILE = 4096;              // slots per compaction tile
+constexpr int SLOT_TILE = 1024;              // slots per compaction tile (4 per thread)
 constexpr int RADIX_TILE = 1024;             // elements per radix tile (1 wave)
-constexpr int SCAN_TILE = 4096;              // u32 per look-back scan tile
+constexpr int SCAN_TILE = 4096;              // u32 per look-back scan tile (16 per thread)
 constexpr int MC_WAVES = 4;                  // blocks (one per wave) per MC tile
 
 // look-back status words: 2 flag bits on top, value below
@@ -65,12 +65,15 @@ struct DevState {
     int32_t *S_block = nullptr;
     uint32_t *S_age = nullptr;
     float *slots = nullptr;         // [max_slots][64] decoded blocks
+    uint64_t *masks = nullptr;      // [max_slots] per slot: bit i = sample i below iso
     uint32_t *sort_key[2] = {nullptr, nullptr};  // ~age of available slots
     uint32_t *sort_val[2] = {nullptr, nullptr};  // slot ids
     uint32_t *radix_hist = nullptr;              // 256 * radix tiles
     // MC
     uint32_t *blk_cnt = nullptr;    // per active block vertex count
     uint64_t *blk_off = nullptr;    // per active block first vertex
+    uint32_t *part_cand = nullptr;  // per compaction tile: blocks that may emit
+    uint32_t *part_occ = nullptr;   // per block-count scan tile: blocks with triangles
     uint64_t *status = nullptr;     // look-back status words (all kernels)
     Counters *ctr = nullptr;
     uint64_t *mc_table = nullptr;   // 256 packed cases

@@ -15,6 +15,7 @@
 
 #include "common.h"
 #include "mc_device.h"
+#include "mc_ntri.h"
 
 namespace bcmc {
 namespace {
@@ -25,6 +26,13 @@ namespace {
 // that is:  (lo_b < iso <= HI)  or  (LO < iso <= hi_b).
 // Also resets the call's counters and clears the look-back status words.
 // ---------------------------------------------------------------------------
+// Tiled: a workgroup owns a CULL_TX x CULL_TY column of blocks over
+// CULL_TZ z-layers.  Each layer's ranges (with a one-block halo, +inf / -inf
+// outside the volume) are staged in LDS once; the 3x3 in-plane min / max and
+// the 2x2 positive-quadrant min / max come from LDS and are combined across z
+// in registers, so every range is read about 1.5 times.
+constexpr int CULL_TX = 32, CULL_TY = 8, CULL_TZ = 16;
+
 __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
                                              uint8_t *__restrict__ active, Counters *ctr,
                                              uint64_t n_slots_host, uint64_t *status,
@@ -40,38 +48,63 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
         *ctr = c;
     }
     for (uint64_t w = gid; w < status_words; w += gsz) status[w] = 0;
-    for (uint64_t b = gid; b < g.nb; b += gsz) {
-        uint32_t bx = (uint32_t)(b % g.nbx);
-        uint64_t r = b / g.nbx;
-        uint32_t by = (uint32_t)(r % g.nby), bz = (uint32_t)(r / g.nby);
-        float2 own = ranges[b];
-        float LO = own.x, HI = own.y;    // over the 3x3x3 neighbourhood
-        float PLO = own.x, PHI = own.y;  // over the block and its + neighbours
-        for (int dz = -1; dz <= 1; dz++) {
-            int z = (int)bz + dz;
-            if (z < 0 || z >= (int)g.nbz) continue;
-            for (int dy = -1; dy <= 1; dy++) {
-                int y = (int)by + dy;
-                if (y < 0 || y >= (int)g.nby) continue;
-                const float2 *row = ranges + ((uint64_t)z * g.nby + y) * g.nbx;
-                for (int dx = -1; dx <= 1; dx++) {
-                    int x = (int)bx + dx;
-                    if (x < 0 || x >= (int)g.nbx) continue;
-                    float2 q = row[x];
-                    LO = fminf(LO, q.x);
-                    HI = fmaxf(HI, q.y);
-                    if (dx >= 0 && dy >= 0 && dz >= 0) {
-                        PLO = fminf(PLO, q.x);
-                        PHI = fmaxf(PHI, q.y);
-                    }
+
+    __shared__ float2 sh[CULL_TY + 2][CULL_TX + 2];
+    const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
+    uint32_t t = blockIdx.x;
+    const uint32_t tx = t % ntx;
+    t /= ntx;
+    const uint32_t ty = t % nty, tz = t / nty;
+    const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
+    const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
+    const bool inxy = bx < g.nbx && by < g.nby;
+    const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+    // per layer: 3x3 min / max, 2x2 positive min / max, own range
+    float l3a = INFINITY, h3a = -INFINITY;                       // layer zl - 2
+    float l3b = INFINITY, h3b = -INFINITY, p2lb = INFINITY, p2hb = -INFINITY;
+    float2 ownb = make_float2(INFINITY, -INFINITY);             // layer zl - 1
+    for (int zl = z0 - 1; zl <= z1; zl++) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < (CULL_TY + 2) * (CULL_TX + 2); i += 256) {
+            const int hy = i / (CULL_TX + 2), hx = i - hy * (CULL_TX + 2);
+            const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
+            float2 v = make_float2(INFINITY, -INFINITY);
+            if (zl >= 0 && zl < (int)g.nbz && x >= 0 && x < (int)g.nbx && y >= 0 && y < (int)g.nby)
+                v = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
+            sh[hy][hx] = v;
+        }
+        __syncthreads();
+        float l3 = INFINITY, h3 = -INFINITY, p2l = INFINITY, p2h = -INFINITY;
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+            for (int dx = -1; dx <= 1; dx++) {
+                const float2 q = sh[ly + 1 + dy][lx + 1 + dx];
+                l3 = fminf(l3, q.x);
+                h3 = fmaxf(h3, q.y);
+                if (dx >= 0 && dy >= 0) {
+                    p2l = fminf(p2l, q.x);
+                    p2h = fmaxf(p2h, q.y);
                 }
             }
+        const float2 own = sh[ly + 1][lx + 1];
+        if (zl > z0 && inxy) {   // layer zl - 1 has both z neighbours now
+            const float LO = fminf(l3a, fminf(l3b, l3)), HI = fmaxf(h3a, fmaxf(h3b, h3));
+            const float PLO = fminf(p2lb, p2l), PHI = fmaxf(p2hb, p2h);
+            const bool act = (ownb.x < iso && iso <= HI) || (LO < iso && iso <= ownb.y);
+            // "can emit": the hull of the 2x2x2 group headed by the block
+            // contains iso (implies act, as that group contains the block)
+            const bool can_emit = PLO < iso && iso <= PHI;
+            active[((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx] =
+                (act ? 1u : 0u) | (can_emit ? 2u : 0u);
         }
-        bool act = (own.x < iso && iso <= HI) || (LO < iso && iso <= own.y);
-        // "can emit": the hull of the 2x2x2 group headed by b contains iso
-        // (implies act, as that group contains b)
-        bool can_emit = PLO < iso && iso <= PHI;
-        active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u);
+        l3a = l3b;
+        h3a = h3b;
+        l3b = l3;
+        h3b = h3;
+        p2lb = p2l;
+        p2hb = p2h;
+        ownb = own;
     }
 }
 
@@ -82,6 +115,7 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
                                                        const int32_t *__restrict__ I_slot,
                                                        int identity, uint32_t *__restrict__ I_active,
                                                        uint32_t *__restrict__ I_new, Counters *ctr,
+                                                       uint32_t *__restrict__ part_cand,
                                                        uint64_t *status) {
     const uint64_t n_tiles = (g.nb + BLK_TILE - 1) / BLK_TILE;
     const uint32_t t = take_tile(&ctr->tile_ctr[TC_BLK]);
@@ -98,6 +132,10 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
         for (int j = 0; j < 16; j++)
             if (base + j < g.nb && active[base + j]) actb |= 1u << j;
     }
+    uint32_t cand = 0;   // blocks that may emit (bit 1 of the flag), summed per tile
+    for (uint32_t m = actb; m; m &= m - 1) cand += (active[base + __builtin_ctz(m)] >> 1) & 1u;
+    cand = wg_sum_u32(cand);
+    if (threadIdx.x == 0) part_cand[t] = cand;
     if (!identity) {
         for (uint32_t m = actb; m; m &= m - 1) {
             int j = __builtin_ctz(m);
@@ -129,20 +167,32 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
     const uint32_t t = take_tile(&ctr->tile_ctr[TC_SLOT]);
     if (t >= n_tiles) return;
     const bool need_list = ctr->n_new != 0;
-    const uint64_t base = (uint64_t)t * SLOT_TILE + threadIdx.x * 16u;
+    constexpr int PER = SLOT_TILE / 256;   // consecutive slots per thread (16-byte loads)
+    static_assert(PER == 4, "the vector path loads 4 slots per thread");
+    const uint64_t base = (uint64_t)t * SLOT_TILE + threadIdx.x * PER;
     uint32_t availb = 0;
-    uint32_t age[16];
+    uint32_t age[PER];
+    int32_t blk[PER];
     uint32_t kor = 0, kand = ~0u;
+    const bool full = base + PER <= n_slots;
+    if (full) {
+        const int4 bq = *reinterpret_cast<const int4 *>(S_block + base);
+        const uint4 aq = *reinterpret_cast<const uint4 *>(S_age + base);
+        blk[0] = bq.x; blk[1] = bq.y; blk[2] = bq.z; blk[3] = bq.w;
+        age[0] = aq.x; age[1] = aq.y; age[2] = aq.z; age[3] = aq.w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
-        uint64_t s = base + j;
-        age[j] = 0;
-        if (s < n_slots) {
-            int32_t b = S_block[s];
-            bool act = b >= 0 && active[b];
-            uint32_t a = S_age[s];
+        for (int j = 0; j < PER; j++) {
+            blk[j] = base + j < n_slots ? S_block[base + j] : -1;
+            age[j] = base + j < n_slots ? S_age[base + j] : 0u;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        if (base + j < n_slots) {
+            const bool act = blk[j] >= 0 && active[blk[j]];
+            uint32_t a = age[j];
             a = act ? 0u : (a == 0xFFFFFFFFu ? a : a + 1u);
-            S_age[s] = a;
             age[j] = a;
             if (!act) {
                 availb |= 1u << j;
@@ -151,25 +201,38 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
             }
         }
     }
+    if (full) {
+        *reinterpret_cast<uint4 *>(S_age + base) = make_uint4(age[0], age[1], age[2], age[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < PER; j++)
+            if (base + j < n_slots) S_age[base + j] = age[j];
+    }
     if (!need_list) return;
     uint64_t incl_end;
     uint64_t e = tile_scan_lookback((uint64_t)__popc(availb), status, t, &incl_end);
 #pragma unroll
-    for (int j = 0; j < 16; j++)
+    for (int j = 0; j < PER; j++)
         if ((availb >> j) & 1u) {
             keys[e] = ~age[j];
             vals[e] = (uint32_t)(base + j);
             e++;
         }
-    // OR / AND of the keys: which radix digits vary
+    // OR / AND of the keys: which radix digits vary (one atomic pair per workgroup)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         kor |= __shfl_xor(kor, d, 64);
         kand &= __shfl_xor(kand, d, 64);
     }
+    __shared__ uint32_t s_or[4], s_and[4];
     if (lane() == 0) {
-        atomicOr(&ctr->key_or, kor);
-        atomicAnd(&ctr->key_and, kand);
+        s_or[threadIdx.x >> 6] = kor;
+        s_and[threadIdx.x >> 6] = kand;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicOr(&ctr->key_or, s_or[0] | s_or[1] | s_or[2] | s_or[3]);
+        atomicAnd(&ctr->key_and, s_and[0] & s_and[1] & s_and[2] & s_and[3]);
     }
     if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_avail_old = incl_end;
 }
@@ -280,18 +343,19 @@ __global__ __launch_bounds__(256) void k_radix_scan(Counters *ctr, int p, uint32
     for (;;) {
         const uint32_t t = take_tile(&ctr->tile_ctr[TC_SCAN0 + p]);
         if (t >= scan_tiles) return;
-        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * 16u;
-        uint32_t x[16];
+        constexpr int PER = SCAN_TILE / 256;   // consecutive entries per thread
+        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * PER;
+        uint32_t x[PER];
         uint64_t sum = 0;
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
+        for (int j = 0; j < PER; j++) {
             x[j] = base + j < len ? hist[base + j] : 0u;
             sum += x[j];
         }
         uint64_t incl_end;
         uint64_t e = tile_scan_lookback(sum, status, t, &incl_end);
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
+        for (int j = 0; j < PER; j++) {
             if (base + j < len) hist[base + j] = (uint32_t)e;
             e += x[j];
         }
@@ -354,95 +418,165 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Counters *ctr, int p,
     }
 }
 
-// Count pass: vertex count of every active block (0 unless it can emit).
+// Sign masks (Sec. 4.4's per-cell classification, one bit per sample): for
+// every active block, bit i of masks[slot] is set when sample i of the
+// block (x fastest) is below iso.  One lane per block: its 16 float4 loads
+// are all in flight before the first compare.
+__global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_active,
+                                              const int32_t *__restrict__ I_slot, int identity,
+                                              const float *__restrict__ slots, float iso,
+                                              uint64_t *__restrict__ masks, const Counters *ctr) {
+    if (ctr->err) return;
+    const uint64_t n_act = ctr->n_act;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_act;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = I_active[i];
+        const int32_t s = identity ? (int32_t)b : I_slot[b];
+        if (s < 0) continue;
+        const float4 *src = reinterpret_cast<const float4 *>(slots) + (uint64_t)s * 16;
+        float4 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) v[q] = src[q];
+        uint64_t m = 0;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const uint64_t nib = (v[q].x < iso ? 1u : 0u) | (v[q].y < iso ? 2u : 0u) |
+                                 (v[q].z < iso ? 4u : 0u) | (v[q].w < iso ? 8u : 0u);
+            m |= nib << (4 * q);
+        }
+        masks[s] = m;
+    }
+}
+
+// Corner masks of the 64 cells of a block from the sign masks of the block
+// and its 7 positive neighbours (M[dx | dy<<1 | dz<<2]): bit i of c[k] is the
+// sign bit of corner k = (k&1, k>>1&1, k>>2&1) of cell i.  sx / sy / sz give,
+// for every cell, the sample one step along x / y / z: from the block itself,
+// or from the neighbour for the cells on its far face.
+__device__ __forceinline__ uint64_t sx(uint64_t a, uint64_t b) {
+    return ((a >> 1) & 0x7777777777777777ull) | ((b << 3) & 0x8888888888888888ull);
+}
+__device__ __forceinline__ uint64_t sy(uint64_t a, uint64_t b) {
+    return ((a >> 4) & 0x0FFF0FFF0FFF0FFFull) | ((b << 12) & 0xF000F000F000F000ull);
+}
+__device__ __forceinline__ uint64_t sz(uint64_t a, uint64_t b) { return (a >> 16) | (b << 48); }
+
+__device__ __forceinline__ void corner_masks(const uint64_t M[8], uint64_t c[8]) {
+    const uint64_t x01 = sx(M[0], M[1]), x23 = sx(M[2], M[3]);
+    const uint64_t x45 = sx(M[4], M[5]), x67 = sx(M[6], M[7]);
+    c[0] = M[0];
+    c[1] = x01;
+    c[2] = sy(M[0], M[2]);
+    c[3] = sy(x01, x23);
+    c[4] = sz(M[0], M[4]);
+    c[5] = sz(x01, x45);
+    c[6] = sz(c[2], sy(M[4], M[6]));
+    c[7] = sz(c[3], sy(x45, x67));
+}
+
+// Cells of block (bx, by, bz) whose 8 corners lie in the volume.
+__device__ __forceinline__ uint64_t valid_cells(const Geom &g, uint32_t bx, uint32_t by, uint32_t bz) {
+    const int vx = min(4, (int)g.nx - 1 - 4 * (int)bx);
+    const int vy = min(4, (int)g.ny - 1 - 4 * (int)by);
+    const int vz = min(4, (int)g.nz - 1 - 4 * (int)bz);
+    if (vx <= 0 || vy <= 0 || vz <= 0) return 0;
+    const uint64_t mx = 0x1111111111111111ull * ((1ull << vx) - 1);
+    const uint64_t my = 0x0001000100010001ull * ((1ull << (4 * vy)) - 1);
+    const uint64_t mz = vz == 4 ? ~0ull : ((1ull << (16 * vz)) - 1);
+    return mx & my & mz;
+}
+
+// Count pass (Sec. 4.4): vertex count of every active block (0 unless it can
+// emit), one lane per block.  The cases of all 64 cells are evaluated at once
+// on the corner masks, and the triangle count per case by the bit-sliced
+// diagram of the marching-cubes table (mc_ntri_bits, generated at build time).
 __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__restrict__ I_active,
                                                  const uint8_t *__restrict__ active,
                                                  const int32_t *__restrict__ I_slot, int identity,
-                                                 const float *__restrict__ slots,
-                                                 const uint64_t *__restrict__ mc_table, float iso,
+                                                 const uint64_t *__restrict__ masks,
                                                  uint32_t *__restrict__ blk_cnt, Counters *ctr) {
-    __shared__ uint8_t ntri[256];
-    __shared__ float tiles[MC_WAVES][MC_SB][128];
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) ntri[i] = (uint8_t)(3u * (uint32_t)(mc_table[i] >> 60));
-    __syncthreads();
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
-    const int w = threadIdx.x >> 6, l = lane();
-    const LaneGeom q = lane_geom();
-    uint32_t occ = 0, cand = 0;
     uint64_t lo, hi;
     xcd_wave_range(n_act, lo, hi);
-    for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
-        const uint64_t idx = i0 + l;
-        const bool valid = idx < hi;
-        const uint32_t b = valid ? I_active[idx] : 0u;
-        bool want = valid && (active[b] & 2u);
-        uint32_t so[8];
-        bool ok = octet(g, b, I_slot, identity, so) || !want;
-        if (!ok) atomicOr(&ctr->err, ERR_INTERNAL);
-        uint64_t todo = __ballot(want && ok);
-        cand += __popcll(todo);
-        uint32_t mycnt = 0;
-        while (todo) {
-            int jl[MC_SB], nsb = 0;
+    for (uint64_t i = lo + lane(); i < hi; i += 64) {
+        const uint32_t b = I_active[i];
+        uint32_t cnt = 0;
+        if (active[b] & 2u) {
+            uint32_t so[8], bx, by, bz;
+            if (!octet(g, b, I_slot, identity, so, bx, by, bz)) {
+                atomicOr(&ctr->err, ERR_INTERNAL);
+            } else {
+                uint64_t M[8], c[8];
 #pragma unroll
-            for (int k = 0; k < MC_SB; k++) {
-                jl[k] = k ? jl[0] : 0;
-                if (todo) {
-                    jl[k] = (int)__builtin_ctzll(todo);
-                    todo &= todo - 1;
-                    nsb++;
-                }
+                for (int m = 0; m < 8; m++) M[m] = masks[so[m]];
+                corner_masks(M, c);
+                uint64_t n0, n1, n2;
+                mc_ntri_bits(c, n0, n1, n2);
+                const uint64_t V = valid_cells(g, bx, by, bz);
+                const uint32_t tris = (uint32_t)__popcll(n0 & V) + 2u * (uint32_t)__popcll(n1 & V) +
+                                      4u * (uint32_t)__popcll(n2 & V);
+                cnt = 3u * tris;
             }
-            stage_batch(q, slots, so, jl, tiles[w]);
-            wave_lds_sync();
-#pragma unroll
-            for (int k = 0; k < MC_SB; k++) {
-                if (k < nsb) {
-                    const uint32_t bj = bcast(b, jl[k]);
-                    const uint32_t bx = bj % g.nbx, r = bj / g.nbx, by = r % g.nby, bz = r / g.nby;
-                    const int cs = tile_case(g, bx, by, bz, tiles[w][k], iso);
-                    const uint32_t total = wave_sum(cs < 0 ? 0u : (uint32_t)ntri[cs]);
-                    if (l == jl[k]) mycnt = total;
-                    occ += total != 0;
-                }
-            }
-            wave_lds_sync();
         }
-        if (valid) blk_cnt[idx] = mycnt;
-    }
-    if (l == 0 && (occ | cand)) {
-        atomicAdd(&ctr->n_occ, (unsigned long long)occ);
-        atomicAdd(&ctr->n_cand, (unsigned long long)cand);
+        blk_cnt[i] = cnt;
     }
 }
 
 // Exclusive scan of the block vertex counts into 64-bit offsets; the last
 // tile records the total (Sec. 4.4: the per-block offsets and the output
-// size come from one prefix sum over the blocks).
+// size come from one prefix sum over the blocks).  Each tile also records
+// how many of its blocks have triangles.
 __global__ __launch_bounds__(256) void k_scan_counts(const uint32_t *__restrict__ cnt,
                                                     uint64_t *__restrict__ off, Counters *ctr,
+                                                    uint32_t *__restrict__ part_occ,
                                                     uint64_t *status) {
     if (ctr->err) return;
     const uint64_t n = ctr->n_act;
     const uint64_t n_tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    constexpr int PER = SCAN_TILE / 256;   // consecutive counts per thread
+    static_assert(PER % 4 == 0, "counts are loaded 4 at a time");
     for (;;) {
         const uint32_t t = take_tile(&ctr->tile_ctr[TC_MC]);
         if (t >= n_tiles) return;
-        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * 16u;
-        uint32_t x[16];
-        uint64_t sum = 0;
+        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * PER;
+        const bool full = base + PER <= n;
+        uint32_t x[PER];
+        if (full) {
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
-            x[j] = base + j < n ? cnt[base + j] : 0u;
-            sum += x[j];
+            for (int j = 0; j < PER; j += 4) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(cnt + base + j);
+                x[j] = q.x; x[j + 1] = q.y; x[j + 2] = q.z; x[j + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < PER; j++) x[j] = base + j < n ? cnt[base + j] : 0u;
         }
+        uint64_t sum = 0;
+        uint32_t occ = 0;
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            sum += x[j];
+            occ += x[j] != 0;
+        }
+        occ = wg_sum_u32(occ);
+        if (threadIdx.x == 0) part_occ[t] = occ;
         uint64_t incl_end;
         uint64_t e = tile_scan_lookback(sum, status, t, &incl_end);
+        uint64_t o[PER];
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
-            if (base + j < n) off[base + j] = e;
+        for (int j = 0; j < PER; j++) {
+            o[j] = e;
             e += x[j];
+        }
+        if (full) {
+            ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(off + base);
+#pragma unroll
+            for (int j = 0; j < PER; j += 2) dst[j / 2] = make_ulonglong2(o[j], o[j + 1]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < PER; j++)
+                if (base + j < n) off[base + j] = o[j];
         }
         if (t == n_tiles - 1 && threadIdx.x == 0) ctr->total_verts = incl_end;
     }
@@ -458,12 +592,26 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
                                                 const uint32_t *__restrict__ blk_cnt,
                                                 const uint64_t *__restrict__ blk_off,
                                                 uint4 *__restrict__ out, uint64_t cap,
+                                                const uint32_t *__restrict__ part_cand,
+                                                const uint32_t *__restrict__ part_occ,
                                                 Counters *ctr) {
     __shared__ EmitShared sh;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
     __syncthreads();
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
+    if (blockIdx.x == 0) {   // the call's statistics from the per-tile counts
+        const uint64_t n_ct = (g.nb + BLK_TILE - 1) / BLK_TILE, n_st = (n_act + SCAN_TILE - 1) / SCAN_TILE;
+        uint32_t cand = 0, occ = 0;
+        for (uint64_t i = threadIdx.x; i < n_ct; i += blockDim.x) cand += part_cand[i];
+        for (uint64_t i = threadIdx.x; i < n_st; i += blockDim.x) occ += part_occ[i];
+        cand = wg_sum_u32(cand);
+        occ = wg_sum_u32(occ);
+        if (threadIdx.x == 0) {
+            ctr->n_cand = cand;
+            ctr->n_occ = occ;
+        }
+    }
     const int w = threadIdx.x >> 6, l = lane();
     const LaneGeom q = lane_geom();
     uint64_t lo, hi;
@@ -474,8 +622,8 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
         const uint32_t cnt = valid ? blk_cnt[idx] : 0u;
         const uint32_t b = cnt ? I_active[idx] : 0u;
         const uint64_t boff = cnt ? blk_off[idx] : 0ull;
-        uint32_t so[8];
-        octet(g, b, I_slot, identity, so);
+        uint32_t so[8], lbx, lby, lbz;
+        octet(g, b, I_slot, identity, so, lbx, lby, lbz);
         uint64_t todo = __ballot(cnt != 0);
         while (todo) {
             int jl[MC_SB], nsb = 0;
@@ -494,7 +642,8 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
                 const uint32_t bj = bcast(b, jl[k]);
                 const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
                                       bcast((uint32_t)boff, jl[k]);
-                emit_block(g, bj, sh.tiles[w][k], iso, sh, w, base, out, cap);
+                emit_block(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
+                           sh.tiles[w][k], iso, sh, w, base, out, cap);
             }
         }
     }
@@ -615,16 +764,17 @@ unsigned grid_cap(uint64_t n_threads, unsigned cap) {
 
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
                  uint64_t n_slots_host, hipStream_t s) {
-    uint64_t work = g.nb > sl.total ? g.nb : sl.total;
-    k_cull<<<grid_cap(work, 16384), 256, 0, s>>>(g, d.ranges, iso, d.active, d.ctr, n_slots_host,
-                                                 d.status, sl.total);
+    const uint64_t tiles = (uint64_t)((g.nbx + CULL_TX - 1) / CULL_TX) *
+                           ((g.nby + CULL_TY - 1) / CULL_TY) * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
+    k_cull<<<(unsigned)tiles, 256, 0, s>>>(g, d.ranges, iso, d.active, d.ctr, n_slots_host,
+                                           d.status, sl.total);
 }
 
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
                            int identity_cache, hipStream_t s) {
     unsigned tiles = (unsigned)((g.nb + BLK_TILE - 1) / BLK_TILE);
     k_compact_blocks<<<tiles, 256, 0, s>>>(g, d.active, d.I_slot, identity_cache, d.I_active,
-                                           d.I_new, d.ctr, d.status + sl.blk);
+                                           d.I_new, d.ctr, d.part_cand, d.status + sl.blk);
 }
 
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
@@ -684,16 +834,19 @@ static unsigned mc_grid(uint64_t max_blocks) {
 
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                      int identity_cache, float iso, hipStream_t s) {
-    static unsigned grid = 0;
-    if (!grid) grid = resident_grid(k_mc_count, ~0ull >> 4);
-    k_mc_count<<<std::min<unsigned>(grid, mc_grid(g.nb)), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
-                                              slots, d.mc_table, iso, d.blk_cnt, d.ctr);
+    static unsigned mgrid = 0, cgrid = 0;
+    if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
+    if (!cgrid) cgrid = resident_grid(k_mc_count, ~0ull >> 4);
+    k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
+        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.ctr);
+    k_mc_count<<<std::min<unsigned>(cgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
+        g, d.I_active, d.active, I_slot, identity_cache, d.masks, d.blk_cnt, d.ctr);
 }
 
 void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s) {
     uint64_t tiles = (g.nb + SCAN_TILE - 1) / SCAN_TILE;
     unsigned grid = (unsigned)(tiles < 1024 ? (tiles ? tiles : 1) : 1024);
-    k_scan_counts<<<grid, 256, 0, s>>>(d.blk_cnt, d.blk_off, d.ctr, d.status + sl.mc);
+    k_scan_counts<<<grid, 256, 0, s>>>(d.blk_cnt, d.blk_off, d.ctr, d.part_occ, d.status + sl.mc);
 }
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
@@ -702,7 +855,8 @@ void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const 
     if (!grid) grid = resident_grid(k_mc_emit, ~0ull >> 4);
     k_mc_emit<<<std::min<unsigned>(grid, mc_grid(g.nb)), 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots,
                                              d.mc_table, iso, d.blk_cnt, d.blk_off,
-                                             reinterpret_cast<uint4 *>(out), cap_verts, d.ctr);
+                                             reinterpret_cast<uint4 *>(out), cap_verts, d.part_cand,
+                                             d.part_occ, d.ctr);
 }
 
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,

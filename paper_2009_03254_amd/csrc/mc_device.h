@@ -104,6 +104,19 @@ __device__ uint64_t tile_scan_lookback(uint64_t v, uint64_t *status, uint64_t t,
     return e + woff + incl - v;
 }
 
+// Sum of one value per thread over a 256-thread workgroup, returned to every
+// thread (all threads must call it).  Device-wide counters are then bumped
+// once per workgroup: same-address atomics from every wave serialise.
+__device__ __forceinline__ uint32_t wg_sum_u32(uint32_t v) {
+    __shared__ uint32_t s_part[4];
+    v = wave_sum(v);
+    if (lane() == 0) s_part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const uint32_t t = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+    __syncthreads();
+    return t;
+}
+
 __device__ __forceinline__ uint32_t take_tile(unsigned int *ctr) {
     __shared__ uint32_t s_tile;
     if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
@@ -274,10 +287,16 @@ __device__ __forceinline__ LaneGeom lane_geom() {
 
 // Slots of block b and its 7 positive neighbours; false if one is missing.
 // The 8 lookups are issued unconditionally (an out-of-volume neighbour reads
-// block b's own entry) so that they are in flight together.
+// block b's own entry) so that they are in flight together.  Also returns the
+// block's coordinates (bx, by, bz), so that the per-block loops broadcast them
+// instead of dividing again.
 __device__ __forceinline__ bool octet(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
-                                      int identity, uint32_t so[8]) {
-    const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
+                                      int identity, uint32_t so[8], uint32_t &bx, uint32_t &by,
+                                      uint32_t &bz) {
+    const uint32_t r = b / g.nbx;
+    bx = b - r * g.nbx;
+    by = r % g.nby;
+    bz = r / g.nby;
     uint32_t nb[8];
     bool in[8];
 #pragma unroll
@@ -372,9 +391,9 @@ __device__ __forceinline__ void xcd_wave_range(uint64_t n, uint64_t &lo, uint64_
 struct EmitShared {
     uint64_t tab[256];
     float tiles[MC_WAVES][MC_SB][128];
-    uint32_t pref[MC_WAVES][64];
+    uint32_t pref[MC_WAVES][64];     // first triangle of each cell
     uint8_t cs[MC_WAVES][64];
-    uint8_t map[MC_WAVES][64 * 15];
+    uint8_t map[MC_WAVES][64 * 5];   // cell of each triangle
 };
 
 }  // namespace
@@ -383,25 +402,26 @@ struct EmitShared {
 namespace bcmc {
 namespace {
 
-// Emission of one staged block (Sec. 4.5): cases, in-block exclusive scan of
-// the per-cell vertex counts, then lane per vertex in canonical order (cell,
-// triangle, vertex), written from `base` on (records past `cap` dropped).
-__device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, const float *tile, float iso,
-                                           EmitShared &sh, int w, uint64_t base,
-                                           uint4 *__restrict__ out, uint64_t cap) {
+// Emission of one staged block (Sec. 4.5) at block coordinates (bx, by, bz):
+// cases, in-block exclusive scan of the per-cell triangle counts, the cell of
+// every triangle, then lane per vertex in canonical order (cell, triangle,
+// vertex), written from `base` on (records past `cap` dropped).
+__device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t bx, uint32_t by,
+                                           uint32_t bz, const float *tile, float iso, EmitShared &sh,
+                                           int w, uint64_t base, uint4 *__restrict__ out, uint64_t cap) {
     const int l = lane();
-    const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
     const int cs = tile_case(g, bx, by, bz, tile, iso);
-    const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
-    const uint32_t incl = wave_incl_scan(nv);
-    const int total = (int)__shfl(incl, 63, 64);
-    sh.pref[w][l] = incl - nv;
+    const uint32_t nt = cs < 0 ? 0u : (uint32_t)(sh.tab[cs] >> 60);
+    const uint32_t incl = wave_incl_scan(nt);
+    const int total = 3 * (int)__shfl(incl, 63, 64);
+    sh.pref[w][l] = incl - nt;
     sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
-    for (uint32_t v = 0; v < nv; v++) sh.map[w][incl - nv + v] = (uint8_t)l;
+    for (uint32_t t = 0; t < nt; t++) sh.map[w][incl - nt + t] = (uint8_t)l;
     wave_lds_sync();
     for (int j = l; j < total; j += 64) {
-        const int c = sh.map[w][j];
-        const int kk = j - (int)sh.pref[w][c];
+        const int t = (j * 43691) >> 17;               // j / 3 for j < 3 * 64 * 5
+        const int c = sh.map[w][t];
+        const int kk = j - 3 * (int)sh.pref[w][c];     // vertex index within the cell
         const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * kk)) & 15u);
         int ox, oy, oz, axis;
         edge_geom(e, ox, oy, oz, axis);

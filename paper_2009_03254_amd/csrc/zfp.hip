@@ -163,7 +163,9 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
 #pragma unroll
         for (int q = 0; q < 16; q++) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     }
-    if (evicted) atomicAdd(&ctr->n_evicted, (unsigned long long)evicted);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) evicted += __shfl_xor(evicted, d, 64);   // one atomic per wave
+    if (__lane_id() == 0 && evicted) atomicAdd(&ctr->n_evicted, (unsigned long long)evicted);
 }
 
 template <bool F64>

@@ -29,7 +29,12 @@ __all__ = [
     "percentile_iso",
     "turbulence_torch",
     "percentile_iso_torch",
+    "channel_flow_slab",
+    "CHANNEL_FLOW_DIMS",
 ]
+
+# Large channel-flow-like volume: (nx, ny, nz) in voxels.
+CHANNEL_FLOW_DIMS = (5120, 3840, 768)
 
 
 def _grid(nx, ny, nz):
@@ -194,3 +199,40 @@ def percentile_iso_torch(values, p):
     t = h - lo
     # numpy's linear interpolation, including its form for t >= 1/2
     return np.float32(b - (b - a) * (1.0 - t) if t >= 0.5 else a + (b - a) * t)
+
+
+def channel_flow_slab(z0, z1, dims=CHANNEL_FLOW_DIMS, seed=5, n_modes=256, delta=None,
+                      rel_amp=0.1, kmin=1.0 / 1024.0, kmax=1.0 / 16.0, device="cuda"):
+    """z-planes [z0, z1) of a channel-flow-like float64 field, generated on
+    ``device`` with torch so that the whole volume never exists at once:
+
+        f(p) = tanh((y - (ny - 1)/2) / delta) + rel_amp * T(p) / sigma_T
+
+    T is a sum of random Fourier modes with the k^(-5/3) law of
+    ``turbulence_modes`` (wavelengths 16..1024 voxels by default) and
+    sigma_T = sqrt(sum a_m^2 / 2) its analytic standard deviation; delta
+    defaults to ny / 10.  Returns a float64 tensor [z1 - z0, ny, nx]; the
+    value of a sample does not depend on which slab it is generated in, up to
+    the rounding of the mode sum."""
+    import torch
+    nx, ny, nz = (int(d) for d in dims)
+    delta = ny / 10.0 if delta is None else float(delta)
+    k, amp, phase = turbulence_modes(seed, n_modes, kmin, kmax)
+    sigma = float(np.sqrt(np.sum(amp ** 2) / 2.0))
+    kt = torch.tensor(k, dtype=torch.float64, device=device)
+    c = torch.tensor(amp * np.exp(1j * phase) * (rel_amp / sigma), dtype=torch.complex128,
+                     device=device)
+
+    def axis(lo, hi, col):
+        x = torch.arange(lo, hi, dtype=torch.float64, device=device)
+        return torch.exp(2j * np.pi * torch.outer(kt[:, col], x))      # [M, n]
+
+    X, Y, Z = axis(0, nx, 0), axis(0, ny, 1), axis(z0, z1, 2)
+    yv = torch.arange(ny, dtype=torch.float64, device=device)
+    mean = torch.tanh((yv - (ny - 1) / 2.0) / delta)                  # [ny]
+    out = torch.empty((z1 - z0, ny, nx), dtype=torch.float64, device=device)
+    for zz in range(z1 - z0):
+        G = c[None, :] * Z[:, zz][None, :] * Y.T                       # [ny, M]
+        out[zz] = torch.real(G @ X)
+        out[zz] += mean[:, None]
+    return out

@@ -63,3 +63,37 @@ def test_validation_before_device_work(L):
     assert b"rate" in L.bcmc_last_error() or len(L.bcmc_last_error()) > 0
     assert L.bcmc_extract(None, C.c_float(0.0), None, 0, None, None) == -1
     assert L.bcmc_encode(None, 0, 4, 4, 4, 8, None, None) == -1
+
+
+def test_generated_triangle_count_circuit(L, orc):
+    """The build-time bit-sliced triangle count (mc_ntri.h) gives, for every
+    one of the 256 cases, the oracle table's triangle count: the 256 cases are
+    evaluated at once, case c in bit c of four 64-bit words per corner."""
+    from paper_2009_03254_amd import build
+    path = os.path.join(build.GEN, "mc_ntri.h")
+    if not os.path.exists(path):
+        build.build()
+    src = open(path).read()
+    M = (1 << 64) - 1
+    n_ref = orc.mc_tables()[0]
+
+    def py(expr):   # C expression over uint64 -> Python expression on ints
+        e = expr.replace("~0ull", "M").replace("0ull", "0")
+        return re.sub(r"~(c\[\d\]|n\d+)", r"(M ^ \1)", e)
+
+    for w in range(4):                    # cases 64w .. 64w+63
+        c = [0] * 8
+        for k in range(8):
+            for i in range(64):
+                if ((64 * w + i) >> k) & 1:
+                    c[k] |= 1 << i
+        env = {"c": c}
+        for name, expr in re.findall(r"const uint64_t (n\d+) = (.*);", src):
+            env[name] = eval(py(expr), {"M": M}, env) & M
+        outs = {}
+        for b in ("b0", "b1", "b2"):
+            expr = re.search(rf"\b{b} = (.*);", src).group(1)
+            outs[b] = eval(py(expr), {"M": M}, env) & M
+        for i in range(64):
+            n = ((outs["b0"] >> i) & 1) | (((outs["b1"] >> i) & 1) << 1) | (((outs["b2"] >> i) & 1) << 2)
+            assert n == n_ref[64 * w + i], 64 * w + i
