@@ -60,6 +60,23 @@ typedef struct {
     uint32_t block;
 } bcmc_vertex;
 
+/* Record formats bcmc_extract can write (per volume, bcmc_set_vertex_format).
+ * BCMC_VERTEX_EDGE8 keeps the 8 bytes per vertex of Sec. 4.5's output but
+ * names the vertex by its edge instead of quantised coordinates: one
+ * uint64_t per vertex,
+ *     bits  0-31  block id
+ *     bits 32-37  cell l = lx + 4*ly + 16*lz inside the block
+ *     bits 38-41  edge id e (axis e>>2; bits 0 and 1 of e offset the first
+ *                 corner along the other two axes, in increasing axis order)
+ *     bits 42-63  q = min(trunc(t * 2^22), 2^22 - 1), t = (iso - a)/(b - a)
+ *                 in float32 from the edge's first corner (value a)
+ * so the block-relative position is the first corner plus (q + 0.5) / 2^22
+ * along the edge axis, within 2^-23 voxel of the float32 vertex. */
+typedef enum {
+    BCMC_VERTEX_F32 = 0,   /* bcmc_vertex, 16 bytes (default) */
+    BCMC_VERTEX_EDGE8 = 1  /* uint64_t edge record, 8 bytes */
+} bcmc_vertex_format;
+
 /* Statistics of the last bcmc_extract call (Sec. 4.6, tab:mc_benchmark_data
  * and tab:mc_benchmark_table report the same quantities). */
 typedef struct {
@@ -121,7 +138,8 @@ BCMC_API int bcmc_set_cache_budget(bcmc_volume *v, uint64_t initial_bytes, uint6
 BCMC_API int bcmc_reset_cache(bcmc_volume *v, void *hip_stream);
 
 /* Extract the isosurface at `iso` (Sec. 4.1-4.5) into the caller's device
- * buffer d_out of capacity_vertices bcmc_vertex records: a triangle soup,
+ * buffer d_out of capacity_vertices records (bcmc_vertex, or uint64_t edge
+ * records after bcmc_set_vertex_format(v, BCMC_VERTEX_EDGE8)): a triangle soup,
  * 3 vertices per triangle, in canonical order (blocks by id, cells by local
  * index, triangles and vertices in table order).  A cell corner is inside
  * when its value is < iso.  Synchronises hip_stream once to read the count.
@@ -130,6 +148,12 @@ BCMC_API int bcmc_reset_cache(bcmc_volume *v, void *hip_stream);
  * enlarge and call again); BCMC_E_CACHE_CAP (cache reset); BCMC_E_HIP. */
 BCMC_API int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_vertices,
                  uint64_t *n_triangles, void *hip_stream);
+
+/* Record format of this volume's bcmc_extract output (bcmc_vertex_format;
+ * default BCMC_VERTEX_F32).  The order and count of records do not depend on
+ * it; bcmc_backward and the batch API (always bcmc_vertex) are unaffected.
+ * Errors: BCMC_E_INVALID for an unknown format. */
+BCMC_API int bcmc_set_vertex_format(bcmc_volume *v, int format);
 
 /* Backward of the last bcmc_extract of a bcmc_volume_from_blocks handle
  * (same iso), topology held fixed: from d_gV = dL/d(vertex position)

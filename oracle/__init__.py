@@ -66,6 +66,7 @@ def lib():
             "oracle_mc_tables": (None, [_P, _P, _P]),
             "oracle_mc_extract": (_u64, [_P, _u32, _u32, _u32, _f32, _P, _P, _P, _P, _P, _P]),
             "oracle_mc_extract_f32": (_u64, [_P, _u32, _u32, _u32, _f32, _P, _P]),
+            "oracle_mc_extract_edge8": (_u64, [_P, _u32, _u32, _u32, _f32, _P]),
             "oracle_brute_count": (_u64, [_P, _u32, _u32, _u32, _f32]),
             "oracle_brute_count_blocks": (_u64, [_P, _u32, _u32, _u32, _f32]),
             "oracle_block_vertex_counts": (None, [_P, _u32, _u32, _u32, _f32, _P, _u64, _P]),
@@ -272,6 +273,37 @@ def mc_extract_f32(blocks, dims, iso):
     vb = np.empty(3 * T, dtype=np.uint32)
     lib().oracle_mc_extract_f32(_ptr(blocks), nx, ny, nz, float(iso), _ptr(v), _ptr(vb))
     return v, vb
+
+
+def mc_extract_edge8(blocks, dims, iso):
+    """The canonical soup as 64-bit edge records (block | cell << 32 |
+    edge << 38 | q << 42, q = min(trunc(t * 2^22), 2^22 - 1), t in float32)."""
+    nx, ny, nz = dims
+    blocks = np.ascontiguousarray(blocks, dtype=np.float32)
+    T = mc_count(blocks, dims, iso)
+    rec = np.empty(max(3 * T, 1), dtype=np.uint64)
+    lib().oracle_mc_extract_edge8(_ptr(blocks), nx, ny, nz, float(iso), _ptr(rec))
+    return rec[: 3 * T]
+
+
+def edge8_positions(records):
+    """Block-relative float64 positions of 64-bit edge records: the edge's
+    first corner plus (q + 0.5) / 2^22 along its axis; with the block ids."""
+    r = np.asarray(records, dtype=np.uint64)
+    block = (r & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    cell = ((r >> np.uint64(32)) & np.uint64(63)).astype(np.int64)
+    e = ((r >> np.uint64(38)) & np.uint64(15)).astype(np.int64)
+    q = (r >> np.uint64(42)).astype(np.float64)
+    axis = e >> 2
+    b0, b1 = e & 1, (e >> 1) & 1
+    off = np.zeros((len(r), 3), dtype=np.int64)
+    off[:, 0] = np.where(axis == 0, 0, b0)
+    off[:, 1] = np.where(axis == 1, 0, np.where(axis == 0, b0, b1))
+    off[:, 2] = np.where(axis == 2, 0, b1)
+    pos = np.stack([cell & 3, (cell >> 2) & 3, cell >> 4], axis=1) + off
+    pos = pos.astype(np.float64)
+    pos[np.arange(len(r)), axis] += (q + 0.5) / 4194304.0
+    return pos, block
 
 
 def mc_count(blocks, dims, iso):

@@ -679,6 +679,7 @@ typedef struct {
     uint64_t *cell_keys;
     uint8_t *cases;
     uint64_t nv, nc;
+    uint64_t *edge8;
 } emit_ctx;
 
 static void emit_cell(void *vctx, uint64_t b, int l, uint32_t x, uint32_t y,
@@ -708,6 +709,13 @@ static void emit_cell(void *vctx, uint64_t b, int l, uint32_t x, uint32_t y,
                 c->verts32[3 * c->nv + d] = (d == axis) ? base + t : base;
             }
         }
+        if (c->edge8) {
+            float t = (c->iso - a) / (bv - a);
+            uint32_t q = (uint32_t)(t * 4194304.0f);   /* t * 2^22 is exact */
+            if (q > 4194303u) q = 4194303u;
+            c->edge8[c->nv] = (uint64_t)b | ((uint64_t)l << 32) | ((uint64_t)e << 38) |
+                              ((uint64_t)q << 42);
+        }
         if (c->vblock) c->vblock[c->nv] = (uint32_t)b;
         if (c->vedge)
             c->vedge[c->nv] = (int64_t)(g[0] + (uint64_t)c->F->nx *
@@ -736,7 +744,7 @@ uint64_t oracle_mc_extract(const float *blocks, uint32_t nx, uint32_t ny,
         if (n_cells) *n_cells = n[1];
         return n[0];
     }
-    emit_ctx c = {&F, iso, verts, NULL, vblock, vedge, cell_keys, cases, 0, 0};
+    emit_ctx c = {&F, iso, verts, NULL, vblock, vedge, cell_keys, cases, 0, 0, NULL};
     for_each_cell(&F, iso, emit_cell, &c);
     if (n_cells) *n_cells = c.nc;
     return c.nv / 3;
@@ -747,7 +755,16 @@ uint64_t oracle_mc_extract_f32(const float *blocks, uint32_t nx, uint32_t ny,
                                uint32_t *vblock) {
     ensure_tables();
     field_t F = {blocks, nx, ny, nz, ceil4(nx), ceil4(ny)};
-    emit_ctx c = {&F, iso, NULL, verts, vblock, NULL, NULL, NULL, 0, 0};
+    emit_ctx c = {&F, iso, NULL, verts, vblock, NULL, NULL, NULL, 0, 0, NULL};
+    for_each_cell(&F, iso, emit_cell, &c);
+    return c.nv / 3;
+}
+
+uint64_t oracle_mc_extract_edge8(const float *blocks, uint32_t nx, uint32_t ny,
+                                 uint32_t nz, float iso, uint64_t *records) {
+    ensure_tables();
+    field_t F = {blocks, nx, ny, nz, ceil4(nx), ceil4(ny)};
+    emit_ctx c = {&F, iso, NULL, NULL, NULL, NULL, NULL, NULL, 0, 0, records};
     for_each_cell(&F, iso, emit_cell, &c);
     return c.nv / 3;
 }

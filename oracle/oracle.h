@@ -83,6 +83,12 @@ uint64_t oracle_mc_extract(const float *blocks, uint32_t nx, uint32_t ny,
 uint64_t oracle_mc_extract_f32(const float *blocks, uint32_t nx, uint32_t ny,
                                uint32_t nz, float iso, float *verts,
                                uint32_t *vblock);
+/* The same soup with each vertex as one 64-bit edge record: block id (bits
+ * 0-31), cell l = lx + 4 ly + 16 lz inside the block (32-37), edge id of the
+ * table (38-41), and q = min(trunc(t * 2^22), 2^22 - 1) (42-63) with the
+ * float32 t = (iso - a) / (b - a) measured from the edge's first corner. */
+uint64_t oracle_mc_extract_edge8(const float *blocks, uint32_t nx, uint32_t ny,
+                                 uint32_t nz, float iso, uint64_t *records);
 /* Brute force: sum over every valid cell of the number of triangles of its
  * case, visiting the dense field in z,y,x order (no blocks). */
 uint64_t oracle_brute_count(const float *field, uint32_t nx, uint32_t ny,

@@ -24,9 +24,11 @@ from . import _capi
 from ._capi import BcmcError, lib  # noqa: F401
 
 __all__ = ["Volume", "FieldVolume", "Batch", "ExtractFn", "encode", "mc_table", "num_blocks",
-           "blocks_from_field", "split_vertices", "global_positions", "BcmcError", "lib"]
+           "blocks_from_field", "split_vertices", "global_positions", "edge8_positions",
+           "VERTEX_F32", "VERTEX_EDGE8", "BcmcError", "lib"]
 
 F32, F64 = 0, 1
+VERTEX_F32, VERTEX_EDGE8 = 0, 1     # record formats of Volume.extract
 _TYPES = {"f32": F32, "float32": F32, "f64": F64, "float64": F64}
 
 
@@ -104,6 +106,32 @@ def split_vertices(verts):
     return verts.view(torch.float32)[:, :3], verts[:, 3]
 
 
+def edge8_positions(records, dims=None, dtype=None):
+    """Decode 8-byte edge records ([n] int64 CUDA tensor) into block-relative
+    positions [n, 3] (the edge's first corner plus (q + 0.5) / 2^22 along its
+    axis; float64 by default) and block ids [n] (int64); with dims, global
+    voxel coordinates instead of block-relative ones."""
+    torch = _torch()
+    r = records.to(torch.int64)
+    block = r & 0xFFFFFFFF
+    cell = (r >> 32) & 63
+    e = (r >> 38) & 15
+    q = (r >> 42) & ((1 << 22) - 1)
+    axis = e >> 2
+    b0, b1 = e & 1, (e >> 1) & 1
+    zero = torch.zeros_like(e)
+    off = torch.stack([torch.where(axis == 0, zero, b0),
+                       torch.where(axis == 1, zero, torch.where(axis == 0, b0, b1)),
+                       torch.where(axis == 2, zero, b1)], dim=1)
+    corner = torch.stack([cell & 3, (cell >> 2) & 3, cell >> 4], dim=1) + off
+    dt = dtype or torch.float64
+    pos = corner.to(dt)
+    pos[torch.arange(r.numel(), device=r.device), axis] += (q.to(dt) + 0.5) / 4194304.0
+    if dims is not None:
+        pos = global_positions(pos, block, dims, dtype=dt)
+    return pos, block
+
+
 def global_positions(xyz, block, dims, dtype=None):
     """Block-relative positions + block ids -> global voxel coordinates."""
     torch = _torch()
@@ -134,20 +162,34 @@ class _Handle:
         _capi.check(lib().bcmc_get_stats(self._h, C.byref(st)))
         return st.as_dict()
 
+    def set_vertex_format(self, fmt):
+        """"f32" (16-byte records [n, 4] int32: x, y, z as float32 bits, block)
+        or "edge8" (8-byte edge records [n] int64, see edge8_positions)."""
+        code = {"f32": VERTEX_F32, "edge8": VERTEX_EDGE8}[fmt] if isinstance(fmt, str) else int(fmt)
+        _capi.check(lib().bcmc_set_vertex_format(self._h, code))
+        self._vfmt = code
+
     def set_profiling(self, on=True):
         _capi.check(lib().bcmc_set_profiling(self._h, 1 if on else 0))
 
     def _alloc_out(self, cap):
         torch = _torch()
+        if getattr(self, "_vfmt", VERTEX_F32) == VERTEX_EDGE8:
+            return torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
         return torch.empty((max(cap, 1), 4), dtype=torch.int32, device="cuda")
+
+    def _records(self, out):
+        """Capacity of `out` in records of this volume's format."""
+        size = 8 if getattr(self, "_vfmt", VERTEX_F32) == VERTEX_EDGE8 else 16
+        return out.numel() * out.element_size() // size
 
     def extract(self, iso, out=None, stream=None):
         """Triangle soup at `iso`: ([3T, 4] int32 CUDA tensor, T).  `out` is
         reused (and grown when too small)."""
-        cap = 0 if out is None else out.shape[0]
+        cap = 0 if out is None else self._records(out)
         if out is None:
             out = self._alloc_out(getattr(self, "_cap_hint", 1 << 16))
-            cap = out.shape[0]
+            cap = self._records(out)
         T = C.c_uint64(0)
         rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), cap, C.byref(T),
                                 _stream_ptr(stream))
@@ -155,16 +197,17 @@ class _Handle:
             need = 3 * T.value
             self._cap_hint = need + need // 8 + 1024
             out = self._alloc_out(self._cap_hint)
-            rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), out.shape[0],
+            rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), self._records(out),
                                     C.byref(T), _stream_ptr(stream))
         _capi.check(rc)
         self._cap_hint = max(getattr(self, "_cap_hint", 0), 3 * T.value)
         return out[: 3 * T.value], int(T.value)
 
     def extract_into(self, iso, out, stream=None):
-        """Extract into a preallocated [cap, 4] int32 buffer; returns (rc, T)."""
+        """Extract into a preallocated buffer ([cap, 4] int32 for "f32"
+        records, [cap] int64 for "edge8"); returns (rc, T)."""
         T = C.c_uint64(0)
-        rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), out.shape[0],
+        rc = lib().bcmc_extract(self._h, C.c_float(iso), _dev_ptr(out), self._records(out),
                                 C.byref(T), _stream_ptr(stream))
         return rc, int(T.value)
 

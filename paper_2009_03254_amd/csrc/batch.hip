@@ -150,10 +150,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
     __shared__ BatchShared sh;
     const int l = lane(), w = threadIdx.x >> 6;
     const uint64_t gtid = blockIdx.x * (uint64_t)BT + threadIdx.x;
-    for (int i = threadIdx.x; i < 256; i += BT) {
-        sh.emit.tab[i] = p.mc_table[i];
-        sh.ntri[i] = 3u * (uint32_t)(p.mc_table[i] >> 60);
-    }
+    for (int i = threadIdx.x; i < 256; i += BT) sh.ntri[i] = 3u * (uint32_t)(p.mc_table[i] >> 60);
     // phase 0
     if (gtid == 0) {
         p.ctr->n_new = 0;
@@ -420,9 +417,9 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
                     const float iso = __uint_as_float(bcast(__float_as_uint(p.job_iso[j]), jl[k]));
                     const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
                                           bcast((uint32_t)boff, jl[k]);
-                    emit_block(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
-                               sh.emit.tiles[w][k], iso, sh.emit, w, base,
-                               reinterpret_cast<uint4 *>(p.out), p.cap);
+                    emit_block<false>(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
+                               sh.emit.tiles[w][k], iso, p.mc_table, sh.emit, w, base,
+                               p.out, p.cap);
                 }
             }
         }

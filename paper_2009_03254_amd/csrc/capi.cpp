@@ -30,6 +30,7 @@ struct bcmc_volume {
     Counters *h_ctr = nullptr;     // pinned copy of the device counters
     bcmc_stats stats{};
     int profiling = 0;
+    int vertex_format = BCMC_VERTEX_F32;  // output records of bcmc_extract
     hipEvent_t ev[8] = {};
     int have_extract = 0;
     float last_iso = 0.0f;
@@ -327,6 +328,13 @@ int bcmc_reset_cache(bcmc_volume *v, void *hip_stream) {
     return reset_cache_state(v, as_stream(hip_stream));
 }
 
+int bcmc_set_vertex_format(bcmc_volume *v, int format) {
+    if (!v) return invalid("null handle");
+    if (format != BCMC_VERTEX_F32 && format != BCMC_VERTEX_EDGE8) return invalid("unknown vertex format");
+    v->vertex_format = format;
+    return BCMC_OK;
+}
+
 int bcmc_set_profiling(bcmc_volume *v, int on) {
     if (!v) return invalid("null handle");
     if (on && !v->ev[0])
@@ -360,7 +368,8 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     BCMC_HIP_TRY(mark(4));
     launch_scan_counts(v->g, v->d, v->sl, s);
     BCMC_HIP_TRY(mark(5));
-    launch_mc_emit(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices, s);
+    launch_mc_emit(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices,
+                   v->vertex_format == BCMC_VERTEX_EDGE8, s);
     BCMC_HIP_TRY(mark(6));
     BCMC_HIP_TRY(hipGetLastError());
     int rc = sync_counters(v, s);

@@ -97,7 +97,8 @@ void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const
                      int identity_cache, float iso, hipStream_t s);
 void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s);
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                    int identity_cache, float iso, void *out, uint64_t cap_verts, hipStream_t s);
+                    int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
+                    hipStream_t s);
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
                         const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
                         uint64_t max_act, hipStream_t s);

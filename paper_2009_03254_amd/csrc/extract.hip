@@ -585,19 +585,18 @@ __global__ __launch_bounds__(256) void k_scan_counts(const uint32_t *__restrict_
 // Emission pass (Sec. 4.5): restage each occupied block, take the in-block
 // prefix of its per-cell vertex counts and write the triangle soup lane per
 // vertex at the block's offset, in canonical order (cell, triangle, vertex).
+template <bool EDGE8>
 __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
                                                 const int32_t *__restrict__ I_slot, int identity,
                                                 const float *__restrict__ slots,
                                                 const uint64_t *__restrict__ mc_table, float iso,
                                                 const uint32_t *__restrict__ blk_cnt,
                                                 const uint64_t *__restrict__ blk_off,
-                                                uint4 *__restrict__ out, uint64_t cap,
+                                                void *__restrict__ out, uint64_t cap,
                                                 const uint32_t *__restrict__ part_cand,
                                                 const uint32_t *__restrict__ part_occ,
                                                 Counters *ctr) {
     __shared__ EmitShared sh;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
-    __syncthreads();
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     if (blockIdx.x == 0) {   // the call's statistics from the per-tile counts
@@ -642,8 +641,8 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
                 const uint32_t bj = bcast(b, jl[k]);
                 const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
                                       bcast((uint32_t)boff, jl[k]);
-                emit_block(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
-                           sh.tiles[w][k], iso, sh, w, base, out, cap);
+                emit_block<EDGE8>(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
+                                  sh.tiles[w][k], iso, mc_table, sh, w, base, out, cap);
             }
         }
     }
@@ -850,13 +849,20 @@ void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl
 }
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                    int identity_cache, float iso, void *out, uint64_t cap_verts, hipStream_t s) {
-    static unsigned grid = 0;
-    if (!grid) grid = resident_grid(k_mc_emit, ~0ull >> 4);
-    k_mc_emit<<<std::min<unsigned>(grid, mc_grid(g.nb)), 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots,
-                                             d.mc_table, iso, d.blk_cnt, d.blk_off,
-                                             reinterpret_cast<uint4 *>(out), cap_verts, d.part_cand,
-                                             d.part_occ, d.ctr);
+                    int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
+                    hipStream_t s) {
+    static unsigned grid[2] = {0, 0};
+    if (!grid[0]) grid[0] = resident_grid(k_mc_emit<false>, ~0ull >> 4);
+    if (!grid[1]) grid[1] = resident_grid(k_mc_emit<true>, ~0ull >> 4);
+    const unsigned n = std::min<unsigned>(grid[edge8 ? 1 : 0], mc_grid(g.nb));
+    if (edge8)
+        k_mc_emit<true><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table,
+                                          iso, d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand,
+                                          d.part_occ, d.ctr);
+    else
+        k_mc_emit<false><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table,
+                                           iso, d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand,
+                                           d.part_occ, d.ctr);
 }
 
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,

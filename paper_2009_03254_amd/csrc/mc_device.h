@@ -389,11 +389,8 @@ __device__ __forceinline__ void xcd_wave_range(uint64_t n, uint64_t &lo, uint64_
 }
 
 struct EmitShared {
-    uint64_t tab[256];
     float tiles[MC_WAVES][MC_SB][128];
-    uint32_t pref[MC_WAVES][64];     // first triangle of each cell
-    uint8_t cs[MC_WAVES][64];
-    uint8_t map[MC_WAVES][64 * 5];   // cell of each triangle
+    uint32_t tri[MC_WAVES][64 * 5];  // per triangle: cell | its 3 edge ids << 6
 };
 
 }  // namespace
@@ -403,38 +400,52 @@ namespace bcmc {
 namespace {
 
 // Emission of one staged block (Sec. 4.5) at block coordinates (bx, by, bz):
-// cases, in-block exclusive scan of the per-cell triangle counts, the cell of
-// every triangle, then lane per vertex in canonical order (cell, triangle,
-// vertex), written from `base` on (records past `cap` dropped).
+// cases, in-block exclusive scan of the per-cell triangle counts, one record
+// per triangle (its cell and 3 edge ids), then lane per vertex in canonical
+// order (cell, triangle, vertex), written from `base` on (records past `cap`
+// dropped).  EDGE8: 8-byte records block | cell << 32 | edge << 38 | q << 42
+// with q = min(trunc(t * 2^22), 2^22 - 1); otherwise 16-byte records
+// {f32 x, y, z block-relative; u32 block}.
+template <bool EDGE8>
 __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t bx, uint32_t by,
-                                           uint32_t bz, const float *tile, float iso, EmitShared &sh,
-                                           int w, uint64_t base, uint4 *__restrict__ out, uint64_t cap) {
+                                           uint32_t bz, const float *tile, float iso,
+                                           const uint64_t *__restrict__ mc_table, EmitShared &sh,
+                                           int w, uint64_t base, void *__restrict__ out, uint64_t cap) {
     const int l = lane();
     const int cs = tile_case(g, bx, by, bz, tile, iso);
-    const uint32_t nt = cs < 0 ? 0u : (uint32_t)(sh.tab[cs] >> 60);
+    const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table, L1-resident
+    const uint32_t nt = (uint32_t)(tb >> 60);
     const uint32_t incl = wave_incl_scan(nt);
     const int total = 3 * (int)__shfl(incl, 63, 64);
-    sh.pref[w][l] = incl - nt;
-    sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
-    for (uint32_t t = 0; t < nt; t++) sh.map[w][incl - nt + t] = (uint8_t)l;
+    for (uint32_t t = 0; t < nt; t++)
+        sh.tri[w][incl - nt + t] = (uint32_t)l | ((uint32_t)(tb >> (12 * t)) & 0xFFFu) << 6;
     wave_lds_sync();
     for (int j = l; j < total; j += 64) {
         const int t = (j * 43691) >> 17;               // j / 3 for j < 3 * 64 * 5
-        const int c = sh.map[w][t];
-        const int kk = j - 3 * (int)sh.pref[w][c];     // vertex index within the cell
-        const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * kk)) & 15u);
+        const uint32_t rec = sh.tri[w][t];
+        const int c = (int)(rec & 63u);
+        const int e = (int)((rec >> (6 + 4 * (j - 3 * t))) & 15u);
         int ox, oy, oz, axis;
         edge_geom(e, ox, oy, oz, axis);
         const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
         const float a = tile[tix(x0, y0, z0)];
         const float bv = tile[tix(x0 + (axis == 0), y0 + (axis == 1), z0 + (axis == 2))];
         const float tt = (iso - a) / (bv - a);
-        float px = (float)x0, py = (float)y0, pz = (float)z0;
-        if (axis == 0) px += tt;
-        else if (axis == 1) py += tt;
-        else pz += tt;
         const uint64_t o = base + (uint64_t)j;
-        if (o < cap) out[o] = make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+        if (EDGE8) {
+            uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
+            qt = qt < 4194303u ? qt : 4194303u;
+            const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
+            if (o < cap) reinterpret_cast<uint64_t *>(out)[o] = r;
+        } else {
+            float px = (float)x0, py = (float)y0, pz = (float)z0;
+            if (axis == 0) px += tt;
+            else if (axis == 1) py += tt;
+            else pz += tt;
+            if (o < cap)
+                reinterpret_cast<uint4 *>(out)[o] =
+                    make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+        }
     }
     wave_lds_sync();
 }

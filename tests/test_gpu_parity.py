@@ -218,3 +218,40 @@ def test_mc_single_cells_all_cases(bc, orc):
             xyz, blk = verts_np(verts)
             assert np.abs(xyz - r["verts"]).max() < 1e-6
         vol.close()
+
+
+@pytest.mark.parametrize("dims,rate,seed", [((70, 61, 53), 8, 34), ((45, 38, 31), 16, 35)])
+def test_edge8_records_bitexact(bc, orc, dims, rate, seed):
+    """8-byte edge records: bit-exact against the oracle's records over cold,
+    warm and repeated calls; decoded positions within 1e-5 of the float64
+    soup; the 16-byte output of the same volume still matches; the capacity
+    error counts records."""
+    torch = bc._torch()
+    say(f"[edge8] turbulence {dims} rate {rate}")
+    f = fields.turbulence(*dims, seed=seed, n_modes=64)
+    s = orc.zfp_encode(f, rate)
+    D = orc.zfp_decode(s, dims, rate)
+    field = orc.blocks_to_field(D, dims)
+    vol = bc.Volume(s, dims, "f32", rate)
+    vol.set_vertex_format("edge8")
+    small = torch.empty(5, dtype=torch.int64, device="cuda")
+    iso0 = fields.percentile_iso(field, 50)
+    rc, T = vol.extract_into(float(iso0), small)
+    assert rc == bc._capi.E_CAPACITY and T == orc.mc_count(D, dims, iso0)
+    for p in (50, 85, 50, 20):
+        iso = fields.percentile_iso(field, p)
+        ref = orc.mc_extract_edge8(D, dims, iso)
+        out = torch.empty(ref.shape[0] + 7, dtype=torch.int64, device="cuda")
+        rc, T = vol.extract_into(float(iso), out)
+        assert rc == 0 and 3 * T == ref.shape[0]
+        got = out[: 3 * T].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), p
+        r = orc.mc_extract(D, dims, iso, want=("verts", "vblock"))
+        pos, blk = bc.edge8_positions(out[: 3 * T])
+        assert np.array_equal(blk.cpu().numpy(), r["vblock"].astype(np.int64))
+        assert float((pos.cpu() - torch.from_numpy(r["verts"])).abs().max()) <= 1e-5
+    vol.set_vertex_format("f32")
+    iso = fields.percentile_iso(field, 85)
+    _extract_and_compare(bc, orc, vol, D, dims, iso)
+    with pytest.raises(bc.BcmcError):
+        vol.set_vertex_format(7)

@@ -342,3 +342,32 @@ def test_f32_mode_matches_f64_mode(orc):
     v32, vb = orc.mc_extract_f32(B, (32, 32, 32), 0.0)
     assert np.array_equal(vb, r["vblock"])
     assert np.abs(v32 - r["verts"]).max() < 1e-6
+
+
+def test_edge_records_decode_to_the_soup(orc):
+    """64-bit edge records: same blocks and order as the soup, decoded
+    positions within 2^-22 of the float64 vertices (the quantisation of t),
+    q inside [0, 2^22), and every record's edge joins two corners of its cell
+    on opposite sides of iso (checked on the dense field)."""
+    dims = (29, 23, 19)
+    f = fields.turbulence(*dims, seed=12, n_modes=32)
+    blocks = orc.field_to_blocks(f)
+    iso = float(fields.percentile_iso(f, 55))
+    rec = orc.mc_extract_edge8(blocks, dims, iso)
+    r = orc.mc_extract(blocks, dims, iso, want=("verts", "vblock"))
+    assert rec.shape[0] == r["verts"].shape[0] > 0
+    pos, blk = orc.edge8_positions(rec)
+    assert np.array_equal(blk, r["vblock"])
+    assert np.max(np.abs(pos - r["verts"])) <= 2.0 ** -22
+    assert np.max(np.abs(pos - r["verts"])) <= 1e-5
+    q = rec >> np.uint64(42)
+    assert np.all(q < (1 << 22))
+    nbx, nby = (dims[0] + 3) // 4, (dims[1] + 3) // 4
+    org = np.stack([blk % nbx, (blk // nbx) % nby, blk // (nbx * nby)], axis=1).astype(np.int64) * 4
+    g = np.floor(pos).astype(np.int64) + org              # first corner of each edge
+    e = ((rec >> np.uint64(38)) & np.uint64(15)).astype(np.int64)
+    step = np.eye(3, dtype=np.int64)[e >> 2]
+    a = f[g[:, 2], g[:, 1], g[:, 0]]
+    g1 = g + step
+    b = f[g1[:, 2], g1[:, 1], g1[:, 0]]
+    assert np.all((a < iso) != (b < iso))
