@@ -46,6 +46,13 @@ struct Counters {
 enum { TC_BLK = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */,
        TC_MCCOUNT = 7, TC_MCEMIT = 8 };
 
+// Block compaction tiles hold BLK_TILE * m blocks (16 * m per thread), with m
+// the smallest making at most 1024 tiles: one look-back ticket per tile.
+__host__ __device__ inline uint32_t compact_blocks_per_thread16(uint64_t nb) {
+    const uint64_t tiles = (nb + BLK_TILE - 1) / BLK_TILE;
+    return (uint32_t)((tiles + 1023) / 1024);
+}
+
 // Geometry of a volume in blocks.
 struct Geom {
     uint32_t nx, ny, nz;

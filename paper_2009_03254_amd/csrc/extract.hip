@@ -26,12 +26,13 @@ namespace {
 // that is:  (lo_b < iso <= HI)  or  (LO < iso <= hi_b).
 // Also resets the call's counters and clears the look-back status words.
 // ---------------------------------------------------------------------------
-// Tiled: a workgroup owns a CULL_TX x CULL_TY column of blocks over
-// CULL_TZ z-layers.  Each layer's ranges (with a one-block halo, +inf / -inf
-// outside the volume) are staged in LDS once; the 3x3 in-plane min / max and
-// the 2x2 positive-quadrant min / max come from LDS and are combined across z
-// in registers, so every range is read about 1.5 times.
-constexpr int CULL_TX = 32, CULL_TY = 8, CULL_TZ = 16;
+// Tiled: a workgroup owns a CULL_TX x CULL_TY x CULL_TZ box of blocks.  The
+// box's ranges with a one-block halo (+inf / -inf outside the volume) are
+// staged in LDS with all loads in flight at once; the 3x3 in-plane min / max
+// and the 2x2 positive-quadrant min / max are then combined across z in
+// registers, so every range is read about 1.6 times and no load waits inside
+// the sweep.
+constexpr int CULL_TX = 32, CULL_TY = 8, CULL_TZ = 8;
 
 __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
                                              uint8_t *__restrict__ active, Counters *ctr,
@@ -49,37 +50,43 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
     }
     for (uint64_t w = gid; w < status_words; w += gsz) status[w] = 0;
 
-    __shared__ float2 sh[CULL_TY + 2][CULL_TX + 2];
+    constexpr int NL = CULL_TZ + 2, RX = CULL_TX + 2, RY = CULL_TY + 2, SLOTS = RX * RY;
+    __shared__ float2 sh[NL][RY][RX];
     const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
     uint32_t t = blockIdx.x;
     const uint32_t tx = t % ntx;
     t /= ntx;
     const uint32_t ty = t % nty, tz = t / nty;
+    const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+#pragma unroll 4
+    for (int i = threadIdx.x; i < NL * SLOTS; i += 256) {
+        const int li = i / SLOTS, r = i - li * SLOTS;
+        const int hy = r / RX, hx = r - hy * RX;
+        const int zl = z0 - 1 + li;
+        const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
+        float2 v = make_float2(INFINITY, -INFINITY);
+        if (zl >= 0 && zl < (int)g.nbz && zl <= z1 && x >= 0 && x < (int)g.nbx && y >= 0 && y < (int)g.nby)
+            v = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
+        sh[li][hy][hx] = v;
+    }
+    __syncthreads();
+
     const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
     const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
-    const bool inxy = bx < g.nbx && by < g.nby;
-    const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+    if (bx >= g.nbx || by >= g.nby) return;
     // per layer: 3x3 min / max, 2x2 positive min / max, own range
     float l3a = INFINITY, h3a = -INFINITY;                       // layer zl - 2
     float l3b = INFINITY, h3b = -INFINITY, p2lb = INFINITY, p2hb = -INFINITY;
     float2 ownb = make_float2(INFINITY, -INFINITY);             // layer zl - 1
-    for (int zl = z0 - 1; zl <= z1; zl++) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < (CULL_TY + 2) * (CULL_TX + 2); i += 256) {
-            const int hy = i / (CULL_TX + 2), hx = i - hy * (CULL_TX + 2);
-            const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
-            float2 v = make_float2(INFINITY, -INFINITY);
-            if (zl >= 0 && zl < (int)g.nbz && x >= 0 && x < (int)g.nbx && y >= 0 && y < (int)g.nby)
-                v = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
-            sh[hy][hx] = v;
-        }
-        __syncthreads();
+    for (int li = 0; li < NL; li++) {
+        const int zl = z0 - 1 + li;
+        if (zl > z1) break;
         float l3 = INFINITY, h3 = -INFINITY, p2l = INFINITY, p2h = -INFINITY;
 #pragma unroll
         for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
             for (int dx = -1; dx <= 1; dx++) {
-                const float2 q = sh[ly + 1 + dy][lx + 1 + dx];
+                const float2 q = sh[li][ly + 1 + dy][lx + 1 + dx];
                 l3 = fminf(l3, q.x);
                 h3 = fmaxf(h3, q.y);
                 if (dx >= 0 && dy >= 0) {
@@ -87,8 +94,8 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
                     p2h = fmaxf(p2h, q.y);
                 }
             }
-        const float2 own = sh[ly + 1][lx + 1];
-        if (zl > z0 && inxy) {   // layer zl - 1 has both z neighbours now
+        const float2 own = sh[li][ly + 1][lx + 1];
+        if (zl > z0) {   // layer zl - 1 has both z neighbours now
             const float LO = fminf(l3a, fminf(l3b, l3)), HI = fmaxf(h3a, fmaxf(h3b, h3));
             const float PLO = fminf(p2lb, p2l), PHI = fmaxf(p2hb, p2h);
             const bool act = (ownb.x < iso && iso <= HI) || (LO < iso && iso <= ownb.y);
@@ -116,38 +123,62 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
                                                        int identity, uint32_t *__restrict__ I_active,
                                                        uint32_t *__restrict__ I_new, Counters *ctr,
                                                        uint32_t *__restrict__ part_cand,
-                                                       uint64_t *status) {
-    const uint64_t n_tiles = (g.nb + BLK_TILE - 1) / BLK_TILE;
+                                                       uint64_t *status, uint32_t m) {
+    // a tile is 256 threads x 16*m consecutive blocks (m chosen by the host
+    // so that there are about 1024 tiles: one ticket and one look-back each)
+    const uint64_t tile_blocks = (uint64_t)BLK_TILE * m;
+    const uint64_t n_tiles = (g.nb + tile_blocks - 1) / tile_blocks;
     const uint32_t t = take_tile(&ctr->tile_ctr[TC_BLK]);
     if (t >= n_tiles) return;
-    const uint64_t base = (uint64_t)t * BLK_TILE + threadIdx.x * 16u;
-    uint32_t actb = 0, newb = 0;
-    if (base + 16 <= g.nb) {
-        uint4 q = *reinterpret_cast<const uint4 *>(active + base);
-        uint32_t wds[4] = {q.x, q.y, q.z, q.w};
+    const uint64_t lo = t * tile_blocks + (uint64_t)threadIdx.x * 16u * m;
+    uint32_t nact = 0, nnew = 0, cand = 0;
+    for (uint32_t c0 = 0; c0 < m; c0 += 4) {
+        uint4 q[4];   // 4 chunks of 16 flags in flight together
 #pragma unroll
-        for (int j = 0; j < 16; j++)
-            if ((wds[j >> 2] >> (8 * (j & 3))) & 0xFFu) actb |= 1u << j;
-    } else {
-        for (int j = 0; j < 16; j++)
-            if (base + j < g.nb && active[base + j]) actb |= 1u << j;
-    }
-    uint32_t cand = 0;   // blocks that may emit (bit 1 of the flag), summed per tile
-    for (uint32_t m = actb; m; m &= m - 1) cand += (active[base + __builtin_ctz(m)] >> 1) & 1u;
-    cand = wg_sum_u32(cand);
-    if (threadIdx.x == 0) part_cand[t] = cand;
-    if (!identity) {
-        for (uint32_t m = actb; m; m &= m - 1) {
-            int j = __builtin_ctz(m);
-            if (I_slot[base + j] < 0) newb |= 1u << j;
+        for (int k = 0; k < 4; k++) {
+            const uint64_t base = lo + 16u * (c0 + k);
+            if (c0 + k < m && base + 16 <= g.nb) {
+                q[k] = *reinterpret_cast<const uint4 *>(active + base);
+            } else {
+                uint32_t wd[4] = {0, 0, 0, 0};
+                for (int j = 0; j < 16; j++)
+                    if (c0 + k < m && base + j < g.nb) wd[j >> 2] |= (uint32_t)active[base + j] << (8 * (j & 3));
+                q[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint64_t base = lo + 16u * (c0 + k);
+            const uint32_t wds[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+            uint32_t actb = 0;
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+                if (f) actb |= 1u << j;
+                cand += (f >> 1) & 1u;
+            }
+            nact += __popc(actb);
+            if (!identity)
+                for (uint32_t mm = actb; mm; mm &= mm - 1) nnew += I_slot[base + __builtin_ctz(mm)] < 0;
         }
     }
-    uint64_t v = ((uint64_t)__popc(actb) << 31) | (uint64_t)__popc(newb);
+    cand = wg_sum_u32(cand);
+    if (threadIdx.x == 0) part_cand[t] = cand;
     uint64_t incl_end;
-    uint64_t e = tile_scan_lookback(v, status, t, &incl_end);
+    uint64_t e = tile_scan_lookback(((uint64_t)nact << 31) | (uint64_t)nnew, status, t, &incl_end);
     uint64_t oa = e >> 31, on = e & 0x7FFFFFFFull;
-    for (uint32_t m = actb; m; m &= m - 1) I_active[oa++] = (uint32_t)(base + __builtin_ctz(m));
-    for (uint32_t m = newb; m; m &= m - 1) I_new[on++] = (uint32_t)(base + __builtin_ctz(m));
+    if (nact) {
+        for (uint32_t c = 0; c < m; c++) {
+            const uint64_t base = lo + 16u * c;
+            for (int j = 0; j < 16; j++) {
+                const uint64_t b = base + j;
+                if (b < g.nb && active[b]) {
+                    I_active[oa++] = (uint32_t)b;
+                    if (!identity && I_slot[b] < 0) I_new[on++] = (uint32_t)b;
+                }
+            }
+        }
+    }
     if (t == n_tiles - 1 && threadIdx.x == 0) {
         ctr->n_act = incl_end >> 31;
         ctr->n_new = incl_end & 0x7FFFFFFFull;
@@ -600,7 +631,8 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     if (blockIdx.x == 0) {   // the call's statistics from the per-tile counts
-        const uint64_t n_ct = (g.nb + BLK_TILE - 1) / BLK_TILE, n_st = (n_act + SCAN_TILE - 1) / SCAN_TILE;
+        const uint64_t ctile = (uint64_t)BLK_TILE * compact_blocks_per_thread16(g.nb);
+        const uint64_t n_ct = (g.nb + ctile - 1) / ctile, n_st = (n_act + SCAN_TILE - 1) / SCAN_TILE;
         uint32_t cand = 0, occ = 0;
         for (uint64_t i = threadIdx.x; i < n_ct; i += blockDim.x) cand += part_cand[i];
         for (uint64_t i = threadIdx.x; i < n_st; i += blockDim.x) occ += part_occ[i];
@@ -771,9 +803,10 @@ void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float
 
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
                            int identity_cache, hipStream_t s) {
-    unsigned tiles = (unsigned)((g.nb + BLK_TILE - 1) / BLK_TILE);
-    k_compact_blocks<<<tiles, 256, 0, s>>>(g, d.active, d.I_slot, identity_cache, d.I_active,
-                                           d.I_new, d.ctr, d.part_cand, d.status + sl.blk);
+    const uint32_t m = compact_blocks_per_thread16(g.nb);
+    const uint64_t tiles = (g.nb + (uint64_t)BLK_TILE * m - 1) / ((uint64_t)BLK_TILE * m);
+    k_compact_blocks<<<(unsigned)tiles, 256, 0, s>>>(g, d.active, d.I_slot, identity_cache, d.I_active,
+                                                     d.I_new, d.ctr, d.part_cand, d.status + sl.blk, m);
 }
 
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
