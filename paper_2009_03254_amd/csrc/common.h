@@ -73,6 +73,7 @@ struct DevState {
     uint32_t *S_age = nullptr;
     float *slots = nullptr;         // [max_slots][64] decoded blocks
     uint64_t *masks = nullptr;      // [max_slots] per slot: bit i = sample i below iso
+    uint32_t *mask_call = nullptr;  // [max_slots] call whose iso masks[] holds (set by the decode)
     uint32_t *sort_key[2] = {nullptr, nullptr};  // ~age of available slots
     uint32_t *sort_val[2] = {nullptr, nullptr};  // slot ids
     uint32_t *radix_hist = nullptr;              // 256 * radix tiles
@@ -101,7 +102,7 @@ void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slot
 void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound, hipStream_t s);
 void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, hipStream_t s);
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, hipStream_t s);
+                     int identity_cache, float iso, uint32_t call, hipStream_t s);
 void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s);
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                     int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
@@ -121,8 +122,8 @@ void launch_decode_ranges(const Geom &g, const uint64_t *stream, int is_f64, uin
                           float2 *ranges, float *blocks_out, unsigned int *err, hipStream_t s);
 void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *ranges,
                                unsigned int *err, hipStream_t s);
-void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new,
-                          hipStream_t s);
+void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new, float iso,
+                          uint32_t call, hipStream_t s);
 void launch_encode(const Geom &g, const void *field, int is_f64, uint32_t rate,
                    uint64_t *stream, unsigned int *err, hipStream_t s);
 

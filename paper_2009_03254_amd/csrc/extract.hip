@@ -456,7 +456,9 @@ __global__ __launch_bounds__(256) void k_radix_scatter(Counters *ctr, int p,
 __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_active,
                                               const int32_t *__restrict__ I_slot, int identity,
                                               const float *__restrict__ slots, float iso,
-                                              uint64_t *__restrict__ masks, const Counters *ctr) {
+                                              uint64_t *__restrict__ masks,
+                                              const uint32_t *__restrict__ mask_call, uint32_t call,
+                                              const Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_act;
@@ -464,6 +466,7 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
         const uint32_t b = I_active[i];
         const int32_t s = identity ? (int32_t)b : I_slot[b];
         if (s < 0) continue;
+        if (!identity && mask_call[s] == call) continue;   // decoded (and masked) by this call
         const float4 *src = reinterpret_cast<const float4 *>(slots) + (uint64_t)s * 16;
         float4 v[16];
 #pragma unroll
@@ -865,12 +868,12 @@ static unsigned mc_grid(uint64_t max_blocks) {
 }
 
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, hipStream_t s) {
+                     int identity_cache, float iso, uint32_t call, hipStream_t s) {
     static unsigned mgrid = 0, cgrid = 0;
     if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
     if (!cgrid) cgrid = resident_grid(k_mc_count, ~0ull >> 4);
     k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
-        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.ctr);
+        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_call, call, d.ctr);
     k_mc_count<<<std::min<unsigned>(cgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
         g, d.I_active, d.active, I_slot, identity_cache, d.masks, d.blk_cnt, d.ctr);
 }

@@ -28,6 +28,22 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     return v;
 }
 
+// 32-bit inclusive scan over the wave with DPP moves (no LDS round trips):
+// row_shr 1, 2, 4, 8 scan each row of 16 lanes (lanes shifted in from
+// outside the row read 0), row_bcast:15 adds row 0's total to row 1 and row
+// 2's to row 3, row_bcast:31 adds the total of rows 0-1 to rows 2 and 3.
+template <>
+__device__ __forceinline__ uint32_t wave_incl_scan<uint32_t>(uint32_t v) {
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return (uint32_t)x;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -43,9 +59,11 @@ __device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
 }
 
 // Decoupled look-back, run by one whole wave: publishes `agg` for tile t and
-// returns the exclusive prefix of the tile.  64 predecessors are inspected
-// per step: the window is summed up to (and including) the nearest tile
-// that already holds an inclusive prefix.
+// returns the exclusive prefix of the tile.  256 predecessors are inspected
+// per step (4 status words per lane, all loads in flight together): the
+// window is summed up to (and including) the nearest tile that already holds
+// an inclusive prefix.  With ~1000 tiles running at once most windows hold
+// only aggregates, so the step width sets the latency of the walk.
 __device__ uint64_t lookback(uint64_t *status, uint64_t t, uint64_t agg) {
     const int l = lane();
     if (t == 0) {
@@ -56,21 +74,38 @@ __device__ uint64_t lookback(uint64_t *status, uint64_t t, uint64_t agg) {
     uint64_t excl = 0;
     int64_t j = (int64_t)t - 1;
     for (;;) {
-        int64_t idx = j - l;
-        uint64_t w = idx >= 0 ? lb_load(&status[idx]) : LB_PRE;
-        uint64_t flag = w & ~LB_VAL;
-        uint64_t pre = __ballot(flag == LB_PRE);
-        uint64_t notready = __ballot(flag == 0);
-        int first = pre ? (int)__builtin_ctzll(pre) : 64;
-        uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
-        if (notready & upto) {
+        uint64_t w[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int64_t idx = j - l - 64 * r;   // window position 64 r + l
+            w[r] = idx >= 0 ? lb_load(&status[idx]) : LB_PRE;
+        }
+        // first inclusive prefix in window order, and whether anything before it is missing
+        int first = 256;
+        bool missing = false;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint64_t flag = w[r] & ~LB_VAL;
+            const uint64_t pre = __ballot(flag == LB_PRE);
+            const uint64_t notready = __ballot(flag == 0);
+            if (first == 256) {
+                const int f = pre ? (int)__builtin_ctzll(pre) : 64;
+                const uint64_t upto = f >= 63 ? ~0ull : ((2ull << f) - 1);
+                if (notready & upto) missing = true;
+                if (f < 64) first = 64 * r + f;
+            }
+        }
+        if (missing) {
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        uint64_t v = (l <= first) ? (w & LB_VAL) : 0;
+        uint64_t v = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (64 * r + l <= first) v += w[r] & LB_VAL;
         excl += wave_sum(v);
-        if (first < 64) break;
-        j -= 64;
+        if (first < 256) break;
+        j -= 256;
     }
     if (l == 0) lb_store(&status[t], LB_PRE | (excl + agg));
     return excl;
@@ -388,6 +423,24 @@ __device__ __forceinline__ void xcd_wave_range(uint64_t n, uint64_t &lo, uint64_
     hi = lo + chunk < n ? lo + chunk : n;
 }
 
+// Per-edge lookup, 5 bits per edge id e (0..11), built from edge_geom's
+// convention: kEdgeGeom holds ox | oy << 1 | oz << 2 | axis << 3 (first
+// corner offset and axis), kEdgeTile the first corner's offset in the 5^3
+// tile index (ox + 5 oy + 25 oz).
+constexpr uint64_t edge_lut(bool tile_offset) {
+    uint64_t r = 0;
+    for (int e = 0; e < 12; e++) {
+        const int axis = e >> 2, b0 = e & 1, b1 = (e >> 1) & 1;
+        const int ox = axis == 0 ? 0 : b0;
+        const int oy = axis == 1 ? 0 : (axis == 0 ? b0 : b1);
+        const int oz = axis == 2 ? 0 : b1;
+        const int v = tile_offset ? ox + 5 * oy + 25 * oz : (ox | oy << 1 | oz << 2 | axis << 3);
+        r |= (uint64_t)v << (5 * e);
+    }
+    return r;
+}
+constexpr uint64_t kEdgeGeom = edge_lut(false), kEdgeTile = edge_lut(true);
+
 struct EmitShared {
     float tiles[MC_WAVES][MC_SB][128];
     uint32_t tri[MC_WAVES][64 * 5];  // per triangle: cell | its 3 edge ids << 6
@@ -425,11 +478,13 @@ __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t b
         const uint32_t rec = sh.tri[w][t];
         const int c = (int)(rec & 63u);
         const int e = (int)((rec >> (6 + 4 * (j - 3 * t))) & 15u);
-        int ox, oy, oz, axis;
-        edge_geom(e, ox, oy, oz, axis);
-        const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
-        const float a = tile[tix(x0, y0, z0)];
-        const float bv = tile[tix(x0 + (axis == 0), y0 + (axis == 1), z0 + (axis == 2))];
+        const uint32_t d = (uint32_t)(kEdgeGeom >> (5 * e)) & 31u;
+        const int axis = (int)(d >> 3);
+        const int cx = c & 3, cy = (c >> 2) & 3, cz = c >> 4;
+        const int i0 = tix(cx, cy, cz) + (int)((kEdgeTile >> (5 * e)) & 31u);
+        const int i1 = i0 + (int)((0x190501u >> (8 * axis)) & 0xFFu);   // +1 / +5 / +25
+        const float a = tile[i0];
+        const float bv = tile[i1];
         const float tt = (iso - a) / (bv - a);
         const uint64_t o = base + (uint64_t)j;
         if (EDGE8) {
@@ -438,10 +493,11 @@ __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t b
             const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
             if (o < cap) reinterpret_cast<uint64_t *>(out)[o] = r;
         } else {
-            float px = (float)x0, py = (float)y0, pz = (float)z0;
-            if (axis == 0) px += tt;
-            else if (axis == 1) py += tt;
-            else pz += tt;
+            // the edge's first corner plus t along its axis (adding 0 to the
+            // other two coordinates leaves them exact)
+            const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
+            const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
+            const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
             if (o < cap)
                 reinterpret_cast<uint4 *>(out)[o] =
                     make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);

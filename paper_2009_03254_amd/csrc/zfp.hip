@@ -118,7 +118,9 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
                                                       int32_t *S_block, int32_t *I_slot,
                                                       uint32_t *S_age, const uint64_t *__restrict__ stream,
                                                       int rate, float *__restrict__ slots,
-                                                      uint64_t n_blocks) {
+                                                      uint64_t n_blocks, float iso,
+                                                      uint64_t *__restrict__ masks,
+                                                      uint32_t *__restrict__ mask_call, uint32_t call) {
     if (ctr->err) return;
     const uint64_t n_slots = ctr->n_slots;
     const uint64_t n_new = ctr->n_new;
@@ -159,9 +161,19 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
             decode_block<F64>(stream + (uint64_t)b * rate, rate, v);
         }
         if (!valid) continue;
+        // store the block, and its sign mask for this call's isovalue (so the
+        // mask pass need not read the freshly decoded slot back)
         float4 *o = reinterpret_cast<float4 *>(slots + (uint64_t)s * 64);
+        uint32_t mw[2] = {0u, 0u};
 #pragma unroll
-        for (int q = 0; q < 16; q++) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        for (int q = 0; q < 16; q++) {
+            const float4 f = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            o[q] = f;
+            mw[q >> 3] |= ((f.x < iso ? 1u : 0u) | (f.y < iso ? 2u : 0u) | (f.z < iso ? 4u : 0u) |
+                           (f.w < iso ? 8u : 0u)) << (4 * (q & 7));
+        }
+        masks[s] = (uint64_t)mw[1] << 32 | mw[0];
+        mask_call[s] = call;
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) evicted += __shfl_xor(evicted, d, 64);   // one atomic per wave
@@ -219,11 +231,12 @@ void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *range
     k_ranges_from_blocks<<<grid_for(g.nb, 8192), 256, 0, s>>>(g, blocks, ranges, err);
 }
 
-void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new,
-                          hipStream_t s) {
+void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new, float iso,
+                          uint32_t call, hipStream_t s) {
     unsigned grid = grid_for(max_new, 2048);
     BCMC_DECODE_LAUNCH(k_assign_decode, grid, rate, s, d.ctr, d.I_new, d.sort_val[0], d.sort_val[1],
-                       d.S_block, d.I_slot, d.S_age, d.stream, (int)rate, d.slots, max_new);
+                       d.S_block, d.I_slot, d.S_age, d.stream, (int)rate, d.slots, max_new, iso,
+                       d.masks, d.mask_call, call);
 }
 
 void launch_encode(const Geom &g, const void *field, int is_f64, uint32_t rate, uint64_t *stream,
