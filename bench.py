@@ -33,7 +33,8 @@ RATE = 8
 
 # Sources of the single-volume kernels, hashed to tell whether the committed
 # traffic counters were taken on the kernels as they are now.
-KERNEL_SOURCES = ("common.h", "mc_device.h", "zfp_device.h", "extract.hip", "zfp.hip")
+KERNEL_SOURCES = ("common.h", "mc_device.h", "zfp_device.h", "extract.hip", "zfp.hip", "tables.cpp",
+                  "gen_ntri.cpp")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "path_turbulence512_rate8_hbm_counters.md")
 
 
@@ -193,12 +194,15 @@ def batch_bench(steps, warmup):
         return float(np.median(ts)) * 1e3
 
     gpu_ms = {"cold": [], "warm": []}
+    phases = {"cold": [], "warm": []}
 
     def batch_run(kind):
         rc, o = batch.run_into(out)
         if rc != 0 or int(o[-1]) != total_v:
             raise bcmc.BcmcError(rc, bcmc.lib().bcmc_last_error().decode())
-        gpu_ms[kind].append(batch.info()["last_ms"])
+        inf = batch.info()
+        gpu_ms[kind].append(inf["last_ms"])
+        phases[kind].append(inf["phase_ms"])
 
     def batch_cold():
         batch.reset()
@@ -246,6 +250,7 @@ def batch_bench(steps, warmup):
                      "workgroups_per_cu": info["workgroups_per_cu"], "graph": info["graph"]},
         "cold": {"batch_ms": round(cold_ms, 4),
                  "batch_gpu_ms": round(float(np.median(gpu_ms["cold"])), 4),
+                 "phase_ms": [round(float(x), 4) for x in np.median(np.array(phases["cold"]), axis=0)],
                  "plain_ms": round(plain_cold_ms, 4),
                  "speedup_vs_plain": round(plain_cold_ms / cold_ms, 3),
                  "triangles_per_s": round(T / (cold_ms * 1e-3)),
@@ -253,12 +258,14 @@ def batch_bench(steps, warmup):
                  "n_new": info_cold["n_new"]},
         "warm": {"batch_ms": round(warm_ms, 4),
                  "batch_gpu_ms": round(float(np.median(gpu_ms["warm"])), 4),
+                 "phase_ms": [round(float(x), 4) for x in np.median(np.array(phases["warm"]), axis=0)],
                  "plain_ms": round(plain_warm_ms, 4),
                  "speedup_vs_plain": round(plain_warm_ms / warm_ms, 3),
                  "triangles_per_s": round(T / (warm_ms * 1e-3)),
                  "alg_gbs": round(alg["warm"] / (warm_ms * 1e-3) / 1e9, 2)},
         "note": "alg_gbs = the algorithmic bytes of the 192 plain calls over the batch's time; "
-                "ms are wall-clock per pass including the offsets readback",
+                "ms are wall-clock per pass including the offsets readback; phase_ms: reset, "
+                "flags, counts scan, list scatter, decode, count, count scan, emission",
     }
 
 
@@ -458,7 +465,8 @@ def main():
         })
 
     # per-kernel algorithmic bytes / HIP-event durations over the timed region
-    # (stage_ms: 2 = assign+decode, 3 = MC count, 4 = block scan, 5 = MC emit)
+    # (stage_ms: 2 = assign+decode, 3 = sign masks + MC count, 4 = block scan,
+    # 5 = MC emit)
     def kstats(stage, bytes_fn, live_fn):
         ms = sum(r[2]["stage_ms"][stage] for r in records)
         nbytes = sum(bytes_fn(r[2]) for r in records)
@@ -470,7 +478,10 @@ def main():
     kern = {
         "k_assign_decode": kstats(2, lambda st: st["n_new"] * (8.0 * RATE + 256.0),
                                   lambda st: st["n_new"] > 0),
-        "k_mc_count": kstats(3, lambda st: 256.0 * st["n_candidates"], lambda st: True),
+        # masks of active blocks not decoded by the call (their slots are
+        # read once) + one 8-byte mask per active block for the count
+        "k_masks+k_mc_count": kstats(3, lambda st: 256.0 * (st["n_active"] - st["n_new"]) +
+                                     8.0 * st["n_active"], lambda st: True),
         "k_scan_counts": kstats(4, lambda st: 12.0 * st["n_active"], lambda st: True),
         "k_mc_emit": kstats(5, lambda st: 256.0 * st["n_occupied"] + 24.0 * st["n_triangles"],
                             lambda st: True),

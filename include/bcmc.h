@@ -220,6 +220,10 @@ typedef struct {
     int32_t graph;            /* 1: the last run replayed a hipGraph */
     int32_t graph_unsupported;/* 1: capturing the cooperative launch failed */
     float last_ms;            /* GPU time of the last run (HIP events) */
+    float phase_ms[8];        /* the last run's phases (device clock at the grid
+                                 barriers): reset, flags, scan of the counts of new
+                                 blocks and pairs, list scatter, decode, count,
+                                 count scan, emission */
 } bcmc_batch_info;
 
 BCMC_API int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t *job_vol,

@@ -40,10 +40,13 @@ class BatchInfo(C.Structure):
                 ("n_pairs", C.c_uint64), ("n_vertices", C.c_uint64),
                 ("stage_blocks", C.c_uint32), ("grid", C.c_uint32),
                 ("workgroups_per_cu", C.c_uint32), ("graph", C.c_int32),
-                ("graph_unsupported", C.c_int32), ("last_ms", C.c_float)]
+                ("graph_unsupported", C.c_int32), ("last_ms", C.c_float),
+                ("phase_ms", C.c_float * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_ms"] = [float(x) for x in self.phase_ms]
+        return d
 
 
 _P, _u32, _u64, _i32, _f32, _int = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_float, C.c_int

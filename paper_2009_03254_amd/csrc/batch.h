@@ -41,6 +41,7 @@ struct BatchParams {
     uint8_t *emit_flag;          // [n_jblocks]
     uint32_t *new_list;          // [n_gblocks]
     uint32_t *list;              // [n_jblocks] (job-major, block-ascending)
+    uint32_t *list_job;          // [n_jblocks] job of each list entry
     uint32_t *cnt;               // [n_jblocks]
     uint64_t *off;               // [n_jblocks]
     uint64_t *part_new, *part_list;  // [grid]
@@ -51,6 +52,7 @@ struct BatchParams {
     uint64_t cap;
     BatchCounters *ctr;
     unsigned int *bar;           // [2] grid barrier: arrivals, generation
+    unsigned long long *phase_ts;  // [9] real-time clock at the start and after each phase
 };
 
 int batch_max_grid(int is_f64, int sb, int *per_cu);

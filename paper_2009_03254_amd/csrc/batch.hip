@@ -145,11 +145,17 @@ struct BatchShared {
     uint32_t ntri[256];
 };
 
+// Workgroup 0 stamps the device's constant-rate clock at phase boundaries.
+__device__ __forceinline__ void stamp(const BatchParams &p, int k) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.phase_ts[k] = wall_clock64();
+}
+
 template <bool F64, int SB>
 __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
     __shared__ BatchShared sh;
     const int l = lane(), w = threadIdx.x >> 6;
     const uint64_t gtid = blockIdx.x * (uint64_t)BT + threadIdx.x;
+    stamp(p, 0);
     for (int i = threadIdx.x; i < 256; i += BT) sh.ntri[i] = 3u * (uint32_t)(p.mc_table[i] >> 60);
     // phase 0
     if (gtid == 0) {
@@ -160,6 +166,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
     }
     const uint64_t n_slots0 = p.ctr->n_slots;
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 1);
 
     // ---- phase 1: flags and per-workgroup counts ----------------------------
     {
@@ -234,6 +241,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         if (threadIdx.x == 0) p.part_list[blockIdx.x] = tot;
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 2);
 
     // ---- phase 2 -------------------------------------------------------------
     if (blockIdx.x == 0) {
@@ -245,6 +253,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         }
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 3);
 
     // ---- phase 3: ordered scatter of both lists --------------------------------
     {
@@ -268,10 +277,16 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         for (uint64_t i = a; i < z; i++) c += p.emit_flag[i];
         wg_excl_scan(c, excl, sh.w);
         o = p.part_list[blockIdx.x] + excl;
+        SegCursor cur;
+        cur.reset();
         for (uint64_t i = a; i < z; i++)
-            if (p.emit_flag[i]) p.list[o++] = (uint32_t)i;
+            if (p.emit_flag[i]) {
+                p.list[o] = (uint32_t)i;
+                p.list_job[o++] = cur.find(p.job_jbase, p.n_jobs, p.n_jblocks, i);
+            }
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 4);
 
     // ---- phase 4: decode the new blocks; first list entry of every job --------
     const uint64_t n_new = p.ctr->n_new;
@@ -302,6 +317,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         p.I_slot[gb] = (int32_t)slot;
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 5);
 
     // ---- phase 5: count pass over L -------------------------------------------------
     const LaneGeom q = lane_geom();
@@ -312,7 +328,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
             const uint64_t idx = i0 + l;
             const bool valid = idx < hi;
             const uint32_t e = valid ? p.list[idx] : 0u;
-            const uint32_t j = find_base(p.job_jbase, p.n_jobs, e);
+            const uint32_t j = valid ? p.list_job[idx] : 0u;
             const BatchVol &vol = p.vols[p.job_vol[j]];
             const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
             uint32_t so[8], lbx, lby, lbz;
@@ -350,6 +366,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         }
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 6);
 
     // ---- phase 6: scan of the counts ------------------------------------------------
     {
@@ -375,6 +392,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         }
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 7);
 
     // ---- phase 7: emission and job offsets -----------------------------------------
     const uint64_t total = p.ctr->total_verts;
@@ -390,7 +408,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
             const bool valid = idx < hi;
             const uint32_t cnt = valid ? p.cnt[idx] : 0u;
             const uint32_t e = cnt ? p.list[idx] : 0u;
-            const uint32_t j = find_base(p.job_jbase, p.n_jobs, e);
+            const uint32_t j = cnt ? p.list_job[idx] : 0u;
             const BatchVol &vol = p.vols[p.job_vol[j]];
             const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
             const uint64_t boff = cnt ? p.off[idx] : 0ull;
@@ -425,6 +443,7 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         }
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    stamp(p, 8);
     if (gtid == 0) p.ctr->n_slots = n_slots0 + n_new;
 }
 

@@ -47,6 +47,9 @@ struct bcmc_batch {
     unsigned graph_grid = 0;
     int use_graph = 1, graph_failed = 0;
     float last_ms = 0.0f;
+    unsigned long long *h_ts = nullptr;   // phase clock stamps of the last run
+    float phase_ms[8] = {};
+    int clock_khz = 0;
     std::string key;
 };
 
@@ -83,6 +86,7 @@ void destroy_batch(bcmc_batch *b) {
     for (void *p : b->allocs) (void)hipFree(p);
     if (b->h_ctr) (void)hipHostFree(b->h_ctr);
     if (b->h_job_off) (void)hipHostFree(b->h_job_off);
+    if (b->h_ts) (void)hipHostFree(b->h_ts);
     for (hipEvent_t e : {b->ev_in, b->ev_out, b->ev_t0, b->ev_t1})
         if (e) (void)hipEventDestroy(e);
     if (b->gstream) (void)hipStreamDestroy(b->gstream);
@@ -145,10 +149,16 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
                                 b->gstream));
     BCMC_HIP_TRY(hipMemcpyAsync(b->h_job_off, b->p.job_off, (b->n_jobs + 1) * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, b->gstream));
+    BCMC_HIP_TRY(hipMemcpyAsync(b->h_ts, b->p.phase_ts, 9 * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, b->gstream));
     BCMC_HIP_TRY(hipEventRecord(b->ev_out, b->gstream));
     BCMC_HIP_TRY(hipStreamWaitEvent(caller, b->ev_out, 0));
     BCMC_HIP_TRY(hipEventSynchronize(b->ev_out));
     (void)hipEventElapsedTime(&b->last_ms, b->ev_t0, b->ev_t1);
+    for (int k = 0; k < 8; k++)
+        b->phase_ms[k] = b->clock_khz > 0 && b->h_ts[k + 1] >= b->h_ts[k]
+                             ? (float)((double)(b->h_ts[k + 1] - b->h_ts[k]) / b->clock_khz)
+                             : 0.0f;
     if (b->h_ctr->err) {
         const unsigned err = b->h_ctr->err;
         // a failed run may leave the store and the barrier words mid-update
@@ -260,6 +270,8 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        b->clock_khz = 0;
     int rc = set_schedule(b, 8, 1 << 30);
     if (rc) {
         destroy_batch(b);
@@ -279,10 +291,12 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
         (rc = balloc(b, &p.I_slot, gb)) || (rc = balloc(b, &p.slots, gb * 64)) ||
         (rc = balloc(b, &p.need, gb)) || (rc = balloc(b, &p.emit_flag, jb)) ||
         (rc = balloc(b, &p.new_list, gb)) || (rc = balloc(b, &p.list, jb)) ||
+        (rc = balloc(b, &p.list_job, jb)) ||
         (rc = balloc(b, &p.cnt, jb)) || (rc = balloc(b, &p.off, jb)) ||
         (rc = balloc(b, &p.part_new, max_grid)) || (rc = balloc(b, &p.part_list, max_grid)) ||
         (rc = balloc(b, &p.job_first, n_jobs)) || (rc = balloc(b, &p.job_off, n_jobs + 1)) ||
-        (rc = balloc(b, &p.ctr, 1)) || (rc = balloc(b, &p.bar, 2))) {
+        (rc = balloc(b, &p.ctr, 1)) || (rc = balloc(b, &p.bar, 2)) ||
+        (rc = balloc(b, &p.phase_ts, 9))) {
         destroy_batch(b);
         return rc;
     }
@@ -307,6 +321,7 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
         (e = hipMemcpy(d_table, mc_table_host(), 256 * 8, hipMemcpyHostToDevice)) ||
         (e = hipHostMalloc((void **)&b->h_ctr, sizeof(BatchCounters), hipHostMallocDefault)) ||
         (e = hipHostMalloc((void **)&b->h_job_off, 8 * (n_jobs + 1), hipHostMallocDefault)) ||
+        (e = hipHostMalloc((void **)&b->h_ts, 9 * sizeof(unsigned long long), hipHostMallocDefault)) ||
         (e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking)) ||
         (e = hipEventCreate(&b->ev_in)) || (e = hipEventCreate(&b->ev_out)) ||
         (e = hipEventCreate(&b->ev_t0)) || (e = hipEventCreate(&b->ev_t1)))
@@ -442,6 +457,7 @@ int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out) {
     out->graph = (b->use_graph && !b->graph_failed && b->exec) ? 1 : 0;
     out->graph_unsupported = b->graph_failed;
     out->last_ms = b->last_ms;
+    for (int k = 0; k < 8; k++) out->phase_ms[k] = b->phase_ms[k];
     return BCMC_OK;
 }
 

@@ -482,44 +482,6 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
     }
 }
 
-// Corner masks of the 64 cells of a block from the sign masks of the block
-// and its 7 positive neighbours (M[dx | dy<<1 | dz<<2]): bit i of c[k] is the
-// sign bit of corner k = (k&1, k>>1&1, k>>2&1) of cell i.  sx / sy / sz give,
-// for every cell, the sample one step along x / y / z: from the block itself,
-// or from the neighbour for the cells on its far face.
-__device__ __forceinline__ uint64_t sx(uint64_t a, uint64_t b) {
-    return ((a >> 1) & 0x7777777777777777ull) | ((b << 3) & 0x8888888888888888ull);
-}
-__device__ __forceinline__ uint64_t sy(uint64_t a, uint64_t b) {
-    return ((a >> 4) & 0x0FFF0FFF0FFF0FFFull) | ((b << 12) & 0xF000F000F000F000ull);
-}
-__device__ __forceinline__ uint64_t sz(uint64_t a, uint64_t b) { return (a >> 16) | (b << 48); }
-
-__device__ __forceinline__ void corner_masks(const uint64_t M[8], uint64_t c[8]) {
-    const uint64_t x01 = sx(M[0], M[1]), x23 = sx(M[2], M[3]);
-    const uint64_t x45 = sx(M[4], M[5]), x67 = sx(M[6], M[7]);
-    c[0] = M[0];
-    c[1] = x01;
-    c[2] = sy(M[0], M[2]);
-    c[3] = sy(x01, x23);
-    c[4] = sz(M[0], M[4]);
-    c[5] = sz(x01, x45);
-    c[6] = sz(c[2], sy(M[4], M[6]));
-    c[7] = sz(c[3], sy(x45, x67));
-}
-
-// Cells of block (bx, by, bz) whose 8 corners lie in the volume.
-__device__ __forceinline__ uint64_t valid_cells(const Geom &g, uint32_t bx, uint32_t by, uint32_t bz) {
-    const int vx = min(4, (int)g.nx - 1 - 4 * (int)bx);
-    const int vy = min(4, (int)g.ny - 1 - 4 * (int)by);
-    const int vz = min(4, (int)g.nz - 1 - 4 * (int)bz);
-    if (vx <= 0 || vy <= 0 || vz <= 0) return 0;
-    const uint64_t mx = 0x1111111111111111ull * ((1ull << vx) - 1);
-    const uint64_t my = 0x0001000100010001ull * ((1ull << (4 * vy)) - 1);
-    const uint64_t mz = vz == 4 ? ~0ull : ((1ull << (16 * vz)) - 1);
-    return mx & my & mz;
-}
-
 // Count pass (Sec. 4.4): vertex count of every active block (0 unless it can
 // emit), one lane per block.  The cases of all 64 cells are evaluated at once
 // on the corner masks, and the triangle count per case by the bit-sliced
