@@ -199,8 +199,10 @@ BCMC_API int bcmc_copy_calibration(void *d_dst, const void *d_src, uint64_t nbyt
 /* A batch of jobs j = (volume job_vol[j], isovalue job_iso[j]) over
  * compressed volumes that share one scalar type (the volumes must outlive
  * the batch; their own caches are not used).  bcmc_batch_run extracts every
- * job in ONE persistent cooperative kernel (phases separated by grid
- * barriers), replayed from a hipGraph when the runtime allows it.  Job j's
+ * job in two persistent kernels (a front one that culls, lists, decodes and
+ * builds sign masks; a back one that counts, scans and emits; phases
+ * separated by grid barriers), replayed from a hipGraph when the runtime
+ * allows it.  Job j's
  * soup equals, byte for byte, bcmc_extract of its volume at its isovalue,
  * and the jobs' soups are concatenated in job order.  The batch keeps one
  * decoded-block store: a block needed by any job of its volume is decoded
@@ -215,15 +217,17 @@ typedef struct {
     uint64_t n_pairs;         /* (job, block) pairs of the last run that may emit */
     uint64_t n_vertices;      /* vertices of the last run (all jobs) */
     uint32_t stage_blocks;    /* schedule: blocks staged per memory round trip (4 or 8) */
-    uint32_t grid;            /* schedule: workgroups of the persistent launch */
-    uint32_t workgroups_per_cu;
+    uint32_t grid;            /* schedule: workgroups of the back kernel */
+    uint32_t workgroups_per_cu;  /* of the back kernel */
+    uint32_t front_grid;      /* schedule: workgroups of the front kernel */
     int32_t graph;            /* 1: the last run replayed a hipGraph */
     int32_t graph_unsupported;/* 1: capturing the cooperative launch failed */
     float last_ms;            /* GPU time of the last run (HIP events) */
     float phase_ms[8];        /* the last run's phases (device clock at the grid
                                  barriers): reset, flags, scan of the counts of new
-                                 blocks and pairs, list scatter, decode, count,
-                                 count scan, emission */
+                                 blocks and pairs, list scatter, decode and masks,
+                                 count (with the gap between the kernels), count
+                                 scan, emission */
 } bcmc_batch_info;
 
 BCMC_API int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t *job_vol,
@@ -242,8 +246,8 @@ BCMC_API int bcmc_batch_set_graph(bcmc_batch *b, int on);
  * capacity (offsets are set; enlarge and run again). */
 BCMC_API int bcmc_batch_run(bcmc_batch *b, void *d_out, uint64_t capacity_vertices,
                             uint64_t *h_job_off, void *hip_stream);
-/* Autotune the schedule (blocks staged per round trip, workgroups per CU)
- * by timing cold + warm runs of this batch; the best is kept and appended
+/* Autotune the schedule (blocks staged per round trip, workgroups per CU
+ * of the back and the front kernel) by timing cold + warm runs of this batch; the best is kept and appended
  * to cache_path (one JSON object per line, keyed by arch, scalar type and
  * batch shape; NULL: $BCMC_AUTOTUNE_CACHE, or nothing).  Batches created
  * later with a matching key start from the stored schedule.  Empties the

@@ -39,7 +39,8 @@ class BatchInfo(C.Structure):
                 ("n_job_blocks", C.c_uint64), ("n_resident", C.c_uint64), ("n_new", C.c_uint64),
                 ("n_pairs", C.c_uint64), ("n_vertices", C.c_uint64),
                 ("stage_blocks", C.c_uint32), ("grid", C.c_uint32),
-                ("workgroups_per_cu", C.c_uint32), ("graph", C.c_int32),
+                ("workgroups_per_cu", C.c_uint32), ("front_grid", C.c_uint32),
+                ("graph", C.c_int32),
                 ("graph_unsupported", C.c_int32), ("last_ms", C.c_float),
                 ("phase_ms", C.c_float * 8)]
 

@@ -1,10 +1,10 @@
 // Batched extraction: many volumes of uneven size, several isovalues each,
-// in ONE persistent cooperative launch (phases separated by grid barriers),
-// replayable from a hipGraph.
+// in three launches (two of them persistent, their phases separated by grid
+// barriers), replayable from a hipGraph.
 //
 // Each job j = (volume v_j, isovalue iso_j) produces exactly the triangle soup
-// a single-volume extract of v_j at iso_j produces (same kernels' arithmetic,
-// same canonical order); the jobs' soups are concatenated in job order.
+// a single-volume extract of v_j at iso_j produces (same arithmetic, same
+// canonical order); the jobs' soups are concatenated in job order.
 //
 // The batch keeps its own decoded-block store: a block needed by any job of
 // its volume (the union over the volume's isovalues, Sec. 4.1 rule per job)
@@ -12,23 +12,31 @@
 // unbounded cache: nothing is evicted, so later runs decode only blocks no
 // earlier run needed).
 //
-// Phases (grid = all workgroups resident; every thread reaches every barrier):
+// Front kernel (persistent):
 //   0  reset the run's counters
-//   1  per global block: needed by some job of its volume and not yet decoded;
-//      per (job, block): the block may emit for that job (2x2x2 hull rule);
-//      per-workgroup counts of both
-//   2  workgroup 0 scans the per-workgroup counts
+//   1  per global block: used by some job of its volume (new or resident)
+//      and, per job of its volume, whether it may emit for that job (2x2x2
+//      hull rule); per-workgroup counts of new blocks, per-wave counts of
+//      the pairs that may emit
+//   2  workgroup 0 scans the counts and reserves the new blocks' slots
 //   3  scatter: list of new blocks; list L of (job, block) pairs in job-major,
 //      block-ascending order (= the concatenated canonical orders)
-//   4  decode the new blocks into slots n_slots + rank
-//   5  count pass over L (Sec. 4.4)
-//   6  exclusive scan of the counts (reduce, scan partials, distribute)
-//   7  emission over L (Sec. 4.5), per-job output offsets
+// Decode kernel (grid-stride; its grid sized by the decoder's registers):
+//   4  decode the new blocks into slots slot_base + rank; sign masks of every
+//      used block for every job of its volume
+// Back kernel (persistent, grid autotuned; every wave owns one contiguous
+// share of L):
+//   5  count pass over L from the sign masks (Sec. 4.4), per-wave totals
+//   6  workgroup 0 scans the per-wave totals
+//   7  emission over L (Sec. 4.5), offsets by a running wave scan of the
+//      counts; per-job output offsets
+// Every thread of a persistent grid reaches every barrier of its kernel.
 #include <stdint.h>
 
 #include "batch.h"
 #include "common.h"
 #include "mc_device.h"
+#include "mc_ntri.h"
 #include "zfp_device.h"
 
 namespace bcmc {
@@ -63,37 +71,53 @@ struct SegCursor {
     }
 };
 
-// Grid-wide barrier for a grid whose workgroups are all resident: arrival
-// counter + generation word (device-scope atomics).  The spin is bounded: on
-// timeout it raises ERR_TIMEOUT and returns false, and the caller leaves the
-// kernel, so a barrier can never hang the device.
-constexpr unsigned BARRIER_SPIN_LIMIT = 1u << 22;
+// Grid-wide barrier for a grid whose workgroups are all resident.  Arrivals
+// are counted in two levels: workgroup g in group g % BAR_GROUPS, the last of
+// a group in the top-level count, whose last arrival advances the generation.
+// Waiters poll the generation with plain device-scope loads and acquire once
+// when it moves.  The spin is bounded: on timeout it raises ERR_TIMEOUT and
+// returns false, and the caller leaves the kernel, so a barrier can never
+// hang the device.
+constexpr unsigned BARRIER_SPIN_LIMIT = 1u << 21;
+
+__device__ __forceinline__ unsigned ld_relaxed(const unsigned *a) {
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ bool grid_barrier(unsigned int *bar, unsigned int *err) {
     __shared__ int ok;
     __syncthreads();
     if (threadIdx.x == 0) {
         ok = 1;
-        __threadfence();
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = atomicAdd(&bar[0], 1u) + 1u;
-        if (arrived == gridDim.x) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned G = gridDim.x, k = blockIdx.x % BAR_GROUPS;
+        const unsigned groups = G < (unsigned)BAR_GROUPS ? G : (unsigned)BAR_GROUPS;
+        const unsigned members = G / BAR_GROUPS + (k < G % BAR_GROUPS ? 1u : 0u);
+        const unsigned gen = ld_relaxed(&bar[BAR_GEN]);
+        __threadfence();   // release this workgroup's writes; gen read before arriving
+        bool last = false;
+        if (atomicAdd(&bar[BAR_SUB + k * BAR_PAD], 1u) + 1u == members) {
+            __hip_atomic_store(&bar[BAR_SUB + k * BAR_PAD], 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
             __threadfence();
-            atomicAdd(&bar[1], 1u);
-        } else {
+            if (atomicAdd(&bar[BAR_TOP], 1u) + 1u == groups) {
+                __hip_atomic_store(&bar[BAR_TOP], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+                atomicAdd(&bar[BAR_GEN], 1u);
+                last = true;
+            }
+        }
+        if (!last) {
             unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_TIMEOUT ||
-                    ++spins > BARRIER_SPIN_LIMIT) {
+            while (ld_relaxed(&bar[BAR_GEN]) == gen) {
+                if (ld_relaxed(err) & ERR_TIMEOUT || ++spins > BARRIER_SPIN_LIMIT) {
                     atomicOr(err, ERR_TIMEOUT);
                     ok = 0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(4);
             }
         }
-        __threadfence();
+        __threadfence();   // acquire the other workgroups' writes
     }
     __syncthreads();
     return ok;
@@ -124,130 +148,185 @@ __device__ __forceinline__ void wg_range(uint64_t n, uint64_t &lo, uint64_t &hi)
     if (lo > n) lo = n;
 }
 
-// Exclusive scan, by workgroup 0, of partial[0..G) in place; returns total.
-__device__ uint64_t scan_partials(uint64_t *partial, uint32_t *sh_w) {
-    const uint32_t G = gridDim.x;
-    uint64_t carry = 0;
-    for (uint32_t base = 0; base < G; base += BT) {
-        uint32_t i = base + threadIdx.x;
-        uint32_t v = i < G ? (uint32_t)partial[i] : 0u;
-        uint32_t excl;
-        uint32_t tot = wg_excl_scan(v, excl, sh_w);
-        if (i < G) partial[i] = carry + excl;
-        carry += tot;
+// Exclusive scan, by workgroup 0, of partial[0..n) in place; returns total.
+// Each thread takes a contiguous run (its loads all in flight together),
+// the runs' sums are scanned across the workgroup.
+__device__ uint64_t scan_partials(uint64_t *partial, uint32_t n, uint64_t *sh_w) {
+    const int w = threadIdx.x >> 6;
+    const uint32_t per = (n + BT - 1) / BT;
+    const uint32_t a = threadIdx.x * per, z = a + per < n ? a + per : n;
+    uint64_t s = 0;
+#pragma unroll 8
+    for (uint32_t i = a; i < z; i++) s += partial[i];
+    const uint64_t incl = wave_incl_scan(s);
+    if (lane() == 63) sh_w[w] = incl;
+    __syncthreads();
+    uint64_t off = incl - s, tot = 0;
+#pragma unroll
+    for (int k = 0; k < BT / 64; k++) {
+        if (k < w) off += sh_w[k];
+        tot += sh_w[k];
     }
-    return carry;
+    __syncthreads();
+#pragma unroll 8
+    for (uint32_t i = a; i < z; i++) {
+        const uint64_t v = partial[i];
+        partial[i] = off;
+        off += v;
+    }
+    return tot;
 }
 
-struct BatchShared {
-    EmitShared emit;
-    uint32_t w[BT / 64];
-    uint32_t ntri[256];
-};
+// Sign mask of a decoded block for one isovalue: bit i = (sample i < iso),
+// the inside test of the per-cell classification (Sec. 4.4).
+__device__ __forceinline__ uint64_t sign_mask(const float *v, float iso) {
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 64; i++) m |= (uint64_t)(v[i] < iso ? 1u : 0u) << i;
+    return m;
+}
 
-// Workgroup 0 stamps the device's constant-rate clock at phase boundaries.
+// Jobs per volume whose masks the decoder builds in registers.
+constexpr int MASK_JOBS = 4;
+
+// The masks of global block gb (block b of volume vol) for every job of its
+// volume.
+__device__ __forceinline__ void store_masks(const BatchParams &p, const BatchVol &vol, uint32_t b,
+                                            const float *v) {
+    for (uint32_t k = vol.job_lo; k < vol.job_hi; k++) {
+        const uint32_t j = p.vol_jobs[k];
+        p.jmask[p.job_jbase[j] + b] = sign_mask(v, p.job_iso[j]);
+    }
+}
+
+// Clock stamp k by workgroup 0 (after a grid barrier every workgroup has
+// passed the previous phase).
 __device__ __forceinline__ void stamp(const BatchParams &p, int k) {
     if (blockIdx.x == 0 && threadIdx.x == 0) p.phase_ts[k] = wall_clock64();
 }
 
-template <bool F64, int SB>
-__global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
-    __shared__ BatchShared sh;
-    const int l = lane(), w = threadIdx.x >> 6;
+// Clock stamp k by the last workgroup to finish the kernel.
+__device__ __forceinline__ void stamp_last(const BatchParams &p, int k) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&p.bar[BAR_DONE], 1u) + 1u == gridDim.x) {
+            p.phase_ts[k] = wall_clock64();
+            __hip_atomic_store(&p.bar[BAR_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Contiguous share [lo, hi) of n items for the calling wave, as
+// xcd_wave_range; returns the share's rank in item order.
+__device__ __forceinline__ uint32_t wave_share(uint64_t n, uint64_t &lo, uint64_t &hi) {
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    const uint32_t logical = (g % 8u) * (G / 8u) + g / 8u;
+    const uint64_t waves = (uint64_t)G * (BT / 64);
+    const uint32_t wv = logical * (BT / 64) + (threadIdx.x >> 6);
+    const uint64_t chunk = (n + waves - 1) / waves;
+    lo = wv * chunk;
+    if (lo > n) lo = n;
+    hi = lo + chunk < n ? lo + chunk : n;
+    return wv;
+}
+
+// ---- front kernel: phases 0-3 ---------------------------------------------
+__global__ __launch_bounds__(BT) void k_batch_front(BatchParams p) {
+    __shared__ uint32_t sh_w[BT / 64];
+    __shared__ uint64_t sh_w64[BT / 64];
     const uint64_t gtid = blockIdx.x * (uint64_t)BT + threadIdx.x;
     stamp(p, 0);
-    for (int i = threadIdx.x; i < 256; i += BT) sh.ntri[i] = 3u * (uint32_t)(p.mc_table[i] >> 60);
-    // phase 0
+    // phase 0: reset the run's counters
     if (gtid == 0) {
         p.ctr->n_new = 0;
         p.ctr->n_list = 0;
         p.ctr->total_verts = 0;
         p.ctr->err = 0;
     }
-    const uint64_t n_slots0 = p.ctr->n_slots;
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 1);
 
-    // ---- phase 1: flags and per-workgroup counts ----------------------------
+    // ---- phase 1: flags ----------------------------------------------------------
+    // Per global block, with its volume uniform over the workgroup's loop: the
+    // ranges of its 3x3x3 neighbourhood (indices clamped into the volume: a
+    // clamped neighbour is one already in the neighbourhood, so no load is
+    // conditional), whether some job of the volume uses it (Sec. 4.1 rule) and,
+    // per job, whether it may emit (2x2x2 hull of its octet).
     {
         uint64_t lo, hi;
         wg_range(p.n_gblocks, lo, hi);
         uint32_t cnt = 0;
-        SegCursor cur;
-        cur.reset();
-        for (uint64_t gb = lo + threadIdx.x; gb < hi; gb += BT) {
-            const uint32_t v = cur.find(p.vol_gbase, p.n_vols, p.n_gblocks, gb);
+        for (uint32_t v = lo < hi ? find_base(p.vol_gbase, p.n_vols, lo) : p.n_vols; v < p.n_vols; v++) {
             const BatchVol &vol = p.vols[v];
-            const Geom &g = vol.g;
-            const uint32_t b = (uint32_t)(gb - vol.gbase);
-            uint8_t need = 0;
-            if (p.I_slot[gb] < 0) {
-                const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
-                const float2 own = vol.ranges[b];
-                float LO = own.x, HI = own.y;
-                for (int dz = -1; dz <= 1; dz++) {
-                    int z = (int)bz + dz;
-                    if (z < 0 || z >= (int)g.nbz) continue;
-                    for (int dy = -1; dy <= 1; dy++) {
-                        int y = (int)by + dy;
-                        if (y < 0 || y >= (int)g.nby) continue;
-                        const float2 *row = vol.ranges + ((uint64_t)z * g.nby + y) * g.nbx;
-                        for (int dx = -1; dx <= 1; dx++) {
-                            int x = (int)bx + dx;
-                            if (x < 0 || x >= (int)g.nbx) continue;
-                            float2 q = row[x];
-                            LO = fminf(LO, q.x);
-                            HI = fmaxf(HI, q.y);
-                        }
+            if (vol.gbase >= hi) break;
+            const Geom g = vol.g;
+            const uint64_t s0 = vol.gbase > lo ? vol.gbase : lo;
+            const uint64_t s1 = vol.gbase + g.nb < hi ? vol.gbase + g.nb : hi;
+            for (uint64_t gb = s0 + threadIdx.x; gb < s1; gb += BT) {
+                const uint32_t b = (uint32_t)(gb - vol.gbase);
+                const uint32_t r = b / g.nbx, bx = b - r * g.nbx, by = r % g.nby, bz = r / g.nby;
+                uint32_t xs[3], ys[3], zs[3];
+                xs[0] = bx ? bx - 1 : 0; xs[1] = bx; xs[2] = bx + 1 < g.nbx ? bx + 1 : bx;
+                ys[0] = by ? by - 1 : 0; ys[1] = by; ys[2] = by + 1 < g.nby ? by + 1 : by;
+                zs[0] = bz ? bz - 1 : 0; zs[1] = bz; zs[2] = bz + 1 < g.nbz ? bz + 1 : bz;
+                float2 q[27];
+#pragma unroll
+                for (int k = 0; k < 27; k++)
+                    q[k] = vol.ranges[xs[k % 3] + g.nbx * ((uint64_t)ys[(k / 3) % 3] + (uint64_t)g.nby * zs[k / 9])];
+                float LO = q[0].x, HI = q[0].y, PLO = q[13].x, PHI = q[13].y;
+#pragma unroll
+                for (int k = 1; k < 27; k++) {
+                    LO = fminf(LO, q[k].x);
+                    HI = fmaxf(HI, q[k].y);
+                }
+#pragma unroll
+                for (int k = 14; k < 27; k++)
+                    if (k % 3 != 0 && (k / 3) % 3 != 0) {   // offsets in {0, 1}^3
+                        PLO = fminf(PLO, q[k].x);
+                        PHI = fmaxf(PHI, q[k].y);
                     }
+                const float2 own = q[13];
+                bool used = false;
+                for (uint32_t k = vol.job_lo; k < vol.job_hi; k++) {
+                    const uint32_t j = p.vol_jobs[k];
+                    const float iso = p.job_iso[j];
+                    if ((own.x < iso && iso <= HI) || (LO < iso && iso <= own.y)) used = true;
+                    p.emit_flag[p.job_jbase[j] + b] = (PLO < iso && iso <= PHI) ? 1 : 0;
                 }
-                for (uint32_t j = vol.job_lo; j < vol.job_hi; j++) {
-                    const float iso = p.job_iso[p.vol_jobs[j]];
-                    if ((own.x < iso && iso <= HI) || (LO < iso && iso <= own.y)) need = 1;
-                }
+                const uint8_t need = used ? (p.I_slot[gb] < 0 ? 1 : 2) : 0;
+                p.need[gb] = need;
+                cnt += need == 1;
             }
-            p.need[gb] = need;
-            cnt += need;
         }
         uint32_t excl;
-        uint32_t tot = wg_excl_scan(cnt, excl, sh.w);
+        const uint32_t tot = wg_excl_scan(cnt, excl, sh_w);
         if (threadIdx.x == 0) p.part_new[blockIdx.x] = tot;
-
-        wg_range(p.n_jblocks, lo, hi);
-        cnt = 0;
-        cur.reset();
-        for (uint64_t e = lo + threadIdx.x; e < hi; e += BT) {
-            const uint32_t j = cur.find(p.job_jbase, p.n_jobs, p.n_jblocks, e);
-            const BatchVol &vol = p.vols[p.job_vol[j]];
-            const Geom &g = vol.g;
-            const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
-            const uint32_t bx = b % g.nbx, r = b / g.nbx, by = r % g.nby, bz = r / g.nby;
-            const float iso = p.job_iso[j];
-            float PLO = INFINITY, PHI = -INFINITY;
-#pragma unroll
-            for (int m = 0; m < 8; m++) {
-                uint32_t x = bx + (m & 1), y = by + ((m >> 1) & 1), z = bz + (m >> 2);
-                if (x < g.nbx && y < g.nby && z < g.nbz) {
-                    float2 q = vol.ranges[x + g.nbx * (y + g.nby * z)];
-                    PLO = fminf(PLO, q.x);
-                    PHI = fmaxf(PHI, q.y);
-                }
-            }
-            uint8_t em = (PLO < iso && iso <= PHI) ? 1 : 0;
-            p.emit_flag[e] = em;
-            cnt += em;
-        }
-        tot = wg_excl_scan(cnt, excl, sh.w);
-        if (threadIdx.x == 0) p.part_list[blockIdx.x] = tot;
+    }
+    if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    // Pairs that may emit, per wave share of the flags (4 flags per word; the
+    // flag array is zero-padded to a multiple of 4).
+    const uint64_t n_words = (p.n_jblocks + 3) / 4;
+    const uint32_t *flag_words = reinterpret_cast<const uint32_t *>(p.emit_flag);
+    {
+        uint64_t lo, hi;
+        const uint32_t wv = wave_share(n_words, lo, hi);
+        uint64_t c = 0;
+        for (uint64_t i = lo + lane(); i < hi; i += 64) c += __popc(flag_words[i]);
+        c = wave_sum(c);
+        if (lane() == 0) p.part_list[wv] = c;
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 2);
 
-    // ---- phase 2 -------------------------------------------------------------
+    // ---- phase 2: workgroup 0 scans the counts -----------------------------------
     if (blockIdx.x == 0) {
-        uint64_t tn = scan_partials(p.part_new, sh.w);
-        uint64_t tl = scan_partials(p.part_list, sh.w);
+        uint64_t tn = scan_partials(p.part_new, gridDim.x, sh_w64);
+        uint64_t tl = scan_partials(p.part_list, gridDim.x * (BT / 64), sh_w64);
         if (threadIdx.x == 0) {
+            const uint64_t n_slots0 = p.ctr->n_slots;
+            p.ctr->slot_base = n_slots0;
+            p.ctr->n_slots = n_slots0 + tn;
             p.ctr->n_new = tn;
             p.ctr->n_list = tl;
         }
@@ -262,215 +341,315 @@ __global__ __launch_bounds__(BT) void k_batch(BatchParams p) {
         const uint64_t per = (hi - lo + BT - 1) / BT;    // contiguous items per thread
         uint64_t a = lo + threadIdx.x * per, z = a + per < hi ? a + per : hi;
         uint32_t c = 0;
-        for (uint64_t i = a; i < z; i++) c += p.need[i];
+        for (uint64_t i = a; i < z; i++) c += p.need[i] == 1;
         uint32_t excl;
-        wg_excl_scan(c, excl, sh.w);
+        wg_excl_scan(c, excl, sh_w);
         uint64_t o = p.part_new[blockIdx.x] + excl;
         for (uint64_t i = a; i < z; i++)
-            if (p.need[i]) p.new_list[o++] = (uint32_t)i;
+            if (p.need[i] == 1) p.new_list[o++] = (uint32_t)i;
 
-        wg_range(p.n_jblocks, lo, hi);
-        const uint64_t per2 = (hi - lo + BT - 1) / BT;
-        a = lo + threadIdx.x * per2;
-        z = a + per2 < hi ? a + per2 : hi;
-        c = 0;
-        for (uint64_t i = a; i < z; i++) c += p.emit_flag[i];
-        wg_excl_scan(c, excl, sh.w);
-        o = p.part_list[blockIdx.x] + excl;
+        // L: each wave walks its share of the flag words again, 64 words per
+        // step, placing the pairs by a wave scan of the per-word counts.
+        const uint32_t wv = wave_share(n_words, lo, hi);
+        uint64_t base = p.part_list[wv];
         SegCursor cur;
         cur.reset();
-        for (uint64_t i = a; i < z; i++)
-            if (p.emit_flag[i]) {
-                p.list[o] = (uint32_t)i;
-                p.list_job[o++] = cur.find(p.job_jbase, p.n_jobs, p.n_jblocks, i);
-            }
-    }
-    if (!grid_barrier(p.bar, &p.ctr->err)) return;
-    stamp(p, 4);
-
-    // ---- phase 4: decode the new blocks; first list entry of every job --------
-    const uint64_t n_new = p.ctr->n_new;
-    const uint64_t n_list = p.ctr->n_list;
-    for (uint64_t j = gtid; j < p.n_jobs; j += (uint64_t)gridDim.x * BT) {
-        uint64_t lo = 0, hi = n_list;   // first entry with list[i] >= job_jbase[j]
-        const uint64_t key = p.job_jbase[j];
-        while (lo < hi) {
-            uint64_t mid = (lo + hi) >> 1;
-            if (p.list[mid] < key) lo = mid + 1;
-            else hi = mid;
+        for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
+            const uint64_t i = i0 + lane();
+            const uint32_t fw = i < hi ? flag_words[i] : 0u;
+            const uint32_t cw = __popc(fw);
+            const uint32_t incl = wave_incl_scan(cw);
+            uint64_t o2 = base + incl - cw;
+            base += __shfl(incl, 63, 64);
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+                if ((fw >> (8 * t)) & 0xFFu) {
+                    const uint64_t e = 4 * i + t;
+                    p.list[o2] = (uint32_t)e;
+                    p.list_job[o2++] = cur.find(p.job_jbase, p.n_jobs, p.n_jblocks, e);
+                }
         }
-        p.job_first[j] = lo;
     }
-    for (uint64_t i = gtid; i < n_new; i += (uint64_t)gridDim.x * BT) {
-        const uint32_t gb = p.new_list[i];
+    stamp_last(p, 4);
+}
+
+// ---- decode kernel: phase 4 ---------------------------------------------------
+// STAGED: every volume has rate p.uniform_rate <= STAGE_MAX_RATE and each
+// wave stages its blocks' words in LDS before decoding (whole waves iterate
+// together: the staging is a wave-wide copy).
+template <bool F64, bool STAGED>
+__global__ __launch_bounds__(BT) void k_batch_decode(BatchParams p) {
+    if (p.ctr->err) return;   // the front kernel failed: nothing to do
+    const uint64_t gtid = blockIdx.x * (uint64_t)BT + threadIdx.x;
+    const uint64_t gstride = (uint64_t)gridDim.x * BT;
+    const uint64_t n_slots0 = p.ctr->slot_base;
+    const uint64_t n_new = p.ctr->n_new;
+    extern __shared__ uint64_t stage_lds[];
+    const int urate = (int)p.uniform_rate;
+    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGE_STRIDE * (STAGED ? urate : 0));
+    for (uint64_t i0 = gtid & ~63ull; i0 < n_new; i0 += gstride) {
+        const uint64_t i = i0 + lane();
+        bool valid = i < n_new;
+        const uint32_t gb = valid ? p.new_list[i] : 0u;
         const BatchVol &vol = p.vols[find_base(p.vol_gbase, p.n_vols, gb)];
         const uint64_t slot = n_slots0 + i;
-        if (slot >= p.max_slots) {
+        if (valid && slot >= p.max_slots) {   // never expected: report, do not touch memory
             atomicOr(&p.ctr->err, ERR_INTERNAL);
-            continue;
+            valid = false;
         }
+        const uint32_t b = (uint32_t)(gb - vol.gbase);
         float v[64];
-        decode_block<F64>(vol.stream + (uint64_t)(gb - vol.gbase) * vol.rate, (int)vol.rate, v);
+        if (STAGED) {
+            stage_words_at(vol.stream + (uint64_t)b * urate, urate, valid, st);
+            if (valid) decode_block_staged<F64>(st, urate, v);
+            __builtin_amdgcn_wave_barrier();   // st is rewritten by the next round
+        } else if (valid) {
+            decode_block<F64>(vol.stream + (uint64_t)b * vol.rate, (int)vol.rate, v);
+        }
+        if (!valid) continue;
+        // store the block, building the masks of the volume's first
+        // MASK_JOBS jobs on the way
+        const uint32_t nj = vol.job_hi - vol.job_lo;
+        float iso[MASK_JOBS];
+        uint32_t mw[MASK_JOBS][2];
+#pragma unroll
+        for (int t = 0; t < MASK_JOBS; t++) {
+            iso[t] = (uint32_t)t < nj ? p.job_iso[p.vol_jobs[vol.job_lo + t]] : -INFINITY;
+            mw[t][0] = mw[t][1] = 0u;
+        }
         float4 *dst = reinterpret_cast<float4 *>(p.slots + slot * 64);
 #pragma unroll
-        for (int q = 0; q < 16; q++) dst[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        for (int q = 0; q < 16; q++) {
+            const float4 f = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            dst[q] = f;
+#pragma unroll
+            for (int t = 0; t < MASK_JOBS; t++)
+                mw[t][q >> 3] |= ((f.x < iso[t] ? 1u : 0u) | (f.y < iso[t] ? 2u : 0u) |
+                                  (f.z < iso[t] ? 4u : 0u) | (f.w < iso[t] ? 8u : 0u)) << (4 * (q & 7));
+        }
         p.I_slot[gb] = (int32_t)slot;
+#pragma unroll
+        for (int t = 0; t < MASK_JOBS; t++)
+            if ((uint32_t)t < nj)
+                p.jmask[p.job_jbase[p.vol_jobs[vol.job_lo + t]] + b] = (uint64_t)mw[t][1] << 32 | mw[t][0];
     }
-    if (!grid_barrier(p.bar, &p.ctr->err)) return;
-    stamp(p, 5);
-
-    // ---- phase 5: count pass over L -------------------------------------------------
-    const LaneGeom q = lane_geom();
+    if (p.max_vol_jobs > MASK_JOBS) {
+        // the remaining jobs' masks; lane i reads back the block it stored above
+        for (uint64_t i = gtid; i < n_new; i += gstride) {
+            const uint32_t gb = p.new_list[i];
+            const BatchVol &vol = p.vols[find_base(p.vol_gbase, p.n_vols, gb)];
+            const uint64_t slot = n_slots0 + i;
+            if (vol.job_hi - vol.job_lo <= MASK_JOBS || slot >= p.max_slots) continue;
+            const float4 *src = reinterpret_cast<const float4 *>(p.slots + slot * 64);
+            float w[64];
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const float4 t4 = src[q];
+                w[4 * q] = t4.x;
+                w[4 * q + 1] = t4.y;
+                w[4 * q + 2] = t4.z;
+                w[4 * q + 3] = t4.w;
+            }
+            const uint32_t b = (uint32_t)(gb - vol.gbase);
+            for (uint32_t k = vol.job_lo + MASK_JOBS; k < vol.job_hi; k++) {
+                const uint32_t j = p.vol_jobs[k];
+                p.jmask[p.job_jbase[j] + b] = sign_mask(w, p.job_iso[j]);
+            }
+        }
+    }
     {
-        uint64_t lo, hi;
-        xcd_wave_range(n_list, lo, hi);
+        SegCursor cur;
+        cur.reset();
+        for (uint64_t gb = gtid; gb < p.n_gblocks; gb += gstride) {
+            if (p.need[gb] != 2) continue;
+            const BatchVol &vol = p.vols[cur.find(p.vol_gbase, p.n_vols, p.n_gblocks, gb)];
+            const float4 *src = reinterpret_cast<const float4 *>(p.slots) + (uint64_t)p.I_slot[gb] * 16;
+            float v[64];
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const float4 t = src[q];
+                v[4 * q] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+            }
+            store_masks(p, vol, (uint32_t)(gb - vol.gbase), v);
+        }
+    }
+    stamp_last(p, 5);
+}
+
+// ---- back kernel: phases 5-7 ------------------------------------------------
+struct BackShared {
+    EmitShared emit;
+    uint64_t w64[BT / 64];
+};
+
+template <int SB>
+__global__ __launch_bounds__(BT, 6) void k_batch_back(BatchParams p) {
+    __shared__ BackShared sh;
+    const int l = lane(), w = threadIdx.x >> 6;
+    if (p.ctr->err) return;   // the front kernel failed: nothing to do
+    const uint64_t n_list = p.ctr->n_list;
+    uint64_t lo, hi;
+    const uint32_t wv = wave_share(n_list, lo, hi);
+
+    // ---- phase 5: count pass over L (Sec. 4.4) --------------------------------
+    // One lane per (job, block) pair: the cases of the block's 64 cells from
+    // the sign masks of its octet, the triangle count per case by the
+    // bit-sliced table circuit.
+    {
+        uint64_t tot = 0;
         for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
             const uint64_t idx = i0 + l;
-            const bool valid = idx < hi;
-            const uint32_t e = valid ? p.list[idx] : 0u;
-            const uint32_t j = valid ? p.list_job[idx] : 0u;
-            const BatchVol &vol = p.vols[p.job_vol[j]];
-            const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
-            uint32_t so[8], lbx, lby, lbz;
-            octet(vol.g, b, p.I_slot + vol.gbase, 0, so, lbx, lby, lbz);
-            uint64_t todo = __ballot(valid);
-            uint32_t mycnt = 0;
-            while (todo) {
-                int jl[SB], nsb = 0;
+            uint32_t c = 0;
+            if (idx < hi) {
+                const uint32_t j = p.list_job[idx];
+                const uint64_t jb = p.job_jbase[j];
+                const BatchVol &vol = p.vols[p.job_vol[j]];
+                const uint32_t b = (uint32_t)(p.list[idx] - jb);
+                uint32_t so[8], bx, by, bz;
+                octet(vol.g, b, nullptr, 1, so, bx, by, bz);
+                uint64_t M[8], cm[8];
 #pragma unroll
-                for (int k = 0; k < SB; k++) {
-                    jl[k] = k ? jl[0] : 0;
-                    if (todo) {
-                        jl[k] = (int)__builtin_ctzll(todo);
-                        todo &= todo - 1;
-                        nsb++;
-                    }
-                }
-                stage_batch_n<SB>(q, p.slots, so, jl, sh.emit.tiles[w]);
-                wave_lds_sync();
-#pragma unroll
-                for (int k = 0; k < SB; k++) {
-                    if (k < nsb) {
-                        const uint32_t vj = bcast(p.job_vol[j], jl[k]);
-                        const Geom &g = p.vols[vj].g;
-                        const uint32_t bx = bcast(lbx, jl[k]), by = bcast(lby, jl[k]), bz = bcast(lbz, jl[k]);
-                        const float iso = __uint_as_float(bcast(__float_as_uint(p.job_iso[j]), jl[k]));
-                        const int cs = tile_case(g, bx, by, bz, sh.emit.tiles[w][k], iso);
-                        const uint32_t total = wave_sum(cs < 0 ? 0u : sh.ntri[cs]);
-                        if (l == jl[k]) mycnt = total;
-                    }
-                }
-                wave_lds_sync();
+                for (int m = 0; m < 8; m++) M[m] = p.jmask[jb + so[m]];
+                corner_masks(M, cm);
+                uint64_t n0, n1, n2;
+                mc_ntri_bits(cm, n0, n1, n2);
+                const uint64_t V = valid_cells(vol.g, bx, by, bz);
+                c = 3u * ((uint32_t)__popcll(n0 & V) + 2u * (uint32_t)__popcll(n1 & V) +
+                          4u * (uint32_t)__popcll(n2 & V));
+                p.cnt[idx] = c;
             }
-            if (valid) p.cnt[idx] = mycnt;
+            tot += wave_sum(c);
         }
+        if (l == 0) p.part_wave[wv] = tot;
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 6);
 
-    // ---- phase 6: scan of the counts ------------------------------------------------
-    {
-        uint64_t lo, hi;
-        wg_range(n_list, lo, hi);
-        const uint64_t per = (hi - lo + BT - 1) / BT;
-        const uint64_t a = lo + threadIdx.x * per, z = a + per < hi ? a + per : hi;
-        uint32_t c = 0;
-        for (uint64_t i = a; i < z; i++) c += p.cnt[i];
-        uint32_t excl;
-        uint32_t tot = wg_excl_scan(c, excl, sh.w);
-        if (threadIdx.x == 0) p.part_list[blockIdx.x] = tot;
-        if (!grid_barrier(p.bar, &p.ctr->err)) return;
-        if (blockIdx.x == 0) {
-            uint64_t t = scan_partials(p.part_list, sh.w);
-            if (threadIdx.x == 0) p.ctr->total_verts = t;
-        }
-        if (!grid_barrier(p.bar, &p.ctr->err)) return;
-        uint64_t o = p.part_list[blockIdx.x] + excl;
-        for (uint64_t i = a; i < z; i++) {
-            p.off[i] = o;
-            o += p.cnt[i];
-        }
+    // ---- phase 6: workgroup 0 scans the per-wave counts -------------------------
+    if (blockIdx.x == 0) {
+        const uint64_t t = scan_partials(p.part_wave, gridDim.x * (BT / 64), sh.w64);
+        if (threadIdx.x == 0) p.ctr->total_verts = t;
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 7);
 
-    // ---- phase 7: emission and job offsets -----------------------------------------
+    // ---- phase 7: emission (Sec. 4.5) and the jobs' output offsets --------------
     const uint64_t total = p.ctr->total_verts;
-    for (uint64_t j = gtid; j <= p.n_jobs; j += (uint64_t)gridDim.x * BT) {
-        uint64_t f = j < p.n_jobs ? p.job_first[j] : n_list;
-        p.job_off[j] = f < n_list ? p.off[f] : total;
-    }
-    {
-        uint64_t lo, hi;
-        xcd_wave_range(n_list, lo, hi);
-        for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
-            const uint64_t idx = i0 + l;
-            const bool valid = idx < hi;
-            const uint32_t cnt = valid ? p.cnt[idx] : 0u;
-            const uint32_t e = cnt ? p.list[idx] : 0u;
-            const uint32_t j = cnt ? p.list_job[idx] : 0u;
-            const BatchVol &vol = p.vols[p.job_vol[j]];
-            const uint32_t b = (uint32_t)(e - p.job_jbase[j]);
-            const uint64_t boff = cnt ? p.off[idx] : 0ull;
-            uint32_t so[8], lbx, lby, lbz;
-            octet(vol.g, b, p.I_slot + vol.gbase, 0, so, lbx, lby, lbz);
-            uint64_t todo = __ballot(cnt != 0);
-            while (todo) {
-                int jl[SB], nsb = 0;
+    if (n_list == 0 && blockIdx.x == 0)
+        for (uint32_t j = threadIdx.x; j <= p.n_jobs; j += BT) p.job_off[j] = 0;
+    const LaneGeom q = lane_geom();
+    uint64_t base = p.part_wave[wv];
+    for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
+        const uint64_t idx = i0 + l;
+        const bool valid = idx < hi;
+        const uint32_t c = valid ? p.cnt[idx] : 0u;
+        const uint32_t incl = wave_incl_scan(c);
+        const uint64_t off = base + incl - c;
+        base += __shfl(incl, 63, 64);
+        uint32_t j = 0;
+        if (valid) {
+            j = p.list_job[idx];
+            // first entry of its job: it starts the soups of the jobs since the
+            // previous entry's job (jobs with no entry have empty soups)
+            const uint32_t jp = idx ? p.list_job[idx - 1] : 0u;
+            if (idx == 0 || jp != j)
+                for (uint32_t k = idx ? jp + 1 : 0u; k <= j; k++) p.job_off[k] = off;
+            if (idx + 1 == n_list)
+                for (uint32_t k = j + 1; k <= p.n_jobs; k++) p.job_off[k] = total;
+        }
+        const BatchVol &vol = p.vols[p.job_vol[j]];
+        const float liso = p.job_iso[j];
+        const uint32_t b = c ? (uint32_t)(p.list[idx] - p.job_jbase[j]) : 0u;
+        uint32_t so[8], lbx, lby, lbz;
+        octet(vol.g, b, p.I_slot + vol.gbase, 0, so, lbx, lby, lbz);
+        uint64_t todo = __ballot(c != 0);
+        while (todo) {
+            int jl[SB], nsb = 0;
 #pragma unroll
-                for (int k = 0; k < SB; k++) {
-                    jl[k] = k ? jl[0] : 0;
-                    if (todo) {
-                        jl[k] = (int)__builtin_ctzll(todo);
-                        todo &= todo - 1;
-                        nsb++;
-                    }
+            for (int k = 0; k < SB; k++) {
+                jl[k] = k ? jl[0] : 0;
+                if (todo) {
+                    jl[k] = (int)__builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    nsb++;
                 }
-                stage_batch_n<SB>(q, p.slots, so, jl, sh.emit.tiles[w]);
-                wave_lds_sync();
-                for (int k = 0; k < nsb; k++) {
-                    const uint32_t vj = bcast(p.job_vol[j], jl[k]);
-                    const Geom &g = p.vols[vj].g;
-                    const uint32_t bj = bcast(b, jl[k]);
-                    const float iso = __uint_as_float(bcast(__float_as_uint(p.job_iso[j]), jl[k]));
-                    const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
-                                          bcast((uint32_t)boff, jl[k]);
-                    emit_block<false>(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
-                               sh.emit.tiles[w][k], iso, p.mc_table, sh.emit, w, base,
-                               p.out, p.cap);
-                }
+            }
+            stage_batch_n<SB>(q, p.slots, so, jl, sh.emit.tiles[w]);
+            wave_lds_sync();
+            for (int k = 0; k < nsb; k++) {
+                Geom gk{};
+                gk.nx = bcast(vol.g.nx, jl[k]);
+                gk.ny = bcast(vol.g.ny, jl[k]);
+                gk.nz = bcast(vol.g.nz, jl[k]);
+                const float iso = __uint_as_float(bcast(__float_as_uint(liso), jl[k]));
+                const uint64_t ob = ((uint64_t)bcast((uint32_t)(off >> 32), jl[k]) << 32) |
+                                    bcast((uint32_t)off, jl[k]);
+                emit_block<false>(gk, bcast(b, jl[k]), bcast(lbx, jl[k]), bcast(lby, jl[k]),
+                                  bcast(lbz, jl[k]), sh.emit.tiles[w][k], iso, p.mc_table, sh.emit, w,
+                                  ob, p.out, p.cap);
             }
         }
     }
-    if (!grid_barrier(p.bar, &p.ctr->err)) return;
-    stamp(p, 8);
-    if (gtid == 0) p.ctr->n_slots = n_slots0 + n_new;
+    stamp_last(p, 8);
+}
+
+const void *decode_kernel(int is_f64, int staged) {
+    if (is_f64)
+        return staged ? (const void *)k_batch_decode<true, true> : (const void *)k_batch_decode<true, false>;
+    return staged ? (const void *)k_batch_decode<false, true> : (const void *)k_batch_decode<false, false>;
+}
+
+unsigned decode_lds(const BatchParams &p) {
+    return p.uniform_rate ? stage_lds_bytes((int)p.uniform_rate) : 0u;
 }
 
 }  // namespace
 
-int batch_max_grid(int is_f64, int sb, int *per_cu) {
+int batch_front_per_cu(int *per_cu) {
     int n = 0;
-    hipError_t e;
-    if (is_f64)
-        e = sb == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<true, 4>, BT, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<true, 8>, BT, 0);
-    else
-        e = sb == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<false, 4>, BT, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<false, 8>, BT, 0);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_front, BT, 0) != hipSuccess) return -1;
+    *per_cu = n;
+    return 0;
+}
+
+
+int batch_decode_per_cu(const BatchParams &p, int is_f64, int *per_cu) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, decode_kernel(is_f64, p.uniform_rate != 0), BT,
+                                                     decode_lds(p)) != hipSuccess)
+        return -1;
+    *per_cu = n;
+    return 0;
+}
+
+int batch_back_per_cu(int sb, int *per_cu) {
+    int n = 0;
+    hipError_t e = sb == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_back<4>, BT, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_back<8>, BT, 0);
     if (e != hipSuccess) return -1;
     *per_cu = n;
     return 0;
 }
 
-hipError_t launch_batch(const BatchParams &p, int is_f64, int sb, unsigned grid, hipStream_t s,
-                        int cooperative) {
+hipError_t launch_batch(const BatchParams &p, int is_f64, int sb, const unsigned grids[3],
+                        hipStream_t s, int cooperative) {
     void *args[] = {const_cast<BatchParams *>(&p)};
-    const void *fn;
-    if (is_f64) fn = sb == 4 ? (const void *)k_batch<true, 4> : (const void *)k_batch<true, 8>;
-    else fn = sb == 4 ? (const void *)k_batch<false, 4> : (const void *)k_batch<false, 8>;
-    if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(BT), args, 0, s);
-    return hipLaunchKernel(fn, dim3(grid), dim3(BT), args, 0, s);
+    const void *decode = decode_kernel(is_f64, p.uniform_rate != 0);
+    const void *back = sb == 4 ? (const void *)k_batch_back<4> : (const void *)k_batch_back<8>;
+    hipError_t e;
+    if (cooperative) {
+        e = hipLaunchCooperativeKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT), args, 0, s);
+        if (e == hipSuccess) e = hipLaunchKernel(decode, dim3(grids[1]), dim3(BT), args, decode_lds(p), s);
+        if (e == hipSuccess) e = hipLaunchCooperativeKernel(back, dim3(grids[2]), dim3(BT), args, 0, s);
+        return e;
+    }
+    e = hipLaunchKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT), args, 0, s);
+    if (e == hipSuccess) e = hipLaunchKernel(decode, dim3(grids[1]), dim3(BT), args, decode_lds(p), s);
+    if (e == hipSuccess) e = hipLaunchKernel(back, dim3(grids[2]), dim3(BT), args, 0, s);
+    return e;
 }
 
 }  // namespace bcmc

@@ -12,6 +12,7 @@
 #include "../../include/bcmc.h"
 #include "batch.h"
 #include "common.h"
+#include "zfp_device.h"
 
 using namespace bcmc;
 
@@ -34,7 +35,10 @@ struct bcmc_batch {
     BatchCounters *h_ctr = nullptr;
     uint64_t *h_job_off = nullptr;
     int sb = 8;
-    unsigned grid = 0;
+    unsigned grid = 0;          // back kernel (count, scan, emission)
+    unsigned front_grid = 0;    // front kernel (flags, lists)
+    int front_pc_max = 1;       // its resident workgroups per CU
+    unsigned decode_grid = 0;   // decode kernel (decode, sign masks)
     int per_cu_max = 1, cus = 256;
     // graph replay on a private stream
     hipStream_t gstream = nullptr;
@@ -98,13 +102,17 @@ unsigned grid_for(bcmc_batch *b, int per_cu) {
     return g < 8 ? 8 : g;
 }
 
-int set_schedule(bcmc_batch *b, int sb, int per_cu) {
+// Back kernel: `sb` blocks staged per round trip, `per_cu` workgroups per
+// CU; front kernel: `front_pc` workgroups per CU (both clamped to what stays
+// resident).
+int set_schedule(bcmc_batch *b, int sb, int per_cu, int front_pc) {
     int maxc = 0;
-    if (batch_max_grid(b->is_f64, sb, &maxc) != 0 || maxc < 1)
+    if (batch_back_per_cu(sb, &maxc) != 0 || maxc < 1)
         return binvalid("the batched kernel cannot be made resident");
     b->sb = sb;
     b->per_cu_max = maxc;
     b->grid = grid_for(b, std::min(std::max(per_cu, 1), maxc));
+    b->front_grid = grid_for(b, std::min(std::max(front_pc, 1), b->front_pc_max));
     return BCMC_OK;
 }
 
@@ -122,7 +130,8 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
             drop_graph(b);
             hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t le = launch_batch(b->p, b->is_f64, b->sb, b->grid, b->gstream, 0);
+                const unsigned grids[3] = {b->front_grid, b->decode_grid, b->grid};
+                hipError_t le = launch_batch(b->p, b->is_f64, b->sb, grids, b->gstream, 0);
                 e = hipStreamEndCapture(b->gstream, &b->graph);
                 if (le != hipSuccess) e = le;
             }
@@ -143,7 +152,10 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
             launched = true;
         }
     }
-    if (!launched) BCMC_HIP_TRY(launch_batch(b->p, b->is_f64, b->sb, b->grid, b->gstream, 1));
+    if (!launched) {
+        const unsigned grids[3] = {b->front_grid, b->decode_grid, b->grid};
+        BCMC_HIP_TRY(launch_batch(b->p, b->is_f64, b->sb, grids, b->gstream, 1));
+    }
     BCMC_HIP_TRY(hipEventRecord(b->ev_t1, b->gstream));
     BCMC_HIP_TRY(hipMemcpyAsync(b->h_ctr, b->p.ctr, sizeof(BatchCounters), hipMemcpyDeviceToHost,
                                 b->gstream));
@@ -165,7 +177,7 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
         launch_fill_u32(reinterpret_cast<uint32_t *>(b->p.I_slot), 0xFFFFFFFFu, b->n_gblocks,
                               b->gstream);
         (void)hipMemsetAsync(b->p.ctr, 0, sizeof(BatchCounters), b->gstream);
-        (void)hipMemsetAsync(b->p.bar, 0, 2 * sizeof(unsigned int), b->gstream);
+        (void)hipMemsetAsync(b->p.bar, 0, BAR_WORDS * sizeof(unsigned int), b->gstream);
         (void)hipStreamSynchronize(b->gstream);
         set_error(err & ERR_TIMEOUT ? "a grid barrier of the batched kernel timed out"
                                     : "internal consistency check failed in the batched extraction");
@@ -177,12 +189,12 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
 int reset_cache(bcmc_batch *b, hipStream_t s) {
     launch_fill_u32(reinterpret_cast<uint32_t *>(b->p.I_slot), 0xFFFFFFFFu, b->n_gblocks, s);
     BCMC_HIP_TRY(hipMemsetAsync(b->p.ctr, 0, sizeof(BatchCounters), s));
-    BCMC_HIP_TRY(hipMemsetAsync(b->p.bar, 0, 2 * sizeof(unsigned int), s));
+    BCMC_HIP_TRY(hipMemsetAsync(b->p.bar, 0, BAR_WORDS * sizeof(unsigned int), s));
     return BCMC_OK;
 }
 
 // ---- schedule cache: one JSON object per line, keyed by arch and shape ----
-bool load_schedule(const char *path, const std::string &key, int *sb, int *per_cu) {
+bool load_schedule(const char *path, const std::string &key, int *sb, int *per_cu, int *front_pc) {
     if (!path || !*path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
@@ -192,14 +204,17 @@ bool load_schedule(const char *path, const std::string &key, int *sb, int *per_c
         if (!strstr(line, ("\"key\": \"" + key + "\"").c_str())) continue;
         const char *a = strstr(line, "\"sb\": ");
         const char *c = strstr(line, "\"per_cu\": ");
-        if (a && c && sscanf(a, "\"sb\": %d", sb) == 1 && sscanf(c, "\"per_cu\": %d", per_cu) == 1)
+        const char *f = strstr(line, "\"front_per_cu\": ");
+        if (a && c && f && sscanf(a, "\"sb\": %d", sb) == 1 && sscanf(c, "\"per_cu\": %d", per_cu) == 1 &&
+            sscanf(f, "\"front_per_cu\": %d", front_pc) == 1)
             found = true;
     }
     fclose(f);
     return found;
 }
 
-void save_schedule(const char *path, const std::string &key, int sb, int per_cu, double ms) {
+void save_schedule(const char *path, const std::string &key, int sb, int per_cu, int front_pc,
+                   double ms) {
     if (!path || !*path) return;
     std::vector<std::string> keep;
     if (FILE *f = fopen(path, "r")) {
@@ -210,8 +225,8 @@ void save_schedule(const char *path, const std::string &key, int sb, int per_cu,
     }
     if (FILE *f = fopen(path, "w")) {
         for (auto &l : keep) fputs(l.c_str(), f);
-        fprintf(f, "{\"key\": \"%s\", \"sb\": %d, \"per_cu\": %d, \"ms\": %.4f}\n", key.c_str(), sb,
-                per_cu, ms);
+        fprintf(f, "{\"key\": \"%s\", \"sb\": %d, \"per_cu\": %d, \"front_per_cu\": %d, \"ms\": %.4f}\n",
+                key.c_str(), sb, per_cu, front_pc, ms);
         fclose(f);
     }
 }
@@ -272,13 +287,25 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
         (void)hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
         b->clock_khz = 0;
-    int rc = set_schedule(b, 8, 1 << 30);
+    int pc4 = 0, pcf = 0, pcd = 0;
+    if (batch_back_per_cu(4, &pc4) != 0) pc4 = 0;
+    for (uint32_t v = 0; v < n_vols; v++)
+        b->p.max_vol_jobs = std::max(b->p.max_vol_jobs, hv[v].job_hi - hv[v].job_lo);
+    b->p.uniform_rate = hv[0].rate;
+    for (uint32_t v = 1; v < n_vols; v++)
+        if (hv[v].rate != hv[0].rate) b->p.uniform_rate = 0;
+    if (b->p.uniform_rate > (uint32_t)STAGE_MAX_RATE) b->p.uniform_rate = 0;
+    if (batch_front_per_cu(&pcf) != 0 || pcf < 1 || batch_decode_per_cu(b->p, f64, &pcd) != 0 || pcd < 1) {
+        destroy_batch(b);
+        return binvalid("the batched kernel cannot be made resident");
+    }
+    b->front_pc_max = pcf;
+    b->decode_grid = grid_for(b, pcd);
+    int rc = set_schedule(b, 8, 1 << 30, pcf);
     if (rc) {
         destroy_batch(b);
         return rc;
     }
-    int pc4 = 0;
-    if (batch_max_grid(f64, 4, &pc4) != 0) pc4 = 0;
     unsigned max_grid = (unsigned)(std::max(b->per_cu_max, pc4) * b->cus);
     BatchParams &p = b->p;
     BatchVol *d_vols;
@@ -289,13 +316,15 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
         (rc = balloc(b, &d_jbase, n_jobs)) || (rc = balloc(b, &d_vol_jobs, n_jobs)) ||
         (rc = balloc(b, &d_job_vol, n_jobs)) || (rc = balloc(b, &d_iso, n_jobs)) ||
         (rc = balloc(b, &p.I_slot, gb)) || (rc = balloc(b, &p.slots, gb * 64)) ||
-        (rc = balloc(b, &p.need, gb)) || (rc = balloc(b, &p.emit_flag, jb)) ||
+        (rc = balloc(b, &p.need, gb)) || (rc = balloc(b, &p.emit_flag, (jb + 3) / 4 * 4)) ||
+        (rc = balloc(b, &p.jmask, jb)) ||
         (rc = balloc(b, &p.new_list, gb)) || (rc = balloc(b, &p.list, jb)) ||
-        (rc = balloc(b, &p.list_job, jb)) ||
-        (rc = balloc(b, &p.cnt, jb)) || (rc = balloc(b, &p.off, jb)) ||
-        (rc = balloc(b, &p.part_new, max_grid)) || (rc = balloc(b, &p.part_list, max_grid)) ||
-        (rc = balloc(b, &p.job_first, n_jobs)) || (rc = balloc(b, &p.job_off, n_jobs + 1)) ||
-        (rc = balloc(b, &p.ctr, 1)) || (rc = balloc(b, &p.bar, 2)) ||
+        (rc = balloc(b, &p.list_job, jb)) || (rc = balloc(b, &p.cnt, jb)) ||
+        (rc = balloc(b, &p.part_new, (uint64_t)pcf * b->cus)) ||
+        (rc = balloc(b, &p.part_list, 4ull * pcf * b->cus)) ||
+        (rc = balloc(b, &p.part_wave, 4ull * max_grid)) ||
+        (rc = balloc(b, &p.job_off, n_jobs + 1)) ||
+        (rc = balloc(b, &p.ctr, 1)) || (rc = balloc(b, &p.bar, BAR_WORDS)) ||
         (rc = balloc(b, &p.phase_ts, 9))) {
         destroy_batch(b);
         return rc;
@@ -319,6 +348,7 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
         (e = hipMemcpy(d_job_vol, job_vol, 4 * n_jobs, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(d_iso, job_iso, 4 * n_jobs, hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(d_table, mc_table_host(), 256 * 8, hipMemcpyHostToDevice)) ||
+        (e = hipMemset(p.emit_flag, 0, (jb + 3) / 4 * 4)) ||   // the padding stays zero
         (e = hipHostMalloc((void **)&b->h_ctr, sizeof(BatchCounters), hipHostMallocDefault)) ||
         (e = hipHostMalloc((void **)&b->h_job_off, 8 * (n_jobs + 1), hipHostMallocDefault)) ||
         (e = hipHostMalloc((void **)&b->h_ts, 9 * sizeof(unsigned long long), hipHostMallocDefault)) ||
@@ -347,9 +377,10 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
     snprintf(key, sizeof key, "gfx950|%s|jobs=%u|vols=%u|blocks~2^%d", f64 ? "f64" : "f32", n_jobs,
              n_vols, 64 - __builtin_clzll(jb));
     b->key = key;
-    int sb = 0, per_cu = 0;
-    if (load_schedule(getenv("BCMC_AUTOTUNE_CACHE"), b->key, &sb, &per_cu) && (sb == 4 || sb == 8))
-        (void)set_schedule(b, sb, per_cu);
+    int sb = 0, per_cu = 0, front_pc = 0;
+    if (load_schedule(getenv("BCMC_AUTOTUNE_CACHE"), b->key, &sb, &per_cu, &front_pc) &&
+        (sb == 4 || sb == 8))
+        (void)set_schedule(b, sb, per_cu, front_pc);
     *out = b;
     return BCMC_OK;
 }
@@ -405,39 +436,45 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
         set_error("no memory for the tuning buffer");
         return BCMC_E_NOMEM;
     }
-    int best_sb = b->sb, best_pc = b->per_cu_max;
+    int best_sb = b->sb, best_pc = b->per_cu_max, best_fpc = b->front_pc_max;
     double best = 1e30;
+    std::vector<int> fpcs = {b->front_pc_max, std::max(1, b->front_pc_max / 2)};
+    fpcs.erase(std::unique(fpcs.begin(), fpcs.end()), fpcs.end());
     for (int sb : {4, 8}) {
         int maxc = 0;
-        if (batch_max_grid(b->is_f64, sb, &maxc) != 0 || maxc < 1) continue;
+        if (batch_back_per_cu(sb, &maxc) != 0 || maxc < 1) continue;
         std::vector<int> pcs = {maxc, std::max(1, maxc - 1), std::max(1, maxc / 2)};
         std::sort(pcs.begin(), pcs.end());
         pcs.erase(std::unique(pcs.begin(), pcs.end()), pcs.end());
         for (int pc : pcs) {
-            if ((rc = set_schedule(b, sb, pc))) break;
-            double t = 0;
-            for (int rep = 0; rep < 3 && !rc; rep++) {
-                // cold run (empty batch cache) + warm run
-                if ((rc = reset_cache(b, s)) || (rc = run_once(b, buf, need, s))) break;
-                double cold = b->last_ms;
-                if ((rc = run_once(b, buf, need, s))) break;
-                if (rep) t += cold + b->last_ms;   // the first repetition warms up
+            for (int fpc : fpcs) {
+                if ((rc = set_schedule(b, sb, pc, fpc))) break;
+                double t = 0;
+                for (int rep = 0; rep < 3 && !rc; rep++) {
+                    // cold run (empty batch cache) + warm run
+                    if ((rc = reset_cache(b, s)) || (rc = run_once(b, buf, need, s))) break;
+                    double cold = b->last_ms;
+                    if ((rc = run_once(b, buf, need, s))) break;
+                    if (rep) t += cold + b->last_ms;   // the first repetition warms up
+                }
+                if (rc) break;
+                if (t < best) {
+                    best = t;
+                    best_sb = sb;
+                    best_pc = pc;
+                    best_fpc = fpc;
+                }
             }
             if (rc) break;
-            if (t < best) {
-                best = t;
-                best_sb = sb;
-                best_pc = pc;
-            }
         }
         if (rc) break;
     }
     (void)hipFree(buf);
     if (rc) return rc;
-    rc = set_schedule(b, best_sb, best_pc);
+    rc = set_schedule(b, best_sb, best_pc, best_fpc);
     if (rc) return rc;
     save_schedule(cache_path ? cache_path : getenv("BCMC_AUTOTUNE_CACHE"), b->key, best_sb, best_pc,
-                  best / 4.0);
+                  best_fpc, best / 4.0);
     return reset_cache(b, s);
 }
 
@@ -454,6 +491,7 @@ int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out) {
     out->stage_blocks = (uint32_t)b->sb;
     out->grid = b->grid;
     out->workgroups_per_cu = b->grid / (unsigned)std::max(b->cus, 1);
+    out->front_grid = b->front_grid;
     out->graph = (b->use_graph && !b->graph_failed && b->exec) ? 1 : 0;
     out->graph_unsupported = b->graph_failed;
     out->last_ms = b->last_ms;

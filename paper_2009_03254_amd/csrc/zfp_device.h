@@ -230,30 +230,38 @@ __device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words,
 constexpr int STAGE_STRIDE = 65;
 constexpr int STAGE_MAX_RATE = 16;   // larger rates decode from global memory
 
-__device__ __forceinline__ void stage_words(const uint64_t *__restrict__ stream, int rate, uint64_t b,
-                                            bool valid, uint64_t *st) {
+// `words`: lane l's block's first word (rate words follow); the rate is
+// uniform over the wave.
+__device__ __forceinline__ void stage_words_at(const uint64_t *__restrict__ words, int rate, bool valid,
+                                               uint64_t *st) {
     const int l = (int)__lane_id();
     const uint64_t vmask = __ballot(valid);
-    const uint64_t b0 = __shfl(b, 0, 64);
+    const uint64_t a = reinterpret_cast<uint64_t>(words);
+    const uint64_t a0 = ((uint64_t)__shfl((uint32_t)(a >> 32), 0, 64) << 32) | __shfl((uint32_t)a, 0, 64);
     const bool prefix = (vmask & (vmask + 1)) == 0;   // valid lanes are 0..nv-1
     const bool consecutive = prefix && (vmask & 1) &&
-                             __ballot(valid && b == b0 + (uint64_t)l) == vmask;
+                             __ballot(valid && a == a0 + 8ull * (uint64_t)rate * (uint64_t)l) == vmask;
     if (consecutive) {
         const uint32_t total = (uint32_t)__popcll(vmask) * (uint32_t)rate;
         // i / rate as (i * ceil(2^32 / rate)) >> 32: exact for i < 2^32 / rate
         const uint64_t magic = ((1ull << 32) + (uint64_t)rate - 1) / (uint64_t)rate;
-        const uint64_t *src = stream + b0 * (uint64_t)rate;
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(a0);
         for (uint32_t i = (uint32_t)l; i < total; i += 64) {
             const uint32_t ln = (uint32_t)(((uint64_t)i * magic) >> 32), wd = i - ln * (uint32_t)rate;
             st[wd * STAGE_STRIDE + ln] = src[i];
         }
     } else if (valid) {
-        const uint64_t *src = stream + b * (uint64_t)rate;
-        for (int wd = 0; wd < rate; wd++) st[wd * STAGE_STRIDE + l] = src[wd];
+        for (int wd = 0; wd < rate; wd++) st[wd * STAGE_STRIDE + l] = words[wd];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block b of `stream` for each lane.
+__device__ __forceinline__ void stage_words(const uint64_t *__restrict__ stream, int rate, uint64_t b,
+                                            bool valid, uint64_t *st) {
+    stage_words_at(stream + b * (uint64_t)rate, rate, valid, st);
 }
 
 // Decode lane l's block from the staging area written by stage_words.

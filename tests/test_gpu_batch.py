@@ -123,3 +123,32 @@ def test_batch_capacity_retry(orc):
     verts, offs2 = batch.run()
     assert np.array_equal(offs, offs2)
     batch.close()
+
+
+@pytest.mark.parametrize("rates", [(4, 8, 32), (8, 8, 8)])
+def test_batch_mixed_rates_many_jobs(orc, rates):
+    """Volumes of different rates (the decoder reads each block's words from
+    global memory) or one shared rate (staged through LDS), and a volume with
+    more jobs than the decoder builds masks for in registers."""
+    torch_cuda()
+    import paper_2009_03254_amd as bc
+    dims_list = [(37, 29, 22), (26, 41, 19), (18, 18, 33)]
+    streams, decoded = [], []
+    for k, ((nx, ny, nz), r) in enumerate(zip(dims_list, rates)):
+        f = fields.turbulence(nx, ny, nz, seed=1200 + k, n_modes=32, dtype=np.float32)
+        s = orc.zfp_encode(f, r)
+        streams.append(s)
+        decoded.append(orc.zfp_decode(s, (nx, ny, nz), r, False))
+    vols = [bc.Volume(s, d, "f32", r) for s, d, r in zip(streams, dims_list, rates)]
+    plain = [bc.Volume(s, d, "f32", r) for s, d, r in zip(streams, dims_list, rates)]
+    fld = [orc.blocks_to_field(decoded[v], dims_list[v]) for v in range(3)]
+    jobs = [(0, fields.percentile_iso(fld[0], p)) for p in (10, 25, 40, 55, 70, 85)]
+    jobs += [(1, fields.percentile_iso(fld[1], 50)), (2, fields.percentile_iso(fld[2], 30)),
+             (2, fields.percentile_iso(fld[2], 60))]
+    say(f"[batch] rates {rates}, {len(jobs)} jobs")
+    batch = bc.Batch(vols, jobs)
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
+    assert batch.info()["n_new"] > 0
+    _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)   # warm: masks from the store
+    assert batch.info()["n_new"] == 0
+    batch.close()
