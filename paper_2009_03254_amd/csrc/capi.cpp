@@ -31,7 +31,7 @@ struct bcmc_volume {
     bcmc_stats stats{};
     int profiling = 0;
     int vertex_format = BCMC_VERTEX_F32;  // output records of bcmc_extract
-    uint32_t call = 0;             // extract calls so far (tags masks decoded by a call)
+    uint32_t calls_since_reset = 0;  // bounds the age of every slot used since the reset
     hipEvent_t ev[8] = {};
     int have_extract = 0;
     float last_iso = 0.0f;
@@ -98,7 +98,9 @@ void free_cache(bcmc_volume *v) {
     dev_free(v->d.S_age);
     dev_free(v->d.slots);
     dev_free(v->d.masks);
-    dev_free(v->d.mask_call);
+    dev_free(v->d.mask_iso);
+    dev_free(v->d.slot_or);
+    dev_free(v->d.slot_and);
     for (int i = 0; i < 2; i++) {
         dev_free(v->d.sort_key[i]);
         dev_free(v->d.sort_val[i]);
@@ -162,9 +164,9 @@ int reset_cache_state(bcmc_volume *v, hipStream_t s) {
     launch_fill_u32(reinterpret_cast<uint32_t *>(v->d.I_slot), 0xFFFFFFFFu, v->g.nb, s);
     launch_fill_u32(reinterpret_cast<uint32_t *>(v->d.S_block), 0xFFFFFFFFu, v->max_slots, s);
     launch_fill_u32(v->d.S_age, HIGH_AGE, v->max_slots, s);
-    launch_fill_u32(v->d.mask_call, 0u, v->max_slots, s);
+    launch_fill_u32(v->d.mask_iso, MASK_NONE, v->max_slots, s);
     BCMC_HIP_TRY(hipGetLastError());
-    v->call = 0;
+    v->calls_since_reset = 0;
     v->n_slots = v->init_slots;
     v->have_extract = 0;
     return BCMC_OK;
@@ -185,7 +187,9 @@ int set_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes, hipSt
     if ((rc = dev_alloc(&v->d.S_age, maxs))) return rc;
     if ((rc = dev_alloc(&v->d.slots, maxs * 64))) return rc;
     if ((rc = dev_alloc(&v->d.masks, maxs))) return rc;
-    if ((rc = dev_alloc(&v->d.mask_call, maxs))) return rc;
+    if ((rc = dev_alloc(&v->d.mask_iso, maxs))) return rc;
+    if ((rc = dev_alloc(&v->d.slot_or, (maxs + SLOT_TILE - 1) / SLOT_TILE))) return rc;
+    if ((rc = dev_alloc(&v->d.slot_and, (maxs + SLOT_TILE - 1) / SLOT_TILE))) return rc;
     for (int i = 0; i < 2; i++) {
         if ((rc = dev_alloc(&v->d.sort_key[i], maxs))) return rc;
         if ((rc = dev_alloc(&v->d.sort_val[i], maxs))) return rc;
@@ -361,20 +365,17 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     launch_compact_blocks(v->g, v->d, v->sl, v->identity, s);
     BCMC_HIP_TRY(mark(1));
     if (!v->identity) {
-        launch_slot_pass(v->d, v->sl, v->n_slots, s);
+        if (v->calls_since_reset < 0x7FFFFFFFu) v->calls_since_reset++;
+        const uint32_t age_cap = v->calls_since_reset;   // used slots are younger
+        launch_slot_pass(v->d, v->sl, v->n_slots, age_cap, s);
         launch_plan_grow(v->d, v->max_slots, v->max_slots - v->n_slots, s);
-        launch_radix(v->d, v->sl, v->max_slots, s);
+        launch_radix(v->d, v->sl, v->max_slots, age_cap, s);
     }
     BCMC_HIP_TRY(mark(2));
-    if (++v->call == 0) {   // tags wrapped: forget every tag (0 is never a call's)
-        if (!v->identity) launch_fill_u32(v->d.mask_call, 0u, v->max_slots, s);
-        v->call = 1;
-    }
-    const uint32_t call = v->call;
-    if (!v->identity) launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, iso, call, s);
+    if (!v->identity) launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, iso, s);
     BCMC_HIP_TRY(mark(3));
     const float *slots = v->identity ? v->ext_blocks : v->d.slots;
-    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, call, s);
+    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, s);
     BCMC_HIP_TRY(mark(4));
     launch_scan_counts(v->g, v->d, v->sl, s);
     BCMC_HIP_TRY(mark(5));

@@ -11,8 +11,11 @@ namespace bcmc {
 
 // ---- constants ----------------------------------------------------------
 constexpr uint32_t HIGH_AGE = 0x80000000u;  // age of a slot created empty
+// Tag of a sign mask built for no isovalue: a NaN pattern (isovalues are
+// never NaN, so no call's tag equals it).
+constexpr uint32_t MASK_NONE = 0x7FC00001u;
 constexpr int BLK_TILE = 4096;               // blocks per compaction tile
-constexpr int SLOT_TILE = 1024;              // slots per compaction tile (4 per thread)
+constexpr int SLOT_TILE = 4096;              // slots per compaction tile (16 per thread)
 constexpr int RADIX_TILE = 1024;             // elements per radix tile (1 wave)
 constexpr int SCAN_TILE = 4096;              // u32 per look-back scan tile (16 per thread)
 constexpr int MC_WAVES = 4;                  // blocks (one per wave) per MC tile
@@ -73,7 +76,10 @@ struct DevState {
     uint32_t *S_age = nullptr;
     float *slots = nullptr;         // [max_slots][64] decoded blocks
     uint64_t *masks = nullptr;      // [max_slots] per slot: bit i = sample i below iso
-    uint32_t *mask_call = nullptr;  // [max_slots] call whose iso masks[] holds (set by the decode)
+    uint32_t *slot_or = nullptr;    // [slot tiles] OR / AND of each tile's sort keys
+    uint32_t *slot_and = nullptr;
+    uint32_t *mask_iso = nullptr;   // [max_slots] bits of the isovalue masks[] was built for
+                                    // (MASK_NONE: none)
     uint32_t *sort_key[2] = {nullptr, nullptr};  // ~age of available slots
     uint32_t *sort_val[2] = {nullptr, nullptr};  // slot ids
     uint32_t *radix_hist = nullptr;              // 256 * radix tiles
@@ -97,12 +103,15 @@ void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float
                  uint64_t n_slots_host, hipStream_t s);
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
                            int identity_cache, hipStream_t s);
+// age_cap: exceeds the age of every slot used since the cache was reset.
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
-                      hipStream_t s);
+                      uint32_t age_cap, hipStream_t s);
 void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound, hipStream_t s);
-void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, hipStream_t s);
+// Radix passes over the digits of keys up to age_cap (the others are zero).
+void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, uint32_t age_cap,
+                  hipStream_t s);
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, uint32_t call, hipStream_t s);
+                     int identity_cache, float iso, hipStream_t s);
 void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s);
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                     int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
@@ -123,7 +132,7 @@ void launch_decode_ranges(const Geom &g, const uint64_t *stream, int is_f64, uin
 void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *ranges,
                                unsigned int *err, hipStream_t s);
 void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new, float iso,
-                          uint32_t call, hipStream_t s);
+                          hipStream_t s);
 void launch_encode(const Geom &g, const void *field, int is_f64, uint32_t rate,
                    uint64_t *stream, unsigned int *err, hipStream_t s);
 

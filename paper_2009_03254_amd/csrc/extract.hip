@@ -191,26 +191,31 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
 __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ active,
                                                   const int32_t *__restrict__ S_block,
                                                   uint32_t *__restrict__ S_age, uint64_t n_slots,
-                                                  uint32_t *__restrict__ keys,
-                                                  uint32_t *__restrict__ vals, Counters *ctr,
+                                                  uint32_t age_cap, uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals,
+                                                  uint32_t *__restrict__ part_or,
+                                                  uint32_t *__restrict__ part_and, Counters *ctr,
                                                   uint64_t *status) {
     const uint64_t n_tiles = (n_slots + SLOT_TILE - 1) / SLOT_TILE;
     const uint32_t t = take_tile(&ctr->tile_ctr[TC_SLOT]);
     if (t >= n_tiles) return;
     const bool need_list = ctr->n_new != 0;
     constexpr int PER = SLOT_TILE / 256;   // consecutive slots per thread (16-byte loads)
-    static_assert(PER == 4, "the vector path loads 4 slots per thread");
+    static_assert(PER % 4 == 0, "the vector path loads 4 slots at a time");
     const uint64_t base = (uint64_t)t * SLOT_TILE + threadIdx.x * PER;
     uint32_t availb = 0;
     uint32_t age[PER];
     int32_t blk[PER];
-    uint32_t kor = 0, kand = ~0u;
+    uint32_t kor = 0, kand = ~0u, key[PER];
     const bool full = base + PER <= n_slots;
     if (full) {
-        const int4 bq = *reinterpret_cast<const int4 *>(S_block + base);
-        const uint4 aq = *reinterpret_cast<const uint4 *>(S_age + base);
-        blk[0] = bq.x; blk[1] = bq.y; blk[2] = bq.z; blk[3] = bq.w;
-        age[0] = aq.x; age[1] = aq.y; age[2] = aq.z; age[3] = aq.w;
+#pragma unroll
+        for (int j = 0; j < PER; j += 4) {
+            const int4 bq = *reinterpret_cast<const int4 *>(S_block + base + j);
+            const uint4 aq = *reinterpret_cast<const uint4 *>(S_age + base + j);
+            blk[j] = bq.x; blk[j + 1] = bq.y; blk[j + 2] = bq.z; blk[j + 3] = bq.w;
+            age[j] = aq.x; age[j + 1] = aq.y; age[j + 2] = aq.z; age[j + 3] = aq.w;
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < PER; j++) {
@@ -220,6 +225,7 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
     }
 #pragma unroll
     for (int j = 0; j < PER; j++) {
+        key[j] = 0u;
         if (base + j < n_slots) {
             const bool act = blk[j] >= 0 && active[blk[j]];
             uint32_t a = age[j];
@@ -227,13 +233,20 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
             age[j] = a;
             if (!act) {
                 availb |= 1u << j;
-                kor |= ~a;
-                kand &= ~a;
+                // sort key, ascending = oldest first: slots never used (age
+                // >= HIGH_AGE, created in slot order) before every used one,
+                // used ones by age descending.  age_cap exceeds every used
+                // slot's age, so the keys keep the exact order in few digits.
+                key[j] = a >= HIGH_AGE ? 0u : age_cap - a;
+                kor |= key[j];
+                kand &= key[j];
             }
         }
     }
     if (full) {
-        *reinterpret_cast<uint4 *>(S_age + base) = make_uint4(age[0], age[1], age[2], age[3]);
+#pragma unroll
+        for (int j = 0; j < PER; j += 4)
+            *reinterpret_cast<uint4 *>(S_age + base + j) = make_uint4(age[j], age[j + 1], age[j + 2], age[j + 3]);
     } else {
 #pragma unroll
         for (int j = 0; j < PER; j++)
@@ -245,11 +258,11 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
 #pragma unroll
     for (int j = 0; j < PER; j++)
         if ((availb >> j) & 1u) {
-            keys[e] = ~age[j];
+            keys[e] = key[j];
             vals[e] = (uint32_t)(base + j);
             e++;
         }
-    // OR / AND of the keys: which radix digits vary (one atomic pair per workgroup)
+    // OR / AND of the keys (which radix digits vary), one entry per tile
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         kor |= __shfl_xor(kor, d, 64);
@@ -262,8 +275,8 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicOr(&ctr->key_or, s_or[0] | s_or[1] | s_or[2] | s_or[3]);
-        atomicAnd(&ctr->key_and, s_and[0] & s_and[1] & s_and[2] & s_and[3]);
+        part_or[t] = s_or[0] | s_or[1] | s_or[2] | s_or[3];
+        part_and[t] = s_and[0] & s_and[1] & s_and[2] & s_and[3];
     }
     if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_avail_old = incl_end;
 }
@@ -276,7 +289,9 @@ __global__ __launch_bounds__(256) void k_plan_grow(Counters *ctr, uint64_t max_s
                                                   int32_t *__restrict__ S_block,
                                                   uint32_t *__restrict__ S_age,
                                                   uint32_t *__restrict__ keys,
-                                                  uint32_t *__restrict__ vals) {
+                                                  uint32_t *__restrict__ vals,
+                                                  const uint32_t *__restrict__ part_or,
+                                                  const uint32_t *__restrict__ part_and) {
     const uint64_t n_new = ctr->n_new;
     if (ctr->err || n_new == 0) return;
     const uint64_t na = ctr->n_avail_old, ns = ctr->n_slots_old;
@@ -292,12 +307,32 @@ __global__ __launch_bounds__(256) void k_plan_grow(Counters *ctr, uint64_t max_s
         if (gid == 0) ctr->err |= ERR_CACHE_CAP;
         return;
     }
+    if (blockIdx.x == 0) {   // the keys' OR / AND from the slot pass's tiles
+        const uint64_t n_tiles = (ns + SLOT_TILE - 1) / SLOT_TILE;
+        uint32_t o = 0u, a = ~0u;
+        for (uint64_t i = threadIdx.x; i < n_tiles; i += blockDim.x) {
+            o |= part_or[i];
+            a &= part_and[i];
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            o |= __shfl_xor(o, d, 64);
+            a &= __shfl_xor(a, d, 64);
+        }
+        __shared__ uint32_t s_or[4], s_and[4];
+        if (lane() == 0) {
+            s_or[threadIdx.x >> 6] = o;
+            s_and[threadIdx.x >> 6] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ctr->key_or = s_or[0] | s_or[1] | s_or[2] | s_or[3];
+            ctr->key_and = s_and[0] & s_and[1] & s_and[2] & s_and[3];
+        }
+    }
     if (gid == 0) {
         uint32_t kor = ctr->key_or, kand = ctr->key_and;
-        if (grow) {
-            kor |= ~HIGH_AGE;
-            kand &= ~HIGH_AGE;
-        }
+        if (grow) kand = 0u;   // appended slots: key 0
         uint32_t vary = kor ^ kand;
         uint32_t mask = 0;
         for (int p = 0; p < 4; p++)
@@ -311,7 +346,7 @@ __global__ __launch_bounds__(256) void k_plan_grow(Counters *ctr, uint64_t max_s
         uint64_t s = ns + i;
         S_block[s] = -1;
         S_age[s] = HIGH_AGE;
-        keys[na + i] = ~HIGH_AGE;
+        keys[na + i] = 0u;
         vals[na + i] = (uint32_t)s;
     }
 }
@@ -457,7 +492,7 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
                                               const int32_t *__restrict__ I_slot, int identity,
                                               const float *__restrict__ slots, float iso,
                                               uint64_t *__restrict__ masks,
-                                              const uint32_t *__restrict__ mask_call, uint32_t call,
+                                              uint32_t *__restrict__ mask_iso,
                                               const Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
@@ -466,7 +501,8 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
         const uint32_t b = I_active[i];
         const int32_t s = identity ? (int32_t)b : I_slot[b];
         if (s < 0) continue;
-        if (!identity && mask_call[s] == call) continue;   // decoded (and masked) by this call
+        const uint32_t tag = __float_as_uint(iso);
+        if (!identity && mask_iso[s] == tag) continue;   // built for this isovalue already
         const float4 *src = reinterpret_cast<const float4 *>(slots) + (uint64_t)s * 16;
         float4 v[16];
 #pragma unroll
@@ -479,6 +515,7 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
             m |= nib << (4 * q);
         }
         masks[s] = m;
+        if (!identity) mask_iso[s] = tag;
     }
 }
 
@@ -775,26 +812,29 @@ void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout 
 }
 
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
-                      hipStream_t s) {
+                      uint32_t age_cap, hipStream_t s) {
     if (n_slots_host == 0) return;
     unsigned tiles = (unsigned)((n_slots_host + SLOT_TILE - 1) / SLOT_TILE);
-    k_slot_pass<<<tiles, 256, 0, s>>>(d.active, d.S_block, d.S_age, n_slots_host, d.sort_key[0],
-                                      d.sort_val[0], d.ctr, d.status + sl.slot);
+    k_slot_pass<<<tiles, 256, 0, s>>>(d.active, d.S_block, d.S_age, n_slots_host, age_cap,
+                                      d.sort_key[0], d.sort_val[0], d.slot_or, d.slot_and, d.ctr,
+                                      d.status + sl.slot);
 }
 
 void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound, hipStream_t s) {
     k_plan_grow<<<grid_cap(grow_bound, 2048), 256, 0, s>>>(d.ctr, max_slots, d.S_block, d.S_age,
-                                                          d.sort_key[0], d.sort_val[0]);
+                                                          d.sort_key[0], d.sort_val[0], d.slot_or,
+                                                          d.slot_and);
 }
 
-void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, hipStream_t s) {
+void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, uint32_t age_cap,
+                  hipStream_t s) {
     uint64_t tiles = (max_elems + RADIX_TILE - 1) / RADIX_TILE;
     unsigned grid = (unsigned)((tiles + 3) / 4 < 2048 ? (tiles + 3) / 4 : 2048);
     if (grid == 0) grid = 1;
     uint64_t scan_tiles = (256 * tiles + SCAN_TILE - 1) / SCAN_TILE;
     unsigned sgrid = (unsigned)(scan_tiles < 2048 ? scan_tiles : 2048);
     if (sgrid == 0) sgrid = 1;
-    for (int p = 0; p < 4; p++) {
+    for (int p = 0; p < 4 && (p == 0 || (age_cap >> (8 * p)) != 0); p++) {
         k_radix_hist<<<grid, 256, 0, s>>>(d.ctr, p, d.sort_key[0], d.sort_key[1], d.radix_hist,
                                           d.status + sl.scan);
         k_radix_scan<<<sgrid, 256, 0, s>>>(d.ctr, p, d.radix_hist, d.status + sl.scan);
@@ -830,12 +870,12 @@ static unsigned mc_grid(uint64_t max_blocks) {
 }
 
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, uint32_t call, hipStream_t s) {
+                     int identity_cache, float iso, hipStream_t s) {
     static unsigned mgrid = 0, cgrid = 0;
     if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
     if (!cgrid) cgrid = resident_grid(k_mc_count, ~0ull >> 4);
     k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
-        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_call, call, d.ctr);
+        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_iso, d.ctr);
     k_mc_count<<<std::min<unsigned>(cgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
         g, d.I_active, d.active, I_slot, identity_cache, d.masks, d.blk_cnt, d.ctr);
 }

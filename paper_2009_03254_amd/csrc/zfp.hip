@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
                                                       int rate, float *__restrict__ slots,
                                                       uint64_t n_blocks, float iso,
                                                       uint64_t *__restrict__ masks,
-                                                      uint32_t *__restrict__ mask_call, uint32_t call) {
+                                                      uint32_t *__restrict__ mask_iso) {
     if (ctr->err) return;
     const uint64_t n_slots = ctr->n_slots;
     const uint64_t n_new = ctr->n_new;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
                            (f.w < iso ? 8u : 0u)) << (4 * (q & 7));
         }
         masks[s] = (uint64_t)mw[1] << 32 | mw[0];
-        mask_call[s] = call;
+        mask_iso[s] = __float_as_uint(iso);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) evicted += __shfl_xor(evicted, d, 64);   // one atomic per wave
@@ -232,11 +232,11 @@ void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *range
 }
 
 void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new, float iso,
-                          uint32_t call, hipStream_t s) {
+                          hipStream_t s) {
     unsigned grid = grid_for(max_new, 2048);
     BCMC_DECODE_LAUNCH(k_assign_decode, grid, rate, s, d.ctr, d.I_new, d.sort_val[0], d.sort_val[1],
                        d.S_block, d.I_slot, d.S_age, d.stream, (int)rate, d.slots, max_new, iso,
-                       d.masks, d.mask_call, call);
+                       d.masks, d.mask_iso);
 }
 
 void launch_encode(const Geom &g, const void *field, int is_f64, uint32_t rate, uint64_t *stream,
