@@ -579,18 +579,21 @@ __global__ __launch_bounds__(BT, 6) void k_batch_back(BatchParams p) {
             }
             stage_batch_n<SB>(q, p.slots, so, jl, sh.emit.tiles[w]);
             wave_lds_sync();
-            for (int k = 0; k < nsb; k++) {
-                Geom gk{};
+            // consecutive entries of L with triangles: adjacent vertex ranges
+            const uint64_t ob = ((uint64_t)bcast((uint32_t)(off >> 32), jl[0]) << 32) |
+                                bcast((uint32_t)off, jl[0]);
+            auto info = [&](int k, Geom &gk, uint32_t &bk, uint32_t &bx, uint32_t &by, uint32_t &bz,
+                            float &isok) {
                 gk.nx = bcast(vol.g.nx, jl[k]);
                 gk.ny = bcast(vol.g.ny, jl[k]);
                 gk.nz = bcast(vol.g.nz, jl[k]);
-                const float iso = __uint_as_float(bcast(__float_as_uint(liso), jl[k]));
-                const uint64_t ob = ((uint64_t)bcast((uint32_t)(off >> 32), jl[k]) << 32) |
-                                    bcast((uint32_t)off, jl[k]);
-                emit_block<false>(gk, bcast(b, jl[k]), bcast(lbx, jl[k]), bcast(lby, jl[k]),
-                                  bcast(lbz, jl[k]), sh.emit.tiles[w][k], iso, p.mc_table, sh.emit, w,
-                                  ob, p.out, p.cap);
-            }
+                bk = bcast(b, jl[k]);
+                bx = bcast(lbx, jl[k]);
+                by = bcast(lby, jl[k]);
+                bz = bcast(lbz, jl[k]);
+                isok = __uint_as_float(bcast(__float_as_uint(liso), jl[k]));
+            };
+            emit_batch<false>(nsb, info, sh.emit.tiles[w], p.mc_table, sh.emit, w, ob, p.out, p.cap);
         }
     }
     stamp_last(p, 8);

@@ -479,9 +479,13 @@ constexpr uint64_t edge_lut(bool tile_offset) {
 }
 constexpr uint64_t kEdgeGeom = edge_lut(false), kEdgeTile = edge_lut(true);
 
+constexpr int EMIT_TRIS = 64 * 5;   // a wave's triangle list (one block's maximum)
+
 struct EmitShared {
     float tiles[MC_WAVES][MC_SB][128];
-    uint32_t tri[MC_WAVES][64 * 5];  // per triangle: cell | its 3 edge ids << 6
+    uint32_t tri[MC_WAVES][EMIT_TRIS];  // per triangle: cell | 3 edge ids << 6 | staged block << 18
+    uint32_t blk[MC_WAVES][MC_SB];      // block id of each staged block
+    float iso[MC_WAVES][MC_SB];         // its isovalue
 };
 
 }  // namespace
@@ -542,6 +546,90 @@ __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t b
         }
     }
     wave_lds_sync();
+}
+
+// Emission (Sec. 4.5) of the nsb blocks staged in tiles[0..nsb), whose
+// vertex ranges follow each other in the output from `base` on (records past
+// `cap` dropped).  Per block: the cases of its cells, an exclusive scan of
+// their triangle counts and one record per triangle (cell, 3 edge ids, staged
+// block) appended to the wave's list; when the next block would overflow the
+// list, and after the last, one lane-per-vertex loop writes the listed
+// triangles in canonical order (block, cell, triangle, vertex).
+// info(k, g, b, bx, by, bz, iso) gives block k's volume geometry, id, block
+// coordinates and isovalue (wave-uniform).
+// EDGE8: 8-byte records block | cell << 32 | edge << 38 | q << 42 with
+// q = min(trunc(t * 2^22), 2^22 - 1); otherwise 16-byte records
+// {f32 x, y, z block-relative; u32 block}.
+template <bool EDGE8, class Info>
+__device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*tiles)[128],
+                                           const uint64_t *__restrict__ mc_table, EmitShared &sh,
+                                           int w, uint64_t base, void *__restrict__ out,
+                                           uint64_t cap) {
+    const int l = lane();
+    uint32_t run = 0;   // triangles listed
+    auto flush = [&]() {
+        wave_lds_sync();
+        const int total = 3 * (int)run;
+        for (int j = l; j < total; j += 64) {
+            const int t = (j * 43691) >> 17;               // j / 3 for j < 3 * EMIT_TRIS
+            const uint32_t rec = sh.tri[w][t];
+            const int c = (int)(rec & 63u);
+            const int e = (int)((rec >> (6 + 4 * (j - 3 * t))) & 15u);
+            const int k = (int)(rec >> 18);
+            const float *tile = tiles[k];
+            const uint32_t d = (uint32_t)(kEdgeGeom >> (5 * e)) & 31u;
+            const int axis = (int)(d >> 3);
+            const int cx = c & 3, cy = (c >> 2) & 3, cz = c >> 4;
+            const int i0 = tix(cx, cy, cz) + (int)((kEdgeTile >> (5 * e)) & 31u);
+            const int i1 = i0 + (int)((0x190501u >> (8 * axis)) & 0xFFu);   // +1 / +5 / +25
+            const float a = tile[i0];
+            const float bv = tile[i1];
+            const float iso = sh.iso[w][k];
+            const uint32_t b = sh.blk[w][k];
+            const float tt = (iso - a) / (bv - a);
+            const uint64_t o = base + (uint64_t)j;
+            if (EDGE8) {
+                uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
+                qt = qt < 4194303u ? qt : 4194303u;
+                const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
+                if (o < cap) reinterpret_cast<uint64_t *>(out)[o] = r;
+            } else {
+                // the edge's first corner plus t along its axis (adding 0 to the
+                // other two coordinates leaves them exact)
+                const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
+                const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
+                const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
+                if (o < cap)
+                    reinterpret_cast<uint4 *>(out)[o] =
+                        make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+            }
+        }
+        base += (uint64_t)total;
+        run = 0;
+        wave_lds_sync();
+    };
+    for (int k = 0; k < nsb; k++) {
+        Geom g;
+        uint32_t b, bx, by, bz;
+        float iso;
+        info(k, g, b, bx, by, bz, iso);
+        const int cs = tile_case(g, bx, by, bz, tiles[k], iso);
+        const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table, L1-resident
+        const uint32_t nt = (uint32_t)(tb >> 60);
+        const uint32_t incl = wave_incl_scan(nt);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        if (run + tot > (uint32_t)EMIT_TRIS) flush();
+        if (l == 0) {
+            sh.blk[w][k] = b;
+            sh.iso[w][k] = iso;
+        }
+        for (uint32_t t = 0; t < nt; t++)
+            sh.tri[w][run + incl - nt + t] =
+                (uint32_t)l | ((uint32_t)(tb >> (12 * t)) & 0xFFFu) << 6 | (uint32_t)k << 18;
+        run += tot;
+    }
+    if (run) flush();
+    else wave_lds_sync();   // the caller restages the tiles next
 }
 
 }  // namespace
