@@ -122,6 +122,7 @@ void layout_status(bcmc_volume *v) {
 int alloc_common(bcmc_volume *v) {
     int rc;
     if ((rc = dev_alloc(&v->d.ranges, v->g.nb))) return rc;
+    if ((rc = dev_alloc(&v->d.tile_ranges, cull_tiles(v->g)))) return rc;
     if ((rc = dev_alloc(&v->d.active, v->g.nb + 16))) return rc;
     if ((rc = dev_alloc(&v->d.I_active, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_cnt, v->g.nb))) return rc;
@@ -144,6 +145,7 @@ void destroy(bcmc_volume *v) {
     free_cache(v);
     dev_free(v->d.stream);
     dev_free(v->d.ranges);
+    dev_free(v->d.tile_ranges);
     dev_free(v->d.active);
     dev_free(v->d.I_active);
     dev_free(v->d.I_new);
@@ -257,6 +259,7 @@ int bcmc_load_compressed(const void *stream, uint64_t nbytes, int stream_is_devi
         return BCMC_E_HIP;
     }
     launch_decode_ranges(g, v->d.stream, v->is_f64, rate, v->d.ranges, nullptr, &v->d.ctr->err, s);
+    launch_tile_ranges(g, v->d.ranges, v->d.tile_ranges, s);
     if ((rc = sync_counters(v, s))) {
         destroy(v);
         return rc;
@@ -301,6 +304,7 @@ int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uin
         return BCMC_E_HIP;
     }
     launch_ranges_from_blocks(v->g, d_blocks, v->d.ranges, &v->d.ctr->err, s);
+    launch_tile_ranges(v->g, v->d.ranges, v->d.tile_ranges, s);
     if ((rc = sync_counters(v, s))) {
         destroy(v);
         return rc;
@@ -321,6 +325,7 @@ int bcmc_rebind_blocks(bcmc_volume *v, const float *d_blocks, void *hip_stream) 
     v->ext_blocks = d_blocks;
     v->have_extract = 0;
     launch_ranges_from_blocks(v->g, d_blocks, v->d.ranges, &v->d.ctr->err, as_stream(hip_stream));
+    launch_tile_ranges(v->g, v->d.ranges, v->d.tile_ranges, as_stream(hip_stream));
     BCMC_HIP_TRY(hipGetLastError());
     return BCMC_OK;
 }
@@ -361,7 +366,7 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     const bool prof = v->profiling;
     auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(v->ev[i], s) : hipSuccess; };
     BCMC_HIP_TRY(mark(0));
-    launch_cull(v->g, v->d, v->sl, iso, v->n_slots, s);
+    launch_cull(v->g, v->d, v->sl, iso, v->n_slots, v->identity, s);
     launch_compact_blocks(v->g, v->d, v->sl, v->identity, s);
     BCMC_HIP_TRY(mark(1));
     if (!v->identity) {
@@ -496,6 +501,7 @@ int bcmc_decode_all(bcmc_volume *v, float *d_blocks, void *hip_stream) {
     if (v->identity) return invalid("identity volumes hold no compressed stream");
     launch_decode_ranges(v->g, v->d.stream, v->is_f64, v->rate, v->d.ranges, d_blocks,
                          &v->d.ctr->err, as_stream(hip_stream));
+    launch_tile_ranges(v->g, v->d.ranges, v->d.tile_ranges, as_stream(hip_stream));
     BCMC_HIP_TRY(hipGetLastError());
     return BCMC_OK;
 }

@@ -67,6 +67,7 @@ struct Geom {
 struct DevState {
     uint64_t *stream = nullptr;     // fixed-rate ZFP words, block b at b*rate
     float2 *ranges = nullptr;       // per block (min, max) of decoded valid samples
+    float2 *tile_ranges = nullptr;  // per cull tile: hull of its blocks' and halo's ranges
     uint8_t *active = nullptr;      // M_active
     uint32_t *I_active = nullptr;   // ascending active block ids
     uint32_t *I_new = nullptr;      // ascending new block ids
@@ -100,7 +101,7 @@ struct StatusLayout {
 
 // ---- launchers (extract.hip) -------------------------------------------
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
-                 uint64_t n_slots_host, hipStream_t s);
+                 uint64_t n_slots_host, int identity_cache, hipStream_t s);
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
                            int identity_cache, hipStream_t s);
 // age_cap: exceeds the age of every slot used since the cache was reset.
@@ -129,6 +130,10 @@ void launch_iota_i32(int32_t *p, uint64_t n, hipStream_t s);
 // ---- launchers (zfp.hip) -----------------------------------------------
 void launch_decode_ranges(const Geom &g, const uint64_t *stream, int is_f64, uint32_t rate,
                           float2 *ranges, float *blocks_out, unsigned int *err, hipStream_t s);
+// Hull of the ranges over each cull tile and its one-block halo (after every
+// change of the ranges).
+uint64_t cull_tiles(const Geom &g);
+void launch_tile_ranges(const Geom &g, const float2 *ranges, float2 *tile_ranges, hipStream_t s);
 void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *ranges,
                                unsigned int *err, hipStream_t s);
 void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new, float iso,

@@ -34,7 +34,47 @@ namespace {
 // the sweep.
 constexpr int CULL_TX = 32, CULL_TY = 8, CULL_TZ = 8;
 
+// Hull of the ranges over a tile's box with its one-block halo (clipped to
+// the volume), one workgroup per tile, at load.  When the hull does not
+// straddle iso, no block of the tile can be active: every block's
+// neighbourhood range lies inside it.
+__global__ __launch_bounds__(256) void k_tile_ranges(Geom g, const float2 *__restrict__ ranges,
+                                                    float2 *__restrict__ tile_ranges) {
+    constexpr int RX = CULL_TX + 2, RY = CULL_TY + 2, RZ = CULL_TZ + 2;
+    const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
+    uint32_t t = blockIdx.x;
+    const uint32_t tx = t % ntx;
+    t /= ntx;
+    const uint32_t ty = t % nty, tz = t / nty;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int i = threadIdx.x; i < RX * RY * RZ; i += 256) {
+        const int hz = i / (RX * RY), r = i - hz * RX * RY, hy = r / RX, hx = r - hy * RX;
+        const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1,
+                  z = (int)(tz * CULL_TZ) + hz - 1;
+        if (x >= 0 && x < (int)g.nbx && y >= 0 && y < (int)g.nby && z >= 0 && z < (int)g.nbz) {
+            const float2 q = ranges[((uint64_t)z * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
+            lo = fminf(lo, q.x);
+            hi = fmaxf(hi, q.y);
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+    }
+    __shared__ float2 s_h[4];
+    if (lane() == 0) s_h[threadIdx.x >> 6] = make_float2(lo, hi);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        tile_ranges[blockIdx.x] = make_float2(fminf(fminf(s_h[0].x, s_h[1].x), fminf(s_h[2].x, s_h[3].x)),
+                                              fmaxf(fmaxf(s_h[0].y, s_h[1].y), fmaxf(s_h[2].y, s_h[3].y)));
+}
+
+// Flags per block: bit 0 active, bit 1 may emit, bit 2 active without a
+// slot (new, Alg. 1 MarkNewBlocks; never set for an identity cache).
 __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
+                                             const float2 *__restrict__ tile_ranges,
+                                             const int32_t *__restrict__ I_slot, int identity,
                                              uint8_t *__restrict__ active, Counters *ctr,
                                              uint64_t n_slots_host, uint64_t *status,
                                              uint64_t status_words) {
@@ -58,6 +98,22 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
     t /= ntx;
     const uint32_t ty = t % nty, tz = t / nty;
     const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+    const float2 hull = tile_ranges[blockIdx.x];
+    if (!(hull.x < iso && iso <= hull.y)) {   // no block of the tile is active
+        static_assert(CULL_TX == 32 && CULL_TY * CULL_TZ * 2 <= 256, "one 16-byte store per half row");
+        if (g.nbx % 16 == 0) {   // rows start 16-byte aligned: two stores per tile row
+            const int r = threadIdx.x >> 1, y = (int)(ty * CULL_TY) + r % CULL_TY, z = z0 + r / CULL_TY;
+            const uint32_t x = tx * CULL_TX + 16 * (threadIdx.x & 1);
+            if (threadIdx.x < 2 * CULL_TY * CULL_TZ && y < (int)g.nby && z < z1 && x < g.nbx)
+                *reinterpret_cast<uint4 *>(active + ((uint64_t)z * g.nby + (uint32_t)y) * g.nbx + x) =
+                    make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            const uint32_t bx = tx * CULL_TX + threadIdx.x % CULL_TX, by = ty * CULL_TY + threadIdx.x / CULL_TX;
+            if (bx < g.nbx && by < g.nby)
+                for (int z = z0; z < z1; z++) active[((uint64_t)z * g.nby + by) * g.nbx + bx] = 0;
+        }
+        return;
+    }
 #pragma unroll 4
     for (int i = threadIdx.x; i < NL * SLOTS; i += 256) {
         const int li = i / SLOTS, r = i - li * SLOTS;
@@ -102,8 +158,9 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
             // "can emit": the hull of the 2x2x2 group headed by the block
             // contains iso (implies act, as that group contains the block)
             const bool can_emit = PLO < iso && iso <= PHI;
-            active[((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx] =
-                (act ? 1u : 0u) | (can_emit ? 2u : 0u);
+            const uint64_t b = ((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx;
+            const bool fresh = act && !identity && I_slot[b] < 0;
+            active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u) | (fresh ? 4u : 0u);
         }
         l3a = l3b;
         h3a = h3b;
@@ -116,11 +173,11 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
 }
 
 // I_active (StreamCompactIDs of M_active) and I_new (active blocks without a
-// slot, Alg. 1 MarkNewBlocks) in one look-back pass over the blocks.  Counts
-// are packed as (active << 31 | new) so one status word carries both.
+// slot, Alg. 1 MarkNewBlocks, flagged by the cull) in one look-back pass over
+// the blocks.  Counts are packed as (active << 31 | new) so one status word
+// carries both.
 __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *__restrict__ active,
-                                                       const int32_t *__restrict__ I_slot,
-                                                       int identity, uint32_t *__restrict__ I_active,
+                                                       uint32_t *__restrict__ I_active,
                                                        uint32_t *__restrict__ I_new, Counters *ctr,
                                                        uint32_t *__restrict__ part_cand,
                                                        uint64_t *status, uint32_t m) {
@@ -132,6 +189,7 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
     if (t >= n_tiles) return;
     const uint64_t lo = t * tile_blocks + (uint64_t)threadIdx.x * 16u * m;
     uint32_t nact = 0, nnew = 0, cand = 0;
+    uint64_t any[2] = {0ull, 0ull};   // chunks holding an active block (m <= 128)
     for (uint32_t c0 = 0; c0 < m; c0 += 4) {
         uint4 q[4];   // 4 chunks of 16 flags in flight together
 #pragma unroll
@@ -148,7 +206,6 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
         }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const uint64_t base = lo + 16u * (c0 + k);
             const uint32_t wds[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
             uint32_t actb = 0;
 #pragma unroll
@@ -156,10 +213,10 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
                 const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
                 if (f) actb |= 1u << j;
                 cand += (f >> 1) & 1u;
+                nnew += (f >> 2) & 1u;
             }
             nact += __popc(actb);
-            if (!identity)
-                for (uint32_t mm = actb; mm; mm &= mm - 1) nnew += I_slot[base + __builtin_ctz(mm)] < 0;
+            if (actb && c0 + k < 128) any[(c0 + k) >> 6] |= 1ull << ((c0 + k) & 63);
         }
     }
     cand = wg_sum_u32(cand);
@@ -168,15 +225,30 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
     uint64_t e = tile_scan_lookback(((uint64_t)nact << 31) | (uint64_t)nnew, status, t, &incl_end);
     uint64_t oa = e >> 31, on = e & 0x7FFFFFFFull;
     if (nact) {
+        // revisit only the chunks with an active block, 16 flags per load
         for (uint32_t c = 0; c < m; c++) {
+            if (c < 128 && !((any[c >> 6] >> (c & 63)) & 1ull)) continue;
             const uint64_t base = lo + 16u * c;
-            for (int j = 0; j < 16; j++) {
-                const uint64_t b = base + j;
-                if (b < g.nb && active[b]) {
-                    I_active[oa++] = (uint32_t)b;
-                    if (!identity && I_slot[b] < 0) I_new[on++] = (uint32_t)b;
+            uint32_t actb = 0, newb = 0;
+            if (base + 16 <= g.nb) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(active + base);
+                const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+                    if (f) actb |= 1u << j;
+                    newb |= ((f >> 2) & 1u) << j;
                 }
+            } else {
+                for (int j = 0; j < 16; j++)
+                    if (base + j < g.nb) {
+                        const uint32_t f = active[base + j];
+                        if (f) actb |= 1u << j;
+                        newb |= ((f >> 2) & 1u) << j;
+                    }
             }
+            for (uint32_t mm = actb; mm; mm &= mm - 1) I_active[oa++] = (uint32_t)(base + __builtin_ctz(mm));
+            for (uint32_t mm = newb; mm; mm &= mm - 1) I_new[on++] = (uint32_t)(base + __builtin_ctz(mm));
         }
     }
     if (t == n_tiles - 1 && threadIdx.x == 0) {
@@ -796,19 +868,28 @@ unsigned grid_cap(uint64_t n_threads, unsigned cap) {
 }  // namespace
 
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
-                 uint64_t n_slots_host, hipStream_t s) {
+                 uint64_t n_slots_host, int identity_cache, hipStream_t s) {
     const uint64_t tiles = (uint64_t)((g.nbx + CULL_TX - 1) / CULL_TX) *
                            ((g.nby + CULL_TY - 1) / CULL_TY) * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
-    k_cull<<<(unsigned)tiles, 256, 0, s>>>(g, d.ranges, iso, d.active, d.ctr, n_slots_host,
-                                           d.status, sl.total);
+    k_cull<<<(unsigned)tiles, 256, 0, s>>>(g, d.ranges, iso, d.tile_ranges, d.I_slot, identity_cache,
+                                           d.active, d.ctr, n_slots_host, d.status, sl.total);
+}
+
+uint64_t cull_tiles(const Geom &g) {
+    return (uint64_t)((g.nbx + CULL_TX - 1) / CULL_TX) * ((g.nby + CULL_TY - 1) / CULL_TY) *
+           ((g.nbz + CULL_TZ - 1) / CULL_TZ);
+}
+
+void launch_tile_ranges(const Geom &g, const float2 *ranges, float2 *tile_ranges, hipStream_t s) {
+    k_tile_ranges<<<(unsigned)cull_tiles(g), 256, 0, s>>>(g, ranges, tile_ranges);
 }
 
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
                            int identity_cache, hipStream_t s) {
     const uint32_t m = compact_blocks_per_thread16(g.nb);
     const uint64_t tiles = (g.nb + (uint64_t)BLK_TILE * m - 1) / ((uint64_t)BLK_TILE * m);
-    k_compact_blocks<<<(unsigned)tiles, 256, 0, s>>>(g, d.active, d.I_slot, identity_cache, d.I_active,
-                                                     d.I_new, d.ctr, d.part_cand, d.status + sl.blk, m);
+    k_compact_blocks<<<(unsigned)tiles, 256, 0, s>>>(g, d.active, d.I_active, d.I_new, d.ctr,
+                                                     d.part_cand, d.status + sl.blk, m);
 }
 
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
