@@ -92,164 +92,197 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
 
     constexpr int NL = CULL_TZ + 2, RX = CULL_TX + 2, RY = CULL_TY + 2, SLOTS = RX * RY;
     __shared__ float2 sh[NL][RY][RX];
+    __shared__ uint32_t live[256];
+    __shared__ uint32_t n_live;
     const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
-    uint32_t t = blockIdx.x;
-    const uint32_t tx = t % ntx;
-    t /= ntx;
-    const uint32_t ty = t % nty, tz = t / nty;
-    const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
-    const float2 hull = tile_ranges[blockIdx.x];
-    if (!(hull.x < iso && iso <= hull.y)) {   // no block of the tile is active
-        static_assert(CULL_TX == 32 && CULL_TY * CULL_TZ * 2 <= 256, "one 16-byte store per half row");
-        if (g.nbx % 16 == 0) {   // rows start 16-byte aligned: two stores per tile row
-            const int r = threadIdx.x >> 1, y = (int)(ty * CULL_TY) + r % CULL_TY, z = z0 + r / CULL_TY;
-            const uint32_t x = tx * CULL_TX + 16 * (threadIdx.x & 1);
-            if (threadIdx.x < 2 * CULL_TY * CULL_TZ && y < (int)g.nby && z < z1 && x < g.nbx)
-                *reinterpret_cast<uint4 *>(active + ((uint64_t)z * g.nby + (uint32_t)y) * g.nbx + x) =
-                    make_uint4(0u, 0u, 0u, 0u);
-        } else {
-            const uint32_t bx = tx * CULL_TX + threadIdx.x % CULL_TX, by = ty * CULL_TY + threadIdx.x / CULL_TX;
-            if (bx < g.nbx && by < g.nby)
-                for (int z = z0; z < z1; z++) active[((uint64_t)z * g.nby + by) * g.nbx + bx] = 0;
+    const uint64_t n_tiles = (uint64_t)ntx * nty * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
+    // The workgroup's tiles are blockIdx.x + gridDim.x * i; their hulls are
+    // read 256 at a time, and only the tiles whose hull straddles iso are
+    // culled block by block (the flags of the others were cleared before
+    // this kernel)
+    const uint64_t G = gridDim.x;
+    for (uint64_t i0 = 0; blockIdx.x + G * i0 < n_tiles; i0 += 256) {
+        if (threadIdx.x == 0) n_live = 0;
+        __syncthreads();
+        const uint64_t ti = blockIdx.x + G * (i0 + threadIdx.x);
+        if (ti < n_tiles) {
+            const float2 hull = tile_ranges[ti];
+            if (hull.x < iso && iso <= hull.y) live[atomicAdd(&n_live, 1u)] = (uint32_t)ti;
         }
-        return;
-    }
+        __syncthreads();
+        const uint32_t nl = n_live;
+        for (uint32_t k = 0; k < nl; k++) {
+            uint32_t t = live[k];
+            const uint32_t tx = t % ntx;
+            t /= ntx;
+            const uint32_t ty = t % nty, tz = t / nty;
+            const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
 #pragma unroll 4
-    for (int i = threadIdx.x; i < NL * SLOTS; i += 256) {
-        const int li = i / SLOTS, r = i - li * SLOTS;
-        const int hy = r / RX, hx = r - hy * RX;
-        const int zl = z0 - 1 + li;
-        const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
-        float2 v = make_float2(INFINITY, -INFINITY);
-        if (zl >= 0 && zl < (int)g.nbz && zl <= z1 && x >= 0 && x < (int)g.nbx && y >= 0 && y < (int)g.nby)
-            v = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
-        sh[li][hy][hx] = v;
-    }
-    __syncthreads();
-
-    const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
-    const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
-    if (bx >= g.nbx || by >= g.nby) return;
-    // per layer: 3x3 min / max, 2x2 positive min / max, own range
-    float l3a = INFINITY, h3a = -INFINITY;                       // layer zl - 2
-    float l3b = INFINITY, h3b = -INFINITY, p2lb = INFINITY, p2hb = -INFINITY;
-    float2 ownb = make_float2(INFINITY, -INFINITY);             // layer zl - 1
-    for (int li = 0; li < NL; li++) {
-        const int zl = z0 - 1 + li;
-        if (zl > z1) break;
-        float l3 = INFINITY, h3 = -INFINITY, p2l = INFINITY, p2h = -INFINITY;
+            for (int i = threadIdx.x; i < NL * SLOTS; i += 256) {
+                const int li = i / SLOTS, r = i - li * SLOTS;
+                const int hy = r / RX, hx = r - hy * RX;
+                const int zl = z0 - 1 + li;
+                const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
+                float2 v = make_float2(INFINITY, -INFINITY);
+                if (zl >= 0 && zl < (int)g.nbz && zl <= z1 && x >= 0 && x < (int)g.nbx && y >= 0 &&
+                    y < (int)g.nby)
+                    v = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
+                sh[li][hy][hx] = v;
+            }
+            __syncthreads();
+            const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
+            const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
+            if (bx < g.nbx && by < g.nby) {
+                // per layer: 3x3 min / max, 2x2 positive min / max, own range
+                float l3a = INFINITY, h3a = -INFINITY;                       // layer zl - 2
+                float l3b = INFINITY, h3b = -INFINITY, p2lb = INFINITY, p2hb = -INFINITY;
+                float2 ownb = make_float2(INFINITY, -INFINITY);             // layer zl - 1
+                for (int li = 0; li < NL; li++) {
+                    const int zl = z0 - 1 + li;
+                    if (zl > z1) break;
+                    float l3 = INFINITY, h3 = -INFINITY, p2l = INFINITY, p2h = -INFINITY;
 #pragma unroll
-        for (int dy = -1; dy <= 1; dy++)
+                    for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
-            for (int dx = -1; dx <= 1; dx++) {
-                const float2 q = sh[li][ly + 1 + dy][lx + 1 + dx];
-                l3 = fminf(l3, q.x);
-                h3 = fmaxf(h3, q.y);
-                if (dx >= 0 && dy >= 0) {
-                    p2l = fminf(p2l, q.x);
-                    p2h = fmaxf(p2h, q.y);
+                        for (int dx = -1; dx <= 1; dx++) {
+                            const float2 q = sh[li][ly + 1 + dy][lx + 1 + dx];
+                            l3 = fminf(l3, q.x);
+                            h3 = fmaxf(h3, q.y);
+                            if (dx >= 0 && dy >= 0) {
+                                p2l = fminf(p2l, q.x);
+                                p2h = fmaxf(p2h, q.y);
+                            }
+                        }
+                    const float2 own = sh[li][ly + 1][lx + 1];
+                    if (zl > z0) {   // layer zl - 1 has both z neighbours now
+                        const float LO = fminf(l3a, fminf(l3b, l3)), HI = fmaxf(h3a, fmaxf(h3b, h3));
+                        const float PLO = fminf(p2lb, p2l), PHI = fmaxf(p2hb, p2h);
+                        const bool act = (ownb.x < iso && iso <= HI) || (LO < iso && iso <= ownb.y);
+                        // "can emit": the hull of the 2x2x2 group headed by the block
+                        // contains iso (implies act, as that group contains the block)
+                        const bool can_emit = PLO < iso && iso <= PHI;
+                        const uint64_t b = ((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx;
+                        const bool fresh = act && !identity && I_slot[b] < 0;
+                        active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u) | (fresh ? 4u : 0u);
+                    }
+                    l3a = l3b;
+                    h3a = h3b;
+                    l3b = l3;
+                    h3b = h3;
+                    p2lb = p2l;
+                    p2hb = p2h;
+                    ownb = own;
                 }
             }
-        const float2 own = sh[li][ly + 1][lx + 1];
-        if (zl > z0) {   // layer zl - 1 has both z neighbours now
-            const float LO = fminf(l3a, fminf(l3b, l3)), HI = fmaxf(h3a, fmaxf(h3b, h3));
-            const float PLO = fminf(p2lb, p2l), PHI = fmaxf(p2hb, p2h);
-            const bool act = (ownb.x < iso && iso <= HI) || (LO < iso && iso <= ownb.y);
-            // "can emit": the hull of the 2x2x2 group headed by the block
-            // contains iso (implies act, as that group contains the block)
-            const bool can_emit = PLO < iso && iso <= PHI;
-            const uint64_t b = ((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx;
-            const bool fresh = act && !identity && I_slot[b] < 0;
-            active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u) | (fresh ? 4u : 0u);
+            __syncthreads();   // sh is restaged for the next live tile
         }
-        l3a = l3b;
-        h3a = h3b;
-        l3b = l3;
-        h3b = h3;
-        p2lb = p2l;
-        p2hb = p2h;
-        ownb = own;
+        __syncthreads();   // live / n_live are rewritten for the next chunk
     }
 }
 
 // I_active (StreamCompactIDs of M_active) and I_new (active blocks without a
 // slot, Alg. 1 MarkNewBlocks, flagged by the cull) in one look-back pass over
-// the blocks.  Counts are packed as (active << 31 | new) so one status word
-// carries both.
+// the blocks.  A tile is m rounds of 4096 consecutive blocks; in a round each
+// thread takes 16 consecutive flags (one 16-byte load, the workgroup's loads
+// contiguous).  The first pass counts, the look-back places the tile, the
+// second pass revisits the rounds holding an active block and places each
+// thread's blocks by a workgroup scan.  Counts are packed as
+// (active << 31 | new) so one status word carries both.
+constexpr int COMPACT_MAX_ROUNDS = 128;   // rounds tracked one by one (more: all revisited)
+
+__device__ __forceinline__ void flag_bits(uint4 q, uint32_t &actb, uint32_t &newb, uint32_t &cand) {
+    const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
+    actb = newb = 0;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        if (f) actb |= 1u << j;
+        newb |= ((f >> 2) & 1u) << j;
+        cand += (f >> 1) & 1u;
+    }
+}
+
+__device__ __forceinline__ uint4 load_flags16(const uint8_t *__restrict__ active, uint64_t base,
+                                              uint64_t nb) {
+    if (base + 16 <= nb) return *reinterpret_cast<const uint4 *>(active + base);
+    uint32_t wd[4] = {0, 0, 0, 0};
+    for (int j = 0; j < 16; j++)
+        if (base + j < nb) wd[j >> 2] |= (uint32_t)active[base + j] << (8 * (j & 3));
+    return make_uint4(wd[0], wd[1], wd[2], wd[3]);
+}
+
 __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *__restrict__ active,
                                                        uint32_t *__restrict__ I_active,
                                                        uint32_t *__restrict__ I_new, Counters *ctr,
                                                        uint32_t *__restrict__ part_cand,
                                                        uint64_t *status, uint32_t m) {
-    // a tile is 256 threads x 16*m consecutive blocks (m chosen by the host
-    // so that there are about 1024 tiles: one ticket and one look-back each)
     const uint64_t tile_blocks = (uint64_t)BLK_TILE * m;
     const uint64_t n_tiles = (g.nb + tile_blocks - 1) / tile_blocks;
     const uint32_t t = take_tile(&ctr->tile_ctr[TC_BLK]);
     if (t >= n_tiles) return;
-    const uint64_t lo = t * tile_blocks + (uint64_t)threadIdx.x * 16u * m;
+    const uint64_t tbase = t * tile_blocks + 16u * threadIdx.x;
     uint32_t nact = 0, nnew = 0, cand = 0;
-    uint64_t any[2] = {0ull, 0ull};   // chunks holding an active block (m <= 128)
-    for (uint32_t c0 = 0; c0 < m; c0 += 4) {
-        uint4 q[4];   // 4 chunks of 16 flags in flight together
+    uint64_t any[2] = {0ull, 0ull};   // rounds in which this thread saw an active block
+    for (uint32_t r0 = 0; r0 < m; r0 += 4) {
+        uint4 q[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            q[k] = r0 + k < m ? load_flags16(active, tbase + (uint64_t)BLK_TILE * (r0 + k), g.nb)
+                              : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const uint64_t base = lo + 16u * (c0 + k);
-            if (c0 + k < m && base + 16 <= g.nb) {
-                q[k] = *reinterpret_cast<const uint4 *>(active + base);
-            } else {
-                uint32_t wd[4] = {0, 0, 0, 0};
-                for (int j = 0; j < 16; j++)
-                    if (c0 + k < m && base + j < g.nb) wd[j >> 2] |= (uint32_t)active[base + j] << (8 * (j & 3));
-                q[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const uint32_t wds[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
-            uint32_t actb = 0;
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-                if (f) actb |= 1u << j;
-                cand += (f >> 1) & 1u;
-                nnew += (f >> 2) & 1u;
-            }
+            uint32_t actb, newb;
+            flag_bits(q[k], actb, newb, cand);
             nact += __popc(actb);
-            if (actb && c0 + k < 128) any[(c0 + k) >> 6] |= 1ull << ((c0 + k) & 63);
+            nnew += __popc(newb);
+            if (actb && r0 + k < COMPACT_MAX_ROUNDS) any[(r0 + k) >> 6] |= 1ull << ((r0 + k) & 63);
         }
     }
     cand = wg_sum_u32(cand);
     if (threadIdx.x == 0) part_cand[t] = cand;
-    uint64_t incl_end;
-    uint64_t e = tile_scan_lookback(((uint64_t)nact << 31) | (uint64_t)nnew, status, t, &incl_end);
-    uint64_t oa = e >> 31, on = e & 0x7FFFFFFFull;
-    if (nact) {
-        // revisit only the chunks with an active block, 16 flags per load
-        for (uint32_t c = 0; c < m; c++) {
-            if (c < 128 && !((any[c >> 6] >> (c & 63)) & 1ull)) continue;
-            const uint64_t base = lo + 16u * c;
-            uint32_t actb = 0, newb = 0;
-            if (base + 16 <= g.nb) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(active + base);
-                const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
+    // rounds holding an active block anywhere in the workgroup
+    __shared__ uint64_t s_any[4][2];
+    __shared__ uint64_t s_base;
 #pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-                    if (f) actb |= 1u << j;
-                    newb |= ((f >> 2) & 1u) << j;
-                }
-            } else {
-                for (int j = 0; j < 16; j++)
-                    if (base + j < g.nb) {
-                        const uint32_t f = active[base + j];
-                        if (f) actb |= 1u << j;
-                        newb |= ((f >> 2) & 1u) << j;
-                    }
-            }
-            for (uint32_t mm = actb; mm; mm &= mm - 1) I_active[oa++] = (uint32_t)(base + __builtin_ctz(mm));
-            for (uint32_t mm = newb; mm; mm &= mm - 1) I_new[on++] = (uint32_t)(base + __builtin_ctz(mm));
+    for (int d = 32; d >= 1; d >>= 1) {
+        any[0] |= __shfl_xor(any[0], d, 64);
+        any[1] |= __shfl_xor(any[1], d, 64);
+    }
+    if (lane() == 0) {
+        s_any[threadIdx.x >> 6][0] = any[0];
+        s_any[threadIdx.x >> 6][1] = any[1];
+    }
+    uint64_t incl_end;
+    const uint64_t e = tile_scan_lookback(((uint64_t)nact << 31) | (uint64_t)nnew, status, t, &incl_end);
+    if (threadIdx.x == 0) s_base = e;   // thread 0's prefix is the tile's
+    __syncthreads();
+    uint64_t oa = s_base >> 31, on = s_base & 0x7FFFFFFFull;
+    const uint64_t wany0 = s_any[0][0] | s_any[1][0] | s_any[2][0] | s_any[3][0];
+    const uint64_t wany1 = s_any[0][1] | s_any[1][1] | s_any[2][1] | s_any[3][1];
+    __shared__ uint32_t s_w[4];
+    for (uint32_t r = 0; r < m; r++) {
+        if (r < COMPACT_MAX_ROUNDS && !(((r < 64 ? wany0 : wany1) >> (r & 63)) & 1ull)) continue;
+        const uint64_t base = tbase + (uint64_t)BLK_TILE * r;
+        uint32_t actb, newb, unused = 0;
+        flag_bits(load_flags16(active, base, g.nb), actb, newb, unused);
+        const uint32_t packed = ((uint32_t)__popc(actb) << 16) | (uint32_t)__popc(newb);
+        // workgroup exclusive scan of the packed counts (each field < 2^16)
+        const uint32_t incl = wave_incl_scan(packed);
+        if (lane() == 63) s_w[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        uint32_t woff = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (i < (int)(threadIdx.x >> 6)) woff += s_w[i];
+            tot += s_w[i];
         }
+        __syncthreads();
+        const uint32_t ex = woff + incl - packed;
+        uint64_t pa = oa + (ex >> 16), pn = on + (ex & 0xFFFFu);
+        for (uint32_t mm = actb; mm; mm &= mm - 1) I_active[pa++] = (uint32_t)(base + __builtin_ctz(mm));
+        for (uint32_t mm = newb; mm; mm &= mm - 1) I_new[pn++] = (uint32_t)(base + __builtin_ctz(mm));
+        oa += tot >> 16;
+        on += tot & 0xFFFFu;
     }
     if (t == n_tiles - 1 && threadIdx.x == 0) {
         ctr->n_act = incl_end >> 31;
@@ -867,11 +900,38 @@ unsigned grid_cap(uint64_t n_threads, unsigned cap) {
 
 }  // namespace
 
+// Workgroups of a persistent kernel that are all resident at once (the
+// static per-wave shares assume no second round), in whole XCD rounds.
+template <typename K>
+static unsigned resident_grid(K kernel, uint64_t max_blocks) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    uint64_t g = (uint64_t)per_cu * cus;
+    uint64_t need = (max_blocks + MC_WAVES - 1) / MC_WAVES;
+    if (need < g) g = need;
+    g = g / 8 * 8;
+    return (unsigned)(g < 8 ? 8 : g);
+}
+static unsigned mc_grid(uint64_t max_blocks) {
+    uint64_t g = (max_blocks + MC_WAVES - 1) / MC_WAVES;
+    g = g < 2048 ? g : 2048;
+    return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
+}
+
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
                  uint64_t n_slots_host, int identity_cache, hipStream_t s) {
-    const uint64_t tiles = (uint64_t)((g.nbx + CULL_TX - 1) / CULL_TX) *
-                           ((g.nby + CULL_TY - 1) / CULL_TY) * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
-    k_cull<<<(unsigned)tiles, 256, 0, s>>>(g, d.ranges, iso, d.tile_ranges, d.I_slot, identity_cache,
+    static unsigned rgrid = 0;
+    if (!rgrid) rgrid = resident_grid(k_cull, ~0ull >> 4);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(d.active), 0u, (g.nb + 3) / 4, s);
+    k_cull<<<(unsigned)std::min<uint64_t>(cull_tiles(g), rgrid), 256, 0, s>>>(g, d.ranges, iso, d.tile_ranges, d.I_slot, identity_cache,
                                            d.active, d.ctr, n_slots_host, d.status, sl.total);
 }
 
@@ -924,31 +984,6 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
     }
 }
 
-// Workgroups of a persistent kernel that are all resident at once (the
-// static per-wave shares assume no second round), in whole XCD rounds.
-template <typename K>
-static unsigned resident_grid(K kernel, uint64_t max_blocks) {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 256;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    uint64_t g = (uint64_t)per_cu * cus;
-    uint64_t need = (max_blocks + MC_WAVES - 1) / MC_WAVES;
-    if (need < g) g = need;
-    g = g / 8 * 8;
-    return (unsigned)(g < 8 ? 8 : g);
-}
-static unsigned mc_grid(uint64_t max_blocks) {
-    uint64_t g = (max_blocks + MC_WAVES - 1) / MC_WAVES;
-    g = g < 2048 ? g : 2048;
-    return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
-}
 
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                      int identity_cache, float iso, hipStream_t s) {
