@@ -724,7 +724,7 @@ __global__ __launch_bounds__(256) void k_scan_counts(const uint32_t *__restrict_
 // prefix of its per-cell vertex counts and write the triangle soup lane per
 // vertex at the block's offset, in canonical order (cell, triangle, vertex).
 template <bool EDGE8>
-__global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
+__global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
                                                 const int32_t *__restrict__ I_slot, int identity,
                                                 const float *__restrict__ slots,
                                                 const uint64_t *__restrict__ mc_table, float iso,
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
                                                 const uint32_t *__restrict__ part_cand,
                                                 const uint32_t *__restrict__ part_occ,
                                                 Counters *ctr) {
-    __shared__ EmitShared sh;
+    __shared__ EmitSharedPlain sh;
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     if (blockIdx.x == 0) {   // the call's statistics from the per-tile counts
@@ -764,9 +764,9 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
         octet(g, b, I_slot, identity, so, lbx, lby, lbz);
         uint64_t todo = __ballot(cnt != 0);
         while (todo) {
-            int jl[MC_SB], nsb = 0;
+            int jl[EMIT_SB], nsb = 0;
 #pragma unroll
-            for (int k = 0; k < MC_SB; k++) {
+            for (int k = 0; k < EMIT_SB; k++) {
                 jl[k] = k ? jl[0] : 0;
                 if (todo) {
                     jl[k] = (int)__builtin_ctzll(todo);
@@ -774,7 +774,7 @@ __global__ __launch_bounds__(256) void k_mc_emit(Geom g, const uint32_t *__restr
                     nsb++;
                 }
             }
-            stage_batch(q, slots, so, jl, sh.tiles[w]);
+            stage_batch_n<EMIT_SB>(q, slots, so, jl, sh.tiles[w]);
             wave_lds_sync();
             for (int k = 0; k < nsb; k++) {
                 const uint32_t bj = bcast(b, jl[k]);

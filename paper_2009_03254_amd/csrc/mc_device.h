@@ -481,11 +481,22 @@ constexpr uint64_t kEdgeGeom = edge_lut(false), kEdgeTile = edge_lut(true);
 
 constexpr int EMIT_TRIS = 64 * 5;   // a wave's triangle list (one block's maximum)
 
-struct EmitShared {
-    float tiles[MC_WAVES][MC_SB][128];
+// Per-wave LDS of the emission: SB staged tiles and the triangle list (the
+// block ids / isovalues are used by the merged emission only).
+template <int SB>
+struct EmitSharedT {
+    float tiles[MC_WAVES][SB][128];
     uint32_t tri[MC_WAVES][EMIT_TRIS];  // per triangle: cell | 3 edge ids << 6 | staged block << 18
-    uint32_t blk[MC_WAVES][MC_SB];      // block id of each staged block
-    float iso[MC_WAVES][MC_SB];         // its isovalue
+    uint32_t blk[MC_WAVES][SB];         // block id of each staged block
+    float iso[MC_WAVES][SB];            // its isovalue
+};
+using EmitShared = EmitSharedT<MC_SB>;
+// The plain emission stages one block fewer: its LDS then fits 8 workgroups
+// per CU.
+constexpr int EMIT_SB = MC_SB - 1;
+struct EmitSharedPlain {
+    float tiles[MC_WAVES][EMIT_SB][128];
+    uint32_t tri[MC_WAVES][EMIT_TRIS];
 };
 
 }  // namespace
@@ -501,10 +512,10 @@ namespace {
 // dropped).  EDGE8: 8-byte records block | cell << 32 | edge << 38 | q << 42
 // with q = min(trunc(t * 2^22), 2^22 - 1); otherwise 16-byte records
 // {f32 x, y, z block-relative; u32 block}.
-template <bool EDGE8>
+template <bool EDGE8, class SH>
 __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t bx, uint32_t by,
                                            uint32_t bz, const float *tile, float iso,
-                                           const uint64_t *__restrict__ mc_table, EmitShared &sh,
+                                           const uint64_t *__restrict__ mc_table, SH &sh,
                                            int w, uint64_t base, void *__restrict__ out, uint64_t cap) {
     const int l = lane();
     const int cs = tile_case(g, bx, by, bz, tile, iso);
