@@ -442,22 +442,33 @@ def _make_extract_fn():
         field_blocks and iso through t = (iso - a)/(b - a), topology fixed."""
 
         @staticmethod
-        def forward(ctx, field_blocks, iso, dims):
+        def forward(ctx, field_blocks, iso, dims, keep=True):
+            # keep: a backward may follow, so the volume (which holds this
+            # extract's layout) stays with ctx until then; otherwise it goes
+            # straight back to the pool.  The soup is a fresh buffer: its
+            # views are returned without a copy.
             vol = _acquire_field_volume(field_blocks.detach(), dims)
             isof = float(iso)
             verts, T = vol.extract(isof)
             xyz, blk = split_vertices(verts)
-            ctx.vol, ctx.iso = vol, isof
+            ctx.iso = isof
             ctx.iso_dtype = iso.dtype if torch.is_tensor(iso) else torch.float32
+            if keep:
+                ctx.vol = vol
+            else:
+                ctx.vol = None
+                _release_field_volume(vol)
             ctx.mark_non_differentiable(blk)
-            return xyz.clone(), blk.clone()
+            return xyz, blk
 
         @staticmethod
         def backward(ctx, g_xyz, g_blk):
+            if ctx.vol is None:
+                raise RuntimeError("ExtractFn: backward of a forward run without gradients")
             dfield, diso = ctx.vol.backward(ctx.iso, g_xyz)
             _release_field_volume(ctx.vol)
             ctx.vol = None
-            return dfield, diso.to(ctx.iso_dtype), None
+            return dfield, diso.to(ctx.iso_dtype), None, None
 
     return ExtractFn
 
@@ -465,10 +476,19 @@ def _make_extract_fn():
 class _LazyFn:
     _fn = None
 
-    def __getattr__(self, name):
+    def _get(self):
         if _LazyFn._fn is None:
             _LazyFn._fn = _make_extract_fn()
-        return getattr(_LazyFn._fn, name)
+        return _LazyFn._fn
+
+    def apply(self, field_blocks, iso, dims):
+        torch = _torch()
+        keep = torch.is_grad_enabled() and (
+            field_blocks.requires_grad or (torch.is_tensor(iso) and iso.requires_grad))
+        return self._get().apply(field_blocks, iso, dims, keep)
+
+    def __getattr__(self, name):
+        return getattr(self._get(), name)
 
 
 ExtractFn = _LazyFn()

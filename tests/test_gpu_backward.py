@@ -55,3 +55,34 @@ def test_backward_no_surface(orc):
     assert xyz.shape[0] == 0
     (xyz.sum() * 1.0).backward()
     assert float(blocks.grad.abs().sum()) == 0.0 and float(iso_t.grad) == 0.0
+
+
+def test_forward_without_grad_reuses_volume(orc):
+    """A forward under no_grad returns its pooled volume at once: repeated
+    calls reuse one handle, give the oracle's soup, and a later forward +
+    backward still matches the oracle's gradient sum identity."""
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bcmc
+    n = 40
+    f = fields.gaussian_blobs(n, 6, seed=77)
+    dims = (n, n, n)
+    B = orc.field_to_blocks(f)
+    iso = fields.percentile_iso(f, 55)
+    blocks = torch.from_numpy(B).cuda().requires_grad_(True)
+    iso_t = torch.tensor(float(iso), device="cuda", requires_grad=True)
+    r = orc.mc_extract(B, dims, iso, want=("verts", "vblock"))
+    v32, vb = orc.mc_extract_f32(B, dims, iso)
+    pool = bcmc._POOL.setdefault(dims, [])
+    for _ in range(3):
+        with torch.no_grad():
+            xyz, blk = bcmc.ExtractFn.apply(blocks, iso_t, dims)
+        assert len(pool) == 1
+        assert xyz.shape[0] == 3 * r["T"]
+        assert np.array_equal(xyz.cpu().numpy().view(np.uint32), v32.view(np.uint32))
+        assert np.array_equal(blk.cpu().numpy().view(np.uint32), vb)
+    xyz, blk = bcmc.ExtractFn.apply(blocks, iso_t, dims)
+    assert len(pool) == 0               # held until the backward
+    (xyz.sum()).backward()
+    assert len(pool) == 1
+    got = blocks.grad.cpu().numpy().astype(np.float64)
+    assert abs(got.sum() + float(iso_t.grad)) <= 1e-4 * (np.abs(got).sum() + abs(float(iso_t.grad)))
