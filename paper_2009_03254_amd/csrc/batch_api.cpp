@@ -301,7 +301,7 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
     }
     b->front_pc_max = pcf;
     b->decode_grid = grid_for(b, pcd);
-    int rc = set_schedule(b, 8, 1 << 30, pcf);
+    int rc = set_schedule(b, 8, 1 << 30, std::max(1, pcf / 2));
     if (rc) {
         destroy_batch(b);
         return rc;
@@ -438,7 +438,9 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
     }
     int best_sb = b->sb, best_pc = b->per_cu_max, best_fpc = b->front_pc_max;
     double best = 1e30;
-    std::vector<int> fpcs = {b->front_pc_max, std::max(1, b->front_pc_max / 2)};
+    // the front kernel's barriers cost more with more workgroups: half and
+    // a quarter of what stays resident
+    std::vector<int> fpcs = {std::max(1, b->front_pc_max / 2), std::max(1, b->front_pc_max / 4)};
     fpcs.erase(std::unique(fpcs.begin(), fpcs.end()), fpcs.end());
     for (int sb : {4, 8}) {
         int maxc = 0;
@@ -449,15 +451,18 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
         for (int pc : pcs) {
             for (int fpc : fpcs) {
                 if ((rc = set_schedule(b, sb, pc, fpc))) break;
-                double t = 0;
-                for (int rep = 0; rep < 3 && !rc; rep++) {
-                    // cold run (empty batch cache) + warm run
+                // median over 5 repetitions of a cold run (empty batch
+                // store) + a warm run; a first repetition warms up
+                std::vector<double> ts;
+                for (int rep = 0; rep < 6 && !rc; rep++) {
                     if ((rc = reset_cache(b, s)) || (rc = run_once(b, buf, need, s))) break;
                     double cold = b->last_ms;
                     if ((rc = run_once(b, buf, need, s))) break;
-                    if (rep) t += cold + b->last_ms;   // the first repetition warms up
+                    if (rep) ts.push_back(cold + b->last_ms);
                 }
                 if (rc) break;
+                std::sort(ts.begin(), ts.end());
+                const double t = ts[ts.size() / 2];
                 if (t < best) {
                     best = t;
                     best_sb = sb;
@@ -474,7 +479,7 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
     rc = set_schedule(b, best_sb, best_pc, best_fpc);
     if (rc) return rc;
     save_schedule(cache_path ? cache_path : getenv("BCMC_AUTOTUNE_CACHE"), b->key, best_sb, best_pc,
-                  best_fpc, best / 4.0);
+                  best_fpc, best / 2.0);
     return reset_cache(b, s);
 }
 

@@ -479,6 +479,17 @@ constexpr uint64_t edge_lut(bool tile_offset) {
 }
 constexpr uint64_t kEdgeGeom = edge_lut(false), kEdgeTile = edge_lut(true);
 
+// Vertex records are written once and not read back by the path: streaming
+// (non-temporal) stores keep them from evicting the staged slots from L2.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void stream_store(void *out, uint64_t o, uint64_t r) {
+    __builtin_nontemporal_store(r, reinterpret_cast<uint64_t *>(out) + o);
+}
+__device__ __forceinline__ void stream_store(void *out, uint64_t o, float x, float y, float z, uint32_t b) {
+    u32x4_t v = {__float_as_uint(x), __float_as_uint(y), __float_as_uint(z), b};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t *>(out) + o);
+}
+
 constexpr int EMIT_TRIS = 64 * 5;   // a wave's triangle list (one block's maximum)
 
 // Per-wave LDS of the emission: SB staged tiles and the triangle list (the
@@ -544,16 +555,14 @@ __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t b
             uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
             qt = qt < 4194303u ? qt : 4194303u;
             const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
-            if (o < cap) reinterpret_cast<uint64_t *>(out)[o] = r;
+            if (o < cap) stream_store(out, o, r);
         } else {
             // the edge's first corner plus t along its axis (adding 0 to the
             // other two coordinates leaves them exact)
             const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
             const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
             const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
-            if (o < cap)
-                reinterpret_cast<uint4 *>(out)[o] =
-                    make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+            if (o < cap) stream_store(out, o, px, py, pz, b);
         }
     }
     wave_lds_sync();
@@ -603,16 +612,14 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
                 uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
                 qt = qt < 4194303u ? qt : 4194303u;
                 const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
-                if (o < cap) reinterpret_cast<uint64_t *>(out)[o] = r;
+                if (o < cap) stream_store(out, o, r);
             } else {
                 // the edge's first corner plus t along its axis (adding 0 to the
                 // other two coordinates leaves them exact)
                 const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
                 const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
                 const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
-                if (o < cap)
-                    reinterpret_cast<uint4 *>(out)[o] =
-                        make_uint4(__float_as_uint(px), __float_as_uint(py), __float_as_uint(pz), b);
+                if (o < cap) stream_store(out, o, px, py, pz, b);
             }
         }
         base += (uint64_t)total;
