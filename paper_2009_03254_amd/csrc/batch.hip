@@ -1,5 +1,5 @@
 // Batched extraction: many volumes of uneven size, several isovalues each,
-// in three launches (two of them persistent, their phases separated by grid
+// in four launches (the first persistent, its phases separated by grid
 // barriers), replayable from a hipGraph.
 //
 // Each job j = (volume v_j, isovalue iso_j) produces exactly the triangle soup
@@ -24,10 +24,10 @@
 // Decode kernel (grid-stride; its grid sized by the decoder's registers):
 //   4  decode the new blocks into slots slot_base + rank; sign masks of every
 //      used block for every job of its volume
-// Back kernel (persistent, grid autotuned; every wave owns one contiguous
-// share of L):
+// Count kernel (grid autotuned; every wave owns one contiguous share of L):
 //   5  count pass over L from the sign masks (Sec. 4.4), per-wave totals
-//   6  workgroup 0 scans the per-wave totals
+// Back kernel (same grid and shares as the count kernel, no barriers):
+//   6  each workgroup sums the per-wave totals before its waves
 //   7  emission over L (Sec. 4.5), offsets by a running wave scan of the
 //      counts; per-job output offsets
 // Every thread of a persistent grid reaches every barrier of its kernel.
@@ -479,69 +479,90 @@ __global__ __launch_bounds__(BT) void k_batch_decode(BatchParams p) {
     stamp_last(p, 5);
 }
 
-// ---- back kernel: phases 5-7 ------------------------------------------------
+// ---- count kernel: phase 5 -----------------------------------------------------
+// One lane per (job, block) pair of L, each wave over its share of L (the
+// partition the emission uses: same grid): the cases of the block's 64 cells
+// from the sign masks of its octet, the triangle count per case by the
+// bit-sliced table circuit (Sec. 4.4); per-wave totals.
+__global__ __launch_bounds__(BT) void k_batch_count(BatchParams p) {
+    const int l = lane();
+    if (p.ctr->err) return;   // an earlier kernel failed: nothing to do
+    const uint64_t n_list = p.ctr->n_list;
+    uint64_t lo, hi;
+    const uint32_t wv = wave_share(n_list, lo, hi);
+    uint64_t tot = 0;
+    for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
+        const uint64_t idx = i0 + l;
+        uint32_t c = 0;
+        if (idx < hi) {
+            const uint32_t j = p.list_job[idx];
+            const uint64_t jb = p.job_jbase[j];
+            const BatchVol &vol = p.vols[p.job_vol[j]];
+            const uint32_t b = (uint32_t)(p.list[idx] - jb);
+            uint32_t so[8], bx, by, bz;
+            octet(vol.g, b, nullptr, 1, so, bx, by, bz);
+            uint64_t M[8], cm[8];
+#pragma unroll
+            for (int m = 0; m < 8; m++) M[m] = p.jmask[jb + so[m]];
+            corner_masks(M, cm);
+            uint64_t n0, n1, n2;
+            mc_ntri_bits(cm, n0, n1, n2);
+            const uint64_t V = valid_cells(vol.g, bx, by, bz);
+            c = 3u * ((uint32_t)__popcll(n0 & V) + 2u * (uint32_t)__popcll(n1 & V) +
+                      4u * (uint32_t)__popcll(n2 & V));
+            p.cnt[idx] = c;
+        }
+        tot += wave_sum(c);
+    }
+    if (l == 0) p.part_wave[wv] = tot;
+    stamp_last(p, 6);
+}
+
+// ---- back kernel: phases 6-7 ----------------------------------------------------
 struct BackShared {
     EmitShared emit;
-    uint64_t w64[BT / 64];
+    uint64_t w64[2][BT / 64];
 };
 
 template <int SB>
-__global__ __launch_bounds__(BT, 6) void k_batch_back(BatchParams p) {
+__global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
     __shared__ BackShared sh;
     const int l = lane(), w = threadIdx.x >> 6;
-    if (p.ctr->err) return;   // the front kernel failed: nothing to do
+    if (p.ctr->err) return;   // an earlier kernel failed: nothing to do
     const uint64_t n_list = p.ctr->n_list;
     uint64_t lo, hi;
     const uint32_t wv = wave_share(n_list, lo, hi);
 
-    // ---- phase 5: count pass over L (Sec. 4.4) --------------------------------
-    // One lane per (job, block) pair: the cases of the block's 64 cells from
-    // the sign masks of its octet, the triangle count per case by the
-    // bit-sliced table circuit.
-    {
-        uint64_t tot = 0;
-        for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
-            const uint64_t idx = i0 + l;
-            uint32_t c = 0;
-            if (idx < hi) {
-                const uint32_t j = p.list_job[idx];
-                const uint64_t jb = p.job_jbase[j];
-                const BatchVol &vol = p.vols[p.job_vol[j]];
-                const uint32_t b = (uint32_t)(p.list[idx] - jb);
-                uint32_t so[8], bx, by, bz;
-                octet(vol.g, b, nullptr, 1, so, bx, by, bz);
-                uint64_t M[8], cm[8];
+    // ---- phase 6: each workgroup sums the per-wave totals before its first
+    // wave and all of them (no grid barrier: the counts are a kernel earlier)
+    const uint32_t W = gridDim.x * (BT / 64), wv0 = wv - (uint32_t)w;
+    uint64_t before = 0, all = 0;
+    for (uint32_t i = threadIdx.x; i < W; i += BT) {
+        const uint64_t v = p.part_wave[i];
+        all += v;
+        if (i < wv0) before += v;
+    }
+    before = wave_sum(before);
+    all = wave_sum(all);
+    if (l == 0) {
+        sh.w64[0][w] = before;
+        sh.w64[1][w] = all;
+    }
+    __syncthreads();
+    uint64_t base = 0, total = 0;
 #pragma unroll
-                for (int m = 0; m < 8; m++) M[m] = p.jmask[jb + so[m]];
-                corner_masks(M, cm);
-                uint64_t n0, n1, n2;
-                mc_ntri_bits(cm, n0, n1, n2);
-                const uint64_t V = valid_cells(vol.g, bx, by, bz);
-                c = 3u * ((uint32_t)__popcll(n0 & V) + 2u * (uint32_t)__popcll(n1 & V) +
-                          4u * (uint32_t)__popcll(n2 & V));
-                p.cnt[idx] = c;
-            }
-            tot += wave_sum(c);
-        }
-        if (l == 0) p.part_wave[wv] = tot;
+    for (int k = 0; k < BT / 64; k++) {
+        base += sh.w64[0][k];
+        total += sh.w64[1][k];
     }
-    if (!grid_barrier(p.bar, &p.ctr->err)) return;
-    stamp(p, 6);
-
-    // ---- phase 6: workgroup 0 scans the per-wave counts -------------------------
-    if (blockIdx.x == 0) {
-        const uint64_t t = scan_partials(p.part_wave, gridDim.x * (BT / 64), sh.w64);
-        if (threadIdx.x == 0) p.ctr->total_verts = t;
-    }
-    if (!grid_barrier(p.bar, &p.ctr->err)) return;
+    for (uint32_t k = 0; k < (uint32_t)w; k++) base += p.part_wave[wv0 + k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) p.ctr->total_verts = total;
     stamp(p, 7);
 
     // ---- phase 7: emission (Sec. 4.5) and the jobs' output offsets --------------
-    const uint64_t total = p.ctr->total_verts;
     if (n_list == 0 && blockIdx.x == 0)
         for (uint32_t j = threadIdx.x; j <= p.n_jobs; j += BT) p.job_off[j] = 0;
     const LaneGeom q = lane_geom();
-    uint64_t base = p.part_wave[wv];
     for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
         const uint64_t idx = i0 + l;
         const bool valid = idx < hi;
@@ -642,15 +663,13 @@ hipError_t launch_batch(const BatchParams &p, int is_f64, int sb, const unsigned
     void *args[] = {const_cast<BatchParams *>(&p)};
     const void *decode = decode_kernel(is_f64, p.uniform_rate != 0);
     const void *back = sb == 4 ? (const void *)k_batch_back<4> : (const void *)k_batch_back<8>;
-    hipError_t e;
-    if (cooperative) {
-        e = hipLaunchCooperativeKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT), args, 0, s);
-        if (e == hipSuccess) e = hipLaunchKernel(decode, dim3(grids[1]), dim3(BT), args, decode_lds(p), s);
-        if (e == hipSuccess) e = hipLaunchCooperativeKernel(back, dim3(grids[2]), dim3(BT), args, 0, s);
-        return e;
-    }
-    e = hipLaunchKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT), args, 0, s);
+    hipError_t e = cooperative
+                       ? hipLaunchCooperativeKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT),
+                                                    args, 0, s)
+                       : hipLaunchKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT), args, 0, s);
     if (e == hipSuccess) e = hipLaunchKernel(decode, dim3(grids[1]), dim3(BT), args, decode_lds(p), s);
+    // count and back share one grid: they partition L the same way
+    if (e == hipSuccess) e = hipLaunchKernel((const void *)k_batch_count, dim3(grids[2]), dim3(BT), args, 0, s);
     if (e == hipSuccess) e = hipLaunchKernel(back, dim3(grids[2]), dim3(BT), args, 0, s);
     return e;
 }
