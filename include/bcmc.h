@@ -95,8 +95,10 @@ typedef struct {
                               [0] cull + active/new compaction,
                               [1] cache update (slot pass, growth, age sort),
                               [2] assign + decode of new blocks,
-                              [3] marching cubes count pass, [4] block scan,
-                              [5] emission pass, [6] unused, [7] total */
+                              [3] sign masks + marching cubes count pass,
+                              [4] empty (the block offsets are formed by the
+                              emission pass from the count pass's per-wave
+                              totals), [5] emission pass, [6] unused, [7] total */
 } bcmc_stats;
 
 /* Upload a fixed-rate ZFP stream (Sec. 4: "uploading the compressed data to

@@ -128,7 +128,8 @@ int alloc_common(bcmc_volume *v) {
     if ((rc = dev_alloc(&v->d.blk_cnt, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_off, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.part_cand, (v->g.nb + BLK_TILE - 1) / BLK_TILE))) return rc;
-    if ((rc = dev_alloc(&v->d.part_occ, (v->g.nb + SCAN_TILE - 1) / SCAN_TILE))) return rc;
+    if ((rc = dev_alloc(&v->d.part_wave, 4 * MC_MAX_GRID))) return rc;
+    if ((rc = dev_alloc(&v->d.part_occw, 4 * MC_MAX_GRID))) return rc;
     if ((rc = dev_alloc(&v->d.ctr, 1))) return rc;
     if ((rc = dev_alloc(&v->d.mc_table, 256))) return rc;
     if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
@@ -153,7 +154,8 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.blk_cnt);
     dev_free(v->d.blk_off);
     dev_free(v->d.part_cand);
-    dev_free(v->d.part_occ);
+    dev_free(v->d.part_wave);
+    dev_free(v->d.part_occw);
     dev_free(v->d.ctr);
     dev_free(v->d.mc_table);
     if (v->h_ctr) (void)hipHostFree(v->h_ctr);
@@ -380,9 +382,9 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     if (!v->identity) launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, iso, s);
     BCMC_HIP_TRY(mark(3));
     const float *slots = v->identity ? v->ext_blocks : v->d.slots;
-    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, s);
-    BCMC_HIP_TRY(mark(4));
-    launch_scan_counts(v->g, v->d, v->sl, s);
+    const int edge8 = v->vertex_format == BCMC_VERTEX_EDGE8;
+    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, edge8, s);
+    BCMC_HIP_TRY(mark(4));   // the block offsets come with the emission (stage 4 is empty)
     BCMC_HIP_TRY(mark(5));
     launch_mc_emit(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices,
                    v->vertex_format == BCMC_VERTEX_EDGE8, s);

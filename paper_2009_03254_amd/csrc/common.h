@@ -17,6 +17,7 @@ constexpr uint32_t MASK_NONE = 0x7FC00001u;
 constexpr int BLK_TILE = 4096;               // blocks per compaction tile
 constexpr int SLOT_TILE = 4096;              // slots per compaction tile (16 per thread)
 constexpr int RADIX_TILE = 1024;             // elements per radix tile (1 wave)
+constexpr int MC_MAX_GRID = 2048;           // workgroups of the count / emission grid at most
 constexpr int SCAN_TILE = 4096;              // u32 per look-back scan tile (16 per thread)
 constexpr int MC_WAVES = 4;                  // blocks (one per wave) per MC tile
 
@@ -88,7 +89,8 @@ struct DevState {
     uint32_t *blk_cnt = nullptr;    // per active block vertex count
     uint64_t *blk_off = nullptr;    // per active block first vertex
     uint32_t *part_cand = nullptr;  // per compaction tile: blocks that may emit
-    uint32_t *part_occ = nullptr;   // per block-count scan tile: blocks with triangles
+    uint64_t *part_wave = nullptr;  // [4 * max MC grid] per-wave vertex totals of the count pass
+    uint32_t *part_occw = nullptr;  // [4 * max MC grid] per-wave occupied blocks
     uint64_t *status = nullptr;     // look-back status words (all kernels)
     Counters *ctr = nullptr;
     uint64_t *mc_table = nullptr;   // 256 packed cases
@@ -112,8 +114,8 @@ void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound
 void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, uint32_t age_cap,
                   hipStream_t s);
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, hipStream_t s);
-void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s);
+                     int identity_cache, float iso, int edge8, hipStream_t s);
+
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                     int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
                     hipStream_t s);

@@ -632,11 +632,14 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
                                                  const uint8_t *__restrict__ active,
                                                  const int32_t *__restrict__ I_slot, int identity,
                                                  const uint64_t *__restrict__ masks,
-                                                 uint32_t *__restrict__ blk_cnt, Counters *ctr) {
+                                                 uint32_t *__restrict__ blk_cnt,
+                                                 uint64_t *__restrict__ part_wave,
+                                                 uint32_t *__restrict__ part_occw, Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
     uint64_t lo, hi;
-    xcd_wave_range(n_act, lo, hi);
+    const uint32_t wv = xcd_wave_range(n_act, lo, hi);
+    uint32_t wsum = 0, wocc = 0;
     for (uint64_t i = lo + lane(); i < hi; i += 64) {
         const uint32_t b = I_active[i];
         uint32_t cnt = 0;
@@ -658,67 +661,19 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
             }
         }
         blk_cnt[i] = cnt;
+        wsum += cnt;
+        wocc += cnt ? 1u : 0u;
+    }
+    // per-wave totals in item order (the emission runs on the same grid, so
+    // its waves own the same shares)
+    wsum = wave_sum(wsum);
+    wocc = wave_sum(wocc);
+    if (lane() == 0) {
+        part_wave[wv] = wsum;
+        part_occw[wv] = wocc;
     }
 }
 
-// Exclusive scan of the block vertex counts into 64-bit offsets; the last
-// tile records the total (Sec. 4.4: the per-block offsets and the output
-// size come from one prefix sum over the blocks).  Each tile also records
-// how many of its blocks have triangles.
-__global__ __launch_bounds__(256) void k_scan_counts(const uint32_t *__restrict__ cnt,
-                                                    uint64_t *__restrict__ off, Counters *ctr,
-                                                    uint32_t *__restrict__ part_occ,
-                                                    uint64_t *status) {
-    if (ctr->err) return;
-    const uint64_t n = ctr->n_act;
-    const uint64_t n_tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    constexpr int PER = SCAN_TILE / 256;   // consecutive counts per thread
-    static_assert(PER % 4 == 0, "counts are loaded 4 at a time");
-    for (;;) {
-        const uint32_t t = take_tile(&ctr->tile_ctr[TC_MC]);
-        if (t >= n_tiles) return;
-        const uint64_t base = (uint64_t)t * SCAN_TILE + threadIdx.x * PER;
-        const bool full = base + PER <= n;
-        uint32_t x[PER];
-        if (full) {
-#pragma unroll
-            for (int j = 0; j < PER; j += 4) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(cnt + base + j);
-                x[j] = q.x; x[j + 1] = q.y; x[j + 2] = q.z; x[j + 3] = q.w;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < PER; j++) x[j] = base + j < n ? cnt[base + j] : 0u;
-        }
-        uint64_t sum = 0;
-        uint32_t occ = 0;
-#pragma unroll
-        for (int j = 0; j < PER; j++) {
-            sum += x[j];
-            occ += x[j] != 0;
-        }
-        occ = wg_sum_u32(occ);
-        if (threadIdx.x == 0) part_occ[t] = occ;
-        uint64_t incl_end;
-        uint64_t e = tile_scan_lookback(sum, status, t, &incl_end);
-        uint64_t o[PER];
-#pragma unroll
-        for (int j = 0; j < PER; j++) {
-            o[j] = e;
-            e += x[j];
-        }
-        if (full) {
-            ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(off + base);
-#pragma unroll
-            for (int j = 0; j < PER; j += 2) dst[j / 2] = make_ulonglong2(o[j], o[j + 1]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < PER; j++)
-                if (base + j < n) off[base + j] = o[j];
-        }
-        if (t == n_tiles - 1 && threadIdx.x == 0) ctr->total_verts = incl_end;
-    }
-}
 
 // Emission pass (Sec. 4.5): restage each occupied block, take the in-block
 // prefix of its per-cell vertex counts and write the triangle soup lane per
@@ -729,37 +684,69 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
                                                 const float *__restrict__ slots,
                                                 const uint64_t *__restrict__ mc_table, float iso,
                                                 const uint32_t *__restrict__ blk_cnt,
-                                                const uint64_t *__restrict__ blk_off,
+                                                uint64_t *__restrict__ blk_off,
                                                 void *__restrict__ out, uint64_t cap,
                                                 const uint32_t *__restrict__ part_cand,
-                                                const uint32_t *__restrict__ part_occ,
+                                                const uint64_t *__restrict__ part_wave,
+                                                const uint32_t *__restrict__ part_occw,
                                                 Counters *ctr) {
     __shared__ EmitSharedPlain sh;
+    __shared__ uint64_t s_base[MC_WAVES];
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
-    if (blockIdx.x == 0) {   // the call's statistics from the per-tile counts
-        const uint64_t ctile = (uint64_t)BLK_TILE * compact_blocks_per_thread16(g.nb);
-        const uint64_t n_ct = (g.nb + ctile - 1) / ctile, n_st = (n_act + SCAN_TILE - 1) / SCAN_TILE;
-        uint32_t cand = 0, occ = 0;
-        for (uint64_t i = threadIdx.x; i < n_ct; i += blockDim.x) cand += part_cand[i];
-        for (uint64_t i = threadIdx.x; i < n_st; i += blockDim.x) occ += part_occ[i];
-        cand = wg_sum_u32(cand);
-        occ = wg_sum_u32(occ);
-        if (threadIdx.x == 0) {
-            ctr->n_cand = cand;
-            ctr->n_occ = occ;
+    const int w = threadIdx.x >> 6, l = lane();
+    uint64_t lo, hi;
+    const uint32_t wv = xcd_wave_range(n_act, lo, hi);
+    // Sec. 4.4's prefix sum over the block counts, without a pass of its
+    // own: the count pass left per-wave totals for the same shares, and each
+    // workgroup sums those before its waves; workgroup 0 also forms the
+    // call's totals
+    uint64_t before = 0;
+    {
+        const uint32_t W = gridDim.x * MC_WAVES, wv0 = wv - (uint32_t)w;
+        uint64_t all = 0;
+        uint32_t occ = 0;
+        const bool first = blockIdx.x == 0;
+        for (uint32_t i = threadIdx.x; i < (first ? W : wv0); i += blockDim.x) {
+            const uint64_t v = part_wave[i];
+            if (i < wv0) before += v;
+            all += v;
+            if (first) occ += part_occw[i];
+        }
+        before = wave_sum(before);
+        if (lane() == 0) s_base[w] = before;
+        __syncthreads();
+        before = s_base[0] + s_base[1] + s_base[2] + s_base[3];
+        __syncthreads();
+        if (first) {
+            const uint64_t ctile = (uint64_t)BLK_TILE * compact_blocks_per_thread16(g.nb);
+            const uint64_t n_ct = (g.nb + ctile - 1) / ctile;
+            uint32_t cand = 0;
+            for (uint64_t i = threadIdx.x; i < n_ct; i += blockDim.x) cand += part_cand[i];
+            all = wave_sum(all);
+            if (lane() == 0) s_base[w] = all;
+            cand = wg_sum_u32(cand);
+            occ = wg_sum_u32(occ);   // its barriers also publish s_base
+            if (threadIdx.x == 0) {
+                ctr->n_cand = cand;
+                ctr->n_occ = occ;
+                ctr->total_verts = s_base[0] + s_base[1] + s_base[2] + s_base[3];
+            }
         }
     }
-    const int w = threadIdx.x >> 6, l = lane();
+    uint64_t base = before;   // the wave's first vertex (wave-uniform)
+    for (int k = 0; k < w; k++) base += part_wave[wv - (uint32_t)w + (uint32_t)k];
     const LaneGeom q = lane_geom();
-    uint64_t lo, hi;
-    xcd_wave_range(n_act, lo, hi);
     for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
         const uint64_t idx = i0 + l;
         const bool valid = idx < hi;
         const uint32_t cnt = valid ? blk_cnt[idx] : 0u;
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint64_t off = base + (incl - cnt);
+        base += __shfl(incl, 63, 64);
+        if (valid) blk_off[idx] = off;
         const uint32_t b = cnt ? I_active[idx] : 0u;
-        const uint64_t boff = cnt ? blk_off[idx] : 0ull;
+        const uint64_t boff = off;
         uint32_t so[8], lbx, lby, lbz;
         octet(g, b, I_slot, identity, so, lbx, lby, lbz);
         uint64_t todo = __ballot(cnt != 0);
@@ -922,7 +909,7 @@ static unsigned resident_grid(K kernel, uint64_t max_blocks) {
 }
 static unsigned mc_grid(uint64_t max_blocks) {
     uint64_t g = (max_blocks + MC_WAVES - 1) / MC_WAVES;
-    g = g < 2048 ? g : 2048;
+    g = g < MC_MAX_GRID ? g : MC_MAX_GRID;
     return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
 }
 
@@ -985,38 +972,38 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
 }
 
 
-void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, hipStream_t s) {
-    static unsigned mgrid = 0, cgrid = 0;
-    if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
-    if (!cgrid) cgrid = resident_grid(k_mc_count, ~0ull >> 4);
-    k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
-        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_iso, d.ctr);
-    k_mc_count<<<std::min<unsigned>(cgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
-        g, d.I_active, d.active, I_slot, identity_cache, d.masks, d.blk_cnt, d.ctr);
+// The emission's grid; the count pass runs on the same one, so that both
+// give each wave the same share of the active blocks.
+static unsigned emit_grid(const Geom &g, int edge8) {
+    static unsigned grid[2] = {0, 0};
+    if (!grid[0]) grid[0] = resident_grid(k_mc_emit<false>, ~0ull >> 4);
+    if (!grid[1]) grid[1] = resident_grid(k_mc_emit<true>, ~0ull >> 4);
+    return std::min<unsigned>(grid[edge8 ? 1 : 0], mc_grid(g.nb));
 }
 
-void launch_scan_counts(const Geom &g, const DevState &d, const StatusLayout &sl, hipStream_t s) {
-    uint64_t tiles = (g.nb + SCAN_TILE - 1) / SCAN_TILE;
-    unsigned grid = (unsigned)(tiles < 1024 ? (tiles ? tiles : 1) : 1024);
-    k_scan_counts<<<grid, 256, 0, s>>>(d.blk_cnt, d.blk_off, d.ctr, d.part_occ, d.status + sl.mc);
+void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
+                     int identity_cache, float iso, int edge8, hipStream_t s) {
+    static unsigned mgrid = 0;
+    if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
+    k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
+        d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_iso, d.ctr);
+    k_mc_count<<<emit_grid(g, edge8), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
+                                                   d.masks, d.blk_cnt, d.part_wave, d.part_occw,
+                                                   d.ctr);
 }
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
                     int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
                     hipStream_t s) {
-    static unsigned grid[2] = {0, 0};
-    if (!grid[0]) grid[0] = resident_grid(k_mc_emit<false>, ~0ull >> 4);
-    if (!grid[1]) grid[1] = resident_grid(k_mc_emit<true>, ~0ull >> 4);
-    const unsigned n = std::min<unsigned>(grid[edge8 ? 1 : 0], mc_grid(g.nb));
+    const unsigned n = emit_grid(g, edge8);
     if (edge8)
         k_mc_emit<true><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table,
                                           iso, d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand,
-                                          d.part_occ, d.ctr);
+                                          d.part_wave, d.part_occw, d.ctr);
     else
         k_mc_emit<false><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table,
                                            iso, d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand,
-                                           d.part_occ, d.ctr);
+                                           d.part_wave, d.part_occw, d.ctr);
 }
 
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,

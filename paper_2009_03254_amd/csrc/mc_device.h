@@ -413,14 +413,17 @@ __device__ __forceinline__ int tile_case(const Geom &g, uint32_t bx, uint32_t by
 // the workgroups of one XCD one contiguous eighth of the range, so blocks
 // whose halos overlap are staged through the same L2.  gridDim.x must be a
 // multiple of 8.
-__device__ __forceinline__ void xcd_wave_range(uint64_t n, uint64_t &lo, uint64_t &hi) {
+// Returns the share's rank in item order.
+__device__ __forceinline__ uint32_t xcd_wave_range(uint64_t n, uint64_t &lo, uint64_t &hi) {
     const uint32_t G = gridDim.x, g = blockIdx.x;
     const uint32_t logical = (g % 8u) * (G / 8u) + g / 8u;
     const uint64_t waves = (uint64_t)G * MC_WAVES;
     const uint64_t wv = (uint64_t)logical * MC_WAVES + (threadIdx.x >> 6);
     const uint64_t chunk = (n + waves - 1) / waves;
     lo = wv * chunk;
+    if (lo > n) lo = n;
     hi = lo + chunk < n ? lo + chunk : n;
+    return (uint32_t)wv;
 }
 
 // Corner masks of the 64 cells of a block from the sign masks of the block
