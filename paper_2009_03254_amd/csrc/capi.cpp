@@ -3,6 +3,7 @@
 #include "../../include/bcmc.h"
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -35,6 +36,7 @@ struct bcmc_volume {
     hipEvent_t ev[8] = {};
     int have_extract = 0;
     float last_iso = 0.0f;
+    float cull_iso = NAN;          // isovalue of the last cull (NaN: the flags are all zero)
 };
 
 namespace bcmc {
@@ -47,6 +49,12 @@ int volume_is_identity(const bcmc_volume *v) { return v->identity; }
 }  // namespace bcmc
 
 namespace {
+
+// After the ranges change: all flags zero, no tile culled before.
+void clear_flags(bcmc_volume *v, hipStream_t s) {
+    launch_fill_u32(reinterpret_cast<uint32_t *>(v->d.active), 0u, (v->g.nb + 3) / 4, s);
+    v->cull_iso = NAN;
+}
 
 int invalid(const std::string &msg) {
     set_error(msg);
@@ -262,6 +270,7 @@ int bcmc_load_compressed(const void *stream, uint64_t nbytes, int stream_is_devi
     }
     launch_decode_ranges(g, v->d.stream, v->is_f64, rate, v->d.ranges, nullptr, &v->d.ctr->err, s);
     launch_tile_ranges(g, v->d.ranges, v->d.tile_ranges, s);
+    clear_flags(v, s);
     if ((rc = sync_counters(v, s))) {
         destroy(v);
         return rc;
@@ -307,6 +316,7 @@ int bcmc_volume_from_blocks(const float *d_blocks, uint32_t nx, uint32_t ny, uin
     }
     launch_ranges_from_blocks(v->g, d_blocks, v->d.ranges, &v->d.ctr->err, s);
     launch_tile_ranges(v->g, v->d.ranges, v->d.tile_ranges, s);
+    clear_flags(v, s);
     if ((rc = sync_counters(v, s))) {
         destroy(v);
         return rc;
@@ -328,6 +338,7 @@ int bcmc_rebind_blocks(bcmc_volume *v, const float *d_blocks, void *hip_stream) 
     v->have_extract = 0;
     launch_ranges_from_blocks(v->g, d_blocks, v->d.ranges, &v->d.ctr->err, as_stream(hip_stream));
     launch_tile_ranges(v->g, v->d.ranges, v->d.tile_ranges, as_stream(hip_stream));
+    clear_flags(v, as_stream(hip_stream));
     BCMC_HIP_TRY(hipGetLastError());
     return BCMC_OK;
 }
@@ -368,7 +379,8 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     const bool prof = v->profiling;
     auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(v->ev[i], s) : hipSuccess; };
     BCMC_HIP_TRY(mark(0));
-    launch_cull(v->g, v->d, v->sl, iso, v->n_slots, v->identity, s);
+    launch_cull(v->g, v->d, v->sl, iso, v->cull_iso, v->n_slots, v->identity, s);
+    v->cull_iso = iso;
     launch_compact_blocks(v->g, v->d, v->sl, v->identity, s);
     BCMC_HIP_TRY(mark(1));
     if (!v->identity) {
@@ -376,7 +388,9 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
         const uint32_t age_cap = v->calls_since_reset;   // used slots are younger
         launch_slot_pass(v->d, v->sl, v->n_slots, age_cap, s);
         launch_plan_grow(v->d, v->max_slots, v->max_slots - v->n_slots, s);
-        launch_radix(v->d, v->sl, v->max_slots, age_cap, s);
+        // the first call after a reset finds every slot unused: all sort keys
+        // are 0 and the order is the slot order already
+        if (age_cap > 1) launch_radix(v->d, v->sl, v->max_slots, age_cap, s);
     }
     BCMC_HIP_TRY(mark(2));
     if (!v->identity) launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, iso, s);
@@ -389,7 +403,11 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     launch_mc_emit(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices,
                    v->vertex_format == BCMC_VERTEX_EDGE8, s);
     BCMC_HIP_TRY(mark(6));
-    BCMC_HIP_TRY(hipGetLastError());
+    if (hipError_t le = hipGetLastError()) {   // a launch failed: the flags are unknown
+        clear_flags(v, s);
+        set_error(std::string("extract launch: ") + hipGetErrorString(le));
+        return BCMC_E_HIP;
+    }
     int rc = sync_counters(v, s);
     if (rc) return rc;
     const Counters &c = *v->h_ctr;
@@ -504,6 +522,7 @@ int bcmc_decode_all(bcmc_volume *v, float *d_blocks, void *hip_stream) {
     launch_decode_ranges(v->g, v->d.stream, v->is_f64, v->rate, v->d.ranges, d_blocks,
                          &v->d.ctr->err, as_stream(hip_stream));
     launch_tile_ranges(v->g, v->d.ranges, v->d.tile_ranges, as_stream(hip_stream));
+    clear_flags(v, as_stream(hip_stream));
     BCMC_HIP_TRY(hipGetLastError());
     return BCMC_OK;
 }

@@ -102,7 +102,8 @@ struct StatusLayout {
 };
 
 // ---- launchers (extract.hip) -------------------------------------------
-void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
+// prev_iso: the previous cull's isovalue (NaN after the flags were cleared).
+void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
                  uint64_t n_slots_host, int identity_cache, hipStream_t s);
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
                            int identity_cache, hipStream_t s);

@@ -72,8 +72,12 @@ __global__ __launch_bounds__(256) void k_tile_ranges(Geom g, const float2 *__res
 
 // Flags per block: bit 0 active, bit 1 may emit, bit 2 active without a
 // slot (new, Alg. 1 MarkNewBlocks; never set for an identity cache).
+// prev_iso: the isovalue of the previous cull (NaN: none since the flags
+// were cleared).  The flags are zero outside the tiles that call culled, so
+// a tile live then and dead now is cleared here, a live tile is rewritten
+// in full, and no other flag is touched.
 __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
-                                             const float2 *__restrict__ tile_ranges,
+                                             float prev_iso, const float2 *__restrict__ tile_ranges,
                                              const int32_t *__restrict__ I_slot, int identity,
                                              uint8_t *__restrict__ active, Counters *ctr,
                                              uint64_t n_slots_host, uint64_t *status,
@@ -92,24 +96,34 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
 
     constexpr int NL = CULL_TZ + 2, RX = CULL_TX + 2, RY = CULL_TY + 2, SLOTS = RX * RY;
     __shared__ float2 sh[NL][RY][RX];
-    __shared__ uint32_t live[256];
-    __shared__ uint32_t n_live;
+    __shared__ uint32_t live[256], stale[256];
+    __shared__ uint32_t n_live, n_stale;
     const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
     const uint64_t n_tiles = (uint64_t)ntx * nty * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
     // The workgroup's tiles are blockIdx.x + gridDim.x * i; their hulls are
     // read 256 at a time, and only the tiles whose hull straddles iso are
-    // culled block by block (the flags of the others were cleared before
-    // this kernel)
+    // culled block by block
     const uint64_t G = gridDim.x;
     for (uint64_t i0 = 0; blockIdx.x + G * i0 < n_tiles; i0 += 256) {
-        if (threadIdx.x == 0) n_live = 0;
+        if (threadIdx.x == 0) n_live = n_stale = 0;
         __syncthreads();
         const uint64_t ti = blockIdx.x + G * (i0 + threadIdx.x);
         if (ti < n_tiles) {
             const float2 hull = tile_ranges[ti];
             if (hull.x < iso && iso <= hull.y) live[atomicAdd(&n_live, 1u)] = (uint32_t)ti;
+            else if (hull.x < prev_iso && prev_iso <= hull.y) stale[atomicAdd(&n_stale, 1u)] = (uint32_t)ti;
         }
         __syncthreads();
+        for (uint32_t k = 0; k < n_stale; k++) {   // clear the tiles culled last time only
+            uint32_t t = stale[k];
+            const uint32_t tx = t % ntx;
+            t /= ntx;
+            const uint32_t ty = t % nty, tz = t / nty;
+            const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+            const uint32_t bx = tx * CULL_TX + threadIdx.x % CULL_TX, by = ty * CULL_TY + threadIdx.x / CULL_TX;
+            if (bx < g.nbx && by < g.nby)
+                for (int z = z0; z < z1; z++) active[((uint64_t)z * g.nby + by) * g.nbx + bx] = 0;
+        }
         const uint32_t nl = n_live;
         for (uint32_t k = 0; k < nl; k++) {
             uint32_t t = live[k];
@@ -913,13 +927,13 @@ static unsigned mc_grid(uint64_t max_blocks) {
     return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
 }
 
-void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso,
+void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
                  uint64_t n_slots_host, int identity_cache, hipStream_t s) {
     static unsigned rgrid = 0;
     if (!rgrid) rgrid = resident_grid(k_cull, ~0ull >> 4);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(d.active), 0u, (g.nb + 3) / 4, s);
-    k_cull<<<(unsigned)std::min<uint64_t>(cull_tiles(g), rgrid), 256, 0, s>>>(g, d.ranges, iso, d.tile_ranges, d.I_slot, identity_cache,
-                                           d.active, d.ctr, n_slots_host, d.status, sl.total);
+    k_cull<<<(unsigned)std::min<uint64_t>(cull_tiles(g), rgrid), 256, 0, s>>>(
+        g, d.ranges, iso, prev_iso, d.tile_ranges, d.I_slot, identity_cache, d.active, d.ctr, n_slots_host,
+        d.status, sl.total);
 }
 
 uint64_t cull_tiles(const Geom &g) {

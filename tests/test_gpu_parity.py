@@ -255,3 +255,21 @@ def test_edge8_records_bitexact(bc, orc, dims, rate, seed):
     _extract_and_compare(bc, orc, vol, D, dims, iso)
     with pytest.raises(bc.BcmcError):
         vol.set_vertex_format(7)
+
+
+def test_flags_follow_tiles_across_isovalues(bc, orc):
+    """A ramp along x over three cull tiles: successive isovalues make
+    different tiles live, then none; the active flags (written only in live
+    tiles, cleared in tiles live the call before) match the oracle every
+    time."""
+    dims = (260, 70, 38)
+    nx, ny, nz = dims
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    f = np.broadcast_to(x + 0.25 * np.sin(0.7 * np.arange(ny))[None, :, None], (nz, ny, nx)).astype(np.float32)
+    s = orc.zfp_encode(np.ascontiguousarray(f), 8)
+    D = orc.zfp_decode(s, dims, 8)
+    vol = bc.Volume(s, dims, "f32", 8)
+    say(f"[flags] ramp {dims}")
+    for iso in (20.5, 200.5, 250.5, 20.5, -5.0, 130.5, 130.5):
+        T = _extract_and_compare(bc, orc, vol, D, dims, np.float32(iso), check_cells=False)
+        assert (T > 0) == (iso > 0), (iso, T)
