@@ -273,30 +273,46 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
     uint64_t oa = s_base >> 31, on = s_base & 0x7FFFFFFFull;
     const uint64_t wany0 = s_any[0][0] | s_any[1][0] | s_any[2][0] | s_any[3][0];
     const uint64_t wany1 = s_any[0][1] | s_any[1][1] | s_any[2][1] | s_any[3][1];
-    __shared__ uint32_t s_w[4];
-    for (uint32_t r = 0; r < m; r++) {
-        if (r < COMPACT_MAX_ROUNDS && !(((r < 64 ? wany0 : wany1) >> (r & 63)) & 1ull)) continue;
-        const uint64_t base = tbase + (uint64_t)BLK_TILE * r;
-        uint32_t actb, newb, unused = 0;
-        flag_bits(load_flags16(active, base, g.nb), actb, newb, unused);
-        const uint32_t packed = ((uint32_t)__popc(actb) << 16) | (uint32_t)__popc(newb);
-        // workgroup exclusive scan of the packed counts (each field < 2^16)
-        const uint32_t incl = wave_incl_scan(packed);
-        if (lane() == 63) s_w[threadIdx.x >> 6] = incl;
-        __syncthreads();
-        uint32_t woff = 0, tot = 0;
+    // 4 rounds at a time: their loads in flight together, one pair of
+    // barriers for the 4 workgroup scans
+    __shared__ uint32_t s_w[4][4];   // [round of the group][wave]
+    for (uint32_t r0 = 0; r0 < m; r0 += 4) {
+        bool use[4];
+        uint4 q[4];
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            if (i < (int)(threadIdx.x >> 6)) woff += s_w[i];
-            tot += s_w[i];
+        for (int k = 0; k < 4; k++) {
+            const uint32_t r = r0 + k;
+            use[k] = r < m && (r >= COMPACT_MAX_ROUNDS || (((r < 64 ? wany0 : wany1) >> (r & 63)) & 1ull));
+            q[k] = use[k] ? load_flags16(active, tbase + (uint64_t)BLK_TILE * r, g.nb)
+                          : make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (!(use[0] || use[1] || use[2] || use[3])) continue;   // uniform: wany is
+        uint32_t actb[4], newb[4], packed[4], incl[4], unused = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            flag_bits(q[k], actb[k], newb[k], unused);
+            packed[k] = ((uint32_t)__popc(actb[k]) << 16) | (uint32_t)__popc(newb[k]);
+            incl[k] = wave_incl_scan(packed[k]);   // workgroup scans (each field < 2^16)
+            if (lane() == 63) s_w[k][threadIdx.x >> 6] = incl[k];
         }
         __syncthreads();
-        const uint32_t ex = woff + incl - packed;
-        uint64_t pa = oa + (ex >> 16), pn = on + (ex & 0xFFFFu);
-        for (uint32_t mm = actb; mm; mm &= mm - 1) I_active[pa++] = (uint32_t)(base + __builtin_ctz(mm));
-        for (uint32_t mm = newb; mm; mm &= mm - 1) I_new[pn++] = (uint32_t)(base + __builtin_ctz(mm));
-        oa += tot >> 16;
-        on += tot & 0xFFFFu;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            uint32_t woff = 0, tot = 0;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                if (i < (int)(threadIdx.x >> 6)) woff += s_w[k][i];
+                tot += s_w[k][i];
+            }
+            const uint64_t base = tbase + (uint64_t)BLK_TILE * (r0 + k);
+            const uint32_t ex = woff + incl[k] - packed[k];
+            uint64_t pa = oa + (ex >> 16), pn = on + (ex & 0xFFFFu);
+            for (uint32_t mm = actb[k]; mm; mm &= mm - 1) I_active[pa++] = (uint32_t)(base + __builtin_ctz(mm));
+            for (uint32_t mm = newb[k]; mm; mm &= mm - 1) I_new[pn++] = (uint32_t)(base + __builtin_ctz(mm));
+            oa += tot >> 16;
+            on += tot & 0xFFFFu;
+        }
+        __syncthreads();
     }
     if (t == n_tiles - 1 && threadIdx.x == 0) {
         ctr->n_act = incl_end >> 31;
