@@ -201,10 +201,11 @@ BCMC_API int bcmc_copy_calibration(void *d_dst, const void *d_src, uint64_t nbyt
 /* A batch of jobs j = (volume job_vol[j], isovalue job_iso[j]) over
  * compressed volumes that share one scalar type (the volumes must outlive
  * the batch; their own caches are not used).  bcmc_batch_run extracts every
- * job in two persistent kernels (a front one that culls, lists, decodes and
- * builds sign masks; a back one that counts, scans and emits; phases
- * separated by grid barriers), replayed from a hipGraph when the runtime
- * allows it.  Job j's
+ * job in four launches: a persistent front kernel that culls and lists (its
+ * phases separated by grid barriers), a decode kernel that decodes the new
+ * blocks and builds sign masks, a count kernel, and an emission kernel in
+ * which each workgroup sums the count kernel's per-wave totals before it;
+ * replayed from a hipGraph when the runtime allows it.  Job j's
  * soup equals, byte for byte, bcmc_extract of its volume at its isovalue,
  * and the jobs' soups are concatenated in job order.  The batch keeps one
  * decoded-block store: a block needed by any job of its volume is decoded
@@ -226,10 +227,11 @@ typedef struct {
     int32_t graph_unsupported;/* 1: capturing the cooperative launch failed */
     float last_ms;            /* GPU time of the last run (HIP events) */
     float phase_ms[8];        /* the last run's phases (device clock at the grid
-                                 barriers): reset, flags, scan of the counts of new
-                                 blocks and pairs, list scatter, decode and masks,
-                                 count (with the gap between the kernels), count
-                                 scan, emission */
+                                 barriers and kernel ends): reset, flags, scan of
+                                 the counts of new blocks and pairs, list scatter,
+                                 decode and masks, count, the emission kernel's
+                                 prefix of the per-wave totals (each of the last
+                                 three with the gap before its kernel), emission */
 } bcmc_batch_info;
 
 BCMC_API int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t *job_vol,
