@@ -386,7 +386,7 @@ __global__ __launch_bounds__(BT) void k_batch_decode(BatchParams p) {
     const uint64_t n_new = p.ctr->n_new;
     extern __shared__ uint64_t stage_lds[];
     const int urate = (int)p.uniform_rate;
-    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGE_STRIDE * (STAGED ? urate : 0));
+    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGED ? stage_wave_words(urate, F64) : 0u);
     for (uint64_t i0 = gtid & ~63ull; i0 < n_new; i0 += gstride) {
         const uint64_t i = i0 + lane();
         bool valid = i < n_new;
@@ -626,8 +626,8 @@ const void *decode_kernel(int is_f64, int staged) {
     return staged ? (const void *)k_batch_decode<false, true> : (const void *)k_batch_decode<false, false>;
 }
 
-unsigned decode_lds(const BatchParams &p) {
-    return p.uniform_rate ? stage_lds_bytes((int)p.uniform_rate) : 0u;
+unsigned decode_lds(const BatchParams &p, int is_f64) {
+    return p.uniform_rate ? stage_lds_bytes((int)p.uniform_rate, is_f64 != 0) : 0u;
 }
 
 }  // namespace
@@ -643,7 +643,7 @@ int batch_front_per_cu(int *per_cu) {
 int batch_decode_per_cu(const BatchParams &p, int is_f64, int *per_cu) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, decode_kernel(is_f64, p.uniform_rate != 0), BT,
-                                                     decode_lds(p)) != hipSuccess)
+                                                     decode_lds(p, is_f64)) != hipSuccess)
         return -1;
     *per_cu = n;
     return 0;
@@ -667,7 +667,7 @@ hipError_t launch_batch(const BatchParams &p, int is_f64, int sb, const unsigned
                        ? hipLaunchCooperativeKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT),
                                                     args, 0, s)
                        : hipLaunchKernel((const void *)k_batch_front, dim3(grids[0]), dim3(BT), args, 0, s);
-    if (e == hipSuccess) e = hipLaunchKernel(decode, dim3(grids[1]), dim3(BT), args, decode_lds(p), s);
+    if (e == hipSuccess) e = hipLaunchKernel(decode, dim3(grids[1]), dim3(BT), args, decode_lds(p, is_f64), s);
     // count and back share one grid: they partition L the same way
     if (e == hipSuccess) e = hipLaunchKernel((const void *)k_batch_count, dim3(grids[2]), dim3(BT), args, 0, s);
     if (e == hipSuccess) e = hipLaunchKernel(back, dim3(grids[2]), dim3(BT), args, 0, s);

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_decode_ranges(Geom g, const uint64_t *_
                                                       unsigned int *err) {
     extern __shared__ uint64_t stage_lds[];
     constexpr bool staged = STAGED;
-    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGE_STRIDE * rate);
+    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGED ? stage_wave_words(rate, F64) : 0u);
     // whole waves iterate together (the staging is a wave-wide copy)
     for (uint64_t b0 = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); b0 < g.nb;
          b0 += (uint64_t)gridDim.x * blockDim.x) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
     const uint32_t *sorted = (__popc(ctr->pass_mask) & 1) ? sorted1 : sorted0;
     extern __shared__ uint64_t stage_lds[];
     constexpr bool staged = STAGED;
-    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGE_STRIDE * rate);
+    uint64_t *st = stage_lds + (threadIdx.x >> 6) * (STAGED ? stage_wave_words(rate, F64) : 0u);
     uint32_t evicted = 0;
     // whole waves iterate together (the staging is a wave-wide copy)
     for (uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~63u); i0 < n_new;
@@ -213,7 +213,7 @@ unsigned grid_for(uint64_t n, unsigned cap) {
 // staging LDS the rate needs.
 #define BCMC_DECODE_LAUNCH(KERNEL, grid, rate, s, ...)                                      \
     do {                                                                                    \
-        const unsigned lds_ = stage_lds_bytes((int)(rate));                                 \
+        const unsigned lds_ = stage_lds_bytes((int)(rate), is_f64 != 0);                                 \
         if (is_f64 && lds_) KERNEL<true, true><<<grid, 256, lds_, s>>>(__VA_ARGS__);         \
         else if (is_f64) KERNEL<true, false><<<grid, 256, 0, s>>>(__VA_ARGS__);              \
         else if (lds_) KERNEL<false, true><<<grid, 256, lds_, s>>>(__VA_ARGS__);             \

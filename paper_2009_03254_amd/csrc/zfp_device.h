@@ -57,7 +57,7 @@ __device__ __forceinline__ void fwd4(Int &a, Int &b, Int &c, Int &d) {
 }
 // Inverse: the same steps undone in reverse order.
 template <typename Int>
-__device__ __forceinline__ void inv4(Int &a, Int &b, Int &c, Int &d) {
+__host__ __device__ __forceinline__ void inv4(Int &a, Int &b, Int &c, Int &d) {
     using U = typename std::make_unsigned<Int>::type;
     b = (Int)((U)b + (U)(d >> 1)); d = (Int)((U)d - (U)(b >> 1));
     b = (Int)((U)b + (U)d); d = (Int)(((U)d << 1) - (U)b);
@@ -80,7 +80,7 @@ __device__ __forceinline__ void fwd_xyz(Int *v) {
 }
 
 template <typename Int>
-__device__ __forceinline__ void inv_zyx(Int *v) {
+__host__ __device__ __forceinline__ void inv_zyx(Int *v) {
 #pragma unroll
     for (int i = 0; i < 16; i++) inv4(v[i], v[i + 16], v[i + 32], v[i + 48]);
 #pragma unroll
@@ -92,6 +92,12 @@ __device__ __forceinline__ void inv_zyx(Int *v) {
     for (int i = 0; i < 16; i++) inv4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
 }
 
+// ---- staging layout ---------------------------------------------------------
+// A wave's staging area holds word w of lane l's block at st[w * STAGE_STRIDE + l]
+// (see stage_words below).
+constexpr int STAGE_STRIDE = 65;
+constexpr int STAGE_MAX_RATE = 16;   // larger rates decode from global memory
+
 // ---- bit reader over one block's words ------------------------------------
 // Word w of the block sits at p[w * STRIDE]: STRIDE = 1 reads the stream in
 // global memory, STRIDE = STAGE_STRIDE reads a wave's LDS staging area
@@ -102,23 +108,23 @@ struct BitReader {
     uint64_t cur;  // unread bits, LSB first; bits above cnt are zero
     int cnt;
 
-    __device__ __forceinline__ void refill() {
+    __host__ __device__ __forceinline__ void refill() {
         cur = *p;
         p += STRIDE;
         cnt = 64;
     }
-    __device__ __forceinline__ void skip(int n) {  // n <= cnt
+    __host__ __device__ __forceinline__ void skip(int n) {  // n <= cnt
         cur = (n >= 64) ? 0 : (cur >> n);
         cnt -= n;
     }
-    __device__ __forceinline__ uint32_t bit() {
+    __host__ __device__ __forceinline__ uint32_t bit() {
         if (cnt == 0) refill();
         uint32_t b = (uint32_t)(cur & 1u);
         cur >>= 1;
         cnt--;
         return b;
     }
-    __device__ __forceinline__ uint64_t read(int n) {  // 0 <= n <= 64
+    __host__ __device__ __forceinline__ uint64_t read(int n) {  // 0 <= n <= 64
         if (n <= cnt) {
             uint64_t v = (n >= 64) ? cur : (cur & ((1ull << n) - 1));
             skip(n);
@@ -135,12 +141,33 @@ struct BitReader {
     }
 };
 
+// One stage of an in-place 32x32 bit-matrix transpose (bit i of a[k] is
+// element (k, i)): within every 2J x 2J block the two off-diagonal J x J
+// blocks trade places.  M selects the bits i with (i & J) == 0.
+template <int J, uint32_t M>
+__host__ __device__ __forceinline__ void transpose_stage(uint32_t *a) {
+#pragma unroll
+    for (int k = 0; k < 32; k++) {
+        if (k & J) continue;
+        const uint32_t t = ((a[k] >> J) ^ a[k + J]) & M;
+        a[k] ^= t << J;
+        a[k + J] ^= t;
+    }
+}
+__host__ __device__ __forceinline__ void transpose32(uint32_t *a) {
+    transpose_stage<16, 0x0000FFFFu>(a);
+    transpose_stage<8, 0x00FF00FFu>(a);
+    transpose_stage<4, 0x0F0F0F0Fu>(a);
+    transpose_stage<2, 0x33333333u>(a);
+    transpose_stage<1, 0x55555555u>(a);
+}
+
 // Decode one block (64*rate bits read through `br`) into 64 floats in block
 // order.  The bits of bit plane k are deposited only into the coefficients
 // below n (the number of significant coefficients after the plane), in
 // groups of 8: higher coefficients have no bit in the plane.
 template <bool F64, class BR>
-__device__ __forceinline__ void decode_block_from(BR br, int rate, float *out) {
+__host__ __device__ __forceinline__ void decode_block_from(BR br, int rate, float *out) {
     using T = Prec<F64>;
     using UInt = typename T::UInt;
     using Int = typename T::Int;
@@ -212,9 +239,137 @@ __device__ __forceinline__ void decode_block_from(BR br, int rate, float *out) {
     }
 }
 
+// ---- single precision from a staging area: two passes ---------------------
+// Lanes of a wave decode different blocks, and the group tests of one plane
+// take a data-dependent number of steps, so a plane-by-plane decode makes
+// every lane wait for the wave's slowest lane in every plane.  Here a lane
+// first walks its whole stream on its own (pass 1), one group-test step per
+// iteration, recording for each plane only the length of its group-test
+// part and how far it advanced n; the coefficients found significant are
+// kept as one 64-bit set.  Pass 2 then rebuilds every plane word in
+// lockstep: plane k holds the stream bits of its first n_k coefficients,
+// read again at the plane's offset, and ones at the found coefficients in
+// [n_k, n_{k+1}) (the coefficients its group tests passed over; exactly one
+// plane visits each coefficient this way).  The 32 plane words become the
+// coefficients by two 32x32 bit transposes.
+//
+// Word w of the lane's block is st[w * STAGE_STRIDE]; rec holds the lane's
+// 16 record words (plane k's record is the low half of word k/2 for even k,
+// the high half for odd k: group-test bits in the low byte, the advance of n
+// in the high byte; whole words are written, an odd plane's record waits
+// for its even neighbour).
+constexpr int REC_STRIDE = 17;                    // 32-bit words per lane (odd: no bank conflicts)
+constexpr int REC_WORDS = 64 * REC_STRIDE / 2;    // 64-bit words of record area per wave
+
+// The 64 stream bits from bit offset off (< 64 * rate) on; bits past the
+// block's last word read as that word's (callers mask them).
+__host__ __device__ __forceinline__ uint64_t peek_staged(const uint64_t *st, int rate, int off) {
+    const int wi = off >> 6, sh = off & 63;
+    const int wj = wi + 1 < rate ? wi + 1 : rate - 1;
+    const uint64_t w0 = st[wi * STAGE_STRIDE], w1 = st[wj * STAGE_STRIDE];
+    return (w0 >> sh) | ((w1 << 1) << (63 - sh));
+}
+
+__host__ __device__ __forceinline__ int ctz64(uint64_t x) {   // x != 0
+    return (int)__builtin_ctzll(x);
+}
+
+__host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t *st, uint32_t *rec,
+                                                                 int rate, float *out) {
+    using T = Prec<false>;
+    const uint64_t head = st[0];
+    if (!(head & 1u)) {
+#pragma unroll
+        for (int i = 0; i < 64; i++) out[i] = 0.0f;
+        return;
+    }
+    const int emax = (int)((head >> 1) & 0xFFu) - T::BIAS;
+    const int end_bits = 64 * rate;
+    // ---- pass 1: group tests of every plane, lane by lane ----
+    int off = 1 + T::EBITS, budget = end_bits - off, n = 0, k = T::P - 1;
+    int gstart = 0, nstart = 0;
+    bool at_start = true;
+    uint64_t found = 0;
+    uint32_t pend = 0;   // record of the odd plane above, written with its even neighbour
+    while (k >= 0 && budget > 0) {
+        if (at_start) {   // skip the bits of the n significant coefficients
+            const int m = n < budget ? n : budget;
+            off += m;
+            budget -= m;
+            gstart = off;
+            nstart = n;
+            at_start = false;
+        }
+        bool end = true;
+        if (n < 64 && budget > 0) {
+            // one group test: a 0 ends the plane; a 1 is followed by zeros up
+            // to the next significant coefficient, which the run may not
+            // pass: coefficient 63 (implied) and the budget (the run stops
+            // where the bits end) bound it at lim
+            const uint64_t w = peek_staged(st, rate, off);
+            const int lim = (63 - n < budget - 1) ? 63 - n : budget - 1;
+            const int z = ctz64((w >> 1) | (1ull << lim));
+            const bool g = (w & 1u) != 0;
+            const int adv = g ? 2 + z - (z == lim ? 1 : 0) : 1;
+            off += adv;
+            budget -= adv;
+            if (g) {
+                found |= 1ull << (n + z);
+                n += z + 1;
+            }
+            end = !g || n == 64 || budget == 0;
+        }
+        if (end) {
+            const uint32_t r = (uint32_t)(off - gstart) | ((uint32_t)(n - nstart) << 8);
+            if (k & 1) pend = r;
+            else rec[k >> 1] = r | (pend << 16);
+            k--;
+            at_start = true;
+        }
+    }
+    const int kend = k + 1;   // planes kend..31 were visited
+    if (kend & 1) rec[kend >> 1] = pend << 16;
+    // ---- pass 2: plane words, in lockstep ----
+    uint32_t R[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) R[j] = rec[j];
+    uint32_t lo[32], hi[32];
+    int o = 1 + T::EBITS, nn = 0;
+    uint64_t below = 0;   // coefficients below nn
+#pragma unroll
+    for (int kk = T::P - 1; kk >= 0; kk--) {
+        uint64_t x = 0;
+        if (kk >= kend) {
+            const uint32_t rk = (kk & 1) ? (R[kk >> 1] >> 16) : (R[kk >> 1] & 0xFFFFu);
+            const int m = nn < end_bits - o ? nn : end_bits - o;
+            if (m > 0) x = peek_staged(st, rate, o) & (~0ull >> (64 - m));
+            const int nn2 = nn + (int)(rk >> 8);
+            const uint64_t below2 = nn2 >= 64 ? ~0ull : ((1ull << nn2) - 1);
+            x |= found & below2 & ~below;
+            below = below2;
+            nn = nn2;
+            o += m + (int)(rk & 0xFFu);
+        }
+        lo[kk] = (uint32_t)x;
+        hi[kk] = (uint32_t)(x >> 32);
+    }
+    transpose32(lo);
+    transpose32(hi);
+    int32_t v[64];
+#pragma unroll
+    for (int r = 0; r < 32; r++) {
+        v[kOrder.idx[r]] = (int32_t)((lo[r] ^ T::NB) - T::NB);
+        v[kOrder.idx[r + 32]] = (int32_t)((hi[r] ^ T::NB) - T::NB);
+    }
+    inv_zyx(v);
+    const float s = ldexpf(1.0f, emax - 30);
+#pragma unroll
+    for (int i = 0; i < 64; i++) out[i] = (float)v[i] * s;
+}
+
 // Decode one block straight from the stream in global memory.
 template <bool F64>
-__device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words, int rate,
+__host__ __device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words, int rate,
                                              float *out) {
     decode_block_from<F64>(BitReader<1>{words, 0, 0}, rate, out);
 }
@@ -227,8 +382,6 @@ __device__ __forceinline__ void decode_block(const uint64_t *__restrict__ words,
 // holds block b0 + l, the usual case: new blocks are listed in ascending
 // order) the copy reads one contiguous run of the stream, 512 bytes per
 // instruction; otherwise each lane copies its own block's words.
-constexpr int STAGE_STRIDE = 65;
-constexpr int STAGE_MAX_RATE = 16;   // larger rates decode from global memory
 
 // `words`: lane l's block's first word (rate words follow); the rate is
 // uniform over the wave.
@@ -264,16 +417,28 @@ __device__ __forceinline__ void stage_words(const uint64_t *__restrict__ stream,
     stage_words_at(stream + b * (uint64_t)rate, rate, valid, st);
 }
 
-// Decode lane l's block from the staging area written by stage_words.
+// 64-bit words of LDS one wave uses at `rate`: the staged words, then (for
+// single precision) the per-lane plane records of the two-pass decoder.
+__host__ __device__ inline unsigned stage_wave_words(int rate, bool f64) {
+    return (unsigned)(STAGE_STRIDE * rate + (f64 ? 0 : REC_WORDS));
+}
+
+// Decode lane l's block from the staging area (stage_wave_words(rate, F64)
+// words per wave) written by stage_words.
 template <bool F64>
-__device__ __forceinline__ void decode_block_staged(const uint64_t *st, int rate, float *out) {
-    decode_block_from<F64>(BitReader<STAGE_STRIDE>{st + __lane_id(), 0, 0}, rate, out);
+__device__ __forceinline__ void decode_block_staged(uint64_t *st, int rate, float *out) {
+    if constexpr (F64) {
+        decode_block_from<F64>(BitReader<STAGE_STRIDE>{st + __lane_id(), 0, 0}, rate, out);
+    } else {
+        uint32_t *rec = reinterpret_cast<uint32_t *>(st + STAGE_STRIDE * rate) + __lane_id() * REC_STRIDE;
+        decode_block_staged_f32(st + __lane_id(), rec, rate, out);
+    }
 }
 
 // Bytes of dynamic LDS a 256-thread workgroup needs for staging at `rate`
 // (0: the rate is decoded from global memory).
-__host__ __device__ inline unsigned stage_lds_bytes(int rate) {
-    return rate <= STAGE_MAX_RATE ? 4u * STAGE_STRIDE * (unsigned)rate * 8u : 0u;
+__host__ __device__ inline unsigned stage_lds_bytes(int rate, bool f64) {
+    return rate <= STAGE_MAX_RATE ? 4u * stage_wave_words(rate, f64) * 8u : 0u;
 }
 
 // ---- bit writer ------------------------------------------------------------

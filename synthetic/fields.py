@@ -31,6 +31,7 @@ __all__ = [
     "percentile_iso_torch",
     "channel_flow_slab",
     "CHANNEL_FLOW_DIMS",
+    "random_block_stream",
 ]
 
 # Large channel-flow-like volume: (nx, ny, nz) in voxels.
@@ -147,6 +148,30 @@ def batched_dims(n_volumes=48, seed=4, lo=32, hi=256):
     """Per-volume (nx, ny, nz), each axis an independent integer in [lo, hi]."""
     rng = np.random.default_rng(seed)
     return [tuple(int(v) for v in row) for row in rng.integers(lo, hi + 1, size=(n_volumes, 3))]
+
+
+def random_block_stream(dims, rate, is_f64=False, density=0.5, seed=0, exp_spread=20,
+                        zero_every=0):
+    """Random fixed-rate block words for a (nx, ny, nz) volume: every bit of
+    every block drawn independently with P(1) = density, except the block
+    header (the nonzero flag, set, and the biased exponent, drawn within
+    +-exp_spread of the bias so that every decoded value is finite).  With
+    zero_every > 0 every zero_every-th block is flagged all-zero.  Exercises
+    the decoders on bit patterns a smooth field rarely produces (long zero
+    runs, budgets that end inside a run).  Returns uint64 words, rate per
+    block, blocks x-fastest."""
+    nx, ny, nz = dims
+    nb = ((nx + 3) // 4) * ((ny + 3) // 4) * ((nz + 3) // 4)
+    rng = np.random.default_rng(seed)
+    bits = rng.random((nb, 64 * rate)) < density
+    ebits, bias = (11, 1023) if is_f64 else (8, 127)
+    e = bias + rng.integers(-exp_spread, exp_spread + 1, size=nb)
+    bits[:, 0] = True
+    for i in range(ebits):
+        bits[:, 1 + i] = ((e >> i) & 1).astype(bool)
+    if zero_every > 0:
+        bits[::zero_every, 0] = False
+    return np.packbits(bits, axis=1, bitorder="little").view("<u8").reshape(-1).copy()
 
 
 def percentile_iso(values, p):

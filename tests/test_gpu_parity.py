@@ -59,6 +59,38 @@ def test_encode_decode_bitexact(bc, orc, name, make, rate):
     vol.close()
 
 
+RANDOM_STREAMS = [
+    (1, False, 0.5), (3, False, 0.2), (5, False, 0.05), (8, False, 0.5), (8, False, 0.02),
+    (8, False, 0.9), (16, False, 0.3), (24, False, 0.1), (2, True, 0.5), (8, True, 0.05),
+]
+
+
+@pytest.mark.parametrize("rate,is64,density", RANDOM_STREAMS)
+def test_random_streams_decode_bitexact(bc, orc, rate, is64, density):
+    """Random block bits (finite exponents, some all-zero blocks): both GPU
+    decoders (the load-time one behind decode_all, and the one extraction
+    runs on new blocks) give the oracle's values bit for bit, on bit
+    patterns a smooth field rarely produces (long zero runs, budgets ending
+    inside a run, the implied last coefficient)."""
+    dims = (64, 48, 40)
+    say(f"[random stream] rate={rate} f64={is64} density={density}")
+    s = fields.random_block_stream(dims, rate, is64, density, seed=100 + rate, zero_every=13)
+    vol = bc.Volume(s, dims, "f64" if is64 else "f32", rate)
+    dec = vol.decode_all().cpu().numpy()
+    D = orc.zfp_decode(s, dims, rate, is64)
+    assert np.array_equal(dec.view(np.uint32), D.view(np.uint32))
+    # an extraction decodes every active block into the cache
+    iso = float(np.median(D))
+    T = _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=False)
+    assert T > 0
+    _, ids = vol.active()
+    I_slot, _, _ = vol.cache_state()
+    slots = vol.slot_data()
+    assert (I_slot[ids] >= 0).all()
+    assert np.array_equal(slots[I_slot[ids]].view(np.uint32), D[ids].view(np.uint32))
+    vol.close()
+
+
 def _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=True):
     import torch
     r = orc.mc_extract(D, dims, iso, want=("verts", "vblock", "cell_keys", "cases"))
