@@ -261,13 +261,15 @@ __host__ __device__ __forceinline__ void decode_block_from(BR br, int rate, floa
 constexpr int REC_STRIDE = 17;                    // 32-bit words per lane (odd: no bank conflicts)
 constexpr int REC_WORDS = 64 * REC_STRIDE / 2;    // 64-bit words of record area per wave
 
-// The 64 stream bits from bit offset off (< 64 * rate) on; bits past the
-// block's last word read as that word's (callers mask them).
-__host__ __device__ __forceinline__ uint64_t peek_staged(const uint64_t *st, int rate, int off) {
-    const int wi = off >> 6, sh = off & 63;
-    const int wj = wi + 1 < rate ? wi + 1 : rate - 1;
-    const uint64_t w0 = st[wi * STAGE_STRIDE], w1 = st[wj * STAGE_STRIDE];
-    return (w0 >> sh) | ((w1 << 1) << (63 - sh));
+// The 64 stream bits from bit offset off (< 64 * rate) on.  Reads words
+// off/64 and off/64 + 1: past the block's last word that is the first word
+// of the lane's record area (or of the next row of staging), in bounds of
+// the wave's LDS and masked out by every caller.
+__host__ __device__ __forceinline__ uint64_t peek_staged(const uint64_t *st, int off) {
+    const uint32_t wi = (uint32_t)off >> 6, sh = (uint32_t)off & 63u;
+    const uint64_t *p = st + wi * (uint32_t)STAGE_STRIDE;
+    const uint64_t w0 = p[0], w1 = p[STAGE_STRIDE];
+    return (w0 >> sh) | ((w1 << 1) << (63u - sh));
 }
 
 __host__ __device__ __forceinline__ int ctz64(uint64_t x) {   // x != 0
@@ -306,17 +308,15 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
             // to the next significant coefficient, which the run may not
             // pass: coefficient 63 (implied) and the budget (the run stops
             // where the bits end) bound it at lim
-            const uint64_t w = peek_staged(st, rate, off);
+            const uint64_t w = peek_staged(st, off);
             const int lim = (63 - n < budget - 1) ? 63 - n : budget - 1;
             const int z = ctz64((w >> 1) | (1ull << lim));
             const bool g = (w & 1u) != 0;
             const int adv = g ? 2 + z - (z == lim ? 1 : 0) : 1;
             off += adv;
             budget -= adv;
-            if (g) {
-                found |= 1ull << (n + z);
-                n += z + 1;
-            }
+            found |= (uint64_t)g << (n + z);
+            n += g ? z + 1 : 0;
             end = !g || n == 64 || budget == 0;
         }
         if (end) {
@@ -342,7 +342,7 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
         if (kk >= kend) {
             const uint32_t rk = (kk & 1) ? (R[kk >> 1] >> 16) : (R[kk >> 1] & 0xFFFFu);
             const int m = nn < end_bits - o ? nn : end_bits - o;
-            if (m > 0) x = peek_staged(st, rate, o) & (~0ull >> (64 - m));
+            if (m > 0) x = peek_staged(st, o) & (~0ull >> (64 - m));
             const int nn2 = nn + (int)(rk >> 8);
             const uint64_t below2 = nn2 >= 64 ? ~0ull : ((1ull << nn2) - 1);
             x |= found & below2 & ~below;
