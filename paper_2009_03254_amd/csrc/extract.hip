@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <numeric>
 
 #include "common.h"
 #include "mc_device.h"
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
                                              const int32_t *__restrict__ I_slot, int identity,
                                              uint8_t *__restrict__ active, Counters *ctr,
                                              uint64_t n_slots_host, uint64_t *status,
-                                             uint64_t status_words) {
+                                             uint64_t status_words, uint64_t tile_mul) {
     const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
     if (gid == 0) {
@@ -100,15 +101,18 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
     __shared__ uint32_t n_live, n_stale;
     const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
     const uint64_t n_tiles = (uint64_t)ntx * nty * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
-    // The workgroup's tiles are blockIdx.x + gridDim.x * i; their hulls are
-    // read 256 at a time, and only the tiles whose hull straddles iso are
-    // culled block by block
+    // The workgroup's tiles are (j * tile_mul) mod n_tiles for j = blockIdx.x
+    // + gridDim.x * i (tile_mul coprime with n_tiles: a permutation that
+    // spreads the runs of consecutive live tiles a surface makes over all
+    // workgroups); their hulls are read 256 at a time, and only the tiles
+    // whose hull straddles iso are culled block by block
     const uint64_t G = gridDim.x;
     for (uint64_t i0 = 0; blockIdx.x + G * i0 < n_tiles; i0 += 256) {
         if (threadIdx.x == 0) n_live = n_stale = 0;
         __syncthreads();
-        const uint64_t ti = blockIdx.x + G * (i0 + threadIdx.x);
-        if (ti < n_tiles) {
+        const uint64_t j = blockIdx.x + G * (i0 + threadIdx.x);
+        if (j < n_tiles) {
+            const uint64_t ti = (j * tile_mul) % n_tiles;
             const float2 hull = tile_ranges[ti];
             if (hull.x < iso && iso <= hull.y) live[atomicAdd(&n_live, 1u)] = (uint32_t)ti;
             else if (hull.x < prev_iso && prev_iso <= hull.y) stale[atomicAdd(&n_stale, 1u)] = (uint32_t)ti;
@@ -204,15 +208,22 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
 // (active << 31 | new) so one status word carries both.
 constexpr int COMPACT_MAX_ROUNDS = 128;   // rounds tracked one by one (more: all revisited)
 
+// Bit 0 of each byte of w, gathered into bits 0..3: the four bits land on
+// bits 21..24 of the product with no carries between them.
+__device__ __forceinline__ uint32_t byte_bits(uint32_t w) {
+    return (((w & 0x01010101u) * 0x00204081u) >> 21) & 0xFu;
+}
+
 __device__ __forceinline__ void flag_bits(uint4 q, uint32_t &actb, uint32_t &newb, uint32_t &cand) {
-    const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
     actb = newb = 0;
+    if ((q.x | q.y | q.z | q.w) == 0) return;   // the common case of a sparse volume
+    const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
-        const uint32_t f = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        if (f) actb |= 1u << j;
-        newb |= ((f >> 2) & 1u) << j;
-        cand += (f >> 1) & 1u;
+    for (int i = 0; i < 4; i++) {   // flags use bits 0..2 of each byte
+        const uint32_t w = wds[i];
+        actb |= byte_bits(w | (w >> 1) | (w >> 2)) << (4 * i);
+        newb |= byte_bits(w >> 2) << (4 * i);
+        cand += (uint32_t)__popc(w & 0x02020202u);
     }
 }
 
@@ -943,13 +954,22 @@ static unsigned mc_grid(uint64_t max_blocks) {
     return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
 }
 
+// A multiplier near 0.618 n, coprime with n: j -> (j * a) mod n permutes [0, n).
+static uint64_t coprime_mul(uint64_t n) {
+    if (n <= 2) return 1;
+    uint64_t a = (uint64_t)(0.6180339887 * (double)n) | 1u;
+    while (std::gcd(a, n) != 1) a += 2;
+    return a % n;
+}
+
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
                  uint64_t n_slots_host, int identity_cache, hipStream_t s) {
     static unsigned rgrid = 0;
     if (!rgrid) rgrid = resident_grid(k_cull, ~0ull >> 4);
-    k_cull<<<(unsigned)std::min<uint64_t>(cull_tiles(g), rgrid), 256, 0, s>>>(
+    const uint64_t nt = cull_tiles(g);
+    k_cull<<<(unsigned)std::min<uint64_t>(nt, rgrid), 256, 0, s>>>(
         g, d.ranges, iso, prev_iso, d.tile_ranges, d.I_slot, identity_cache, d.active, d.ctr, n_slots_host,
-        d.status, sl.total);
+        d.status, sl.total, coprime_mul(nt));
 }
 
 uint64_t cull_tiles(const Geom &g) {
