@@ -149,9 +149,9 @@ __host__ __device__ __forceinline__ void transpose_stage(uint32_t *a) {
 #pragma unroll
     for (int k = 0; k < 32; k++) {
         if (k & J) continue;
-        const uint32_t t = ((a[k] >> J) ^ a[k + J]) & M;
-        a[k] ^= t << J;
-        a[k + J] ^= t;
+        const uint32_t x = a[k], y = a[k + J];
+        a[k] = (x & M) | ((y << J) & ~M);       // bit-field inserts: one shift and
+        a[k + J] = ((x >> J) & M) | (y & ~M);   // one v_bfi_b32 per word
     }
 }
 __host__ __device__ __forceinline__ void transpose32(uint32_t *a) {
