@@ -521,6 +521,7 @@ __global__ __launch_bounds__(BT) void k_batch_count(BatchParams p) {
 // ---- back kernel: phases 6-7 ----------------------------------------------------
 struct BackShared {
     EmitShared emit;
+    uint64_t tab[256];   // the triangle table (per-lane lookups at LDS latency)
     uint64_t w64[2][BT / 64];
 };
 
@@ -535,6 +536,7 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
 
     // ---- phase 6: each workgroup sums the per-wave totals before its first
     // wave and all of them (no grid barrier: the counts are a kernel earlier)
+    for (int i = threadIdx.x; i < 256; i += BT) sh.tab[i] = p.mc_table[i];   // published by the barrier below
     const uint32_t W = gridDim.x * (BT / 64), wv0 = wv - (uint32_t)w;
     uint64_t before = 0, all = 0;
     for (uint32_t i = threadIdx.x; i < W; i += BT) {
@@ -614,7 +616,7 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
                 bz = bcast(lbz, jl[k]);
                 isok = __uint_as_float(bcast(__float_as_uint(liso), jl[k]));
             };
-            emit_batch<false>(nsb, info, sh.emit.tiles[w], p.mc_table, sh.emit, w, ob, p.out, p.cap);
+            emit_batch<false>(nsb, info, sh.emit.tiles[w], sh.tab, sh.emit, w, ob, p.out, p.cap);
         }
     }
     stamp_last(p, 8);

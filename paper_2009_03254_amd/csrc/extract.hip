@@ -734,6 +734,7 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
     __shared__ EmitSharedPlain sh;
     __shared__ uint64_t s_base[MC_WAVES];
     if (ctr->err) return;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];   // the barriers below publish it
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
     uint64_t lo, hi;
@@ -809,7 +810,7 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
                 const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
                                       bcast((uint32_t)boff, jl[k]);
                 emit_block<EDGE8>(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
-                                  sh.tiles[w][k], iso, mc_table, sh, w, base, out, cap);
+                                  sh.tiles[w][k], iso, sh.tab, sh, w, base, out, cap);
             }
         }
     }

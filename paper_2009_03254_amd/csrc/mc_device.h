@@ -505,10 +505,12 @@ struct EmitSharedT {
     float iso[MC_WAVES][SB];            // its isovalue
 };
 using EmitShared = EmitSharedT<MC_SB>;
-// The plain emission stages one block fewer: its LDS then fits 8 workgroups
-// per CU.
-constexpr int EMIT_SB = MC_SB - 1;
+// The plain emission stages two blocks fewer and keeps the triangle table in
+// LDS (a per-lane lookup per block that global memory serves only after the
+// staged slots have evicted it from L1): its LDS then fits 8 workgroups per CU.
+constexpr int EMIT_SB = MC_SB - 2;
 struct EmitSharedPlain {
+    uint64_t tab[256];
     float tiles[MC_WAVES][EMIT_SB][128];
     uint32_t tri[MC_WAVES][EMIT_TRIS];
 };
@@ -533,7 +535,7 @@ __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t b
                                            int w, uint64_t base, void *__restrict__ out, uint64_t cap) {
     const int l = lane();
     const int cs = tile_case(g, bx, by, bz, tile, iso);
-    const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table, L1-resident
+    const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table (LDS-resident for the callers)
     const uint32_t nt = (uint32_t)(tb >> 60);
     const uint32_t incl = wave_incl_scan(nt);
     const int total = 3 * (int)__shfl(incl, 63, 64);
@@ -635,7 +637,7 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
         float iso;
         info(k, g, b, bx, by, bz, iso);
         const int cs = tile_case(g, bx, by, bz, tiles[k], iso);
-        const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table, L1-resident
+        const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table (LDS-resident for the callers)
         const uint32_t nt = (uint32_t)(tb >> 60);
         const uint32_t incl = wave_incl_scan(nt);
         const uint32_t tot = __shfl(incl, 63, 64);
