@@ -34,6 +34,7 @@ struct bcmc_volume {
     int vertex_format = BCMC_VERTEX_F32;  // output records of bcmc_extract
     uint32_t calls_since_reset = 0;  // bounds the age of every slot used since the reset
     hipEvent_t ev[8] = {};
+    hipEvent_t ev_done = nullptr;  // after the counters' readback (polled, not slept on)
     int have_extract = 0;
     float last_iso = 0.0f;
     float cull_iso = NAN;          // isovalue of the last cull (NaN: the flags are all zero)
@@ -169,6 +170,7 @@ void destroy(bcmc_volume *v) {
     if (v->h_ctr) (void)hipHostFree(v->h_ctr);
     for (auto &e : v->ev)
         if (e) (void)hipEventDestroy(e);
+    if (v->ev_done) (void)hipEventDestroy(v->ev_done);
     delete v;
 }
 
@@ -214,9 +216,17 @@ int set_budget(bcmc_volume *v, uint64_t initial_bytes, uint64_t max_bytes, hipSt
 
 hipStream_t as_stream(void *p) { return reinterpret_cast<hipStream_t>(p); }
 
+// Reads the counters back.  The caller waits for them anyway, so the wait
+// polls an event instead of sleeping in the runtime (a sleeping wait adds
+// its wake-up latency to every call).
 int sync_counters(bcmc_volume *v, hipStream_t s) {
     BCMC_HIP_TRY(hipMemcpyAsync(v->h_ctr, v->d.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    BCMC_HIP_TRY(hipStreamSynchronize(s));
+    if (!v->ev_done) BCMC_HIP_TRY(hipEventCreateWithFlags(&v->ev_done, hipEventDisableTiming));
+    BCMC_HIP_TRY(hipEventRecord(v->ev_done, s));
+    hipError_t e;
+    while ((e = hipEventQuery(v->ev_done)) == hipErrorNotReady) {
+    }
+    BCMC_HIP_TRY(e);
     return BCMC_OK;
 }
 

@@ -239,7 +239,7 @@ __host__ __device__ __forceinline__ void decode_block_from(BR br, int rate, floa
     }
 }
 
-// ---- single precision from a staging area: two passes ---------------------
+// ---- decoding from a staging area: two passes -------------------------------
 // Lanes of a wave decode different blocks, and the group tests of one plane
 // take a data-dependent number of steps, so a plane-by-plane decode makes
 // every lane wait for the wave's slowest lane in every plane.  Here a lane
@@ -250,16 +250,20 @@ __host__ __device__ __forceinline__ void decode_block_from(BR br, int rate, floa
 // lockstep: plane k holds the stream bits of its first n_k coefficients,
 // read again at the plane's offset, and ones at the found coefficients in
 // [n_k, n_{k+1}) (the coefficients its group tests passed over; exactly one
-// plane visits each coefficient this way).  The 32 plane words become the
-// coefficients by two 32x32 bit transposes.
+// plane visits each coefficient this way).  Single precision turns its 32
+// plane words into the coefficients by two 32x32 bit transposes; double
+// precision deposits each plane word into the coefficients below n_{k+1}.
 //
 // Word w of the lane's block is st[w * STAGE_STRIDE]; rec holds the lane's
-// 16 record words (plane k's record is the low half of word k/2 for even k,
-// the high half for odd k: group-test bits in the low byte, the advance of n
-// in the high byte; whole words are written, an odd plane's record waits
-// for its even neighbour).
-constexpr int REC_STRIDE = 17;                    // 32-bit words per lane (odd: no bank conflicts)
-constexpr int REC_WORDS = 64 * REC_STRIDE / 2;    // 64-bit words of record area per wave
+// P/2 record words (plane k's record is the low half of word k/2 for even
+// k, the high half for odd k: group-test bits in the low byte, the advance
+// of n in the high byte; whole words are written, an odd plane's record
+// waits for its even neighbour).
+template <bool F64>
+struct RecLayout {
+    static constexpr int STRIDE = Prec<F64>::P / 2 + 1;   // 32-bit words per lane (odd: no bank conflicts)
+    static constexpr int WORDS = 64 * STRIDE / 2;          // 64-bit words of record area per wave
+};
 
 // The 64 stream bits from bit offset off (< 64 * rate) on.  Reads words
 // off/64 and off/64 + 1: past the block's last word that is the first word
@@ -276,18 +280,13 @@ __host__ __device__ __forceinline__ int ctz64(uint64_t x) {   // x != 0
     return (int)__builtin_ctzll(x);
 }
 
-__host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t *st, uint32_t *rec,
-                                                                 int rate, float *out) {
-    using T = Prec<false>;
-    const uint64_t head = st[0];
-    if (!(head & 1u)) {
-#pragma unroll
-        for (int i = 0; i < 64; i++) out[i] = 0.0f;
-        return;
-    }
-    const int emax = (int)((head >> 1) & 0xFFu) - T::BIAS;
+// Pass 1 (after a nonzero block header): returns the found set; kend is the
+// lowest plane visited, and the records of planes kend..P-1 are written.
+template <bool F64>
+__host__ __device__ __forceinline__ uint64_t staged_pass1(const uint64_t *st, uint32_t *rec, int rate,
+                                                          int &kend) {
+    using T = Prec<F64>;
     const int end_bits = 64 * rate;
-    // ---- pass 1: group tests of every plane, lane by lane ----
     int off = 1 + T::EBITS, budget = end_bits - off, n = 0, k = T::P - 1;
     int gstart = 0, nstart = 0;
     bool at_start = true;
@@ -327,8 +326,24 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
             at_start = true;
         }
     }
-    const int kend = k + 1;   // planes kend..31 were visited
+    kend = k + 1;
     if (kend & 1) rec[kend >> 1] = pend << 16;
+    return found;
+}
+
+__host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t *st, uint32_t *rec,
+                                                                 int rate, float *out) {
+    using T = Prec<false>;
+    const uint64_t head = st[0];
+    if (!(head & 1u)) {
+#pragma unroll
+        for (int i = 0; i < 64; i++) out[i] = 0.0f;
+        return;
+    }
+    const int emax = (int)((head >> 1) & 0xFFu) - T::BIAS;
+    const int end_bits = 64 * rate;
+    int kend;
+    const uint64_t found = staged_pass1<false>(st, rec, rate, kend);
     // ---- pass 2: plane words, in lockstep ----
     uint32_t R[16];
 #pragma unroll
@@ -365,6 +380,55 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
     const float s = ldexpf(1.0f, emax - 30);
 #pragma unroll
     for (int i = 0; i < 64; i++) out[i] = (float)v[i] * s;
+}
+
+__host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t *st, uint32_t *rec,
+                                                                 int rate, float *out) {
+    using T = Prec<true>;
+    const uint64_t head = st[0];
+    if (!(head & 1u)) {
+#pragma unroll
+        for (int i = 0; i < 64; i++) out[i] = 0.0f;
+        return;
+    }
+    const int emax = (int)((head >> 1) & 0x7FFu) - T::BIAS;
+    const int end_bits = 64 * rate;
+    int kend;
+    const uint64_t found = staged_pass1<true>(st, rec, rate, kend);
+    // ---- pass 2: plane words in lockstep, each deposited into the
+    // coefficients below n_{k+1} in groups of 8 ----
+    uint64_t c[64];
+#pragma unroll
+    for (int i = 0; i < 64; i++) c[i] = 0;
+    int o = 1 + T::EBITS, nn = 0;
+    uint64_t below = 0;
+    for (int kk = T::P - 1; kk >= kend; kk--) {
+        const uint32_t rw = rec[kk >> 1], rk = (kk & 1) ? (rw >> 16) : (rw & 0xFFFFu);
+        const int m = nn < end_bits - o ? nn : end_bits - o;
+        uint64_t x = m > 0 ? peek_staged(st, o) & (~0ull >> (64 - m)) : 0ull;
+        const int nn2 = nn + (int)(rk >> 8);
+        const uint64_t below2 = nn2 >= 64 ? ~0ull : ((1ull << nn2) - 1);
+        x |= found & below2 & ~below;
+        below = below2;
+        nn = nn2;
+        o += m + (int)(rk & 0xFFu);
+        const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+#pragma unroll
+        for (int g = 0; g < 8; g++) {
+            if (nn > 8 * g) {
+                const uint32_t wv = g < 4 ? xl : xh;
+#pragma unroll
+                for (int i = 8 * g; i < 8 * g + 8; i++) c[i] |= (uint64_t)((wv >> (i & 31)) & 1u) << kk;
+            }
+        }
+    }
+    int64_t v[64];
+#pragma unroll
+    for (int r = 0; r < 64; r++) v[kOrder.idx[r]] = (int64_t)((c[r] ^ T::NB) - T::NB);
+    inv_zyx(v);
+    const double s = ldexp(1.0, emax - 62);
+#pragma unroll
+    for (int i = 0; i < 64; i++) out[i] = (float)((double)v[i] * s);
 }
 
 // Decode one block straight from the stream in global memory.
@@ -417,22 +481,19 @@ __device__ __forceinline__ void stage_words(const uint64_t *__restrict__ stream,
     stage_words_at(stream + b * (uint64_t)rate, rate, valid, st);
 }
 
-// 64-bit words of LDS one wave uses at `rate`: the staged words, then (for
-// single precision) the per-lane plane records of the two-pass decoder.
+// 64-bit words of LDS one wave uses at `rate`: the staged words, then the
+// per-lane plane records of the two-pass decoder.
 __host__ __device__ inline unsigned stage_wave_words(int rate, bool f64) {
-    return (unsigned)(STAGE_STRIDE * rate + (f64 ? 0 : REC_WORDS));
+    return (unsigned)(STAGE_STRIDE * rate + (f64 ? RecLayout<true>::WORDS : RecLayout<false>::WORDS));
 }
 
 // Decode lane l's block from the staging area (stage_wave_words(rate, F64)
 // words per wave) written by stage_words.
 template <bool F64>
 __device__ __forceinline__ void decode_block_staged(uint64_t *st, int rate, float *out) {
-    if constexpr (F64) {
-        decode_block_from<F64>(BitReader<STAGE_STRIDE>{st + __lane_id(), 0, 0}, rate, out);
-    } else {
-        uint32_t *rec = reinterpret_cast<uint32_t *>(st + STAGE_STRIDE * rate) + __lane_id() * REC_STRIDE;
-        decode_block_staged_f32(st + __lane_id(), rec, rate, out);
-    }
+    uint32_t *rec = reinterpret_cast<uint32_t *>(st + STAGE_STRIDE * rate) + __lane_id() * RecLayout<F64>::STRIDE;
+    if constexpr (F64) decode_block_staged_f64(st + __lane_id(), rec, rate, out);
+    else decode_block_staged_f32(st + __lane_id(), rec, rate, out);
 }
 
 // Bytes of dynamic LDS a 256-thread workgroup needs for staging at `rate`

@@ -1,7 +1,7 @@
 // Host build of the library's block decoders (the device header compiled for
 // the CPU), checked value for value against the oracle's decoder on random
 // block bits at every rate: the plain plane-by-plane decoder for both
-// precisions, and the two-pass single-precision decoder over an emulated
+// precisions, and the two-pass decoders of both precisions over an emulated
 // LDS staging area (one lane's view; the row past the block's words holds
 // garbage, as the next row or the record area does on the GPU).
 // Exit status 0 iff every value matches bit for bit.
@@ -52,13 +52,14 @@ int main() {
                 }
                 long n1 = 0, n2 = 0;
                 for (size_t i = 0; i < got.size(); i++) n1 += memcmp(&got[i], &ref[i], 4) != 0;
-                if (!f64 && rate <= bcmc::STAGE_MAX_RATE) {
+                if (rate <= bcmc::STAGE_MAX_RATE) {
                     std::vector<uint64_t> st((size_t)bcmc::STAGE_STRIDE * (rate + 1), 0x5A5A5A5A5A5A5A5Aull);
-                    uint32_t rec[bcmc::REC_STRIDE];
+                    uint32_t rec[bcmc::RecLayout<true>::STRIDE];
                     for (int b = 0; b < nb; b++) {
                         for (int w = 0; w < rate; w++) st[(size_t)w * bcmc::STAGE_STRIDE] = s[(size_t)b * rate + w];
                         for (auto &r : rec) r = 0xDEADBEEFu;   // written before read
-                        bcmc::decode_block_staged_f32(st.data(), rec, rate, got.data() + (size_t)b * 64);
+                        if (f64) bcmc::decode_block_staged_f64(st.data(), rec, rate, got.data() + (size_t)b * 64);
+                        else bcmc::decode_block_staged_f32(st.data(), rec, rate, got.data() + (size_t)b * 64);
                     }
                     for (size_t i = 0; i < got.size(); i++) n2 += memcmp(&got[i], &ref[i], 4) != 0;
                 }

@@ -1,9 +1,9 @@
 """The library's ZFP block decoders (device code, compiled here for the
 host) against the oracle's decoder, bit for bit, on random block bits at
 rates 1..32: long zero runs, budgets that end inside a group test, the
-implied last coefficient.  Covers the plane-by-plane decoder (both
-precisions) and the two-pass single-precision decoder the staged kernels
-run.  No GPU needed; skipped when hipcc is absent."""
+implied last coefficient.  Covers the plane-by-plane decoder and the
+two-pass decoder the staged kernels run, both precisions.  No GPU needed;
+skipped when hipcc is absent."""
 import os
 import subprocess
 import tempfile
