@@ -294,7 +294,7 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
     b->p.uniform_rate = hv[0].rate;
     for (uint32_t v = 1; v < n_vols; v++)
         if (hv[v].rate != hv[0].rate) b->p.uniform_rate = 0;
-    if (b->p.uniform_rate > (uint32_t)STAGE_MAX_RATE) b->p.uniform_rate = 0;
+    if (stage_lds_bytes((int)b->p.uniform_rate, f64 != 0) == 0) b->p.uniform_rate = 0;   // not staged
     if (batch_front_per_cu(&pcf) != 0 || pcf < 1 || batch_decode_per_cu(b->p, f64, &pcd) != 0 || pcd < 1) {
         destroy_batch(b);
         return binvalid("the batched kernel cannot be made resident");

@@ -497,9 +497,14 @@ __device__ __forceinline__ void decode_block_staged(uint64_t *st, int rate, floa
 }
 
 // Bytes of dynamic LDS a 256-thread workgroup needs for staging at `rate`
-// (0: the rate is decoded from global memory).
+// (0: the rate is decoded from global memory: above STAGE_MAX_RATE, or when
+// the staged words and records would pass 64 KB, as double precision does
+// at rate 16).
+constexpr unsigned STAGE_MAX_LDS = 64u * 1024u;
 __host__ __device__ inline unsigned stage_lds_bytes(int rate, bool f64) {
-    return rate <= STAGE_MAX_RATE ? 4u * stage_wave_words(rate, f64) * 8u : 0u;
+    if (rate < 1 || rate > STAGE_MAX_RATE) return 0u;
+    const unsigned b = 4u * stage_wave_words(rate, f64) * 8u;
+    return b <= STAGE_MAX_LDS ? b : 0u;
 }
 
 // ---- bit writer ------------------------------------------------------------

@@ -62,6 +62,7 @@ def test_encode_decode_bitexact(bc, orc, name, make, rate):
 RANDOM_STREAMS = [
     (1, False, 0.5), (3, False, 0.2), (5, False, 0.05), (8, False, 0.5), (8, False, 0.02),
     (8, False, 0.9), (16, False, 0.3), (24, False, 0.1), (2, True, 0.5), (8, True, 0.05),
+    (12, True, 0.3), (16, True, 0.3),
 ]
 
 
