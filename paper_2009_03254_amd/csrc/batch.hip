@@ -539,10 +539,15 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
     for (int i = threadIdx.x; i < 256; i += BT) sh.tab[i] = p.mc_table[i];   // published by the barrier below
     const uint32_t W = gridDim.x * (BT / 64), wv0 = wv - (uint32_t)w;
     uint64_t before = 0, all = 0;
-    for (uint32_t i = threadIdx.x; i < W; i += BT) {
-        const uint64_t v = p.part_wave[i];
-        all += v;
-        if (i < wv0) before += v;
+    for (uint32_t i0 = threadIdx.x; i0 < W; i0 += 8u * BT) {   // 8 loads in flight at a time
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = i0 + (uint32_t)j * BT < W ? p.part_wave[i0 + (uint32_t)j * BT] : 0ull;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            all += v[j];
+            if (i0 + (uint32_t)j * BT < wv0) before += v[j];
+        }
     }
     before = wave_sum(before);
     all = wave_sum(all);
