@@ -266,9 +266,9 @@ struct RecLayout {
 };
 
 // The 64 stream bits from bit offset off (< 64 * rate) on.  Reads words
-// off/64 and off/64 + 1: past the block's last word that is the first word
-// of the lane's record area (or of the next row of staging), in bounds of
-// the wave's LDS and masked out by every caller.
+// off/64 and off/64 + 1: the word past the block's last one lies in the
+// wave's record area (which follows the staged words), in bounds of the
+// wave's LDS; its bits are masked out by every caller.
 __host__ __device__ __forceinline__ uint64_t peek_staged(const uint64_t *st, int off) {
     const uint32_t wi = (uint32_t)off >> 6, sh = (uint32_t)off & 63u;
     const uint64_t *p = st + wi * (uint32_t)STAGE_STRIDE;
