@@ -91,14 +91,16 @@ typedef struct {
     uint64_t calls;        /* extract calls on this handle */
     double hit_rate;       /* 1 - n_new / n_active (1 when nothing is active) */
     double alg_bytes;      /* 8*N_b + n_new*(8*rate+256) + 256*n_active + 24*T */
-    double stage_ms[8];    /* with profiling on (HIP events on the stream):
+    double stage_ms[8];    /* for the profiled stages (HIP events on the
+                              stream; 0 for stages not profiled):
                               [0] cull + active/new compaction,
                               [1] cache update (slot pass, growth, age sort),
                               [2] assign + decode of new blocks,
                               [3] sign masks + marching cubes count pass,
                               [4] empty (the block offsets are formed by the
                               emission pass from the count pass's per-wave
-                              totals), [5] emission pass, [6] unused, [7] total */
+                              totals), [5] emission pass, [6] unused, [7] total
+                              (when stages 0 and 5 are both profiled) */
 } bcmc_stats;
 
 /* Upload a fixed-rate ZFP stream (Sec. 4: "uploading the compressed data to
@@ -169,8 +171,16 @@ BCMC_API int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_
                   float *d_dfield, float *d_diso, void *hip_stream);
 
 BCMC_API int bcmc_get_stats(const bcmc_volume *v, bcmc_stats *out);
-/* 1 = record per-stage HIP events in bcmc_extract (bcmc_stats.stage_ms). */
+/* Nonzero: record HIP events around every stage of bcmc_extract
+ * (bcmc_stats.stage_ms); 0: none.  Same as bcmc_set_profiling_stages with
+ * BCMC_PROFILE_ALL or 0. */
 BCMC_API int bcmc_set_profiling(bcmc_volume *v, int on);
+/* Record HIP events only around the stages whose bit is set in stage_mask
+ * (bit i = stage_ms[i], i < 6).  Each event costs a few microseconds of
+ * stream time, so timing one kernel inside a measured loop profiles only
+ * its stage.  Errors: BCMC_E_INVALID (bits above 5), BCMC_E_HIP. */
+#define BCMC_PROFILE_ALL 0x3Fu
+BCMC_API int bcmc_set_profiling_stages(bcmc_volume *v, uint32_t stage_mask);
 BCMC_API void bcmc_free(bcmc_volume *v);
 /* Message of the last error on this thread (empty when none). */
 BCMC_API const char *bcmc_last_error(void);

@@ -169,8 +169,16 @@ class _Handle:
         _capi.check(lib().bcmc_set_vertex_format(self._h, code))
         self._vfmt = code
 
-    def set_profiling(self, on=True):
-        _capi.check(lib().bcmc_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on=True, stages=None):
+        """HIP events around every extract stage (on), none (off), or only
+        around the stages listed in `stages` (indices into stats()["stage_ms"])."""
+        if stages is None:
+            _capi.check(lib().bcmc_set_profiling(self._h, 1 if on else 0))
+        else:
+            mask = 0
+            for i in stages:
+                mask |= 1 << int(i)
+            _capi.check(lib().bcmc_set_profiling_stages(self._h, mask if on else 0))
 
     def _alloc_out(self, cap):
         torch = _torch()

@@ -62,6 +62,7 @@ SIGNATURES = {
     "bcmc_backward": (_int, [_P, _f32, _P, _u64, _P, _P, _P]),
     "bcmc_get_stats": (_int, [_P, _P]),
     "bcmc_set_profiling": (_int, [_P, _int]),
+    "bcmc_set_profiling_stages": (_int, [_P, _u32]),
     "bcmc_set_vertex_format": (_int, [_P, _int]),
     "bcmc_free": (None, [_P]),
     "bcmc_last_error": (C.c_char_p, []),

@@ -30,7 +30,7 @@ struct bcmc_volume {
     uint64_t init_slots = 0, max_slots = 0, n_slots = 0;  // host mirror
     Counters *h_ctr = nullptr;     // pinned copy of the device counters
     bcmc_stats stats{};
-    int profiling = 0;
+    uint32_t profiling = 0;   // stage mask (bit i: events around stage i)
     int vertex_format = BCMC_VERTEX_F32;  // output records of bcmc_extract
     uint32_t calls_since_reset = 0;  // bounds the age of every slot used since the reset
     hipEvent_t ev[8] = {};
@@ -372,12 +372,17 @@ int bcmc_set_vertex_format(bcmc_volume *v, int format) {
     return BCMC_OK;
 }
 
-int bcmc_set_profiling(bcmc_volume *v, int on) {
+int bcmc_set_profiling_stages(bcmc_volume *v, uint32_t stage_mask) {
     if (!v) return invalid("null handle");
-    if (on && !v->ev[0])
+    if (stage_mask & ~BCMC_PROFILE_ALL) return invalid("stage mask has bits beyond stage 5");
+    if (stage_mask && !v->ev[0])
         for (auto &e : v->ev) BCMC_HIP_TRY(hipEventCreate(&e));
-    v->profiling = on;
+    v->profiling = stage_mask;
     return BCMC_OK;
+}
+
+int bcmc_set_profiling(bcmc_volume *v, int on) {
+    return bcmc_set_profiling_stages(v, on ? BCMC_PROFILE_ALL : 0u);
 }
 
 int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_vertices,
@@ -386,8 +391,11 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     if (!d_out && capacity_vertices) return invalid("null output buffer with nonzero capacity");
     if (iso != iso) return invalid("iso is NaN");
     hipStream_t s = as_stream(hip_stream);
-    const bool prof = v->profiling;
-    auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(v->ev[i], s) : hipSuccess; };
+    // event i opens stage i and closes stage i - 1: record it when either is profiled
+    const uint32_t prof = v->profiling, marks = prof | (prof << 1);
+    auto mark = [&](int i) -> hipError_t {
+        return (marks >> i) & 1u ? hipEventRecord(v->ev[i], s) : hipSuccess;
+    };
     BCMC_HIP_TRY(mark(0));
     launch_cull(v->g, v->d, v->sl, iso, v->cull_iso, v->n_slots, v->identity, s);
     v->cull_iso = iso;
@@ -452,12 +460,13 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     st.alg_bytes = 8.0 * v->g.nb + (double)st.n_new * (8.0 * v->rate + 256.0) +
                    256.0 * (double)c.n_act + 24.0 * (double)T;
     for (int i = 0; i < 8; i++) st.stage_ms[i] = 0.0;
-    if (prof) {
-        for (int i = 0; i < 6; i++) {
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, v->ev[i], v->ev[i + 1]);
-            st.stage_ms[i] = ms;
-        }
+    for (int i = 0; i < 6; i++) {
+        if (!((prof >> i) & 1u)) continue;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, v->ev[i], v->ev[i + 1]);
+        st.stage_ms[i] = ms;
+    }
+    if ((prof & 1u) && (prof & (1u << 5))) {
         float tot = 0;
         (void)hipEventElapsedTime(&tot, v->ev[0], v->ev[6]);
         st.stage_ms[7] = tot;

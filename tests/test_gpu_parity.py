@@ -233,6 +233,37 @@ def test_invalid_arguments(bc, orc):
     vol = bc.Volume(s, (8, 8, 8), "f32", 4)   # all-zero stream: valid, no surface
     v, T = vol.extract(0.5)
     assert T == 0
+    with pytest.raises(bc.BcmcError):
+        vol.set_profiling(True, stages=[6])
+
+
+def test_profiling_stage_mask(bc, orc):
+    say("[profile] 48^3 sphere, rate 8: stage mask selects which stage times exist")
+    f = fields.sphere_sdf_noisy(48, 15.0, 0.5, seed=4)
+    s = orc.zfp_encode(f, 8)
+    vol = bc.Volume(s, (48, 48, 48), "f32", 8)
+    vol.set_profiling(True)
+    v_all, T_all = vol.extract(0.0)
+    st = vol.stats()["stage_ms"]
+    assert all(st[i] > 0 for i in (0, 2, 3, 5)) and st[7] >= st[5] > 0
+    vol.reset_cache()
+    vol.set_profiling(True, stages=[5])
+    v5, T5 = vol.extract(0.0)
+    st = vol.stats()["stage_ms"]
+    assert st[5] > 0 and all(st[i] == 0 for i in (0, 1, 2, 3, 4, 6, 7))
+    assert T5 == T_all and _same_soup(v5, v_all)
+    vol.set_profiling(False)
+    vol.reset_cache()
+    v0, T0 = vol.extract(0.0)
+    assert all(x == 0 for x in vol.stats()["stage_ms"]) and T0 == T_all and _same_soup(v0, v_all)
+
+
+def _same_soup(a, b):
+    """Same triangles as a set (rows of whole triangles, order free)."""
+    def rows(v):
+        r = v.cpu().numpy().reshape(-1, 12)
+        return r[np.lexsort(r.T[::-1])]
+    return np.array_equal(rows(a), rows(b))
 
 
 def test_mc_single_cells_all_cases(bc, orc):

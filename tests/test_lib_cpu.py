@@ -63,6 +63,8 @@ def test_validation_before_device_work(L):
     assert b"rate" in L.bcmc_last_error() or len(L.bcmc_last_error()) > 0
     assert L.bcmc_extract(None, C.c_float(0.0), None, 0, None, None) == -1
     assert L.bcmc_encode(None, 0, 4, 4, 4, 8, None, None) == -1
+    assert L.bcmc_set_profiling(None, 1) == -1
+    assert L.bcmc_set_profiling_stages(None, 0x20) == -1
 
 
 def test_generated_triangle_count_circuit(L, orc):
