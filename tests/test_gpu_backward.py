@@ -33,7 +33,7 @@ def test_backward_matches_oracle(orc, n, radius):
     loss.backward()
     vg = orc.verts_global(r["verts"], r["vblock"], dims)
     L, gV = orc.sphere_loss(vg, c, radius)
-    assert float(loss) == pytest.approx(L, rel=1e-5)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-5)
     df, di = orc.mc_backward(B, dims, iso, gV)
     got = blocks.grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(got - df) <= 1e-4 * np.linalg.norm(df)

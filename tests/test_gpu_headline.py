@@ -1,0 +1,172 @@
+"""GPU parity at full size on the 512^3 float32 turbulence field, ZFP rate 8,
+in the call sequence the throughput measurement times: the cache is emptied,
+then p50 (cold), p90, p50 (warm), p50 (repeat), with an initial cache of a
+quarter of the blocks that grows on demand.
+
+The field is generated on the GPU and copied to the host, so the oracle's
+inputs come from the generator, never from the GPU path.  The isovalues are
+percentiles of the generated field.  The oracle cannot run every block fast
+enough, so sampled blocks are compared bit for bit (encode, decode, cull
+rule, plain marching cubes over the decoded 3x3x3 neighbourhood) with the
+GPU's stream words, flags, per-block counts and the block's slice of the
+triangle soup.  Properties that hold at any size (counts, offsets, totals,
+vertex bounds, the cache's hit and miss counts across the sequence) are
+checked on the whole output of every call."""
+import numpy as np
+import pytest
+
+from synthetic import fields
+from tests.gpu_common import say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+N = 512
+RATE = 8
+
+
+def _samples(f, iso, rng, n_surface, n_loose, nbx):
+    """Blocks away from the border: n_surface whose 5^3 samples (the block
+    and its +x/+y/+z halo) straddle iso in the generated field, n_loose
+    uniform."""
+    out = []
+    tries = 0
+    while len(out) < n_surface and tries < 20000:
+        tries += 1
+        b = tuple(int(x) for x in rng.integers(1, nbx - 1, size=3))
+        c = f[4 * b[2]: 4 * b[2] + 5, 4 * b[1]: 4 * b[1] + 5, 4 * b[0]: 4 * b[0] + 5]
+        if c.min() < iso <= c.max():
+            out.append(b)
+    out += [tuple(int(x) for x in rng.integers(1, nbx - 1, size=3)) for _ in range(n_loose)]
+    return out
+
+
+def _check_call(orc, vol, out, T, st, samples, iso, cache, nbx):
+    """Whole-output properties plus the sampled blocks against the oracle."""
+    active, I_active, may = vol.active(with_flags=True)
+    cnt, off = vol.block_counts()
+    assert len(I_active) == st["n_active"] == int(active.sum())
+    assert np.all(np.diff(I_active.astype(np.int64)) > 0)
+    assert int(cnt.sum()) == 3 * T and np.all(cnt % 3 == 0)
+    assert off[0] == 0 and np.array_equal(off[1:], np.cumsum(cnt[:-1], dtype=np.uint64))
+    occ = cnt > 0
+    assert int(occ.sum()) == st["n_occupied"]
+    assert int(may[I_active].sum()) == st["n_candidates"]
+    assert np.all(may[I_active[occ]] == 1)
+    vblk = out[: 3 * T, 3].cpu().numpy().view(np.uint32)
+    assert np.array_equal(vblk, np.repeat(I_active[occ], cnt[occ]))
+    import torch
+    xyz = out[: 3 * T, :3].view(torch.float32)
+    assert float(xyz.min()) >= 0.0 and float(xyz.max()) <= 4.0
+
+    n_checked = 0
+    for b3, D in samples:
+        bx, by, bz = b3
+        if (b3, iso) not in cache:
+            rng_sub = orc.block_ranges(D, (12, 12, 12))
+            act_sub = orc.active_blocks(rng_sub, (12, 12, 12), iso)
+            group = [13 + dx + 3 * dy + 9 * dz for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
+            lo, hi = float(rng_sub[group, 0].min()), float(rng_sub[group, 1].max())
+            r = orc.mc_extract(D, (12, 12, 12), iso, want=("verts", "vblock"))
+            v32, vb = orc.mc_extract_f32(D, (12, 12, 12), iso)
+            cache[(b3, iso)] = (int(act_sub[13]), int(lo < iso <= hi), r["verts"][r["vblock"] == 13],
+                                v32[vb == 13])
+        act, can, ref64, ref32 = cache[(b3, iso)]
+        b = bx + nbx * (by + nbx * bz)
+        assert int(active[b]) == act, b3
+        if not act:
+            assert ref64.shape[0] == 0, b3
+            continue
+        assert int(may[b]) == can, b3
+        i = int(np.searchsorted(I_active, b))
+        assert I_active[i] == b
+        assert int(cnt[i]) == ref64.shape[0], b3
+        if cnt[i]:
+            got = out[int(off[i]): int(off[i]) + int(cnt[i])].cpu().numpy()
+            assert np.all(got[:, 3].view(np.uint32) == b)
+            g32 = got[:, :3].view(np.float32)
+            assert np.array_equal(g32.view(np.uint32), ref32.astype(np.float32).view(np.uint32)), b3
+            assert np.max(np.abs(g32.astype(np.float64) - ref64)) <= 1e-5
+            n_checked += 1
+    return I_active, n_checked
+
+
+def test_turbulence512_bench_sequence_sampled_parity(orc):
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bc
+    nbx = N // 4
+    nb = nbx ** 3
+    say(f"[headline] {N}^3 f32 turbulence, rate {RATE}, {nb} blocks")
+    field = fields.turbulence_torch(N, seed=2, device=torch.device("cuda:0"))
+    f = field.cpu().numpy()
+    words = bc.encode(field, RATE)
+    del field
+    sub = f.ravel()[::7]
+    iso50, iso90 = (np.float32(np.percentile(sub, q)) for q in (50, 90))
+    rng = np.random.default_rng(77)
+    picks = (_samples(f, iso50, rng, 40, 6, nbx) + _samples(f, iso90, rng, 16, 2, nbx))
+
+    # stream words of every block around the samples: bit-exact against the
+    # oracle encoder; the oracle's neighbourhoods decode those words
+    w = words.view(torch.int64).cpu().numpy().view(np.uint64).reshape(nb, RATE)
+    samples = []
+    for (bx, by, bz) in picks:
+        kept = np.ascontiguousarray(f[4 * bz - 4: 4 * bz + 8, 4 * by - 4: 4 * by + 8, 4 * bx - 4: 4 * bx + 8])
+        s = np.asarray(orc.zfp_encode(kept, RATE), dtype=np.uint64).reshape(27, RATE)
+        ids = [(bx + dx - 1) + nbx * ((by + dy - 1) + nbx * (bz + dz - 1))
+               for dz in range(3) for dy in range(3) for dx in range(3)]
+        assert np.array_equal(s, w[ids]), (bx, by, bz)
+        samples.append(((bx, by, bz), orc.zfp_decode(s.ravel(), (12, 12, 12), RATE)))
+    del w, f, sub
+    say(f"  iso50={float(iso50):.6f} iso90={float(iso90):.6f}; {len(samples)} samples, stream words match")
+
+    vol = bc.Volume(words, (N, N, N), "f32", RATE)
+    del words
+    vol.set_cache_budget(initial_bytes=(nb // 4) * 256, max_bytes=0)
+    probe = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    cap = 0
+    for iso in (iso50, iso90):
+        rc, T = vol.extract_into(float(iso), probe)
+        assert rc in (0, bc._capi.E_CAPACITY)
+        cap = max(cap, T)
+    out = torch.empty((3 * cap + 1024, 4), dtype=torch.int32, device="cuda")
+
+    vol.reset_cache()
+    cache = {}
+    seq = (("cold_p50", iso50), ("p90", iso90), ("warm_p50", iso50), ("repeat_p50", iso50))
+    soups = {}
+    checked = 0
+    I_slot_before = vol.cache_state()[0]
+    assert np.all(I_slot_before < 0)
+    for name, iso in seq:
+        rc, T = vol.extract_into(float(iso), out)
+        assert rc == 0, name
+        st = vol.stats()
+        I_active, n = _check_call(orc, vol, out, T, st, samples, iso, cache, nbx)
+        checked += n
+        say(f"  {name}: T={T} n_active={st['n_active']} n_new={st['n_new']} "
+            f"n_evicted={st['n_evicted']} n_slots={st['n_slots']}; sampled blocks with triangles {n}")
+        # cache (Alg. 1): every active block holds a slot; the new ones are
+        # exactly the active blocks that held none before the call; a slot
+        # holds the decoded block (sampled blocks against the oracle)
+        I_slot, S_block, S_age = vol.cache_state()
+        assert len(S_block) == st["n_slots"]
+        sl = I_slot[I_active]
+        assert np.all(sl >= 0) and np.array_equal(S_block[sl], I_active.astype(np.int32)), name
+        assert np.all(S_age[sl] == 0), name
+        assert st["n_new"] == int(np.count_nonzero(I_slot_before[I_active] < 0)), name
+        kept = I_slot >= 0
+        assert int(kept.sum()) == int(np.count_nonzero(S_block >= 0))
+        data = vol.slot_data()
+        for b3, D in samples:
+            b = b3[0] + nbx * (b3[1] + nbx * b3[2])
+            if I_slot[b] >= 0:
+                assert np.array_equal(data[I_slot[b]].view(np.uint32), D[13].view(np.uint32)), (name, b3)
+        del data
+        I_slot_before = I_slot
+        soups[name] = (T, out[: 3 * T].clone())
+    assert soups["cold_p50"][0] == soups["warm_p50"][0] == soups["repeat_p50"][0]
+    assert torch.equal(soups["cold_p50"][1], soups["warm_p50"][1])
+    assert torch.equal(soups["cold_p50"][1], soups["repeat_p50"][1])
+    assert vol.stats()["n_new"] == 0
+    assert checked >= 30
+    vol.close()
