@@ -716,9 +716,11 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
 }
 
 
-// Emission pass (Sec. 4.5): restage each occupied block, take the in-block
-// prefix of its per-cell vertex counts and write the triangle soup lane per
-// vertex at the block's offset, in canonical order (cell, triangle, vertex).
+// Emission pass (Sec. 4.5): restage the occupied blocks a few at a time, take
+// each block's in-block prefix of its per-cell triangle counts, list the
+// triangles of the staged blocks together and write them lane per vertex
+// from the first block's offset, in canonical order (block, cell, triangle,
+// vertex).
 template <bool EDGE8>
 __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
                                                 const int32_t *__restrict__ I_slot, int identity,
@@ -826,13 +828,22 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
             }
             stage_batch_n<EMIT_SB>(q, slots, so, jl, sh.tiles[w]);
             wave_lds_sync();
-            for (int k = 0; k < nsb; k++) {
-                const uint32_t bj = bcast(b, jl[k]);
-                const uint64_t base = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[k]) << 32) |
-                                      bcast((uint32_t)boff, jl[k]);
-                emit_block<EDGE8>(g, bj, bcast(lbx, jl[k]), bcast(lby, jl[k]), bcast(lbz, jl[k]),
-                                  sh.tiles[w][k], iso, sh.tab, sh, w, base, out, cap);
-            }
+            // the staged blocks are consecutive occupied blocks: their vertex
+            // ranges follow each other from the first one's offset, so their
+            // triangles are listed together and written by one lane-per-vertex
+            // loop (a block's last partial pass of 64 lanes is shared)
+            const uint64_t ob = ((uint64_t)bcast((uint32_t)(boff >> 32), jl[0]) << 32) |
+                                bcast((uint32_t)boff, jl[0]);
+            auto info = [&](int k, Geom &gk, uint32_t &bk, uint32_t &bx, uint32_t &by, uint32_t &bz,
+                            float &isok) {
+                gk = g;
+                bk = bcast(b, jl[k]);
+                bx = bcast(lbx, jl[k]);
+                by = bcast(lby, jl[k]);
+                bz = bcast(lbz, jl[k]);
+                isok = iso;
+            };
+            emit_batch<EDGE8>(nsb, info, sh.tiles[w], sh.tab, sh, w, ob, out, cap);
         }
     }
 }

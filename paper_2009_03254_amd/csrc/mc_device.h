@@ -495,8 +495,8 @@ __device__ __forceinline__ void stream_store(void *out, uint64_t o, float x, flo
 
 constexpr int EMIT_TRIS = 64 * 5;   // a wave's triangle list (one block's maximum)
 
-// Per-wave LDS of the emission: SB staged tiles and the triangle list (the
-// block ids / isovalues are used by the merged emission only).
+// Per-wave LDS of the emission: SB staged tiles, the triangle list of the
+// staged blocks and each staged block's id and isovalue.
 template <int SB>
 struct EmitSharedT {
     float tiles[MC_WAVES][SB][128];
@@ -513,6 +513,8 @@ struct EmitSharedPlain {
     uint64_t tab[256];
     float tiles[MC_WAVES][EMIT_SB][128];
     uint32_t tri[MC_WAVES][EMIT_TRIS];
+    uint32_t blk[MC_WAVES][EMIT_SB];
+    float iso[MC_WAVES][EMIT_SB];
 };
 
 }  // namespace
@@ -520,58 +522,6 @@ struct EmitSharedPlain {
 
 namespace bcmc {
 namespace {
-
-// Emission of one staged block (Sec. 4.5) at block coordinates (bx, by, bz):
-// cases, in-block exclusive scan of the per-cell triangle counts, one record
-// per triangle (its cell and 3 edge ids), then lane per vertex in canonical
-// order (cell, triangle, vertex), written from `base` on (records past `cap`
-// dropped).  EDGE8: 8-byte records block | cell << 32 | edge << 38 | q << 42
-// with q = min(trunc(t * 2^22), 2^22 - 1); otherwise 16-byte records
-// {f32 x, y, z block-relative; u32 block}.
-template <bool EDGE8, class SH>
-__device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t bx, uint32_t by,
-                                           uint32_t bz, const float *tile, float iso,
-                                           const uint64_t *__restrict__ mc_table, SH &sh,
-                                           int w, uint64_t base, void *__restrict__ out, uint64_t cap) {
-    const int l = lane();
-    const int cs = tile_case(g, bx, by, bz, tile, iso);
-    const uint64_t tb = cs < 0 ? 0ull : mc_table[cs];   // 2 KB table (LDS-resident for the callers)
-    const uint32_t nt = (uint32_t)(tb >> 60);
-    const uint32_t incl = wave_incl_scan(nt);
-    const int total = 3 * (int)__shfl(incl, 63, 64);
-    for (uint32_t t = 0; t < nt; t++)
-        sh.tri[w][incl - nt + t] = (uint32_t)l | ((uint32_t)(tb >> (12 * t)) & 0xFFFu) << 6;
-    wave_lds_sync();
-    for (int j = l; j < total; j += 64) {
-        const int t = (j * 43691) >> 17;               // j / 3 for j < 3 * 64 * 5
-        const uint32_t rec = sh.tri[w][t];
-        const int c = (int)(rec & 63u);
-        const int e = (int)((rec >> (6 + 4 * (j - 3 * t))) & 15u);
-        const uint32_t d = (uint32_t)(kEdgeGeom >> (5 * e)) & 31u;
-        const int axis = (int)(d >> 3);
-        const int cx = c & 3, cy = (c >> 2) & 3, cz = c >> 4;
-        const int i0 = tix(cx, cy, cz) + (int)((kEdgeTile >> (5 * e)) & 31u);
-        const int i1 = i0 + (int)((0x190501u >> (8 * axis)) & 0xFFu);   // +1 / +5 / +25
-        const float a = tile[i0];
-        const float bv = tile[i1];
-        const float tt = (iso - a) / (bv - a);
-        const uint64_t o = base + (uint64_t)j;
-        if (EDGE8) {
-            uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
-            qt = qt < 4194303u ? qt : 4194303u;
-            const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
-            if (o < cap) stream_store(out, o, r);
-        } else {
-            // the edge's first corner plus t along its axis (adding 0 to the
-            // other two coordinates leaves them exact)
-            const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
-            const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
-            const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
-            if (o < cap) stream_store(out, o, px, py, pz, b);
-        }
-    }
-    wave_lds_sync();
-}
 
 // Emission (Sec. 4.5) of the nsb blocks staged in tiles[0..nsb), whose
 // vertex ranges follow each other in the output from `base` on (records past
@@ -585,9 +535,9 @@ __device__ __forceinline__ void emit_block(const Geom &g, uint32_t b, uint32_t b
 // EDGE8: 8-byte records block | cell << 32 | edge << 38 | q << 42 with
 // q = min(trunc(t * 2^22), 2^22 - 1); otherwise 16-byte records
 // {f32 x, y, z block-relative; u32 block}.
-template <bool EDGE8, class Info>
+template <bool EDGE8, class Info, class SH>
 __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*tiles)[128],
-                                           const uint64_t *__restrict__ mc_table, EmitShared &sh,
+                                           const uint64_t *__restrict__ mc_table, SH &sh,
                                            int w, uint64_t base, void *__restrict__ out,
                                            uint64_t cap) {
     const int l = lane();
