@@ -372,8 +372,9 @@ def main():
                          "the dominant kernel's time from the untimed profiled steps)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); the path "
-              "has no multi-GPU form in this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}): the extraction "
+              "path has no multi-GPU form; a volume would be split into z-slabs, one per GPU",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
