@@ -103,9 +103,9 @@ typedef struct {
                               (when stages 0 and 5 are both profiled) */
 } bcmc_stats;
 
-/* Upload a fixed-rate ZFP stream (Sec. 4: "uploading the compressed data to
- * the GPU") and decode every block once to record its value range over the
- * valid samples (Sec. 4.1: ranges precomputed at load).
+/* Upload a fixed-rate ZFP stream to the device once (Sec. 4: the compressed
+ * volume lives on the GPU) and decode every block once to record its value
+ * range over the valid samples (Sec. 4.1: ranges precomputed at load).
  *   stream, nbytes   compressed words; nbytes must equal N_b * 8 * rate.
  *                    Copied: the caller keeps ownership.
  *   stream_is_device 1 when `stream` is a device pointer, 0 for host memory.

@@ -385,7 +385,7 @@ void oracle_block_ranges(const float *blocks, uint32_t nx, uint32_t ny,
             }
 }
 
-/* "contains the isovalue": lo < iso <= hi, the same side convention as the
+/* A range contains the isovalue when lo < iso <= hi, the same side convention as the
  * cell classification (a corner is inside when its value is < iso). */
 static int contains(float lo, float hi, float iso) { return lo < iso && iso <= hi; }
 

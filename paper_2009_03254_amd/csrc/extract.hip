@@ -427,7 +427,8 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
     if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_avail_old = incl_end;
 }
 
-// Alg. 1 "exit if n_new = 0" / "grow if n_new > n_avail": every workgroup
+// Alg. 1's early exit (nothing new) and growth (more new blocks than available
+// slots): every workgroup
 // derives the same plan from values no kernel of this launch writes; block 0
 // publishes it and all threads initialise the appended slots (empty,
 // available, age HIGH_AGE) and append them to the available list.
