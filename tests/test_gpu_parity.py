@@ -237,6 +237,36 @@ def test_invalid_arguments(bc, orc):
         vol.set_profiling(True, stages=[6])
 
 
+@pytest.mark.parametrize("fmt", ["f32", "edge8"])
+def test_checkerboard_every_cell_full(bc, orc, fmt):
+    """Every cell of a sign checkerboard has case 105 or 150 (four
+    triangles): 256 per interior block, so the emission's triangle list is
+    flushed before nearly every staged block and blocks straddle flushes.
+    Ragged dims, rate 32 (signs survive the codec); the output against the
+    oracle bit for bit."""
+    dims = (45, 38, 41)
+    say(f"[extract] checkerboard {dims}, rate 32, {fmt}")
+    z, y, x = np.meshgrid(np.arange(dims[2]), np.arange(dims[1]), np.arange(dims[0]), indexing="ij")
+    f = np.where((x + y + z) % 2 == 0, 1.0, -1.0).astype(np.float32)
+    f += 0.25 * np.sin(0.3 * x + 0.2 * y + 0.1 * z).astype(np.float32)   # distinct edge crossings
+    s = orc.zfp_encode(f, 32)
+    D = orc.zfp_decode(s, dims, 32)
+    vol = bc.Volume(s, dims, "f32", 32)
+    if fmt == "f32":
+        T = _extract_and_compare(bc, orc, vol, D, dims, np.float32(0.0))
+        cells = (dims[0] - 1) * (dims[1] - 1) * (dims[2] - 1)
+        assert T == 4 * cells
+    else:
+        import torch
+        vol.set_vertex_format("edge8")
+        ref = orc.mc_extract_edge8(D, dims, np.float32(0.0))
+        out = torch.empty(len(ref) + 16, dtype=torch.int64, device="cuda")
+        rc, T = vol.extract_into(0.0, out)
+        assert rc == 0 and 3 * T == len(ref)
+        got = out[: 3 * T].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, np.asarray(ref, dtype=np.uint64))
+
+
 def test_profiling_stage_mask(bc, orc):
     say("[profile] 48^3 sphere, rate 8: stage mask selects which stage times exist")
     f = fields.sphere_sdf_noisy(48, 15.0, 0.5, seed=4)
