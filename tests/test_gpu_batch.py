@@ -152,3 +152,29 @@ def test_batch_mixed_rates_many_jobs(orc, rates):
     _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)   # warm: masks from the store
     assert batch.info()["n_new"] == 0
     batch.close()
+
+
+def test_batch_checkerboard_with_turbulence(orc):
+    """A sign checkerboard (four triangles in every cell, so the batched
+    emission's triangle list flushes before nearly every staged block) in
+    one batch with a turbulence volume, at several isovalues: every job's
+    slice against the plain extract and the oracle's float32 soup."""
+    torch_cuda()
+    import paper_2009_03254_amd as bc
+    dc = (37, 30, 26)
+    z, y, x = np.meshgrid(np.arange(dc[2]), np.arange(dc[1]), np.arange(dc[0]), indexing="ij")
+    fc = np.where((x + y + z) % 2 == 0, 1.0, -1.0).astype(np.float32)
+    fc += 0.25 * np.sin(0.3 * x + 0.2 * y + 0.1 * z).astype(np.float32)
+    sc = orc.zfp_encode(fc, 32)
+    dims_list = [dc, (29, 35, 22)]
+    streams, decoded = _make(orc, dims_list[1:], 32, seed0=1200)
+    streams = [sc] + streams
+    decoded = [orc.zfp_decode(sc, dc, 32)] + decoded
+    vols = [bc.Volume(s, d, "f32", 32) for s, d in zip(streams, dims_list)]
+    plain = [bc.Volume(s, d, "f32", 32) for s, d in zip(streams, dims_list)]
+    jobs = [(0, 0.0), (1, 0.0), (0, 0.1), (1, 0.3), (0, -0.1)]
+    batch = bc.Batch(vols, jobs)
+    offs = _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
+    cells = (dc[0] - 1) * (dc[1] - 1) * (dc[2] - 1)
+    assert int(offs[1] - offs[0]) == 3 * 4 * cells
+    batch.close()
