@@ -367,3 +367,33 @@ def test_flags_follow_tiles_across_isovalues(bc, orc):
     for iso in (20.5, 200.5, 250.5, 20.5, -5.0, 130.5, 130.5):
         T = _extract_and_compare(bc, orc, vol, D, dims, np.float32(iso), check_cells=False)
         assert (T > 0) == (iso > 0), (iso, T)
+
+
+@pytest.mark.parametrize("iso", [1.0, 2.0, 0.5])
+def test_isovalue_ties_integer_field(bc, orc, iso):
+    """An integer-valued field (0..3) at an integer isovalue puts many
+    corners exactly on iso: a corner is inside only when its value is below
+    iso, a block's range contains iso only when lo < iso <= hi, and t is
+    exactly 0 or 1 on edges ending at iso.  Identity volume (no codec, the
+    ties survive) against the oracle bit for bit and the brute-force count
+    on the raw field; the compressed path (rate 32) against the oracle's
+    decode.  iso 0.5 is the tie-free control."""
+    dims = (35, 27, 30)
+    say(f"[extract] integer field {dims}, iso {iso}")
+    rng = np.random.default_rng(61)
+    f = rng.integers(0, 4, size=(dims[2], dims[1], dims[0])).astype(np.float32)
+    B = orc.field_to_blocks(f)
+    vol = bc.FieldVolume(to_cuda(B), dims)
+    verts, T = vol.extract(iso)
+    iso32 = np.float32(iso)
+    assert T == orc.brute_count(f, iso32) > 0
+    v32, vb = orc.mc_extract_f32(B, dims, iso32)
+    xyz, blk = verts_np(verts)
+    assert np.array_equal(blk, vb)
+    assert np.array_equal(xyz.view(np.uint32), v32.view(np.uint32))
+    r = orc.mc_extract(B, dims, iso32, want=("verts", "vblock"))
+    assert np.abs(xyz.astype(np.float64) - r["verts"]).max() <= 1e-5
+    s = orc.zfp_encode(f, 32)
+    D = orc.zfp_decode(s, dims, 32)
+    vc = bc.Volume(s, dims, "f32", 32)
+    _extract_and_compare(bc, orc, vc, D, dims, iso32)
