@@ -235,6 +235,15 @@ def test_invalid_arguments(bc, orc):
     assert T == 0
     with pytest.raises(bc.BcmcError):
         vol.set_profiling(True, stages=[6])
+    with pytest.raises(bc.BcmcError):
+        vol.extract(float("nan"))
+    # a real field: an infinite isovalue lies outside every (finite) range
+    f = fields.sphere_sdf_noisy(16, 5.0, 0.5, seed=3)
+    v2 = bc.Volume(orc.zfp_encode(f, 8), (16, 16, 16), "f32", 8)
+    assert v2.extract(0.0)[1] > 0
+    for iso in (float("inf"), float("-inf")):
+        _, T = v2.extract(iso)
+        assert T == 0 and v2.stats()["n_active"] == 0
 
 
 @pytest.mark.parametrize("fmt", ["f32", "edge8"])
