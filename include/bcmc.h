@@ -164,9 +164,14 @@ BCMC_API int bcmc_set_vertex_format(bcmc_volume *v, int format);
  * ([3T][3] float, device) accumulates dL/d(field) into d_dfield ([N_b][64]
  * float, device, overwritten) and dL/d(iso) into d_diso (one float, device,
  * overwritten), through t = (iso - a)/(b - a).  Float atomics: the
- * summation order is not fixed.
+ * summation order is not fixed, so results vary in the last bits from run
+ * to run.  Each block's vertex count is recomputed from the bound field and
+ * compared with the forward's; synchronises hip_stream once to read that
+ * check.
  * Errors: BCMC_E_INVALID (not an identity handle, no extract, n_verts
- * differs from the last extract). */
+ * differs from the last extract, or the field changed since the extract so
+ * that some block's vertex count differs: the gradient is then not valid and
+ * the extract must be repeated). */
 BCMC_API int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_t n_verts,
                   float *d_dfield, float *d_diso, void *hip_stream);
 
@@ -233,6 +238,10 @@ typedef struct {
     uint32_t grid;            /* schedule: workgroups of the back kernel */
     uint32_t workgroups_per_cu;  /* of the back kernel */
     uint32_t front_grid;      /* schedule: workgroups of the front kernel */
+    uint32_t decode_grid;     /* workgroups of the decode kernel */
+    uint32_t ran_front_grid;  /* grids the last run's kernels were launched with, */
+    uint32_t ran_decode_grid; /* as each kernel recorded them (0: that kernel */
+    uint32_t ran_grid;        /* did not run, e.g. nothing to decode) */
     int32_t graph;            /* 1: the last run replayed a hipGraph */
     int32_t graph_unsupported;/* 1: capturing the cooperative launch failed */
     float last_ms;            /* GPU time of the last run (HIP events) */
@@ -260,6 +269,13 @@ BCMC_API int bcmc_batch_set_graph(bcmc_batch *b, int on);
  * capacity (offsets are set; enlarge and run again). */
 BCMC_API int bcmc_batch_run(bcmc_batch *b, void *d_out, uint64_t capacity_vertices,
                             uint64_t *h_job_off, void *hip_stream);
+/* Set the schedule by hand: stage_blocks (4 or 8) blocks staged per round
+ * trip, per_cu workgroups per CU of the back kernel and front_per_cu of the
+ * front kernel, each clamped to what stays resident (bcmc_batch_get_info
+ * reports the grids).  The next run captures its graph again.
+ * Errors: BCMC_E_INVALID. */
+BCMC_API int bcmc_batch_set_schedule(bcmc_batch *b, int stage_blocks, int per_cu,
+                                     int front_per_cu);
 /* Autotune the schedule (blocks staged per round trip, workgroups per CU
  * of the back and the front kernel) by timing cold + warm runs of this batch; the best is kept and appended
  * to cache_path (one JSON object per line, keyed by arch, scalar type and
@@ -281,6 +297,13 @@ BCMC_API int bcmc_debug_cache_state(const bcmc_volume *v, int32_t *h_I_slot /* [
                            int32_t *h_S_block /* [n_slots] */,
                            uint32_t *h_S_age /* [n_slots] */, uint64_t *h_n_slots);
 BCMC_API int bcmc_debug_slot_data(const bcmc_volume *v, float *h_slots /* [n_slots][64] */);
+/* Advance the cache by k calls at which no block is active, as k
+ * bcmc_extract calls at an isovalue outside the data would (Alg. 1's age
+ * update: every slot's age += k, saturating at 2^32 - 1; every cached block
+ * becomes available), without running them.  The cache's age clock counts
+ * at most 2^31 - 1 calls since its reset.  A test hook for the age sort's
+ * wide keys.  Errors: BCMC_E_INVALID (identity volume, clock overflow). */
+BCMC_API int bcmc_debug_age_cache(bcmc_volume *v, uint32_t k, void *hip_stream);
 BCMC_API int bcmc_debug_block_counts(const bcmc_volume *v, uint32_t *h_cnt, uint64_t *h_off,
                             uint64_t n /* <= n_active */);
 /* Cases of the 64 cells of every active block of the last extract (which

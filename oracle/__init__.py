@@ -74,6 +74,7 @@ def lib():
             "oracle_lru_free": (None, [_P]),
             "oracle_lru_update": (_int, [_P, _P, _P, _P, _P]),
             "oracle_lru_n_slots": (_u64, [_P]),
+            "oracle_lru_idle": (None, [_P, _u64]),
             "oracle_lru_state": (None, [_P, _P, _P, _P]),
             "oracle_sphere_loss": (_f64, [_P, _u64, _P, _f64, _P]),
             "oracle_mc_backward": (None, [_P, _u32, _u32, _u32, _f32, _P, _P, _P]),
@@ -358,6 +359,10 @@ class LRU:
         rc = lib().oracle_lru_update(self._h, _ptr(active), _ptr(I_new), C.byref(n_new),
                                      C.byref(n_ev))
         return rc, I_new[: n_new.value].copy(), int(n_ev.value)
+
+    def idle(self, k):
+        """k updates at which no block is active, at once."""
+        lib().oracle_lru_idle(self._h, int(k))
 
     @property
     def n_slots(self):

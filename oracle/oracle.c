@@ -971,6 +971,17 @@ int oracle_lru_update(oracle_lru *c, const uint8_t *active, uint32_t *I_new_out,
     return 0;
 }
 
+void oracle_lru_idle(oracle_lru *c, uint64_t k) {
+    /* k calls of Alg. 1 at which no block is active: each increments every
+     * slot's age (saturating) and marks every cached block available, and
+     * none has a new block, so the update stops there */
+    for (uint64_t s = 0; s < c->n_slots; s++) {
+        uint64_t a = (uint64_t)c->S_age[s] + k;
+        c->S_age[s] = a > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)a;
+        if (c->S_block[s] != -1) c->M_avail[s] = 1;
+    }
+}
+
 /* ======================================================================= */
 /* gradient through t = (iso - a) / (b - a), topology fixed (FP64)         */
 /* ======================================================================= */

@@ -111,6 +111,8 @@ void oracle_lru_free(oracle_lru *c);
  * active set (the cache is then reset to its initial empty state). */
 int oracle_lru_update(oracle_lru *c, const uint8_t *active, uint32_t *I_new,
                       uint64_t *n_new, uint64_t *n_evicted);
+/* k updates at which no block is active, at once (ages += k, saturating). */
+void oracle_lru_idle(oracle_lru *c, uint64_t k);
 uint64_t oracle_lru_n_slots(const oracle_lru *c);
 /* Copies of the state: I_slot[n_blocks], S_block[n_slots], S_age[n_slots]. */
 void oracle_lru_state(const oracle_lru *c, int32_t *I_slot, int32_t *S_block,

@@ -291,6 +291,10 @@ class Volume(_Handle):
         _capi.check(lib().bcmc_decode_all(self._h, _dev_ptr(out), _stream_ptr(stream)))
         return out
 
+    def age_cache(self, k, stream=None):
+        """Advance the cache by k calls at which no block is active (test hook)."""
+        _capi.check(lib().bcmc_debug_age_cache(self._h, int(k), _stream_ptr(stream)))
+
     def cache_state(self):
         ns = C.c_uint64(0)
         _capi.check(lib().bcmc_debug_cache_state(self._h, None, None, None, C.byref(ns)))
@@ -390,6 +394,10 @@ class Batch:
     def set_graph(self, on=True):
         _capi.check(lib().bcmc_batch_set_graph(self._h, 1 if on else 0))
 
+    def set_schedule(self, stage_blocks, per_cu, front_per_cu):
+        _capi.check(lib().bcmc_batch_set_schedule(self._h, int(stage_blocks), int(per_cu),
+                                                  int(front_per_cu)))
+
     def tune(self, cache_path=None, stream=None):
         _capi.check(lib().bcmc_batch_tune(self._h, cache_path.encode() if cache_path else None,
                                           _stream_ptr(stream)))
@@ -456,12 +464,18 @@ def _make_extract_fn():
             # straight back to the pool.  The soup is a fresh buffer: its
             # views are returned without a copy.
             vol = _acquire_field_volume(field_blocks.detach(), dims)
+            # the isovalue is a kernel argument, read on the host; the extract
+            # reads its triangle count back anyway, so the forward synchronises
+            # with the stream once in any case
             isof = float(iso)
             verts, T = vol.extract(isof)
             xyz, blk = split_vertices(verts)
             ctx.iso = isof
             ctx.iso_dtype = iso.dtype if torch.is_tensor(iso) else torch.float32
             if keep:
+                # autograd's version counter then rejects an in-place edit of
+                # the field between this forward and its backward
+                ctx.save_for_backward(field_blocks)
                 ctx.vol = vol
             else:
                 ctx.vol = None
@@ -473,9 +487,12 @@ def _make_extract_fn():
         def backward(ctx, g_xyz, g_blk):
             if ctx.vol is None:
                 raise RuntimeError("ExtractFn: backward of a forward run without gradients")
-            dfield, diso = ctx.vol.backward(ctx.iso, g_xyz)
-            _release_field_volume(ctx.vol)
-            ctx.vol = None
+            vol, ctx.vol = ctx.vol, None
+            try:
+                ctx.saved_tensors          # raises if the field was modified in place
+                dfield, diso = vol.backward(ctx.iso, g_xyz)
+            finally:
+                _release_field_volume(vol)
             return dfield, diso.to(ctx.iso_dtype), None, None
 
     return ExtractFn

@@ -40,6 +40,8 @@ class BatchInfo(C.Structure):
                 ("n_pairs", C.c_uint64), ("n_vertices", C.c_uint64),
                 ("stage_blocks", C.c_uint32), ("grid", C.c_uint32),
                 ("workgroups_per_cu", C.c_uint32), ("front_grid", C.c_uint32),
+                ("decode_grid", C.c_uint32), ("ran_front_grid", C.c_uint32),
+                ("ran_decode_grid", C.c_uint32), ("ran_grid", C.c_uint32),
                 ("graph", C.c_int32),
                 ("graph_unsupported", C.c_int32), ("last_ms", C.c_float),
                 ("phase_ms", C.c_float * 8)]
@@ -76,6 +78,7 @@ SIGNATURES = {
     "bcmc_batch_reset": (_int, [_P, _P]),
     "bcmc_batch_set_graph": (_int, [_P, _int]),
     "bcmc_batch_run": (_int, [_P, _P, _u64, _P, _P]),
+    "bcmc_batch_set_schedule": (_int, [_P, _int, _int, _int]),
     "bcmc_batch_tune": (_int, [_P, C.c_char_p, _P]),
     "bcmc_batch_get_info": (_int, [_P, _P]),
     "bcmc_batch_free": (None, [_P]),
@@ -84,6 +87,7 @@ SIGNATURES = {
     "bcmc_debug_new": (_int, [_P, _P, _P]),
     "bcmc_debug_cache_state": (_int, [_P, _P, _P, _P, _P]),
     "bcmc_debug_slot_data": (_int, [_P, _P]),
+    "bcmc_debug_age_cache": (_int, [_P, _u32, _P]),
     "bcmc_debug_block_counts": (_int, [_P, _P, _P, _u64]),
     "bcmc_debug_cases": (_int, [_P, _f32, _P, _P]),
 }

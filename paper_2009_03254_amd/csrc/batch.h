@@ -24,7 +24,8 @@ struct BatchCounters {
     unsigned long long total_verts;
     unsigned long long slot_base;    // first slot of this run's new blocks
     unsigned int err;
-    unsigned int pad[5];
+    unsigned int grid_front, grid_decode, grid_back;   // grids the kernels ran with
+    unsigned int pad[2];
 };
 
 // Grid barrier words (u32 units): the generation, the top-level arrival

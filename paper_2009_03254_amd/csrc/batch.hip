@@ -243,6 +243,7 @@ __global__ __launch_bounds__(BT) void k_batch_front(BatchParams p) {
         p.ctr->n_list = 0;
         p.ctr->total_verts = 0;
         p.ctr->err = 0;
+        p.ctr->grid_front = gridDim.x;
     }
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 1);
@@ -381,6 +382,7 @@ template <bool F64, bool STAGED>
 __global__ __launch_bounds__(BT) void k_batch_decode(BatchParams p) {
     if (p.ctr->err) return;   // the front kernel failed: nothing to do
     const uint64_t gtid = blockIdx.x * (uint64_t)BT + threadIdx.x;
+    if (gtid == 0) p.ctr->grid_decode = gridDim.x;
     const uint64_t gstride = (uint64_t)gridDim.x * BT;
     const uint64_t n_slots0 = p.ctr->slot_base;
     const uint64_t n_new = p.ctr->n_new;
@@ -563,7 +565,10 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
         total += sh.w64[1][k];
     }
     for (uint32_t k = 0; k < (uint32_t)w; k++) base += p.part_wave[wv0 + k];
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.ctr->total_verts = total;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.ctr->total_verts = total;
+        p.ctr->grid_back = gridDim.x;
+    }
     stamp(p, 7);
 
     // ---- phase 7: emission (Sec. 4.5) and the jobs' output offsets --------------

@@ -48,7 +48,7 @@ struct bcmc_batch {
     void *graph_out = nullptr;
     uint64_t graph_cap = 0;
     int graph_sb = 0;
-    unsigned graph_grid = 0;
+    unsigned graph_grid = 0, graph_front_grid = 0, graph_decode_grid = 0;
     int use_graph = 1, graph_failed = 0;
     float last_ms = 0.0f;
     unsigned long long *h_ts = nullptr;   // phase clock stamps of the last run
@@ -125,8 +125,11 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
     BCMC_HIP_TRY(hipEventRecord(b->ev_t0, b->gstream));
     bool launched = false;
     if (b->use_graph && !b->graph_failed) {
+        // a captured graph holds the launch configuration: capture again when
+        // any schedule dimension or the output changes
         if (!b->exec || b->graph_out != d_out || b->graph_cap != cap || b->graph_sb != b->sb ||
-            b->graph_grid != b->grid) {
+            b->graph_grid != b->grid || b->graph_front_grid != b->front_grid ||
+            b->graph_decode_grid != b->decode_grid) {
             drop_graph(b);
             hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
@@ -145,6 +148,8 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
                 b->graph_cap = cap;
                 b->graph_sb = b->sb;
                 b->graph_grid = b->grid;
+                b->graph_front_grid = b->front_grid;
+                b->graph_decode_grid = b->decode_grid;
             }
         }
         if (b->exec) {
@@ -421,6 +426,13 @@ int bcmc_batch_run(bcmc_batch *b, void *d_out, uint64_t capacity_vertices, uint6
     return BCMC_OK;
 }
 
+int bcmc_batch_set_schedule(bcmc_batch *b, int stage_blocks, int per_cu, int front_per_cu) {
+    if (!b) return binvalid("null handle");
+    if (stage_blocks != 4 && stage_blocks != 8) return binvalid("stage_blocks must be 4 or 8");
+    if (per_cu < 1 || front_per_cu < 1) return binvalid("workgroups per CU must be >= 1");
+    return set_schedule(b, stage_blocks, per_cu, front_per_cu);
+}
+
 int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
     if (!b) return binvalid("null handle");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -497,6 +509,10 @@ int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out) {
     out->grid = b->grid;
     out->workgroups_per_cu = b->grid / (unsigned)std::max(b->cus, 1);
     out->front_grid = b->front_grid;
+    out->decode_grid = b->decode_grid;
+    out->ran_front_grid = b->h_ctr ? b->h_ctr->grid_front : 0;
+    out->ran_decode_grid = b->h_ctr ? b->h_ctr->grid_decode : 0;
+    out->ran_grid = b->h_ctr ? b->h_ctr->grid_back : 0;
     out->graph = (b->use_graph && !b->graph_failed && b->exec) ? 1 : 0;
     out->graph_unsupported = b->graph_failed;
     out->last_ms = b->last_ms;

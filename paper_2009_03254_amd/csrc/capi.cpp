@@ -365,6 +365,18 @@ int bcmc_reset_cache(bcmc_volume *v, void *hip_stream) {
     return reset_cache_state(v, as_stream(hip_stream));
 }
 
+int bcmc_debug_age_cache(bcmc_volume *v, uint32_t k, void *hip_stream) {
+    if (!v) return invalid("null handle");
+    if (v->identity) return invalid("identity volumes have no cache");
+    if (k > 0x7FFFFFFFu - v->calls_since_reset)
+        return invalid("the age clock would pass 2^31 - 1 calls since the cache reset");
+    hipStream_t s = as_stream(hip_stream);
+    launch_age_slots(v->d.S_age, v->n_slots, k, s);
+    BCMC_HIP_TRY(hipGetLastError());
+    v->calls_since_reset += k;
+    return BCMC_OK;
+}
+
 int bcmc_set_vertex_format(bcmc_volume *v, int format) {
     if (!v) return invalid("null handle");
     if (format != BCMC_VERTEX_F32 && format != BCMC_VERTEX_EDGE8) return invalid("unknown vertex format");
@@ -490,9 +502,21 @@ int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_t n_verts
     hipStream_t s = as_stream(hip_stream);
     BCMC_HIP_TRY(hipMemsetAsync(d_dfield, 0, v->g.nb * 64 * sizeof(float), s));
     BCMC_HIP_TRY(hipMemsetAsync(d_diso, 0, sizeof(float), s));
-    if (n_verts)
-        launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, d_dfield, d_diso, v->g.nb, s);
+    if (!n_verts) return BCMC_OK;
+    BCMC_HIP_TRY(hipMemsetAsync(&v->d.ctr->err, 0, sizeof(unsigned int), s));
+    launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, d_dfield, d_diso, v->g.nb, s);
     BCMC_HIP_TRY(hipGetLastError());
+    // the kernel compares each block's vertex count with the forward's
+    BCMC_HIP_TRY(hipMemcpyAsync(&v->h_ctr->err, &v->d.ctr->err, sizeof(unsigned int),
+                                hipMemcpyDeviceToHost, s));
+    BCMC_HIP_TRY(hipStreamSynchronize(s));
+    if (v->h_ctr->err) {
+        v->h_ctr->err = 0;
+        v->have_extract = 0;
+        set_error("the field changed between the forward extract and the backward "
+                  "(per-block vertex counts differ)");
+        return BCMC_E_INVALID;
+    }
     return BCMC_OK;
 }
 

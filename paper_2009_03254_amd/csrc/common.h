@@ -127,6 +127,7 @@ void launch_backward(const Geom &g, const DevState &d, const float *slots, float
                      const float *gV, float *dfield, float *diso, uint64_t max_act,
                      hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_age_slots(uint32_t *S_age, uint64_t n, uint32_t k, hipStream_t s);
 void launch_copy_calibration(void *dst, const void *src, uint64_t n16, hipStream_t s);
 void launch_iota_i32(int32_t *p, uint64_t n, hipStream_t s);
 

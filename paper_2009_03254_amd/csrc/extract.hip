@@ -892,7 +892,7 @@ __global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__rest
                                                  const uint64_t *__restrict__ blk_off,
                                                  const float *__restrict__ gV,
                                                  float *__restrict__ dfield, float *diso,
-                                                 const Counters *ctr) {
+                                                 Counters *ctr) {
     __shared__ McShared sh;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
     __syncthreads();
@@ -902,11 +902,19 @@ __global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__rest
     const float *tile = sh.tile[w];
     float giso = 0.0f;
     for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
-        if (blk_cnt[i] == 0) continue;
+        const uint32_t cnt = blk_cnt[i];
+        if (cnt == 0) continue;
         const uint32_t b = I_active[i];
         const uint64_t base = blk_off[i];
         Halo h;
-        const int total = block_layout(g, b, nullptr, 1, slots, iso, sh, w, h);
+        int total = block_layout(g, b, nullptr, 1, slots, iso, sh, w, h);
+        if ((uint32_t)total != cnt) {
+            // the field changed since the forward pass: its topology (and the
+            // gradient's vertex ranges) no longer hold; stay inside the
+            // forward's range and report
+            if (l == 0) atomicOr(&ctr->err, ERR_INTERNAL);
+            total = (uint32_t)total < cnt ? total : (int)cnt;
+        }
         for (int j = l; j < total; j += 64) {
             const int c = sh.map[w][j];
             const int k = j - (int)sh.pref[w][c];
@@ -940,6 +948,15 @@ __global__ __launch_bounds__(256) void k_copy_calibration(uint4 *__restrict__ ds
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+// Ages of the first n slots advanced by k, saturating at 2^32 - 1.
+__global__ void k_age_slots(uint32_t *S_age, uint64_t n, uint32_t k) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = S_age[i];
+        S_age[i] = a > 0xFFFFFFFFu - k ? 0xFFFFFFFFu : a + k;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
@@ -1107,6 +1124,10 @@ void launch_backward(const Geom &g, const DevState &d, const float *slots, float
 void launch_copy_calibration(void *dst, const void *src, uint64_t n16, hipStream_t s) {
     if (n16) k_copy_calibration<<<grid_cap(n16, 16384), 256, 0, s>>>(
         reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n16);
+}
+
+void launch_age_slots(uint32_t *S_age, uint64_t n, uint32_t k, hipStream_t s) {
+    if (n && k) k_age_slots<<<grid_cap(n, 8192), 256, 0, s>>>(S_age, n, k);
 }
 
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s) {

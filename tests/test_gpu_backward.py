@@ -86,3 +86,95 @@ def test_forward_without_grad_reuses_volume(orc):
     assert len(pool) == 1
     got = blocks.grad.cpu().numpy().astype(np.float64)
     assert abs(got.sum() + float(iso_t.grad)) <= 1e-4 * (np.abs(got).sum() + abs(float(iso_t.grad)))
+
+
+def _loss_backward(torch, bcmc, blocks_np, dims, iso, c, radius):
+    blocks = torch.from_numpy(blocks_np).cuda().requires_grad_(True)
+    iso_t = torch.tensor(float(iso), device="cuda", requires_grad=True)
+    xyz, blk = bcmc.ExtractFn.apply(blocks, iso_t, dims)
+    g = bcmc.global_positions(xyz, blk, dims, dtype=torch.float64)
+    loss = ((g - torch.tensor(c, device="cuda")).norm(dim=1) - radius).pow(2).sum()
+    loss.backward()
+    return blocks, iso_t, xyz, blk, loss
+
+
+def test_backward_config_workload_256(orc):
+    """The differentiable workload at its full size, as the benchmark runs it:
+    256^3 Gaussian blobs (16 blobs, seed 3), iso 0.5, L = sum (|v - c| - 64)^2
+    with c the grid centre, against the oracle's FP64 analytic gradient."""
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bcmc
+    n, radius, iso = 256, 64.0, 0.5
+    say("[backward] blobs 256^3, 16 blobs, seed 3, iso 0.5")
+    f = fields.gaussian_blobs(n, 16, seed=3)
+    dims = (n, n, n)
+    B = orc.field_to_blocks(f)
+    c = np.full(3, (n - 1) / 2.0)
+    blocks, iso_t, xyz, blk, loss = _loss_backward(torch, bcmc, B, dims, iso, c, radius)
+    r = orc.mc_extract(B, dims, iso, want=("verts", "vblock"))
+    assert xyz.shape[0] == 3 * r["T"] and r["T"] > 100000
+    assert np.array_equal(blk.cpu().numpy().view(np.uint32), r["vblock"])
+    assert np.abs(xyz.detach().cpu().numpy().astype(np.float64) - r["verts"]).max() <= 1e-5
+    vg = orc.verts_global(r["verts"], r["vblock"], dims)
+    L, gV = orc.sphere_loss(vg, c, radius)
+    assert float(loss.detach()) == pytest.approx(L, rel=1e-5)
+    df, di = orc.mc_backward(B, dims, iso, gV)
+    got = blocks.grad.cpu().numpy().astype(np.float64)
+    say(f"  T={r['T']} rel {np.linalg.norm(got - df) / np.linalg.norm(df):.2e} "
+        f"diso {float(iso_t.grad):.6e} vs {di:.6e}")
+    assert np.linalg.norm(got - df) <= 1e-4 * np.linalg.norm(df)
+    assert np.abs(got - df).max() <= 1e-3 * np.abs(df).max()
+    assert float(iso_t.grad) == pytest.approx(di, rel=1e-4)
+    assert abs(got.sum() + float(iso_t.grad)) <= 1e-4 * (np.abs(got).sum() + abs(di))
+    D = B.astype(np.float64)
+    assert abs((D * got).sum() + iso * float(iso_t.grad)) <= 1e-4 * (np.abs(D * got).sum() + abs(di))
+
+
+def test_inplace_edit_before_backward_raises(orc):
+    """Editing the field in place between the forward and the backward is
+    refused by autograd's version check on the saved field."""
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bcmc
+    n = 32
+    f = fields.gaussian_blobs(n, 4, seed=21)
+    dims = (n, n, n)
+    B = orc.field_to_blocks(f)
+    iso = fields.percentile_iso(f, 50)
+    blocks = torch.from_numpy(B).cuda().requires_grad_(True)
+    iso_t = torch.tensor(float(iso), device="cuda", requires_grad=True)
+    xyz, blk = bcmc.ExtractFn.apply(blocks, iso_t, dims)
+    assert xyz.shape[0] > 0
+    with torch.no_grad():
+        blocks.mul_(-1.0)
+    with pytest.raises(RuntimeError):
+        xyz.sum().backward()
+    # the pooled volume went back: a fresh forward + backward works
+    with torch.no_grad():
+        blocks.mul_(-1.0)
+    blocks.grad = None
+    xyz, blk = bcmc.ExtractFn.apply(blocks, iso_t, dims)
+    xyz.sum().backward()
+    assert blocks.grad is not None
+
+
+def test_backward_rejects_changed_field(orc):
+    """Through the C ABI, without autograd: the field's memory changes after
+    the extract (negated, so blocks' vertex counts change); the backward
+    reports an error instead of reading outside the forward's vertex ranges."""
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bcmc
+    n = 36
+    f = fields.gaussian_blobs(n, 5, seed=22)
+    dims = (n, n, n)
+    B = orc.field_to_blocks(f)
+    iso = float(fields.percentile_iso(f, 40))
+    blocks = torch.from_numpy(B).cuda()
+    vol = bcmc.FieldVolume(blocks, dims)
+    verts, T = vol.extract(iso)
+    assert T > 0
+    gV = torch.ones((3 * T, 3), dtype=torch.float32, device="cuda")
+    vol.backward(iso, gV)                  # unchanged field: fine
+    blocks.copy_(torch.from_numpy(orc.field_to_blocks(f[::-1].copy())).cuda())
+    with pytest.raises(RuntimeError):
+        vol.backward(iso, gV)
+    vol.close()

@@ -178,3 +178,115 @@ def test_batch_checkerboard_with_turbulence(orc):
     cells = (dc[0] - 1) * (dc[1] - 1) * (dc[2] - 1)
     assert int(offs[1] - offs[0]) == 3 * 4 * cells
     batch.close()
+
+
+def test_batch_schedule_change_recaptures_graph(orc):
+    """Changing one schedule dimension at a time (the front kernel's grid
+    alone, then the back kernel's, then the staging) captures the graph
+    again: every kernel records the grid it ran with, which must be the grid
+    the schedule reports, and the output stays byte-identical."""
+    torch_cuda()
+    import paper_2009_03254_amd as bc
+    dims_list = [(41, 37, 29), (30, 26, 45)]
+    streams, decoded = _make(orc, dims_list, 8, seed0=1300)
+    vols = [bc.Volume(s, d, "f32", 8) for s, d in zip(streams, dims_list)]
+    plain = [bc.Volume(s, d, "f32", 8) for s, d in zip(streams, dims_list)]
+    fld = [orc.blocks_to_field(decoded[v], dims_list[v]) for v in range(2)]
+    jobs = [(v, fields.percentile_iso(fld[v], p)) for v in range(2) for p in (30, 70)]
+    batch = bc.Batch(vols, jobs)
+    batch.set_graph(True)
+    seen = set()
+    for sb, pc, fpc in ((8, 4, 4), (8, 4, 1), (8, 4, 2), (8, 2, 2), (4, 2, 2), (4, 2, 1)):
+        batch.set_schedule(sb, pc, fpc)
+        batch.reset()                   # cold: the decode kernel runs too
+        _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
+        info = batch.info()
+        say(f"  schedule {sb},{pc},{fpc}: {info['front_grid']} {info['decode_grid']} {info['grid']}"
+            f" ran {info['ran_front_grid']} {info['ran_decode_grid']} {info['ran_grid']}"
+            f" graph={info['graph']}")
+        assert info["stage_blocks"] == sb
+        assert info["ran_front_grid"] == info["front_grid"]
+        assert info["ran_decode_grid"] == info["decode_grid"]
+        assert info["ran_grid"] == info["grid"]
+        seen.add((info["front_grid"], info["grid"]))
+        _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)    # warm replay
+        assert batch.info()["ran_front_grid"] == info["front_grid"]
+    assert len(seen) >= 3
+    batch.close()
+
+
+def test_batch_benchmark_workload_full(orc):
+    """The batched workload at its full size, as the benchmark builds it: 48
+    turbulence volumes (each axis uniform in [32, 256], dims seed 4, field
+    seed 4000 + v) generated and encoded on the GPU at rate 8, isovalues at
+    the 20/40/60/80th percentiles of each field, 192 jobs in one autotuned,
+    graph-replayed batch.  Each volume's GPU stream equals the oracle
+    encoder's output for the host copy of its field; every job's slice equals
+    the plain single-volume extract byte for byte and the oracle's plain
+    extract of the stream (count, float32 vertices bit for bit), cold and
+    warm.  The persistent front kernel runs several tiles per workgroup
+    here."""
+    torch = torch_cuda()
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2009_03254_amd as bc
+    dims_list = fields.batched_dims(48, seed=4, lo=32, hi=256)
+    vols, plain, jobs, host = [], [], [], []
+    for v, (nx, ny, nz) in enumerate(dims_list):
+        f = fields.turbulence_torch(nx, ny, nz, seed=4000 + v, device="cuda")
+        isos = [float(fields.percentile_iso_torch(f, p)) for p in (20, 40, 60, 80)]
+        words = bc.encode(f, 8)
+        w = words.view(torch.int64).cpu().numpy().view(np.uint64).copy()
+        host.append((f.cpu().numpy(), w))
+        vols.append(bc.Volume(words, (nx, ny, nz), "f32", 8))
+        plain.append(bc.Volume(words, (nx, ny, nz), "f32", 8))
+        jobs += [(v, i) for i in isos]
+        del f, words
+    nb = sum(orc.num_blocks(*d) for d in dims_list)
+    say(f"[batch] benchmark workload: 48 volumes, {nb} blocks, 192 jobs")
+
+    def oracle_volume(v):
+        f, w = host[v]
+        assert np.array_equal(orc.zfp_encode(f, 8), w), v
+        D = orc.zfp_decode(w, dims_list[v], 8)
+        return [orc.mc_extract_f32(D, dims_list[v], iso) for _, iso in jobs[4 * v: 4 * v + 4]]
+
+    with ThreadPoolExecutor(16) as ex:
+        ref = list(ex.map(oracle_volume, range(48)))
+    total = sum(len(vb) for r in ref for _, vb in r)
+    say(f"  oracle: {total // 3} triangles")
+
+    batch = bc.Batch(vols, jobs)
+    batch.tune()
+    info = batch.info()
+    say(f"  tuned: stage_blocks={info['stage_blocks']} grid={info['grid']} "
+        f"front_grid={info['front_grid']} graph={info['graph']}")
+    tiles_per_wg = nb / max(1, info["front_grid"])
+    out = torch.empty((total + 1024, 4), dtype=torch.int32, device="cuda")
+    pbuf = torch.empty((max(len(vb) for r in ref for _, vb in r) + 16, 4), dtype=torch.int32,
+                       device="cuda")
+    for kind in ("cold", "warm"):
+        if kind == "cold":
+            batch.reset()
+        rc, offs = batch.run_into(out)
+        assert rc == 0, bc.lib().bcmc_last_error()
+        assert int(offs[-1]) == total
+        inf = batch.info()
+        assert inf["ran_front_grid"] == inf["front_grid"] and inf["ran_grid"] == inf["grid"]
+        if kind == "cold":
+            assert inf["n_new"] > 0
+        else:
+            assert inf["n_new"] == 0
+        got = out[:total].cpu().numpy()
+        for j, (v, iso) in enumerate(jobs):
+            sl = got[int(offs[j]): int(offs[j + 1])]
+            v32, vb = ref[v][j - 4 * v]
+            assert sl.shape[0] == len(vb), (kind, j)
+            assert np.array_equal(sl[:, 3].view(np.uint32), vb), (kind, j)
+            assert np.array_equal(sl[:, :3].view(np.float32).view(np.uint32), v32.view(np.uint32)), (kind, j)
+            if kind == "cold":
+                rc, T = plain[v].extract_into(iso, pbuf)
+                assert rc == 0 and 3 * T == len(vb)
+                assert np.array_equal(pbuf[: 3 * T].cpu().numpy(), sl), j
+        say(f"  {kind}: all 192 job slices equal the oracle's soup and the plain extract "
+            f"({tiles_per_wg:.0f} blocks per front workgroup)")
+    batch.close()

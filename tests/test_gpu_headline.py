@@ -11,12 +11,15 @@ rule, plain marching cubes over the decoded 3x3x3 neighbourhood) with the
 GPU's stream words, flags, per-block counts and the block's slice of the
 triangle soup.  Properties that hold at any size (counts, offsets, totals,
 vertex bounds, the cache's hit and miss counts across the sequence) are
-checked on the whole output of every call."""
+checked on the whole output of every call.  Then the whole soups of the p50
+and p90 calls are compared with the oracle's plain extract of the same
+stream (decoded and run slab by slab on host threads): triangle counts,
+float32 vertices bit for bit and float64 vertices within 1e-5 voxel."""
 import numpy as np
 import pytest
 
 from synthetic import fields
-from tests.gpu_common import say, torch_cuda
+from tests.gpu_common import oracle_soup_by_slabs, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +111,7 @@ def test_turbulence512_bench_sequence_sampled_parity(orc):
     # stream words of every block around the samples: bit-exact against the
     # oracle encoder; the oracle's neighbourhoods decode those words
     w = words.view(torch.int64).cpu().numpy().view(np.uint64).reshape(nb, RATE)
+    w_all = w.ravel()
     samples = []
     for (bx, by, bz) in picks:
         kept = np.ascontiguousarray(f[4 * bz - 4: 4 * bz + 8, 4 * by - 4: 4 * by + 8, 4 * bx - 4: 4 * bx + 8])
@@ -170,3 +174,22 @@ def test_turbulence512_bench_sequence_sampled_parity(orc):
     assert vol.stats()["n_new"] == 0
     assert checked >= 30
     vol.close()
+
+    # the whole soups against the oracle's plain extract of the same stream
+    for name, iso in (("cold_p50", iso50), ("p90", iso90)):
+        T, soup = soups[name]
+        got = soup.cpu().numpy()
+        pos, n_tri = 0, 0
+        for first, t, v32, vb, v64 in oracle_soup_by_slabs(orc, w_all, (N, N, N), RATE, iso,
+                                                           layers=4, workers=16):
+            n = 3 * t
+            part = got[pos: pos + n]
+            assert np.array_equal(part[:, 3].view(np.uint32), vb), (name, first)
+            assert np.array_equal(part[:, :3].view(np.float32).view(np.uint32),
+                                  v32.view(np.uint32)), (name, first)
+            assert np.max(np.abs(part[:, :3].view(np.float32).astype(np.float64) - v64),
+                          initial=0.0) <= 1e-5, (name, first)
+            pos += n
+            n_tri += t
+        assert n_tri == T and pos == 3 * T, (name, n_tri, T)
+        say(f"  {name}: whole soup ({T} triangles) equals the oracle's")

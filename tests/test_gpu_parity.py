@@ -203,6 +203,76 @@ def test_lru_cache_matches_simulator(bc, orc):
         assert T == orc.mc_count(D, dims, iso)
 
 
+def _lru_step(bc, orc, vol, sim, out, D, dims, rg, iso, check_data=False):
+    rc, T = vol.extract_into(float(iso), out)
+    assert rc == 0, bc.lib().bcmc_last_error()
+    act = orc.active_blocks(rg, dims, iso)
+    rc, I_new, ev = sim.update(act)
+    assert rc == 0
+    st = vol.stats()
+    assert st["n_new"] == len(I_new) and st["n_evicted"] == ev
+    if len(I_new):
+        assert np.array_equal(vol.new_blocks(), I_new)
+    I_slot, S_block, S_age = vol.cache_state()
+    sI, sB, sA = sim.state()
+    assert st["n_slots"] == sim.n_slots
+    assert np.array_equal(I_slot, sI)
+    assert np.array_equal(S_block, sB)
+    assert np.array_equal(S_age, sA)
+    if check_data:
+        data = vol.slot_data()
+        used = S_block >= 0
+        assert np.array_equal(data[used].view(np.uint32), D[S_block[used]].view(np.uint32))
+    return st, T
+
+
+def test_lru_long_sequence_wide_age_keys(bc, orc):
+    """Hundreds of calls after one reset under eviction pressure, checked
+    against the simulator after every call: the age sort's keys (the call of
+    each slot's last use) then span two radix digits.  Advancing the age
+    clock past 2^16 and then 2^24 calls (as that many calls with nothing
+    active would) makes the third and fourth digits vary too, so every
+    radix pass and both choices of the sorted buffer (an odd or even number
+    of live passes) decide evictions."""
+    torch = torch_cuda()
+    dims = (48, 48, 48)
+    f = fields.gaussian_blobs(48, 6, seed=43)
+    s = orc.zfp_encode(f, 8)
+    D = orc.zfp_decode(s, dims, 8)
+    nb = orc.num_blocks(*dims)
+    rg = orc.block_ranges(D, dims)
+    field = orc.blocks_to_field(D, dims)
+    rng = np.random.default_rng(44)
+    isos = [fields.percentile_iso(field, p) for p in rng.uniform(5, 95, 360)]
+    n_act = [int(orc.active_blocks(rg, dims, iso).sum()) for iso in isos]
+    cap = max(n_act) + 8
+    assert cap < 0.8 * nb
+    init = 16
+    say(f"[cache] long LRU sequence {dims}: {nb} blocks, cap {cap} slots, {len(isos)} calls")
+    vol = bc.Volume(s, dims, "f32", 8)
+    vol.set_cache_budget(initial_bytes=init * 256, max_bytes=cap * 256)
+    sim = orc.LRU(nb, init, cap)
+    out = torch.empty((3 * max(orc.mc_count(D, dims, i) for i in isos) + 16, 4),
+                      dtype=torch.int32, device="cuda")
+    evictions = 0
+    for k, iso in enumerate(isos[:300]):
+        st, T = _lru_step(bc, orc, vol, sim, out, D, dims, rg, iso, check_data=(k % 50 == 49))
+        evictions += st["n_evicted"]
+    assert T == orc.mc_count(D, dims, isos[299])
+    assert evictions > 1000
+    say(f"  300 calls: {evictions} evictions, {vol.stats()['n_slots']} slots")
+    for k_idle, span in ((70000, range(300, 330)), (1 << 24, range(330, 360))):
+        vol.age_cache(k_idle)
+        sim.idle(k_idle)
+        ev = 0
+        for k in span:
+            st, T = _lru_step(bc, orc, vol, sim, out, D, dims, rg, isos[k], check_data=True)
+            ev += st["n_evicted"]
+        say(f"  after {k_idle} idle calls: {ev} evictions")
+        assert ev > 50
+        assert T == orc.mc_count(D, dims, isos[span[-1]])
+
+
 def test_cache_cap_error_and_capacity_retry(bc, orc):
     dims = (40, 40, 40)
     f = fields.turbulence(*dims, seed=51, n_modes=32)

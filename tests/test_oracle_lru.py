@@ -108,3 +108,29 @@ def test_invariants_random_sequences(orc, seed):
         if prev is not None and np.array_equal(prev, act):
             assert len(I_new) == 0
         prev = act
+
+
+def test_idle_equals_repeated_empty_updates(orc):
+    """k idle calls at once == k updates with nothing active, from a cache
+    with mixed ages, empty slots and a grown slot range; then both caches
+    evolve identically (the availability marks agree too)."""
+    rng = np.random.default_rng(5)
+    n = 40
+    a, b = orc.LRU(n, 6, 30), orc.LRU(n, 6, 30)
+    for _ in range(12):
+        m = (rng.random(n) < 0.2).astype(np.uint8)
+        assert a.update(m)[0] == b.update(m)[0]
+    for k in (1, 7, 1000):
+        a.idle(k)
+        for _ in range(k):
+            b.update(np.zeros(n, np.uint8))
+        for x, y in zip(a.state(), b.state()):
+            assert np.array_equal(x, y)
+        m = (rng.random(n) < 0.3).astype(np.uint8)
+        ra, rb = a.update(m), b.update(m)
+        assert ra[0] == rb[0] and np.array_equal(ra[1], rb[1]) and ra[2] == rb[2]
+        for x, y in zip(a.state(), b.state()):
+            assert np.array_equal(x, y)
+    # ages saturate at 2^32 - 1
+    a.idle(2 ** 33)
+    assert np.all(a.state()[2] == 2 ** 32 - 1)

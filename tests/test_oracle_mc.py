@@ -371,3 +371,21 @@ def test_edge_records_decode_to_the_soup(orc):
     g1 = g + step
     b = f[g1[:, 2], g1[:, 1], g1[:, 0]]
     assert np.all((a < iso) != (b < iso))
+
+
+def test_slab_orchestration_equals_whole_volume(orc):
+    """The slab-by-slab driver the full-size GPU checks use (each slab decoded
+    with one halo layer, block ids offset) gives the whole volume's soup."""
+    from tests.gpu_common import oracle_soup_by_slabs
+    for dims, layers, rate in (((37, 29, 45), 3, 8), ((24, 20, 32), 2, 4)):
+        f = fields.turbulence(*dims, seed=3, n_modes=32)
+        s = orc.zfp_encode(f, rate)
+        D = orc.zfp_decode(s, dims, rate)
+        iso = fields.percentile_iso(f, 50)
+        v32, vb = orc.mc_extract_f32(D, dims, iso)
+        r = orc.mc_extract(D, dims, iso)
+        parts = list(oracle_soup_by_slabs(orc, s, dims, rate, iso, layers=layers, workers=4))
+        assert sum(p[1] for p in parts) == len(vb) // 3 > 0
+        assert np.array_equal(np.concatenate([p[2] for p in parts]).view(np.uint32), v32.view(np.uint32))
+        assert np.array_equal(np.concatenate([p[3] for p in parts]), vb)
+        assert np.array_equal(np.concatenate([p[4] for p in parts]), r["verts"])
