@@ -286,6 +286,30 @@ BCMC_API int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_st
 BCMC_API int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out);
 BCMC_API void bcmc_batch_free(bcmc_batch *b);
 
+/* ---- extraction without allocation ------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * extraction of bcmc_volume_from_blocks + bcmc_extract over caller-owned
+ * decoded blocks d_blocks ([N_b][64] float, device), written as bcmc_vertex
+ * records into d_out (capacity_vertices records, device), byte for byte the
+ * same soup.  Every other buffer (ranges, flags, block lists, counts,
+ * offsets, sign masks, scan state, counters, the case table) lives in one
+ * static device array of 24 MiB per GPU, held until the process ends, so a
+ * volume may have at most about 2^19 blocks (the exact bound depends on the
+ * shape); larger volumes are rejected with BCMC_E_INVALID before any work.
+ * The function calls no hipMalloc, hipFree or allocating routine.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams or host threads) race and must not be issued.  Calls in
+ * sequence are independent (each clears what must start at zero).
+ * Synchronises hip_stream once to read the triangle count.
+ * Errors: BCMC_E_INVALID (dims, size above the scratch, NaN iso),
+ * BCMC_E_CAPACITY (*n_triangles set, the first capacity_vertices records
+ * written), BCMC_E_NONFINITE, BCMC_E_HIP. */
+BCMC_API int bcmc_extract_blocks_noalloc(const float *d_blocks, uint32_t nx, uint32_t ny,
+                                         uint32_t nz, float iso, void *d_out,
+                                         uint64_t capacity_vertices, uint64_t *n_triangles,
+                                         void *hip_stream);
+
 /* ---- inspection of the last extract (host copies; synchronous) -------- */
 BCMC_API int bcmc_debug_ranges(const bcmc_volume *v, float *h_ranges /* [N_b][2] */);
 /* h_active[b]: bit 0 = active (M_active), bit 1 = may emit (the value hull

@@ -428,6 +428,26 @@ class Batch:
         return self._out[: int(offs[-1])], offs
 
 
+def extract_blocks_noalloc(blocks, dims, iso, out, stream=None):
+    """Extraction over decoded blocks ([N_b, 64] CUDA float32) into a
+    preallocated [cap, 4] int32 CUDA tensor without any device allocation
+    (every scratch buffer lives in the library's static array of about 2^19
+    blocks).  Returns (rc, T); rc is 0 or an error code (E_CAPACITY: T is set,
+    enlarge `out` and call again)."""
+    nx, ny, nz = (int(d) for d in dims)
+    if tuple(blocks.shape) != (num_blocks(nx, ny, nz), 64) or not blocks.is_cuda:
+        raise ValueError("blocks must be a CUDA tensor of shape [N_b, 64]")
+    if not blocks.is_contiguous() or not out.is_contiguous():
+        raise ValueError("blocks and out must be contiguous")
+    T = C.c_uint64(0)
+    rc = lib().bcmc_extract_blocks_noalloc(_dev_ptr(blocks), nx, ny, nz, C.c_float(iso),
+                                           _dev_ptr(out) if out.shape[0] else None, out.shape[0],
+                                           C.byref(T), _stream_ptr(stream))
+    if rc not in (_capi.OK, _capi.E_CAPACITY):
+        _capi.check(rc)
+    return rc, int(T.value)
+
+
 _POOL = {}
 
 

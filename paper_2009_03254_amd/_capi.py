@@ -82,6 +82,7 @@ SIGNATURES = {
     "bcmc_batch_tune": (_int, [_P, C.c_char_p, _P]),
     "bcmc_batch_get_info": (_int, [_P, _P]),
     "bcmc_batch_free": (None, [_P]),
+    "bcmc_extract_blocks_noalloc": (_int, [_P, _u32, _u32, _u32, _f32, _P, _u64, _P, _P]),
     "bcmc_debug_ranges": (_int, [_P, _P]),
     "bcmc_debug_active": (_int, [_P, _P, _P, _P]),
     "bcmc_debug_new": (_int, [_P, _P, _P]),

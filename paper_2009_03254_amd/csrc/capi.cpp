@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -118,15 +119,18 @@ void free_cache(bcmc_volume *v) {
     dev_free(v->d.status);
 }
 
-void layout_status(bcmc_volume *v) {
-    StatusLayout &s = v->sl;
+StatusLayout status_layout(const Geom &g, uint64_t max_slots) {
+    StatusLayout s;
     s.blk = 0;
-    s.slot = s.blk + (v->g.nb + BLK_TILE - 1) / BLK_TILE;
-    s.mc = s.slot + (v->max_slots + SLOT_TILE - 1) / SLOT_TILE;
-    s.scan = s.mc + (v->g.nb + SCAN_TILE - 1) / SCAN_TILE + 1;
-    uint64_t rtiles = (v->max_slots + RADIX_TILE - 1) / RADIX_TILE;
+    s.slot = s.blk + (g.nb + BLK_TILE - 1) / BLK_TILE;
+    s.mc = s.slot + (max_slots + SLOT_TILE - 1) / SLOT_TILE;
+    s.scan = s.mc + (g.nb + SCAN_TILE - 1) / SCAN_TILE + 1;
+    uint64_t rtiles = (max_slots + RADIX_TILE - 1) / RADIX_TILE;
     s.total = s.scan + (256 * rtiles + SCAN_TILE - 1) / SCAN_TILE + 1;
+    return s;
 }
+
+void layout_status(bcmc_volume *v) { v->sl = status_layout(v->g, v->max_slots); }
 
 int alloc_common(bcmc_volume *v) {
     int rc;
@@ -651,3 +655,126 @@ int bcmc_debug_cases(bcmc_volume *v, float iso, uint8_t *d_cases, void *hip_stre
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Extraction over caller-owned decoded blocks without any allocation: every
+// buffer the kernels need beyond the caller's input and output lives in one
+// file-scope device array.  Each GPU holds its own copy of the array (it is
+// loaded with the module on that device) until the process ends; host code
+// never passes the array's name to a kernel, only the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint64_t kScratchBytes = 24ull << 20;   // about 2^19 blocks (a 320^3 volume)
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`, looked up once per device.
+int scratch_address(void **out) {
+    int dev = 0;
+    BCMC_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return invalid("device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return BCMC_E_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return BCMC_OK;
+}
+
+// Carves the extraction's buffers out of the scratch array (256-byte
+// aligned pieces); returns the bytes needed.
+uint64_t carve_scratch(const Geom &g, const StatusLayout &sl, uintptr_t base, DevState &d,
+                       unsigned int **range_err) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        unsigned char *p = reinterpret_cast<unsigned char *>(base + off);
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    d.ctr = reinterpret_cast<Counters *>(take(sizeof(Counters)));
+    *range_err = reinterpret_cast<unsigned int *>(take(sizeof(unsigned int)));
+    d.mc_table = reinterpret_cast<uint64_t *>(take(256 * sizeof(uint64_t)));
+    d.ranges = reinterpret_cast<float2 *>(take(g.nb * sizeof(float2)));
+    d.tile_ranges = reinterpret_cast<float2 *>(take(cull_tiles(g) * sizeof(float2)));
+    d.active = take((g.nb + 16 + 3) / 4 * 4);
+    d.I_active = reinterpret_cast<uint32_t *>(take(g.nb * sizeof(uint32_t)));
+    d.blk_cnt = reinterpret_cast<uint32_t *>(take(g.nb * sizeof(uint32_t)));
+    d.blk_off = reinterpret_cast<uint64_t *>(take(g.nb * sizeof(uint64_t)));
+    d.masks = reinterpret_cast<uint64_t *>(take(g.nb * sizeof(uint64_t)));
+    d.part_cand = reinterpret_cast<uint32_t *>(take((g.nb + BLK_TILE - 1) / BLK_TILE * sizeof(uint32_t)));
+    d.part_wave = reinterpret_cast<uint64_t *>(take(4 * MC_MAX_GRID * sizeof(uint64_t)));
+    d.part_occw = reinterpret_cast<uint32_t *>(take(4 * MC_MAX_GRID * sizeof(uint32_t)));
+    d.status = reinterpret_cast<uint64_t *>(take(sl.total * sizeof(uint64_t)));
+    return off;
+}
+
+}  // namespace
+
+extern "C" int bcmc_extract_blocks_noalloc(const float *d_blocks, uint32_t nx, uint32_t ny,
+                                           uint32_t nz, float iso, void *d_out,
+                                           uint64_t capacity_vertices, uint64_t *n_triangles,
+                                           void *hip_stream) {
+    if (!d_blocks || !n_triangles) return invalid("null argument");
+    if (!d_out && capacity_vertices) return invalid("null output buffer with nonzero capacity");
+    if (iso != iso) return invalid("iso is NaN");
+    *n_triangles = 0;
+    int rc = check_dims(nx, ny, nz);
+    if (rc) return rc;
+    if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
+    const Geom g = make_geom(nx, ny, nz);
+    const StatusLayout sl = status_layout(g, 0);
+    DevState d;
+    unsigned int *range_err = nullptr;
+    const uint64_t need = carve_scratch(g, sl, 0, d, &range_err);   // sizes only
+    if (need > kScratchBytes)
+        return invalid("volume of " + std::to_string(g.nb) + " blocks needs " + std::to_string(need) +
+                       " bytes of scratch; the static scratch holds " + std::to_string(kScratchBytes));
+    void *base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    carve_scratch(g, sl, reinterpret_cast<uintptr_t>(base), d, &range_err);
+    hipStream_t s = as_stream(hip_stream);
+    // the previous call on this device left its own contents: clear what
+    // must start at zero (counters, error word, flags), rewrite the table
+    launch_fill_u32(reinterpret_cast<uint32_t *>(d.ctr), 0u, sizeof(Counters) / 4, s);
+    launch_fill_u32(range_err, 0u, 1, s);
+    BCMC_HIP_TRY(hipMemcpyAsync(d.mc_table, mc_table_host(), 256 * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, s));
+    launch_ranges_from_blocks(g, d_blocks, d.ranges, range_err, s);
+    launch_tile_ranges(g, d.ranges, d.tile_ranges, s);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(d.active), 0u, (g.nb + 3) / 4, s);
+    launch_cull(g, d, sl, iso, NAN, 0, 1, s);
+    launch_compact_blocks(g, d, sl, 1, s);
+    launch_mc_count(g, d, d_blocks, nullptr, 1, iso, 0, s);
+    launch_mc_emit(g, d, d_blocks, nullptr, 1, iso, d_out, capacity_vertices, 0, s);
+    BCMC_HIP_TRY(hipGetLastError());
+    Counters c;
+    unsigned int rerr = 0;
+    BCMC_HIP_TRY(hipMemcpyAsync(&c, d.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    BCMC_HIP_TRY(hipMemcpyAsync(&rerr, range_err, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    BCMC_HIP_TRY(hipStreamSynchronize(s));
+    if (rerr & ERR_NONFINITE) {
+        set_error("the blocks hold non-finite values");
+        return BCMC_E_NONFINITE;
+    }
+    if (c.err) {
+        set_error("internal consistency check failed in the extraction");
+        return BCMC_E_HIP;
+    }
+    *n_triangles = c.total_verts / 3;
+    if (c.total_verts > capacity_vertices) {
+        set_error("vertex buffer too small: need " + std::to_string(c.total_verts) + " vertices");
+        return BCMC_E_CAPACITY;
+    }
+    return BCMC_OK;
+}
