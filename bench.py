@@ -1,26 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the block-compressed isosurface extraction path on one MI355X.
 
-Workload: 512^3 float32 turbulence (256 random Fourier modes, k^-5/3
-spectrum, unit variance), fixed-rate ZFP at 8 bits/value, isovalues at the
-50th and 90th percentiles of the decoded field, LRU block cache with an
-initial budget of 25% of the blocks (growable).  One step = one pass of the
-whole path over that sequence:
+Headline workload (the largest configuration that fits one GPU): a
+5120 x 3840 x 768 float64 channel-flow-like field (tanh mean profile in y plus
+Fourier turbulence of 0.1 relative amplitude, seed 5), generated and
+fixed-rate ZFP-encoded at 2 bits/value slab by slab on the GPU (3.8 GB of
+compressed words resident in HBM before timing), isovalue 0.5, LRU block cache
+capped at 64 GiB of decoded float32.  One step = one cold extraction: cull,
+cache update, decode of every needed block, marching cubes count and emission,
+triangle-count readback (paper Sec. 4).  Before each step, outside its
+timing, the cache is emptied and the 256 MB last-level cache is flushed by a
+1 GiB write.  `value` = triangles per second over the timed steps.
 
-    empty the cache -> p50 (cold) -> p90 -> p50 (warm) -> p50 (repeat)
-
-each call being cull + cache update + decode of the new blocks + marching
-cubes + count readback (paper Sec. 4).  The compressed stream is resident in
-HBM before timing starts.  Prints one JSON line on stdout; progress goes to
-stderr.
+Extra keys: the 512^3 turbulence call sequence (cold p50, p90, warm p50,
+repeat p50), its 8-byte record variants, the differentiable form, the batched
+form, and the oracle timed on a bounded sample on one host core.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,63 +33,114 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
-RATE = 8
+RATE = 8                # the 512^3 turbulence workload
+FLUSH_BYTES = 1 << 30   # write that evicts the 256 MB last-level cache
 
 
 # Sources of the single-volume kernels, hashed to tell whether the committed
 # traffic counters were taken on the kernels as they are now.
 KERNEL_SOURCES = ("common.h", "mc_device.h", "zfp_device.h", "extract.hip", "zfp.hip", "tables.cpp",
                   "gen_ntri.cpp")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "path_turbulence512_rate8_hbm_counters.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "path_channelflow_f64_rate2_hbm_counters.md")
+COUNTERS_FILE_512 = os.path.join(ROOT, "profiles", "path_turbulence512_rate8_hbm_counters.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when there is
-    none or the kernel sources changed since it was taken."""
+def sources_sha256():
     import hashlib
-    import re
-    try:
-        text = open(COUNTERS_FILE).read()
-    except OSError:
-        return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2009_03254_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, counters_file=None):
+    """HBM bytes per dispatch of `kernel` from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when there is
+    none or the kernel sources changed since it was taken."""
+    import re
+    try:
+        text = open(counters_file or COUNTERS_FILE).read()
+    except OSError:
+        return None
     m = re.search(rf"^traffic {re.escape(kernel)} bytes_per_dispatch=(\d+) sources_sha256=(\w+)$",
                   text, re.M)
-    if not m or m.group(2) != h.hexdigest():
+    if not m or m.group(2) != sources_sha256():
         return None
     return int(m.group(1))
 
 
-def cpu_baseline(stream_np, n, nz_sample, iso):
-    """The oracle as it stands (decode every block, plain marching cubes),
-    single-threaded, on the first nz_sample z-planes of the same stream."""
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def flush_last_level_cache(buf):
+    """One write of FLUSH_BYTES: evicts the 256 MB last-level cache (and L2)."""
+    buf.fill_(float(time.perf_counter_ns() & 0xFFFF))
+
+
+def cpu_baseline_oracle(words_np, dims, rate, is_f64, iso, sample):
+    """The oracle as it stands (decode every block, plain marching cubes over
+    every cell), single-threaded, on a bounded sample: the first z-planes of
+    the same stream given by `dims`."""
     import oracle
     oracle.build(force=False)
-    nbx = (n + 3) // 4
-    nb_sample = nbx * nbx * ((nz_sample + 3) // 4)
-    words = stream_np[: nb_sample * RATE]
-    dims = (n, n, nz_sample)
     t0 = time.perf_counter()
-    blocks = oracle.zfp_decode(words, dims, RATE)
+    blocks = oracle.zfp_decode(words_np, dims, rate, is_f64)
     r = oracle.mc_extract(blocks, dims, iso, want=("verts", "vblock"))
     dt = time.perf_counter() - t0
+    model, nproc = host_cpu()
     return {
         "value": r["T"] / dt,
         "unit": "triangles/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"decode-all + plain MC of the first {nz_sample} z-planes "
-                  f"({nb_sample} blocks, {r['T']} triangles at the p50 isovalue), {dt:.2f} s",
-        "seconds": dt,
+        "sample": f"{sample}: decode-all + plain MC of {dims[0]}x{dims[1]}x{dims[2]} "
+                  f"({oracle.num_blocks(*dims)} blocks, {r['T']} triangles), {dt:.2f} s",
+        "seconds": round(dt, 3),
+        "cpu_model": model,
+        "nproc": nproc,
     }
+
+
+# Per-kernel algorithmic bytes (SURVEY-defined per-unit figures, no
+# bookkeeping) of the stages that hold one kernel each, from a call's stats:
+# stage 2 = assign + decode of the new blocks, stage 5 = emission.
+def kernel_defs(rate):
+    return {
+        "k_assign_decode": (2, lambda st: st["n_new"] * (8.0 * rate + 256.0),
+                            lambda st: st["n_new"] > 0),
+        "k_mc_emit": (5, lambda st: 256.0 * st["n_occupied"] + 24.0 * st["n_triangles"],
+                      lambda st: True),
+    }
+
+
+def kstats(recs, stage, bytes_fn, live_fn):
+    """Totals over call records (seconds, stats) of one stage's event times."""
+    ms = sum(r[1]["stage_ms"][stage] for r in recs if live_fn(r[1]))
+    nbytes = sum(bytes_fn(r[1]) for r in recs if live_fn(r[1]))
+    launches = sum(1 for r in recs if live_fn(r[1]))
+    return {"total_ms": ms, "bytes": nbytes, "launches": max(launches, 1),
+            "avg_ms": ms / max(launches, 1),
+            "gbs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
+
+
+def stage_medians(recs):
+    import numpy as np
+    return [round(float(np.median([r[1]["stage_ms"][i] for r in recs])), 4) for i in range(8)]
 
 
 def differentiable_bench(steps, warmup):
@@ -270,13 +326,10 @@ def batch_bench(steps, warmup):
     }
 
 
-def large_bench(steps, warmup):
-    """5120 x 3840 x 768 float64 channel-flow-like field (tanh mean profile +
-    0.1 relative Fourier turbulence, seed 5), generated and ZFP-encoded at
-    rate 2 slab by slab on the GPU (3.8 GB compressed), iso 0.5, cache capped
-    at 64 GiB of decoded float32: cold extract (cache emptied) and warm
-    repeat, medians of `steps` runs, with per-stage HIP-event times."""
-    import numpy as np
+
+def channel_flow_volume():
+    """The 5120 x 3840 x 768 float64 channel flow, encoded at rate 2 slab by
+    slab on the GPU: (Volume, words kept for the CPU sample, seconds)."""
     import torch
 
     import paper_2009_03254_amd as bcmc
@@ -296,106 +349,158 @@ def large_bench(steps, warmup):
         del f, w
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
+    # the CPU sample: the words of the first two block layers (8 z-planes)
+    sample = words[: 2 * per_layer * rate].view(torch.int64).cpu().numpy().view("uint64").copy()
     vol = bcmc.Volume(words, (nx, ny, nz), "f64", rate)
     del words
     torch.cuda.empty_cache()
     vol.set_cache_budget(initial_bytes=0, max_bytes=64 << 30)
-    probe = torch.empty((1, 4), dtype=torch.int32, device="cuda")
-    _, T = vol.extract_into(0.5, probe)
-    out = torch.empty((3 * T + 64, 4), dtype=torch.int32, device="cuda")
-
-    def calls(cold, n_warm):
-        recs = []
-        for k in range(n_warm + steps):
-            if cold:
-                vol.reset_cache()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            rc, T2 = vol.extract_into(0.5, out)
-            dt = time.perf_counter() - t
-            if rc != 0 or T2 != T:
-                raise bcmc.BcmcError(rc, bcmc.lib().bcmc_last_error().decode())
-            if k >= n_warm:
-                recs.append((dt, vol.stats()))
-        return recs
-
-    def run(cold):
-        recs = calls(cold, warmup)          # host-timed, no events
-        vol.set_profiling(True)             # per-stage times from more calls
-        prof = calls(cold, 0)
-        vol.set_profiling(False)
-        ms = float(np.median([r[0] for r in recs])) * 1e3
-        st = recs[-1][1]
-        return {"ms": round(ms, 4), "triangles_per_s": round(T / (ms * 1e-3)),
-                "alg_gbs": round(st["alg_bytes"] / (ms * 1e-3) / 1e9, 2),
-                "n_active": st["n_active"], "n_new": st["n_new"], "n_occupied": st["n_occupied"],
-                "stage_ms": [round(float(np.median([r[1]["stage_ms"][i] for r in prof])), 4)
-                             for i in range(8)]}
-
-    cold = run(True)
-    warm = run(False)
-    vol.close()
-    cull_ms = warm["stage_ms"][0]
-    return {
-        "workload": f"channel flow {nx}x{ny}x{nz} f64 (tanh profile + 0.1 Fourier turbulence, "
-                    "seed 5), ZFP rate 2, iso 0.5, cache cap 64 GiB",
-        "n_blocks": nb, "triangles": T, "generate_encode_s": round(gen_s, 2),
-        "cold": cold, "warm": warm,
-        "cull_range_gbs": round(8.0 * nb / (cull_ms * 1e-3) / 1e9, 1) if cull_ms > 0 else None,
-        "note": "cull_range_gbs = the 8-byte range table over the cull + compaction stage time",
-    }
+    return vol, sample, gen_s
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=512, help="volume edge (default 512)")
-    ap.add_argument("--cpu-sample-z", type=int, default=160,
-                    help="z-planes of the oracle's CPU-baseline sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-differentiable", action="store_true",
-                    help="skip the fwd / fwd+bwd measurement of the differentiable form")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched (48 volumes x 4 isovalues) measurement")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 5120x3840x768 float64 measurement")
-    ap.add_argument("--large-only", action="store_true",
-                    help="run only the 5120x3840x768 float64 measurement and print its JSON")
-    ap.add_argument("--batched-only", action="store_true",
-                    help="run only the batched measurement and print its JSON (for profiling)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--no-profile-events", action="store_true",
-                    help="no HIP events inside the timed steps (the roofline then takes "
-                         "the dominant kernel's time from the untimed profiled steps)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}): the extraction "
-              "path has no multi-GPU form; a volume would be split into z-slabs, one per GPU",
-              file=sys.stderr)
-        sys.exit(2)
-
+def headline(args):
+    """Cold extractions of the channel flow: warm-up, profiled steps (events
+    around every stage: the breakdown and the dominant kernel), then the
+    timed steps with events around the dominant kernel's stage only."""
     import numpy as np
     import torch
 
     import paper_2009_03254_amd as bcmc
     from synthetic import fields
 
-    n = args.n
+    rate = 2
+    nx, ny, nz = fields.CHANNEL_FLOW_DIMS
+    iso = 0.5
+    log(f"[bench] channel flow {nx}x{ny}x{nz} f64: generating and encoding at rate {rate} on the GPU")
+    vol, sample_words, gen_s = channel_flow_volume()
+    nb = vol.n_blocks
+    probe = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    _, T = vol.extract_into(iso, probe)
+    out = torch.empty((3 * T + 64, 4), dtype=torch.int32, device="cuda")
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+
+    def call(cold, record):
+        if cold:
+            vol.reset_cache()
+            flush_last_level_cache(flush_buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, T2 = vol.extract_into(iso, out)      # synchronises to read the count
+        dt = time.perf_counter() - t0
+        if rc != 0 or T2 != T:
+            raise bcmc.BcmcError(rc, bcmc.lib().bcmc_last_error().decode())
+        record.append((dt, vol.stats()))
+
+    kdefs = kernel_defs(rate)
+    for _ in range(args.warmup):
+        call(True, [])
+    vol.set_profiling(True)
+    prof = []
+    for _ in range(args.steps):
+        call(True, prof)
+    vol.set_profiling(False)
+    kern = {k: kstats(prof, *d) for k, d in kdefs.items()}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    if not args.no_profile_events:
+        vol.set_profiling(True, stages=[kdefs[dom][0]])
+    recs = []
+    torch.cuda.synchronize()
+    t_region = time.perf_counter()
+    for _ in range(args.steps):
+        call(True, recs)
+    torch.cuda.synchronize()
+    region_s = time.perf_counter() - t_region
+    vol.set_profiling(False)
+    kd = kstats(recs, *kdefs[dom]) if not args.no_profile_events else kern[dom]
+
+    # warm repeats for context
+    call(True, [])
+    warm, warm_prof = [], []
+    for _ in range(args.steps):
+        call(False, warm)
+    vol.set_profiling(True)
+    for _ in range(args.steps):
+        call(False, warm_prof)
+    vol.set_profiling(False)
+    vol.close()
+
+    ext_s = sum(r[0] for r in recs)
+    st = recs[-1][1]
+    ms = ext_s / len(recs) * 1e3
+    alg = st["alg_bytes"]
+    alg_no_rt = alg - 8.0 * nb
+    warm_ms = float(np.mean([r[0] for r in warm])) * 1e3
+    wst = warm[-1][1]
+    gpu_ms = float(np.mean([r[1]["stage_ms"][7] for r in prof]))
+    result = {
+        "metric": "triangles/sec + HBM GB/s for decompress+extract",
+        "value": T * len(recs) / ext_s,
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 stream, f32 decoded",
+        "data": "synthetic",
+        "config": {
+            "workload": f"channel flow {nx}x{ny}x{nz} f64 (tanh profile + 0.1 Fourier "
+                        "turbulence, seed 5), ZFP rate 2, iso 0.5, cache cap 64 GiB; "
+                        "step = one cold extract",
+            "n_blocks": nb, "iso": iso, "parallelism": "single GPU",
+        },
+        "triangles": T,
+        "hbm_gbs_alg": round(alg / (ms * 1e-3) / 1e9, 2),
+        "hbm_frac_alg": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_gbs_alg_without_range_table": round(alg_no_rt / (ms * 1e-3) / 1e9, 2),
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": round(kd["gbs"], 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom), "avg_launch_ms": round(kd["avg_ms"], 5),
+            "launches": kd["launches"],
+            "alg_bytes_per_launch": round(kd["bytes"] / kd["launches"]),
+        },
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_gbs": round(v["gbs"], 1),
+                        "frac": round(v["gbs"] / HBM_PEAK_GBS, 4),
+                        "share_of_gpu_time": round(v["total_ms"] / max(gpu_ms * len(prof), 1e-9), 3)}
+                    for k, v in kern.items()},
+        "cold": {"n_active": st["n_active"], "n_new": st["n_new"], "n_occupied": st["n_occupied"],
+                 "n_candidates": st["n_candidates"], "gpu_ms": round(gpu_ms, 4),
+                 "stage_ms": stage_medians(prof),
+                 "timed_region_s": round(region_s, 4),
+                 "wall_ms_per_step": round(region_s / args.steps * 1e3, 4)},
+        "warm": {"ms": round(warm_ms, 4), "triangles_per_s": round(T / (warm_ms * 1e-3)),
+                 "alg_gbs": round(wst["alg_bytes"] / (warm_ms * 1e-3) / 1e9, 2),
+                 "alg_gbs_without_range_table": round((wst["alg_bytes"] - 8.0 * nb)
+                                                      / (warm_ms * 1e-3) / 1e9, 2),
+                 "n_new": wst["n_new"], "stage_ms": stage_medians(warm_prof)},
+        "generate_encode_s": round(gen_s, 2),
+        "note": "ms_per_step / value: host-timed cold extract calls (count readback included); "
+                "the cache reset and the 1 GiB cache flush before each step are outside that "
+                "time (wall_ms_per_step includes them); stage_ms: [cull+compaction, cache "
+                "update, assign+decode, masks+count, -, emission, -, total] from HIP events "
+                "in separate profiled steps",
+    }
+    return result, sample_words
+
+
+def turbulence512(args):
+    """The 512^3 turbulence call sequence (empty cache -> p50 cold -> p90 ->
+    p50 warm -> p50 repeat, initial cache 25% of the blocks), 16-byte
+    records, then 8-byte edge records."""
+    import numpy as np
+    import torch
+
+    import paper_2009_03254_amd as bcmc
+    from synthetic import fields
+
+    n = 512
     dims = (n, n, n)
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.batched_only:
-        print(json.dumps({"batched": batch_bench(max(args.steps, 5), args.warmup)}), flush=True)
-        return
-    if args.large_only:
-        print(json.dumps({"large_f64": large_bench(max(args.steps, 3), 1)}), flush=True)
-        return
-    log(f"[bench] generating {n}^3 turbulence on the GPU")
+    log(f"[bench] {n}^3 turbulence: generating and encoding at rate {RATE} on the GPU")
     field = fields.turbulence_torch(n, seed=2, device=dev)
-    log("[bench] encoding (fixed-rate ZFP, rate 8) on the GPU")
     words = bcmc.encode(field, RATE)
     del field
     vol = bcmc.Volume(words, dims, "f32", RATE)
@@ -406,8 +511,7 @@ def main():
     iso90 = fields.percentile_iso_torch(D, 90)
     del D
     torch.cuda.empty_cache()
-    log(f"[bench] N_b={nb} iso50={float(iso50):.6f} iso90={float(iso90):.6f}")
-
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
     if args.copy_calibration:
         # 1 GiB read + 1 GiB written by the library's plain copy kernel
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -417,88 +521,54 @@ def main():
             b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
         del a, b
-
-    # output buffer sized from one probe of each isovalue
     out = torch.empty((1, 4), dtype=torch.int32, device=dev)
     cap_T = 0
     for iso in (iso50, iso90):
         rc, T = vol.extract_into(float(iso), out)
         cap_T = max(cap_T, T)
     out = torch.empty((3 * cap_T + 1024, 4), dtype=torch.int32, device=dev)
-
     seq = (("cold_p50", iso50), ("p90", iso90), ("warm_p50", iso50), ("repeat_p50", iso50))
 
-    def step(record=None, buf=None):
+    def step(record, buf=None):
         buf = out if buf is None else buf
         vol.reset_cache()
-        tris = 0
+        flush_last_level_cache(flush_buf)
         for name, iso in seq:
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             rc, T = vol.extract_into(float(iso), buf)
             dt = time.perf_counter() - t0
             if rc != 0:
                 raise bcmc.BcmcError(rc, bcmc.lib().bcmc_last_error().decode())
-            tris += T
-            if record is not None:
-                record.append((name, dt, vol.stats()))
-        return tris
+            record.append((name, dt, vol.stats()))
 
+    def as2(recs):
+        return [(r[1], r[2]) for r in recs]
+
+    kdefs = kernel_defs(RATE)
     for _ in range(args.warmup):
-        step()
-
-    # per-kernel algorithmic bytes / HIP-event durations (stage_ms: 2 = assign
-    # + decode, 3 = sign masks + MC count, 5 = MC emit with the block offsets)
-    def kstats(recs, stage, bytes_fn, live_fn):
-        ms = sum(r[2]["stage_ms"][stage] for r in recs)
-        nbytes = sum(bytes_fn(r[2]) for r in recs)
-        launches = sum(1 for r in recs if live_fn(r[2]))
-        return {"total_ms": ms, "bytes": nbytes, "launches": max(launches, 1),
-                "avg_ms": ms / max(launches, 1),
-                "gbs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0}
-
-    kdefs = {
-        "k_assign_decode": (2, lambda st: st["n_new"] * (8.0 * RATE + 256.0),
-                            lambda st: st["n_new"] > 0),
-        # masks of active blocks not decoded by the call (their slots are
-        # read once) + one 8-byte mask per active block for the count
-        "k_masks+k_mc_count": (3, lambda st: 256.0 * (st["n_active"] - st["n_new"]) +
-                               8.0 * st["n_active"], lambda st: True),
-        # the emission also reads each active block's count and writes its
-        # offset (the block scan is folded into it)
-        "k_mc_emit": (5, lambda st: 256.0 * st["n_occupied"] + 24.0 * st["n_triangles"] +
-                      12.0 * st["n_active"], lambda st: True),
-    }
-
-    # untimed steps with events around every stage: the per-stage breakdown
-    # and the choice of the dominant kernel
+        step([])
     vol.set_profiling(True)
-    prof_recs = []
+    prof = []
     for _ in range(args.steps):
-        step(prof_recs)
+        step(prof)
     vol.set_profiling(False)
-    kern = {k: kstats(prof_recs, *d) for k, d in kdefs.items()}
+    kern = {k: kstats(as2(prof), *d) for k, d in kdefs.items()}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-
-    # timed steps: events only around the dominant kernel's stage (each event
-    # adds a few microseconds of stream time)
     if not args.no_profile_events:
         vol.set_profiling(True, stages=[kdefs[dom][0]])
-    records = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    total_tris = 0
+    recs = []
     for _ in range(args.steps):
-        total_tris += step(records)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        step(recs)
     vol.set_profiling(False)
-
-    # per-call summary (medians over steps; host time from the timed steps,
-    # stage times from the profiled ones)
+    kd = kstats(as2(recs), *kdefs[dom]) if not args.no_profile_events else kern[dom]
+    ext_s = sum(r[1] for r in recs)
+    tris = sum(r[2]["n_triangles"] for r in recs)
+    alg = sum(r[2]["alg_bytes"] for r in recs)
     calls = []
     for name, _ in seq:
-        rs = [r for r in records if r[0] == name]
-        ps = [r for r in prof_recs if r[0] == name]
+        rs = [r for r in recs if r[0] == name]
+        ps = [r for r in prof if r[0] == name]
         st = rs[-1][2]
         ms = float(np.median([r[1] for r in rs]) * 1e3)
         calls.append({
@@ -507,95 +577,116 @@ def main():
             "n_occupied": st["n_occupied"], "n_candidates": st["n_candidates"],
             "hit_rate": round(st["hit_rate"], 4),
             "alg_gbs": round(st["alg_bytes"] / (ms * 1e-3) / 1e9, 2),
-            "stage_ms": [round(float(np.median([r[2]["stage_ms"][i] for r in ps])), 4)
-                         for i in range(8)],
+            "stage_ms": stage_medians([(r[1], r[2]) for r in ps]),
         })
-
-    # the dominant kernel over the timed region (its own events), else from
-    # the profiled steps
-    kd = kstats(records, *kdefs[dom]) if not args.no_profile_events else kern[dom]
-    alg_total = sum(r[2]["alg_bytes"] for r in records)
-
-    ms_per_step = elapsed / args.steps * 1e3
-    result = {
-        "metric": "triangles/sec + HBM GB/s for decompress+extract",
-        "value": total_tris / elapsed,
-        "unit": "triangles/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"turbulence {n}^3 f32 (256 Fourier modes, k^-5/3), ZFP rate {RATE}, "
-                        "iso p50/p90, initial cache 25% of blocks; step = cold p50, p90, "
-                        "warm p50, repeat p50",
-            "n_blocks": nb, "iso_p50": float(iso50), "iso_p90": float(iso90),
-            "parallelism": "single GPU",
-        },
-        "hbm_gbs_alg": round(alg_total / elapsed / 1e9, 2),
-        "hbm_frac_alg": round(alg_total / elapsed / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {
-            "bound": "hbm", "kernel": dom, "achieved": round(kd["gbs"], 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom), "avg_launch_ms": round(kd["avg_ms"], 5),
-            "launches": kd["launches"],
-            "alg_bytes_per_launch": round(kd["bytes"] / kd["launches"]),
-        },
+    res = {
+        "workload": f"turbulence {n}^3 f32 (256 Fourier modes, k^-5/3), ZFP rate {RATE}, iso "
+                    "p50/p90, initial cache 25% of blocks; step = cold p50 (after a cache "
+                    "flush), p90, warm p50, repeat p50",
+        "n_blocks": nb, "iso_p50": float(iso50), "iso_p90": float(iso90),
+        "triangles_per_s": round(tris / ext_s), "ms_per_step": round(ext_s / args.steps * 1e3, 4),
+        "hbm_gbs_alg": round(alg / ext_s / 1e9, 2),
+        "roofline": {"kernel": dom, "achieved": round(kd["gbs"], 2),
+                     "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, COUNTERS_FILE_512),
+                     "avg_launch_ms": round(kd["avg_ms"], 5), "launches": kd["launches"],
+                     "alg_bytes_per_launch": round(kd["bytes"] / kd["launches"])},
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 5), "alg_gbs": round(v["gbs"], 1),
-                        "share_of_gpu_time": round(v["total_ms"] / max(
-                            sum(r[2]["stage_ms"][7] for r in prof_recs), 1e-9), 3)}
-                    for k, v in kern.items()},
+                        "frac": round(v["gbs"] / HBM_PEAK_GBS, 4)} for k, v in kern.items()},
         "calls": calls,
     }
-    if not args.no_differentiable:
-        log("[bench] differentiable form (256^3 blobs)")
-        result["differentiable"] = differentiable_bench(max(args.steps, 5), 2)
-    # the same steps writing 8-byte edge records instead of 16-byte vertices
+    # the same steps with 8-byte edge records
     vol.set_vertex_format("edge8")
     out8 = torch.empty(3 * cap_T + 1024, dtype=torch.int64, device=dev)
     for _ in range(args.warmup):
-        step(buf=out8)
-    if not args.no_profile_events:
-        vol.set_profiling(True, stages=[5])
+        step([], out8)
+    vol.set_profiling(True, stages=[5])
     rec8 = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tris8 = 0
     for _ in range(args.steps):
-        tris8 += step(rec8, buf=out8)
-    torch.cuda.synchronize()
-    el8 = time.perf_counter() - t0
+        step(rec8, out8)
     vol.set_profiling(False)
     vol.set_vertex_format("f32")
-    del out8
-    e_ms = sum(r[2]["stage_ms"][5] for r in rec8) / max(len(rec8), 1)
-    e_bytes = sum(256.0 * r[2]["n_occupied"] + 24.0 * r[2]["n_triangles"] + 12.0 * r[2]["n_active"]
-                  for r in rec8) / max(len(rec8), 1)
-    result["edge8"] = {
-        "value": tris8 / el8, "unit": "triangles/s", "ms_per_step": round(el8 / args.steps * 1e3, 4),
-        "hbm_gbs_alg": round(sum(r[2]["alg_bytes"] for r in rec8) / el8 / 1e9, 2),
-        "k_mc_emit_avg_ms": round(e_ms, 5),
-        "k_mc_emit_frac": round(e_bytes / (e_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if e_ms > 0 else None,
-        "note": "same workload and steps; output as 8-byte edge records (block, cell, edge, "
-                "22-bit t), decoded positions within 2^-23 voxel of the float32 soup",
+    e = kstats(as2(rec8), *kernel_defs(RATE)["k_mc_emit"])
+    t8 = sum(r[1] for r in rec8)
+    res["edge8"] = {
+        "triangles_per_s": round(sum(r[2]["n_triangles"] for r in rec8) / t8),
+        "ms_per_step": round(t8 / args.steps * 1e3, 4),
+        "k_mc_emit_avg_ms": round(e["avg_ms"], 5), "k_mc_emit_frac": round(e["gbs"] / HBM_PEAK_GBS, 4),
+        "note": "8-byte edge records (block, cell, edge, 22-bit t): positions within 2^-23 "
+                "voxel of the float32 soup",
     }
-    if not args.no_large:
-        vol.close()
-        log("[bench] large float64 volume (5120x3840x768, rate 2)")
-        result["large_f64"] = large_bench(max(args.steps // 2, 3), 1)
-    if not args.no_batched:
-        log("[bench] batched form (48 volumes x 4 isovalues)")
-        result["batched"] = batch_bench(max(args.steps, 5), 2)
-    if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle baseline on {args.cpu_sample_z} z-planes")
-        stream_np = words.cpu().numpy()
-        result["cpu_baseline"] = cpu_baseline(stream_np, n, args.cpu_sample_z, float(iso50))
+    del out8
     vol.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-differentiable", action="store_true",
+                    help="skip the fwd / fwd+bwd measurement of the differentiable form")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched (48 volumes x 4 isovalues) measurement")
+    ap.add_argument("--no-512", action="store_true", help="skip the 512^3 turbulence sequence")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline channel-flow measurement (no extra keys)")
+    ap.add_argument("--only-512", action="store_true",
+                    help="only the 512^3 turbulence sequence, printed as its own JSON")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched measurement, printed as its own JSON")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-profile-events", action="store_true",
+                    help="no HIP events inside the timed steps (the roofline then takes "
+                         "the dominant kernel's time from the profiled steps)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}): the extraction "
+              "path has no multi-GPU form here; a volume would be split into slabs of block "
+              "layers, one per GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.batched_only:
+        print(json.dumps({"batched": batch_bench(max(args.steps, 5), args.warmup)}), flush=True)
+        return
+    if args.only_512:
+        print(json.dumps({"turbulence512": turbulence512(args)}), flush=True)
+        return
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        import paper_2009_03254_amd as bcmc
+        bcmc._capi.check(bcmc.lib().bcmc_copy_calibration(
+            b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        del a, b
+    result, sample_words = headline(args)
+    torch.cuda.empty_cache()
+    if not args.headline_only:
+        if not args.no_512:
+            result["turbulence512"] = turbulence512(args)
+            torch.cuda.empty_cache()
+        if not args.no_differentiable:
+            log("[bench] differentiable form (256^3 blobs)")
+            result["differentiable"] = differentiable_bench(max(args.steps, 5), 2)
+        if not args.no_batched:
+            log("[bench] batched form (48 volumes x 4 isovalues)")
+            result["batched"] = batch_bench(max(args.steps, 5), 2)
+    if not args.no_cpu_baseline:
+        from synthetic import fields
+        nx, ny, _ = fields.CHANNEL_FLOW_DIMS
+        log("[bench] CPU oracle baseline on the first 8 z-planes")
+        result["cpu_baseline"] = cpu_baseline_oracle(
+            sample_words, (nx, ny, 8), 2, True, 0.5,
+            "the headline stream's first 2 block layers")
     print(json.dumps(result), flush=True)
 
 

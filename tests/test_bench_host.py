@@ -19,6 +19,10 @@ def _sources_sha():
     return h.hexdigest()
 
 
+def test_sources_hash_matches_bench():
+    assert bench.sources_sha256() == _sources_sha()
+
+
 def test_traffic_only_for_current_sources(tmp_path, monkeypatch):
     f = tmp_path / "counters.md"
     f.write_text("text\n```\n"
@@ -32,9 +36,20 @@ def test_traffic_only_for_current_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("k_mc_emit") is None
 
 
-def test_committed_counters_name_the_dominant_kernel():
-    text = open(bench.COUNTERS_FILE).read()
-    assert "traffic k_mc_emit bytes_per_dispatch=" in text
+def test_committed_counters_name_the_roofline_kernels():
+    for f in (bench.COUNTERS_FILE, bench.COUNTERS_FILE_512):
+        text = open(f).read()
+        for k in bench.kernel_defs(2):
+            assert f"traffic {k} bytes_per_dispatch=" in text, (f, k)
+
+
+def test_kernel_bytes_per_unit():
+    """Algorithmic bytes: 8R + 256 per decoded block; 256 per occupied block
+    plus 8 per vertex (24 per triangle) for the emission, no bookkeeping."""
+    st = {"n_new": 10, "n_occupied": 3, "n_triangles": 7, "n_active": 99}
+    kd = bench.kernel_defs(2)
+    assert kd["k_assign_decode"][1](st) == 10 * (16 + 256)
+    assert kd["k_mc_emit"][1](st) == 3 * 256 + 7 * 24
 
 
 def test_more_than_one_gpu_is_refused():
