@@ -378,14 +378,15 @@ def headline(args):
     _, T = vol.extract_into(iso, probe)
     out = torch.empty((3 * T + 64, 4), dtype=torch.int32, device="cuda")
     flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+    bufs = {"f32": out}
 
-    def call(cold, record):
+    def call(cold, record, fmt="f32"):
         if cold:
             vol.reset_cache()
             flush_last_level_cache(flush_buf)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, T2 = vol.extract_into(iso, out)      # synchronises to read the count
+        rc, T2 = vol.extract_into(iso, bufs[fmt])      # synchronises to read the count
         dt = time.perf_counter() - t0
         if rc != 0 or T2 != T:
             raise bcmc.BcmcError(rc, bcmc.lib().bcmc_last_error().decode())
@@ -412,6 +413,27 @@ def headline(args):
     region_s = time.perf_counter() - t_region
     vol.set_profiling(False)
     kd = kstats(recs, *kdefs[dom]) if not args.no_profile_events else kern[dom]
+
+    # the same cold steps writing 8-byte records: the paper's 10-bit vertex
+    # (Sec. 4.5) and this library's edge record
+    formats = {}
+    for fmt in ("q10", "edge8"):
+        vol.set_vertex_format(fmt)
+        bufs[fmt] = torch.empty(3 * T + 64, dtype=torch.int64, device="cuda")
+        for _ in range(args.warmup):
+            call(True, [], fmt)
+        vol.set_profiling(True, stages=[5])
+        r8 = []
+        for _ in range(args.steps):
+            call(True, r8, fmt)
+        vol.set_profiling(False)
+        e8 = kstats(r8, *kdefs["k_mc_emit"])
+        t8 = sum(r[0] for r in r8)
+        formats[fmt] = {"triangles_per_s": round(T * len(r8) / t8), "ms_per_step": round(t8 / len(r8) * 1e3, 4),
+                        "k_mc_emit_avg_ms": round(e8["avg_ms"], 5),
+                        "k_mc_emit_frac": round(e8["gbs"] / HBM_PEAK_GBS, 4)}
+        del bufs[fmt]
+    vol.set_vertex_format("f32")
 
     # warm repeats for context
     call(True, [])
@@ -476,6 +498,9 @@ def headline(args):
                  "alg_gbs_without_range_table": round((wst["alg_bytes"] - 8.0 * nb)
                                                       / (warm_ms * 1e-3) / 1e9, 2),
                  "n_new": wst["n_new"], "stage_ms": stage_medians(warm_prof)},
+        "formats": dict(formats, note="the same cold steps writing 8-byte records: q10 = the "
+                        "paper's vertex (10-bit block-relative coordinates + block id, within "
+                        "2/1023 voxel); edge8 = edge records within 2^-23 voxel"),
         "generate_encode_s": round(gen_s, 2),
         "note": "ms_per_step / value: host-timed cold extract calls (count readback included); "
                 "the cache reset and the 1 GiB cache flush before each step are outside that "
@@ -614,6 +639,32 @@ def turbulence512(args):
         "k_mc_emit_avg_ms": round(e["avg_ms"], 5), "k_mc_emit_frac": round(e["gbs"] / HBM_PEAK_GBS, 4),
         "note": "8-byte edge records (block, cell, edge, 22-bit t): positions within 2^-23 "
                 "voxel of the float32 soup",
+    }
+    # the same steps with the paper's 10-bit vertices, and their error against
+    # the float32 soup of the same call
+    vol.set_vertex_format("q10")
+    for _ in range(args.warmup):
+        step([], out8)
+    vol.set_profiling(True, stages=[5])
+    rq = []
+    for _ in range(args.steps):
+        step(rq, out8)
+    vol.set_profiling(False)
+    e = kstats(as2(rq), *kernel_defs(RATE)["k_mc_emit"])
+    tq = sum(r[1] for r in rq)
+    rc, Tq = vol.extract_into(float(iso50), out8)
+    vol.set_vertex_format("f32")
+    rc, T16 = vol.extract_into(float(iso50), out)
+    pos, _ = bcmc.q10_positions(out8[: 3 * Tq])
+    xyz, _ = bcmc.split_vertices(out[: 3 * T16])
+    qerr = float((pos - xyz).abs().max()) if Tq == T16 else None
+    res["q10"] = {
+        "triangles_per_s": round(sum(r[2]["n_triangles"] for r in rq) / tq),
+        "ms_per_step": round(tq / args.steps * 1e3, 4),
+        "k_mc_emit_avg_ms": round(e["avg_ms"], 5), "k_mc_emit_frac": round(e["gbs"] / HBM_PEAK_GBS, 4),
+        "max_dequantisation_error_voxel": qerr,
+        "note": "the paper's 8-byte vertex (Sec. 4.5): 10-bit block-relative coordinates + block "
+                "id; error = largest |dequantised - float32 vertex| over the p50 soup",
     }
     del out8
     vol.close()

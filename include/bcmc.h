@@ -61,8 +61,14 @@ typedef struct {
 } bcmc_vertex;
 
 /* Record formats bcmc_extract can write (per volume, bcmc_set_vertex_format).
- * BCMC_VERTEX_EDGE8 keeps the 8 bytes per vertex of Sec. 4.5's output but
- * names the vertex by its edge instead of quantised coordinates: one
+ * BCMC_VERTEX_Q10 is Sec. 4.5's compressed vertex, 8 bytes: one uint64_t per
+ * vertex whose low uint32 packs the block-relative coordinates quantised to
+ * 10 bits each (x in bits 0-9, y in 10-19, z in 20-29; q = trunc(c * 255.75
+ * + 0.5) in float32 from the 16-byte vertex's coordinate c in [0, 4], so c is
+ * q * 4 / 1023 within 2/1023 voxel plus float32 rounding) and whose high
+ * uint32 is the block id.
+ * BCMC_VERTEX_EDGE8 is this library's own 8-byte record, which keeps the
+ * size but names the vertex by its edge, precise to 2^-23 voxel: one
  * uint64_t per vertex,
  *     bits  0-31  block id
  *     bits 32-37  cell l = lx + 4*ly + 16*lz inside the block
@@ -74,7 +80,8 @@ typedef struct {
  * along the edge axis, within 2^-23 voxel of the float32 vertex. */
 typedef enum {
     BCMC_VERTEX_F32 = 0,   /* bcmc_vertex, 16 bytes (default) */
-    BCMC_VERTEX_EDGE8 = 1  /* uint64_t edge record, 8 bytes */
+    BCMC_VERTEX_EDGE8 = 1, /* uint64_t edge record, 8 bytes */
+    BCMC_VERTEX_Q10 = 2    /* uint64_t 10-bit quantised vertex (Sec. 4.5), 8 bytes */
 } bcmc_vertex_format;
 
 /* Statistics of the last bcmc_extract call (Sec. 4.6, tab:mc_benchmark_data
@@ -152,6 +159,14 @@ BCMC_API int bcmc_reset_cache(bcmc_volume *v, void *hip_stream);
  * enlarge and call again); BCMC_E_CACHE_CAP (cache reset); BCMC_E_HIP. */
 BCMC_API int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_vertices,
                  uint64_t *n_triangles, void *hip_stream);
+
+/* Sec. 4.5's 8-byte vertices (BCMC_VERTEX_Q10 records) from n 16-byte
+ * bcmc_vertex records: d_vertices (device, n * 16 bytes) -> d_out (device,
+ * n uint64_t), on hip_stream, without synchronising; the same records the
+ * emission writes in that format.  Errors: BCMC_E_INVALID (null pointers
+ * with n > 0). */
+BCMC_API int bcmc_vertices_to_q10(const void *d_vertices, uint64_t n, void *d_out,
+                                  void *hip_stream);
 
 /* Record format of this volume's bcmc_extract output (bcmc_vertex_format;
  * default BCMC_VERTEX_F32).  The order and count of records do not depend on

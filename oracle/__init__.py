@@ -67,6 +67,7 @@ def lib():
             "oracle_mc_extract": (_u64, [_P, _u32, _u32, _u32, _f32, _P, _P, _P, _P, _P, _P]),
             "oracle_mc_extract_f32": (_u64, [_P, _u32, _u32, _u32, _f32, _P, _P]),
             "oracle_mc_extract_edge8": (_u64, [_P, _u32, _u32, _u32, _f32, _P]),
+            "oracle_mc_extract_q10": (_u64, [_P, _u32, _u32, _u32, _f32, _P]),
             "oracle_brute_count": (_u64, [_P, _u32, _u32, _u32, _f32]),
             "oracle_brute_count_blocks": (_u64, [_P, _u32, _u32, _u32, _f32]),
             "oracle_block_vertex_counts": (None, [_P, _u32, _u32, _u32, _f32, _P, _u64, _P]),
@@ -285,6 +286,27 @@ def mc_extract_edge8(blocks, dims, iso):
     rec = np.empty(max(3 * T, 1), dtype=np.uint64)
     lib().oracle_mc_extract_edge8(_ptr(blocks), nx, ny, nz, float(iso), _ptr(rec))
     return rec[: 3 * T]
+
+
+def mc_extract_q10(blocks, dims, iso):
+    """The canonical soup as Sec. 4.5's 8-byte vertices: 10-bit block-relative
+    coordinates x | y << 10 | z << 20 (low 32 bits), block id (high 32)."""
+    nx, ny, nz = dims
+    blocks = np.ascontiguousarray(blocks, dtype=np.float32)
+    T = mc_count(blocks, dims, iso)
+    rec = np.empty(max(3 * T, 1), dtype=np.uint64)
+    lib().oracle_mc_extract_q10(_ptr(blocks), nx, ny, nz, float(iso), _ptr(rec))
+    return rec[: 3 * T]
+
+
+def q10_positions(records):
+    """Block-relative float64 positions q * 4 / 1023 of Sec. 4.5's 8-byte
+    vertices, with their block ids."""
+    r = np.asarray(records, dtype=np.uint64)
+    code = (r & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    block = (r >> np.uint64(32)).astype(np.uint32)
+    q = np.stack([code & 1023, (code >> 10) & 1023, (code >> 20) & 1023], axis=1)
+    return q.astype(np.float64) * (4.0 / 1023.0), block
 
 
 def edge8_positions(records):

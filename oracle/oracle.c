@@ -680,7 +680,18 @@ typedef struct {
     uint8_t *cases;
     uint64_t nv, nc;
     uint64_t *edge8;
+    uint64_t *q10;
 } emit_ctx;
+
+/* Sec. 4.5: a block-relative coordinate (in [0, 4]) stored in 10 bits.
+ * Reading: the 1024 codes span [0, 4] evenly (code q stands for q * 4/1023)
+ * and the coordinate goes to its nearest code, computed in float32 as
+ * trunc(x * 1023/4 + 1/2). */
+static uint32_t quantise10(float x) {
+    float scaled = x * (1023.0f / 4.0f);
+    uint32_t q = (uint32_t)(scaled + 0.5f);
+    return q > 1023u ? 1023u : q;
+}
 
 static void emit_cell(void *vctx, uint64_t b, int l, uint32_t x, uint32_t y,
                       uint32_t z, int cs, const float v[8]) {
@@ -716,6 +727,17 @@ static void emit_cell(void *vctx, uint64_t b, int l, uint32_t x, uint32_t y,
             c->edge8[c->nv] = (uint64_t)b | ((uint64_t)l << 32) | ((uint64_t)e << 38) |
                               ((uint64_t)q << 42);
         }
+        if (c->q10) {
+            /* the float32 vertex as the 16-byte format computes it, then its
+             * three coordinates packed x | y << 10 | z << 20 beside the block id */
+            float t = (c->iso - a) / (bv - a);
+            uint32_t code = 0;
+            for (int d = 0; d < 3; d++) {
+                float base = (float)(g[d] - o[d]);
+                code |= quantise10(d == axis ? base + t : base) << (10 * d);
+            }
+            c->q10[c->nv] = (uint64_t)code | ((uint64_t)b << 32);
+        }
         if (c->vblock) c->vblock[c->nv] = (uint32_t)b;
         if (c->vedge)
             c->vedge[c->nv] = (int64_t)(g[0] + (uint64_t)c->F->nx *
@@ -744,7 +766,7 @@ uint64_t oracle_mc_extract(const float *blocks, uint32_t nx, uint32_t ny,
         if (n_cells) *n_cells = n[1];
         return n[0];
     }
-    emit_ctx c = {&F, iso, verts, NULL, vblock, vedge, cell_keys, cases, 0, 0, NULL};
+    emit_ctx c = {&F, iso, verts, NULL, vblock, vedge, cell_keys, cases, 0, 0, NULL, NULL};
     for_each_cell(&F, iso, emit_cell, &c);
     if (n_cells) *n_cells = c.nc;
     return c.nv / 3;
@@ -755,7 +777,7 @@ uint64_t oracle_mc_extract_f32(const float *blocks, uint32_t nx, uint32_t ny,
                                uint32_t *vblock) {
     ensure_tables();
     field_t F = {blocks, nx, ny, nz, ceil4(nx), ceil4(ny)};
-    emit_ctx c = {&F, iso, NULL, verts, vblock, NULL, NULL, NULL, 0, 0, NULL};
+    emit_ctx c = {&F, iso, NULL, verts, vblock, NULL, NULL, NULL, 0, 0, NULL, NULL};
     for_each_cell(&F, iso, emit_cell, &c);
     return c.nv / 3;
 }
@@ -764,7 +786,16 @@ uint64_t oracle_mc_extract_edge8(const float *blocks, uint32_t nx, uint32_t ny,
                                  uint32_t nz, float iso, uint64_t *records) {
     ensure_tables();
     field_t F = {blocks, nx, ny, nz, ceil4(nx), ceil4(ny)};
-    emit_ctx c = {&F, iso, NULL, NULL, NULL, NULL, NULL, NULL, 0, 0, records};
+    emit_ctx c = {&F, iso, NULL, NULL, NULL, NULL, NULL, NULL, 0, 0, records, NULL};
+    for_each_cell(&F, iso, emit_cell, &c);
+    return c.nv / 3;
+}
+
+uint64_t oracle_mc_extract_q10(const float *blocks, uint32_t nx, uint32_t ny,
+                               uint32_t nz, float iso, uint64_t *records) {
+    ensure_tables();
+    field_t F = {blocks, nx, ny, nz, ceil4(nx), ceil4(ny)};
+    emit_ctx c = {&F, iso, NULL, NULL, NULL, NULL, NULL, NULL, 0, 0, NULL, records};
     for_each_cell(&F, iso, emit_cell, &c);
     return c.nv / 3;
 }

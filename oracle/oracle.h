@@ -89,6 +89,13 @@ uint64_t oracle_mc_extract_f32(const float *blocks, uint32_t nx, uint32_t ny,
  * float32 t = (iso - a) / (b - a) measured from the edge's first corner. */
 uint64_t oracle_mc_extract_edge8(const float *blocks, uint32_t nx, uint32_t ny,
                                  uint32_t nz, float iso, uint64_t *records);
+/* The same soup in Sec. 4.5's 8-byte vertex: the float32 vertex (as in
+ * oracle_mc_extract_f32) with each block-relative coordinate rounded to the
+ * nearest of 1024 even steps over [0, 4] (code q = trunc(x * 1023/4 + 1/2)
+ * in float32), packed x | y << 10 | z << 20 in the low 32 bits, block id in
+ * the high 32 bits. */
+uint64_t oracle_mc_extract_q10(const float *blocks, uint32_t nx, uint32_t ny,
+                               uint32_t nz, float iso, uint64_t *records);
 /* Brute force: sum over every valid cell of the number of triangles of its
  * case, visiting the dense field in z,y,x order (no blocks). */
 uint64_t oracle_brute_count(const float *field, uint32_t nx, uint32_t ny,

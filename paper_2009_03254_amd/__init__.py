@@ -25,10 +25,11 @@ from ._capi import BcmcError, lib  # noqa: F401
 
 __all__ = ["Volume", "FieldVolume", "Batch", "ExtractFn", "encode", "mc_table", "num_blocks",
            "blocks_from_field", "split_vertices", "global_positions", "edge8_positions",
-           "VERTEX_F32", "VERTEX_EDGE8", "BcmcError", "lib"]
+           "VERTEX_F32", "VERTEX_EDGE8", "VERTEX_Q10", "q10_positions", "vertices_to_q10",
+           "BcmcError", "lib"]
 
 F32, F64 = 0, 1
-VERTEX_F32, VERTEX_EDGE8 = 0, 1     # record formats of Volume.extract
+VERTEX_F32, VERTEX_EDGE8, VERTEX_Q10 = 0, 1, 2     # record formats of Volume.extract
 _TYPES = {"f32": F32, "float32": F32, "f64": F64, "float64": F64}
 
 
@@ -132,6 +133,36 @@ def edge8_positions(records, dims=None, dtype=None):
     return pos, block
 
 
+def q10_positions(records, dims=None, dtype=None):
+    """Dequantise the paper's 8-byte vertices ([n] int64 CUDA tensor, 10-bit
+    block-relative coordinates in the low 32 bits, block id in the high 32):
+    positions q * 4 / 1023 [n, 3] (float32 by default) and block ids [n]
+    (int64); with dims, global voxel coordinates."""
+    torch = _torch()
+    r = records.to(torch.int64)
+    code = r & 0xFFFFFFFF
+    block = (r >> 32) & 0xFFFFFFFF
+    dt = dtype or torch.float32
+    q = torch.stack([code & 1023, (code >> 10) & 1023, (code >> 20) & 1023], dim=1)
+    pos = q.to(dt) * (4.0 / 1023.0)
+    if dims is not None:
+        pos = global_positions(pos, block, dims, dtype=dt)
+    return pos, block
+
+
+def vertices_to_q10(verts, out=None, stream=None):
+    """16-byte vertex records ([n, 4] int32 CUDA tensor) -> the paper's 8-byte
+    records ([n] int64), on the GPU."""
+    torch = _torch()
+    n = verts.shape[0]
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.int64, device=verts.device)
+    verts = verts.contiguous()
+    _capi.check(lib().bcmc_vertices_to_q10(_dev_ptr(verts) if n else None, n,
+                                           _dev_ptr(out) if n else None, _stream_ptr(stream)))
+    return out[:n]
+
+
 def global_positions(xyz, block, dims, dtype=None):
     """Block-relative positions + block ids -> global voxel coordinates."""
     torch = _torch()
@@ -163,9 +194,12 @@ class _Handle:
         return st.as_dict()
 
     def set_vertex_format(self, fmt):
-        """"f32" (16-byte records [n, 4] int32: x, y, z as float32 bits, block)
-        or "edge8" (8-byte edge records [n] int64, see edge8_positions)."""
-        code = {"f32": VERTEX_F32, "edge8": VERTEX_EDGE8}[fmt] if isinstance(fmt, str) else int(fmt)
+        """"f32" (16-byte records [n, 4] int32: x, y, z as float32 bits, block),
+        "edge8" (8-byte edge records [n] int64, see edge8_positions) or "q10"
+        (the paper's 8-byte 10-bit quantised vertices [n] int64, see
+        q10_positions)."""
+        code = ({"f32": VERTEX_F32, "edge8": VERTEX_EDGE8, "q10": VERTEX_Q10}[fmt]
+                if isinstance(fmt, str) else int(fmt))
         _capi.check(lib().bcmc_set_vertex_format(self._h, code))
         self._vfmt = code
 
@@ -182,13 +216,13 @@ class _Handle:
 
     def _alloc_out(self, cap):
         torch = _torch()
-        if getattr(self, "_vfmt", VERTEX_F32) == VERTEX_EDGE8:
+        if getattr(self, "_vfmt", VERTEX_F32) in (VERTEX_EDGE8, VERTEX_Q10):
             return torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
         return torch.empty((max(cap, 1), 4), dtype=torch.int32, device="cuda")
 
     def _records(self, out):
         """Capacity of `out` in records of this volume's format."""
-        size = 8 if getattr(self, "_vfmt", VERTEX_F32) == VERTEX_EDGE8 else 16
+        size = 8 if getattr(self, "_vfmt", VERTEX_F32) in (VERTEX_EDGE8, VERTEX_Q10) else 16
         return out.numel() * out.element_size() // size
 
     def extract(self, iso, out=None, stream=None):

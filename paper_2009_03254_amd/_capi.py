@@ -88,6 +88,7 @@ SIGNATURES = {
     "bcmc_debug_new": (_int, [_P, _P, _P]),
     "bcmc_debug_cache_state": (_int, [_P, _P, _P, _P, _P]),
     "bcmc_debug_slot_data": (_int, [_P, _P]),
+    "bcmc_vertices_to_q10": (_int, [_P, _u64, _P, _P]),
     "bcmc_debug_age_cache": (_int, [_P, _u32, _P]),
     "bcmc_debug_block_counts": (_int, [_P, _P, _P, _u64]),
     "bcmc_debug_cases": (_int, [_P, _f32, _P, _P]),

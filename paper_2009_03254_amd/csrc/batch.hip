@@ -626,7 +626,7 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
                 bz = bcast(lbz, jl[k]);
                 isok = __uint_as_float(bcast(__float_as_uint(liso), jl[k]));
             };
-            emit_batch<false>(nsb, info, sh.emit.tiles[w], sh.tab, sh.emit, w, ob, p.out, p.cap);
+            emit_batch<VFMT_F32>(nsb, info, sh.emit.tiles[w], sh.tab, sh.emit, w, ob, p.out, p.cap);
         }
     }
     stamp_last(p, 8);

@@ -369,6 +369,13 @@ int bcmc_reset_cache(bcmc_volume *v, void *hip_stream) {
     return reset_cache_state(v, as_stream(hip_stream));
 }
 
+int bcmc_vertices_to_q10(const void *d_vertices, uint64_t n, void *d_out, void *hip_stream) {
+    if (n && (!d_vertices || !d_out)) return invalid("null pointer");
+    launch_vertices_q10(d_vertices, n, d_out, as_stream(hip_stream));
+    BCMC_HIP_TRY(hipGetLastError());
+    return BCMC_OK;
+}
+
 int bcmc_debug_age_cache(bcmc_volume *v, uint32_t k, void *hip_stream) {
     if (!v) return invalid("null handle");
     if (v->identity) return invalid("identity volumes have no cache");
@@ -383,7 +390,8 @@ int bcmc_debug_age_cache(bcmc_volume *v, uint32_t k, void *hip_stream) {
 
 int bcmc_set_vertex_format(bcmc_volume *v, int format) {
     if (!v) return invalid("null handle");
-    if (format != BCMC_VERTEX_F32 && format != BCMC_VERTEX_EDGE8) return invalid("unknown vertex format");
+    if (format != BCMC_VERTEX_F32 && format != BCMC_VERTEX_EDGE8 && format != BCMC_VERTEX_Q10)
+        return invalid("unknown vertex format");
     v->vertex_format = format;
     return BCMC_OK;
 }
@@ -430,12 +438,11 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     if (!v->identity) launch_assign_decode(v->d, v->is_f64, v->rate, v->g.nb, iso, s);
     BCMC_HIP_TRY(mark(3));
     const float *slots = v->identity ? v->ext_blocks : v->d.slots;
-    const int edge8 = v->vertex_format == BCMC_VERTEX_EDGE8;
-    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, edge8, s);
+    launch_mc_count(v->g, v->d, slots, v->d.I_slot, v->identity, iso, v->vertex_format, s);
     BCMC_HIP_TRY(mark(4));   // the block offsets come with the emission (stage 4 is empty)
     BCMC_HIP_TRY(mark(5));
     launch_mc_emit(v->g, v->d, slots, v->d.I_slot, v->identity, iso, d_out, capacity_vertices,
-                   v->vertex_format == BCMC_VERTEX_EDGE8, s);
+                   v->vertex_format, s);
     BCMC_HIP_TRY(mark(6));
     if (hipError_t le = hipGetLastError()) {   // a launch failed: the flags are unknown
         clear_flags(v, s);

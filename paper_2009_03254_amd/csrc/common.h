@@ -115,11 +115,14 @@ void launch_plan_grow(const DevState &d, uint64_t max_slots, uint64_t grow_bound
 void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems, uint32_t age_cap,
                   hipStream_t s);
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, int edge8, hipStream_t s);
+                     int identity_cache, float iso, int fmt, hipStream_t s);
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                    int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
+                    int identity_cache, float iso, void *out, uint64_t cap_verts, int fmt,
                     hipStream_t s);
+// fmt: the bcmc_vertex_format codes (0 = 16-byte vertex, 1 = edge record,
+// 2 = 10-bit quantised vertex).
+void launch_vertices_q10(const void *in, uint64_t n, void *out, hipStream_t s);
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
                         const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
                         uint64_t max_act, hipStream_t s);

@@ -722,7 +722,7 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
 // triangles of the staged blocks together and write them lane per vertex
 // from the first block's offset, in canonical order (block, cell, triangle,
 // vertex).
-template <bool EDGE8>
+template <int FMT>
 __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
                                                 const int32_t *__restrict__ I_slot, int identity,
                                                 const float *__restrict__ slots,
@@ -844,7 +844,7 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
                 bz = bcast(lbz, jl[k]);
                 isok = iso;
             };
-            emit_batch<EDGE8>(nsb, info, sh.tiles[w], sh.tab, sh, w, ob, out, cap);
+            emit_batch<FMT>(nsb, info, sh.tiles[w], sh.tab, sh, w, ob, out, cap);
         }
     }
 }
@@ -1075,36 +1075,54 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
 
 // The emission's grid; the count pass runs on the same one, so that both
 // give each wave the same share of the active blocks.
-static unsigned emit_grid(const Geom &g, int edge8) {
-    static unsigned grid[2] = {0, 0};
-    if (!grid[0]) grid[0] = resident_grid(k_mc_emit<false>, ~0ull >> 4);
-    if (!grid[1]) grid[1] = resident_grid(k_mc_emit<true>, ~0ull >> 4);
-    return std::min<unsigned>(grid[edge8 ? 1 : 0], mc_grid(g.nb));
+static unsigned emit_grid(const Geom &g, int fmt) {
+    static unsigned grid[3] = {0, 0, 0};
+    if (!grid[0]) grid[0] = resident_grid(k_mc_emit<VFMT_F32>, ~0ull >> 4);
+    if (!grid[1]) grid[1] = resident_grid(k_mc_emit<VFMT_EDGE8>, ~0ull >> 4);
+    if (!grid[2]) grid[2] = resident_grid(k_mc_emit<VFMT_Q10>, ~0ull >> 4);
+    return std::min<unsigned>(grid[fmt >= 0 && fmt < 3 ? fmt : 0], mc_grid(g.nb));
 }
 
 void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                     int identity_cache, float iso, int edge8, hipStream_t s) {
+                     int identity_cache, float iso, int fmt, hipStream_t s) {
     static unsigned mgrid = 0;
     if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
     k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
         d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_iso, d.ctr);
-    k_mc_count<<<emit_grid(g, edge8), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
+    k_mc_count<<<emit_grid(g, fmt), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
                                                    d.masks, d.blk_cnt, d.part_wave, d.part_occw,
                                                    d.ctr);
 }
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
-                    int identity_cache, float iso, void *out, uint64_t cap_verts, int edge8,
+                    int identity_cache, float iso, void *out, uint64_t cap_verts, int fmt,
                     hipStream_t s) {
-    const unsigned n = emit_grid(g, edge8);
-    if (edge8)
-        k_mc_emit<true><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table,
-                                          iso, d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand,
-                                          d.part_wave, d.part_occw, d.ctr);
-    else
-        k_mc_emit<false><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table,
-                                           iso, d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand,
-                                           d.part_wave, d.part_occw, d.ctr);
+    const unsigned n = emit_grid(g, fmt);
+#define BCMC_EMIT(F)                                                                          \
+    k_mc_emit<F><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table, iso, \
+                                   d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand, d.part_wave,  \
+                                   d.part_occw, d.ctr)
+    if (fmt == VFMT_EDGE8) BCMC_EMIT(VFMT_EDGE8);
+    else if (fmt == VFMT_Q10) BCMC_EMIT(VFMT_Q10);
+    else BCMC_EMIT(VFMT_F32);
+#undef BCMC_EMIT
+}
+
+// 16-byte vertices -> Sec. 4.5's 8-byte records (q10_code | block << 32),
+// two vertices per lane per iteration.
+__global__ __launch_bounds__(256) void k_vertices_q10(const uint4 *__restrict__ in, uint64_t n,
+                                                     uint64_t *__restrict__ out) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 v = in[i];
+        const uint32_t q = q10_code(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z));
+        __builtin_nontemporal_store((uint64_t)q | ((uint64_t)v.w << 32), out + i);
+    }
+}
+
+void launch_vertices_q10(const void *in, uint64_t n, void *out, hipStream_t s) {
+    if (n) k_vertices_q10<<<grid_cap(n, 8192), 256, 0, s>>>(reinterpret_cast<const uint4 *>(in), n,
+                                                            reinterpret_cast<uint64_t *>(out));
 }
 
 void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,

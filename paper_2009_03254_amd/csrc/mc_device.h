@@ -495,6 +495,23 @@ __device__ __forceinline__ void stream_store(void *out, uint64_t o, float x, flo
 
 constexpr int EMIT_TRIS = 64 * 5;   // a wave's triangle list (one block's maximum)
 
+// Output record formats of the emission.
+enum : int { VFMT_F32 = 0, VFMT_EDGE8 = 1, VFMT_Q10 = 2 };
+
+// Sec. 4.5's vertex: each block-relative coordinate (in [0, 4]) quantised to
+// 10 bits, q = trunc(x * (1023 / 4) + 1/2) (round to nearest, in float32,
+// each operation rounded), x in bits 0-9, y in 10-19, z in 20-29.  The
+// dequantised coordinate q * 4 / 1023 is within 2 / 1023 voxel of x plus
+// float32 rounding.
+__host__ __device__ __forceinline__ uint32_t q10_axis(float x) {
+    const float t = x * 255.75f;   // 1023 / 4, exact in float32
+    const uint32_t q = (uint32_t)(t + 0.5f);
+    return q < 1023u ? q : 1023u;
+}
+__host__ __device__ __forceinline__ uint32_t q10_code(float x, float y, float z) {
+    return q10_axis(x) | (q10_axis(y) << 10) | (q10_axis(z) << 20);
+}
+
 // Per-wave LDS of the emission: SB staged tiles, the triangle list of the
 // staged blocks and each staged block's id and isovalue.
 template <int SB>
@@ -532,10 +549,12 @@ namespace {
 // triangles in canonical order (block, cell, triangle, vertex).
 // info(k, g, b, bx, by, bz, iso) gives block k's volume geometry, id, block
 // coordinates and isovalue (wave-uniform).
-// EDGE8: 8-byte records block | cell << 32 | edge << 38 | q << 42 with
-// q = min(trunc(t * 2^22), 2^22 - 1); otherwise 16-byte records
-// {f32 x, y, z block-relative; u32 block}.
-template <bool EDGE8, class Info, class SH>
+// FMT (VFMT_*): VFMT_F32 16-byte records {f32 x, y, z block-relative; u32
+// block}; VFMT_EDGE8 8-byte records block | cell << 32 | edge << 38 | q << 42
+// with q = min(trunc(t * 2^22), 2^22 - 1); VFMT_Q10 8-byte records (Sec. 4.5)
+// of the block-relative float32 coordinates quantised to 10 bits each
+// (q10_code) | block << 32.
+template <int FMT, class Info, class SH>
 __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*tiles)[128],
                                            const uint64_t *__restrict__ mc_table, SH &sh,
                                            int w, uint64_t base, void *__restrict__ out,
@@ -563,7 +582,7 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
             const uint32_t b = sh.blk[w][k];
             const float tt = (iso - a) / (bv - a);
             const uint64_t o = base + (uint64_t)j;
-            if (EDGE8) {
+            if (FMT == VFMT_EDGE8) {
                 uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
                 qt = qt < 4194303u ? qt : 4194303u;
                 const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
@@ -574,7 +593,11 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
                 const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
                 const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
                 const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
-                if (o < cap) stream_store(out, o, px, py, pz, b);
+                if (FMT == VFMT_Q10) {
+                    if (o < cap) stream_store(out, o, (uint64_t)q10_code(px, py, pz) | ((uint64_t)b << 32));
+                } else {
+                    if (o < cap) stream_store(out, o, px, py, pz, b);
+                }
             }
         }
         base += (uint64_t)total;

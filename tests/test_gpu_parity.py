@@ -316,7 +316,7 @@ def test_invalid_arguments(bc, orc):
         assert T == 0 and v2.stats()["n_active"] == 0
 
 
-@pytest.mark.parametrize("fmt", ["f32", "edge8"])
+@pytest.mark.parametrize("fmt", ["f32", "edge8", "q10"])
 def test_checkerboard_every_cell_full(bc, orc, fmt):
     """Every cell of a sign checkerboard has case 105 or 150 (four
     triangles): 256 per interior block, so the emission's triangle list is
@@ -337,8 +337,8 @@ def test_checkerboard_every_cell_full(bc, orc, fmt):
         assert T == 4 * cells
     else:
         import torch
-        vol.set_vertex_format("edge8")
-        ref = orc.mc_extract_edge8(D, dims, np.float32(0.0))
+        vol.set_vertex_format(fmt)
+        ref = (orc.mc_extract_edge8 if fmt == "edge8" else orc.mc_extract_q10)(D, dims, np.float32(0.0))
         out = torch.empty(len(ref) + 16, dtype=torch.int64, device="cuda")
         rc, T = vol.extract_into(0.0, out)
         assert rc == 0 and 3 * T == len(ref)
@@ -428,6 +428,48 @@ def test_edge8_records_bitexact(bc, orc, dims, rate, seed):
     _extract_and_compare(bc, orc, vol, D, dims, iso)
     with pytest.raises(bc.BcmcError):
         vol.set_vertex_format(7)
+
+
+@pytest.mark.parametrize("dims,rate,seed", [((70, 61, 53), 8, 36), ((45, 38, 31), 16, 37)])
+def test_q10_records_bitexact(bc, orc, dims, rate, seed):
+    """Sec. 4.5's 8-byte vertices written by the emission: bit-exact against
+    the oracle's over cold and warm calls, equal to the conversion kernel's
+    records of the 16-byte soup, dequantised within 2/1023 voxel of the
+    float64 soup; the capacity error counts records."""
+    torch = bc._torch()
+    say(f"[q10] turbulence {dims} rate {rate}")
+    f = fields.turbulence(*dims, seed=seed, n_modes=64)
+    s = orc.zfp_encode(f, rate)
+    D = orc.zfp_decode(s, dims, rate)
+    field = orc.blocks_to_field(D, dims)
+    vol = bc.Volume(s, dims, "f32", rate)
+    ref16 = bc.Volume(s, dims, "f32", rate)
+    vol.set_vertex_format("q10")
+    small = torch.empty(5, dtype=torch.int64, device="cuda")
+    iso0 = fields.percentile_iso(field, 50)
+    rc, T = vol.extract_into(float(iso0), small)
+    assert rc == bc._capi.E_CAPACITY and T == orc.mc_count(D, dims, iso0)
+    worst = 0.0
+    for p in (50, 85, 50, 20):
+        iso = fields.percentile_iso(field, p)
+        ref = orc.mc_extract_q10(D, dims, iso)
+        out = torch.empty(ref.shape[0] + 7, dtype=torch.int64, device="cuda")
+        rc, T = vol.extract_into(float(iso), out)
+        assert rc == 0 and 3 * T == ref.shape[0]
+        got = out[: 3 * T].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), p
+        v16, T16 = ref16.extract(float(iso))
+        assert T16 == T
+        conv = bc.vertices_to_q10(v16)
+        assert torch.equal(conv, out[: 3 * T])
+        r = orc.mc_extract(D, dims, iso, want=("verts", "vblock"))
+        pos, blk = bc.q10_positions(out[: 3 * T], dtype=torch.float64)
+        assert np.array_equal(blk.cpu().numpy(), r["vblock"].astype(np.int64))
+        err = float((pos.cpu() - torch.from_numpy(r["verts"])).abs().max())
+        assert err <= 2.0 / 1023 + 1e-6
+        worst = max(worst, err)
+    say(f"  largest dequantisation error {worst:.3e} voxel")
+    assert bc.vertices_to_q10(v16[:0]).numel() == 0
 
 
 def test_flags_follow_tiles_across_isovalues(bc, orc):

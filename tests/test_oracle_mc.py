@@ -389,3 +389,42 @@ def test_slab_orchestration_equals_whole_volume(orc):
         assert np.array_equal(np.concatenate([p[2] for p in parts]).view(np.uint32), v32.view(np.uint32))
         assert np.array_equal(np.concatenate([p[3] for p in parts]), vb)
         assert np.array_equal(np.concatenate([p[4] for p in parts]), r["verts"])
+
+
+def test_q10_vertices(orc):
+    """Sec. 4.5's 8-byte vertex: 10-bit block-relative coordinates (nearest
+    of 1024 even steps over [0, 4]) beside the block id.  Same blocks and
+    order as the soup; dequantised positions within 2/1023 voxel (half a
+    step) of the float64 vertices, the bound reached (about 2e-3 voxel);
+    each code the nearest step to its float32 coordinate."""
+    dims = (29, 23, 19)
+    f = fields.turbulence(*dims, seed=12, n_modes=32)
+    B = orc.field_to_blocks(f)
+    iso = float(fields.percentile_iso(f, 45))
+    rec = orc.mc_extract_q10(B, dims, iso)
+    r = orc.mc_extract(B, dims, iso, want=("verts", "vblock"))
+    v32, vb = orc.mc_extract_f32(B, dims, iso)
+    assert len(rec) == len(vb) > 0
+    pos, blk = orc.q10_positions(rec)
+    assert np.array_equal(blk, r["vblock"])
+    assert np.all((rec & np.uint64(0xC0000000)) == 0)
+    err = np.abs(pos - r["verts"]).max()
+    assert 1.5e-3 < err <= 2.0 / 1023 + 1e-6, err
+    code = (rec & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    q = np.stack([code & 1023, (code >> 10) & 1023, (code >> 20) & 1023], axis=1)
+    assert np.abs(q - v32.astype(np.float64) * (1023 / 4)).max() <= 0.5 + 1e-4
+
+
+def test_q10_axis_plane_hand_worked(orc):
+    """f = z - 10.3 on 9x7x13: every vertex at block-relative z = 2.3 (block
+    layer 2) with x, y on the integer grid; codes worked out by hand:
+    x, y in {0, 1, 2, 3, 4} -> {0, 256, 512, 767, 1023}, z 2.3 -> 588."""
+    dims = (9, 7, 13)
+    f = fields.plane_z(*dims, 10.3)
+    rec = orc.mc_extract_q10(orc.field_to_blocks(f), dims, 0.0)
+    assert len(rec) == 3 * 2 * 8 * 6
+    code = (rec & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    assert set(((code >> 20) & 1023).tolist()) == {588}
+    assert set((code & 1023).tolist()) <= {0, 256, 512, 767, 1023}
+    assert set(((code >> 10) & 1023).tolist()) <= {0, 256, 512, 767, 1023}
+    assert {0, 1023} <= set((code & 1023).tolist())
