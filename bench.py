@@ -537,15 +537,6 @@ def turbulence512(args):
     del D
     torch.cuda.empty_cache()
     flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
-    if args.copy_calibration:
-        # 1 GiB read + 1 GiB written by the library's plain copy kernel
-        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        bcmc._capi.check(bcmc.lib().bcmc_copy_calibration(
-            b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream))
-        torch.cuda.synchronize()
-        del a, b
     out = torch.empty((1, 4), dtype=torch.int32, device=dev)
     cap_T = 0
     for iso in (iso50, iso90):
@@ -671,6 +662,64 @@ def turbulence512(args):
     return res
 
 
+def zfp_throughput(reps=10):
+    """Whole-volume fixed-rate ZFP throughput on the 512^3 float32 turbulence
+    field at rates 2, 4 and 8 (the paper's decompression benchmark, Sec.
+    3.3.4): encode (field -> stream) and decode of every block (stream ->
+    [N_b][64] float32 + block ranges), each the mean of `reps` runs after one
+    untimed run, timed with HIP events on the stream."""
+    import torch
+
+    import paper_2009_03254_amd as bcmc
+    from synthetic import fields
+
+    n = 512
+    dims = (n, n, n)
+    field = fields.turbulence_torch(n, seed=2, device="cuda")
+    nb = bcmc.num_blocks(*dims)
+    blocks = torch.empty((nb, 64), dtype=torch.float32, device="cuda")
+    out = {}
+    for rate in (2, 4, 8):
+        words = bcmc.encode(field, rate)
+        vol = bcmc.Volume(words, dims, "f32", rate)
+
+        def timed(fn):
+            fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]) / reps
+
+        dec_ms = timed(lambda: vol.decode_all(blocks))
+        enc_ms = timed(lambda: bcmc.encode(field, rate, out=words))
+        dec_bytes = nb * (8.0 * rate + 256.0 + 8.0)   # stream read, blocks and ranges written
+        enc_bytes = nb * (256.0 + 8.0 * rate)
+        out[f"rate{rate}"] = {
+            "decode_ms": round(dec_ms, 4),
+            "decode_gbs_decompressed": round(nb * 256.0 / (dec_ms * 1e-3) / 1e9, 1),
+            "decode_hbm_gbs": round(dec_bytes / (dec_ms * 1e-3) / 1e9, 1),
+            "decode_frac": round(dec_bytes / (dec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "decode_gblocks_per_s": round(nb / (dec_ms * 1e-3) / 1e9, 3),
+            "encode_ms": round(enc_ms, 4),
+            "encode_gbs_uncompressed": round(nb * 256.0 / (enc_ms * 1e-3) / 1e9, 1),
+            "encode_hbm_gbs": round(enc_bytes / (enc_ms * 1e-3) / 1e9, 1),
+            "encode_frac": round(enc_bytes / (enc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        }
+        vol.close()
+        del words
+    del field, blocks
+    torch.cuda.empty_cache()
+    out["note"] = ("512^3 float32 turbulence, mean of %d runs per figure (HIP events); decode = "
+                   "bcmc_decode_all (every block decoded, written as [N_b][64] float32 with its "
+                   "range); hbm bytes = stream + decoded blocks + ranges (decode), field + stream "
+                   "(encode); decompressed GB/s counts the 256-byte decoded blocks" % reps)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -686,6 +735,9 @@ def main():
                     help="only the headline channel-flow measurement (no extra keys)")
     ap.add_argument("--only-512", action="store_true",
                     help="only the 512^3 turbulence sequence, printed as its own JSON")
+    ap.add_argument("--zfp-only", action="store_true",
+                    help="only the whole-volume ZFP encode / decode throughput, as its own JSON")
+    ap.add_argument("--no-zfp", action="store_true", help="skip the ZFP throughput measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched measurement, printed as its own JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -707,10 +759,9 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": batch_bench(max(args.steps, 5), args.warmup)}), flush=True)
         return
-    if args.only_512:
-        print(json.dumps({"turbulence512": turbulence512(args)}), flush=True)
-        return
     if args.copy_calibration:
+        # 1 GiB read + 1 GiB written by the library's plain copy kernel: the
+        # known-size reference for the traffic counters
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
@@ -719,12 +770,21 @@ def main():
             b.data_ptr(), a.data_ptr(), a.numel() * 4, torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
         del a, b
+    if args.zfp_only:
+        print(json.dumps({"zfp_throughput": zfp_throughput()}), flush=True)
+        return
+    if args.only_512:
+        print(json.dumps({"turbulence512": turbulence512(args)}), flush=True)
+        return
     result, sample_words = headline(args)
     torch.cuda.empty_cache()
     if not args.headline_only:
         if not args.no_512:
             result["turbulence512"] = turbulence512(args)
             torch.cuda.empty_cache()
+        if not args.no_zfp:
+            log("[bench] whole-volume ZFP encode / decode at rates 2, 4, 8")
+            result["zfp_throughput"] = zfp_throughput()
         if not args.no_differentiable:
             log("[bench] differentiable form (256^3 blobs)")
             result["differentiable"] = differentiable_bench(max(args.steps, 5), 2)

@@ -66,9 +66,10 @@ def mc_table():
     return nt, tri
 
 
-def encode(field, rate, stream=None):
+def encode(field, rate, stream=None, out=None):
     """Fixed-rate ZFP compression of a CUDA tensor [nz, ny, nx] (float32 or
-    float64) -> CUDA uint64 tensor of N_b*rate words."""
+    float64) -> CUDA uint64 tensor of N_b*rate words (into `out` when
+    given)."""
     torch = _torch()
     if not field.is_cuda:
         raise ValueError("encode expects a CUDA tensor")
@@ -80,7 +81,11 @@ def encode(field, rate, stream=None):
     else:
         raise TypeError("field must be float32 or float64")
     nz, ny, nx = field.shape
-    out = torch.empty(num_blocks(nx, ny, nz) * rate, dtype=torch.uint64, device=field.device)
+    n_words = num_blocks(nx, ny, nz) * rate
+    if out is None:
+        out = torch.empty(n_words, dtype=torch.uint64, device=field.device)
+    elif out.numel() != n_words or not out.is_cuda or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous CUDA tensor of {n_words} words")
     _capi.check(lib().bcmc_encode(_dev_ptr(field), typ, nx, ny, nz, rate, _dev_ptr(out),
                                   _stream_ptr(stream)))
     return out
@@ -319,9 +324,13 @@ class Volume(_Handle):
     def reset_cache(self, stream=None):
         _capi.check(lib().bcmc_reset_cache(self._h, _stream_ptr(stream)))
 
-    def decode_all(self, stream=None):
+    def decode_all(self, out=None, stream=None):
+        """Every block decoded: [N_b, 64] float32 CUDA tensor (into `out`)."""
         torch = _torch()
-        out = torch.empty((self.n_blocks, 64), dtype=torch.float32, device="cuda")
+        if out is None:
+            out = torch.empty((self.n_blocks, 64), dtype=torch.float32, device="cuda")
+        elif tuple(out.shape) != (self.n_blocks, 64) or out.dtype != torch.float32:
+            raise ValueError("out must be a [N_b, 64] float32 CUDA tensor")
         _capi.check(lib().bcmc_decode_all(self._h, _dev_ptr(out), _stream_ptr(stream)))
         return out
 
