@@ -720,6 +720,80 @@ def zfp_throughput(reps=10):
     return out
 
 
+INTERACTION_SETS = {
+    # name: (description, iso range)
+    "nested_blobs": ("gaussian blobs 256^3 f32 (16 blobs, seed 3), ZFP rate 4", (0.1, 1.1)),
+    "turbulent_sheet": ("channel flow 1280x960x192 f64 (tanh profile + 0.1 Fourier turbulence, "
+                        "seed 5), ZFP rate 2", (-0.6, 0.6)),
+}
+
+
+def interaction_bench(n_iso=100):
+    """The paper's interaction benchmarks (Sec. 4.6.1, tab:mc_benchmark_table)
+    on a nested-surface volume and a turbulent-sheet volume: Random (100
+    seeded isovalues), Sweep Up and Sweep Down (100 evenly spaced isovalues)
+    over each volume's range, each from an empty cache (initial budget 0,
+    growable to one slot per block), the first extraction discarded.  A first
+    untimed pass sizes the output buffer; the timed pass runs without events
+    and a third pass with HIP events around every stage gives the stage
+    shares."""
+    import torch
+
+    import paper_2009_03254_amd as bcmc
+    from paper_2009_03254_amd import interaction
+    from synthetic import fields
+
+    res = {}
+    for name, (desc, (lo, hi)) in INTERACTION_SETS.items():
+        if name == "nested_blobs":
+            f = torch.from_numpy(fields.gaussian_blobs(256, 16, seed=3)).cuda()
+            dims, typ, rate = (256, 256, 256), "f32", 4
+            words = bcmc.encode(f, rate)
+            del f
+        else:
+            dims, typ, rate = (1280, 960, 192), "f64", 2
+            nbx, nby = dims[0] // 4, dims[1] // 4
+            words = torch.empty(bcmc.num_blocks(*dims) * rate, dtype=torch.uint64, device="cuda")
+            for z0 in range(0, dims[2], 32):
+                f = fields.channel_flow_slab(z0, min(dims[2], z0 + 32), dims=dims)
+                w = bcmc.encode(f, rate)
+                first = (z0 // 4) * nbx * nby * rate
+                words[first: first + w.numel()] = w
+                del f, w
+        vol = bcmc.Volume(words, dims, typ, rate)
+        del words
+        vol.set_cache_budget(initial_bytes=0, max_bytes=0)
+        nb = vol.n_blocks
+        out = torch.empty((1 << 20, 4), dtype=torch.int32, device="cuda")
+        entry = {"workload": desc, "n_blocks": nb, "iso_range": [lo, hi]}
+        for kind in interaction.KINDS:
+            isos = interaction.isovalues(kind, lo, hi, n_iso, seed=11)
+            # sizing pass (untimed): grow the buffer on a capacity error
+            vol.reset_cache()
+            for iso in isos:
+                rc, T = vol.extract_into(float(iso), out)
+                if rc == bcmc._capi.E_CAPACITY:
+                    out = torch.empty((3 * T + 3 * T // 8 + 1024, 4), dtype=torch.int32, device="cuda")
+                    rc, T = vol.extract_into(float(iso), out)
+                bcmc._capi.check(rc)
+            vol.reset_cache()
+            timed = interaction.summarise(interaction.run(vol, isos, out), nb)
+            vol.reset_cache()
+            prof = interaction.summarise(interaction.run(vol, isos, out, profile=True), nb)
+            timed["stage_share"] = prof.get("stage_share")
+            timed["stage_mean_ms"] = prof.get("stage_mean_ms")
+            entry[kind] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in timed.items()}
+        vol.close()
+        del out
+        torch.cuda.empty_cache()
+        res[name] = entry
+    res["note"] = ("per benchmark: mean host-timed extraction per isovalue (count readback "
+                   "included) over isovalues 2..%d, mean hit rate 1 - n_new/n_active, share of "
+                   "the volume's blocks decoded and active per surface, stage shares of the "
+                   "summed HIP-event stage times (cull = cull + compaction)" % n_iso)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -738,6 +812,10 @@ def main():
     ap.add_argument("--zfp-only", action="store_true",
                     help="only the whole-volume ZFP encode / decode throughput, as its own JSON")
     ap.add_argument("--no-zfp", action="store_true", help="skip the ZFP throughput measurement")
+    ap.add_argument("--interaction-only", action="store_true",
+                    help="only the Random / Sweep Up / Sweep Down benchmarks, as their own JSON")
+    ap.add_argument("--no-interaction", action="store_true",
+                    help="skip the Random / Sweep Up / Sweep Down benchmarks")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched measurement, printed as its own JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -773,6 +851,9 @@ def main():
     if args.zfp_only:
         print(json.dumps({"zfp_throughput": zfp_throughput()}), flush=True)
         return
+    if args.interaction_only:
+        print(json.dumps({"interaction": interaction_bench()}), flush=True)
+        return
     if args.only_512:
         print(json.dumps({"turbulence512": turbulence512(args)}), flush=True)
         return
@@ -782,6 +863,9 @@ def main():
         if not args.no_512:
             result["turbulence512"] = turbulence512(args)
             torch.cuda.empty_cache()
+        if not args.no_interaction:
+            log("[bench] interaction benchmarks: Random, Sweep Up, Sweep Down")
+            result["interaction"] = interaction_bench()
         if not args.no_zfp:
             log("[bench] whole-volume ZFP encode / decode at rates 2, 4, 8")
             result["zfp_throughput"] = zfp_throughput()
