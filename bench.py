@@ -720,6 +720,116 @@ def zfp_throughput(reps=10):
     return out
 
 
+def dense_bench(steps, warmup, n_random=100):
+    """The dense data-parallel marching cubes baseline (Sec. 3.3.3) on the
+    512^3 turbulence field decoded from its rate-8 stream (the surface the
+    block path extracts), resident uncompressed in HBM: p50 and p90 (mean of
+    `steps` calls after `warmup`), and the paper's protocol of 100 random
+    isovalues (between p10 and p90, first call discarded), beside the block
+    path on the same stream (cold = empty cache after a cache flush, repeat =
+    everything cached)."""
+    import numpy as np
+    import torch
+
+    import paper_2009_03254_amd as bcmc
+    from synthetic import fields
+
+    n = 512
+    dims = (n, n, n)
+    field = fields.turbulence_torch(n, seed=2, device="cuda")
+    words = bcmc.encode(field, RATE)
+    del field
+    vol = bcmc.Volume(words, dims, "f32", RATE)
+    D = vol.decode_all()
+    nb1 = n // 4
+    dense = D.view(nb1, nb1, nb1, 4, 4, 4).permute(0, 3, 1, 4, 2, 5).reshape(n, n, n).contiguous()
+    del D
+    isos = {p: float(fields.percentile_iso_torch(dense, p)) for p in (10, 50, 90)}
+    dm = bcmc.DenseMC(dims)
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+    probe = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+    T_max = max(dm.extract_into(dense, isos[p], probe)[1] for p in (10, 50, 90))
+    out = torch.empty((3 * T_max + 3 * T_max // 8 + 1024, 4), dtype=torch.int32, device="cuda")
+
+    def host_ms(fn, k, w):
+        ts = []
+        for i in range(w + k):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            dt = time.perf_counter() - t0
+            if i >= w:
+                ts.append(dt)
+        return float(np.mean(ts)) * 1e3
+
+    def dense_call(iso):
+        rc, T = dm.extract_into(dense, iso, out)
+        bcmc._capi.check(rc)
+        return T
+
+    def block_call(iso, cold):
+        if cold:
+            vol.reset_cache()
+            flush_last_level_cache(flush_buf)
+            torch.cuda.synchronize()
+        rc, T = vol.extract_into(iso, out)
+        bcmc._capi.check(rc)
+        return T
+
+    res = {"workload": "512^3 float32 turbulence decoded from its ZFP rate-8 stream, resident "
+                       "uncompressed (dense) / compressed (block path)"}
+    for p in (50, 90):
+        iso = isos[p]
+        T = dense_call(iso)
+        d_ms = host_ms(lambda: dense_call(iso), steps, warmup)
+        n_act = dm.active_cells()
+
+        def cold():
+            vol.reset_cache()
+            flush_last_level_cache(flush_buf)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            block_call(iso, False)
+            return time.perf_counter() - t0
+        c_ms = float(np.mean([cold() for _ in range(steps)])) * 1e3
+        block_call(iso, False)
+        r_ms = host_ms(lambda: block_call(iso, False), steps, warmup)
+        res[f"p{p}"] = {"iso": iso, "triangles": T, "dense_active_cells": n_act,
+                        "dense_ms": round(d_ms, 4),
+                        "dense_triangles_per_s": round(T / (d_ms * 1e-3)),
+                        "block_cold_ms": round(c_ms, 4), "block_repeat_ms": round(r_ms, 4),
+                        "speedup_block_cold": round(d_ms / c_ms, 3),
+                        "speedup_block_repeat": round(d_ms / r_ms, 3)}
+    rng = np.random.default_rng(7)
+    rand = rng.uniform(isos[10], isos[90], n_random).astype(np.float32)
+    ts = []
+    for i, iso in enumerate(rand):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dense_call(float(iso))
+        if i:
+            ts.append(time.perf_counter() - t0)
+    res["random100"] = {"range": [isos[10], isos[90]], "dense_mean_ms": round(float(np.mean(ts)) * 1e3, 4)}
+    vol.reset_cache()
+    ts = []
+    for i, iso in enumerate(rand):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        block_call(float(iso), False)
+        if i:
+            ts.append(time.perf_counter() - t0)
+    res["random100"]["block_mean_ms"] = round(float(np.mean(ts)) * 1e3, 4)
+    res["note"] = ("dense = classify every cell -> prefix sum -> compact -> per-cell vertex counts "
+                   "-> prefix sum -> emit, over the 512 MiB uncompressed field; block = the "
+                   "compressed path (cull, cache, decode, block-wise MC) on the 128 MiB stream; "
+                   "host-timed calls with their count readback")
+    dm.close()
+    vol.close()
+    del dense, out, flush_buf
+    torch.cuda.empty_cache()
+    return res
+
+
 INTERACTION_SETS = {
     # name: (description, iso range)
     "nested_blobs": ("gaussian blobs 256^3 f32 (16 blobs, seed 3), ZFP rate 4", (0.1, 1.1)),
@@ -812,6 +922,9 @@ def main():
     ap.add_argument("--zfp-only", action="store_true",
                     help="only the whole-volume ZFP encode / decode throughput, as its own JSON")
     ap.add_argument("--no-zfp", action="store_true", help="skip the ZFP throughput measurement")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="only the dense marching cubes baseline, as its own JSON")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense baseline")
     ap.add_argument("--interaction-only", action="store_true",
                     help="only the Random / Sweep Up / Sweep Down benchmarks, as their own JSON")
     ap.add_argument("--no-interaction", action="store_true",
@@ -851,6 +964,9 @@ def main():
     if args.zfp_only:
         print(json.dumps({"zfp_throughput": zfp_throughput()}), flush=True)
         return
+    if args.dense_only:
+        print(json.dumps({"dense_baseline": dense_bench(max(args.steps, 5), args.warmup)}), flush=True)
+        return
     if args.interaction_only:
         print(json.dumps({"interaction": interaction_bench()}), flush=True)
         return
@@ -863,6 +979,9 @@ def main():
         if not args.no_512:
             result["turbulence512"] = turbulence512(args)
             torch.cuda.empty_cache()
+        if not args.no_dense:
+            log("[bench] dense marching cubes baseline on the decoded 512^3 field")
+            result["dense_baseline"] = dense_bench(max(args.steps, 5), args.warmup)
         if not args.no_interaction:
             log("[bench] interaction benchmarks: Random, Sweep Up, Sweep Down")
             result["interaction"] = interaction_bench()

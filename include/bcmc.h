@@ -301,6 +301,31 @@ BCMC_API int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_st
 BCMC_API int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out);
 BCMC_API void bcmc_batch_free(bcmc_batch *b);
 
+/* ---- dense baseline (Sec. 3.3.3) --------------------------------------- */
+/* The standard data-parallel marching cubes the paper measures as its
+ * baseline (Sec. 3.3.3, tab:mc_naive_parallel_perf), over an uncompressed
+ * float field resident in device memory: every cell classified, the cells
+ * holding the surface compacted by a prefix sum, their vertex counts
+ * summed by a second prefix sum, then a pass over the compacted cells
+ * writes the soup.  No blocks, culling or cache.  Records are bcmc_vertex
+ * (block-relative, computed as bcmc_extract computes them) with the cells in
+ * global row-major order (x fastest): the same triangles as bcmc_extract of
+ * the same field, in another order.
+ * bcmc_dense_create reserves the scratch for an nx*ny*nz field (13 bytes per
+ * cell; at most 2^32 - 1 samples).
+ * bcmc_dense_extract: d_field ([nz][ny][nx] float, device), output as
+ * bcmc_extract (capacity in records, BCMC_E_CAPACITY with *n_triangles set);
+ * synchronises hip_stream once.  bcmc_dense_active_cells: cells holding the
+ * surface in the last extract.  Errors: BCMC_E_INVALID, BCMC_E_NOMEM,
+ * BCMC_E_CAPACITY, BCMC_E_HIP. */
+typedef struct bcmc_dense bcmc_dense;
+BCMC_API int bcmc_dense_create(uint32_t nx, uint32_t ny, uint32_t nz, bcmc_dense **out);
+BCMC_API int bcmc_dense_extract(bcmc_dense *h, const float *d_field, float iso, void *d_out,
+                                uint64_t capacity_vertices, uint64_t *n_triangles,
+                                void *hip_stream);
+BCMC_API int bcmc_dense_active_cells(const bcmc_dense *h, uint64_t *n_active);
+BCMC_API void bcmc_dense_free(bcmc_dense *h);
+
 /* ---- extraction without allocation ------------------------------------ */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

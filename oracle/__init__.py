@@ -69,6 +69,7 @@ def lib():
             "oracle_mc_extract_edge8": (_u64, [_P, _u32, _u32, _u32, _f32, _P]),
             "oracle_mc_extract_q10": (_u64, [_P, _u32, _u32, _u32, _f32, _P]),
             "oracle_brute_count": (_u64, [_P, _u32, _u32, _u32, _f32]),
+            "oracle_mc_extract_dense": (_u64, [_P, _u32, _u32, _u32, _f32, _P, _P]),
             "oracle_brute_count_blocks": (_u64, [_P, _u32, _u32, _u32, _f32]),
             "oracle_block_vertex_counts": (None, [_P, _u32, _u32, _u32, _f32, _P, _u64, _P]),
             "oracle_lru_create": (_P, [_u64, _u64, _u64]),
@@ -334,6 +335,18 @@ def mc_count(blocks, dims, iso):
     blocks = np.ascontiguousarray(blocks, dtype=np.float32)
     return int(lib().oracle_mc_extract(_ptr(blocks), nx, ny, nz, float(iso), None, None,
                                        None, None, None, None))
+
+
+def mc_extract_dense(field, iso):
+    """Plain MC over a dense [nz][ny][nx] field, cells in global z, y, x
+    order: (float32 block-relative vertices [3T, 3], block ids [3T])."""
+    field = np.ascontiguousarray(field, dtype=np.float32)
+    nz, ny, nx = field.shape
+    T = int(lib().oracle_mc_extract_dense(_ptr(field), nx, ny, nz, float(iso), None, None))
+    v = np.empty((max(3 * T, 1), 3), dtype=np.float32)
+    vb = np.empty(max(3 * T, 1), dtype=np.uint32)
+    lib().oracle_mc_extract_dense(_ptr(field), nx, ny, nz, float(iso), _ptr(v), _ptr(vb))
+    return v[: 3 * T], vb[: 3 * T]
 
 
 def brute_count(field, iso):

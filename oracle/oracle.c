@@ -800,6 +800,47 @@ uint64_t oracle_mc_extract_q10(const float *blocks, uint32_t nx, uint32_t ny,
     return c.nv / 3;
 }
 
+uint64_t oracle_mc_extract_dense(const float *field, uint32_t nx, uint32_t ny,
+                                 uint32_t nz, float iso, float *verts,
+                                 uint32_t *vblock) {
+    /* plain marching cubes over the dense field, cells in z, y, x order (the
+     * order of a global scan over the volume), float32 vertices relative to
+     * the origin of the 4^3 block holding the cell's lowest corner */
+    ensure_tables();
+    uint32_t nbx = ceil4(nx), nby = ceil4(ny);
+    uint64_t nv = 0;
+    for (uint32_t z = 0; z + 1 < nz; z++)
+        for (uint32_t y = 0; y + 1 < ny; y++)
+            for (uint32_t x = 0; x + 1 < nx; x++) {
+                float v[8];
+                int cs = 0;
+                for (int k = 0; k < 8; k++) {
+                    uint64_t idx = (x + (k & 1)) +
+                                   (uint64_t)nx * ((y + ((k >> 1) & 1)) +
+                                                   (uint64_t)ny * (z + ((k >> 2) & 1)));
+                    v[k] = field[idx];
+                    if (v[k] < iso) cs |= 1 << k;
+                }
+                uint32_t b = (x >> 2) + nbx * ((y >> 2) + nby * (z >> 2));
+                uint32_t local[3] = {x & 3u, y & 3u, z & 3u};
+                for (int j = 0; j < 3 * T_num[cs]; j++, nv++) {
+                    int e = T_tri[cs * 16 + j], k0, k1, p0[3];
+                    edge_corners(e, &k0, &k1);
+                    corner_xyz(k0, p0);
+                    int axis = e >> 2;
+                    if (verts) {
+                        float t = (iso - v[k0]) / (v[k1] - v[k0]);
+                        for (int d = 0; d < 3; d++) {
+                            float base = (float)(local[d] + (uint32_t)p0[d]);
+                            verts[3 * nv + d] = d == axis ? base + t : base;
+                        }
+                    }
+                    if (vblock) vblock[nv] = b;
+                }
+            }
+    return nv / 3;
+}
+
 uint64_t oracle_brute_count(const float *field, uint32_t nx, uint32_t ny,
                             uint32_t nz, float iso) {
     ensure_tables();

@@ -96,6 +96,13 @@ uint64_t oracle_mc_extract_edge8(const float *blocks, uint32_t nx, uint32_t ny,
  * the high 32 bits. */
 uint64_t oracle_mc_extract_q10(const float *blocks, uint32_t nx, uint32_t ny,
                                uint32_t nz, float iso, uint64_t *records);
+/* Plain marching cubes over a dense [nz][ny][nx] field with the cells in
+ * global z, y, x order (the dense baseline's order): float32 block-relative
+ * vertices as oracle_mc_extract_f32 computes them, with their block ids.
+ * Returns T; outputs may be NULL. */
+uint64_t oracle_mc_extract_dense(const float *field, uint32_t nx, uint32_t ny,
+                                 uint32_t nz, float iso, float *verts,
+                                 uint32_t *vblock);
 /* Brute force: sum over every valid cell of the number of triangles of its
  * case, visiting the dense field in z,y,x order (no blocks). */
 uint64_t oracle_brute_count(const float *field, uint32_t nx, uint32_t ny,

@@ -471,6 +471,59 @@ class Batch:
         return self._out[: int(offs[-1])], offs
 
 
+class DenseMC:
+    """The dense data-parallel marching cubes baseline (Sec. 3.3.3) over an
+    uncompressed [nz, ny, nx] float32 CUDA field: the same 16-byte records
+    as Volume.extract, cells in global row-major order."""
+
+    def __init__(self, dims):
+        nx, ny, nz = (int(d) for d in dims)
+        self.dims = (nx, ny, nz)
+        h = C.c_void_p()
+        _capi.check(lib().bcmc_dense_create(nx, ny, nz, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bcmc_dense_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def extract_into(self, field, iso, out, stream=None):
+        """Into a preallocated [cap, 4] int32 buffer: (rc, T)."""
+        nx, ny, nz = self.dims
+        if tuple(field.shape) != (nz, ny, nx) or not field.is_cuda or not field.is_contiguous():
+            raise ValueError("field must be a contiguous [nz, ny, nx] CUDA tensor")
+        T = C.c_uint64(0)
+        rc = lib().bcmc_dense_extract(self._h, _dev_ptr(field), C.c_float(iso),
+                                      _dev_ptr(out) if out.shape[0] else None, out.shape[0],
+                                      C.byref(T), _stream_ptr(stream))
+        if rc not in (_capi.OK, _capi.E_CAPACITY):
+            _capi.check(rc)
+        return rc, int(T.value)
+
+    def extract(self, field, iso, stream=None):
+        """([3T, 4] int32 CUDA tensor, T)."""
+        torch = _torch()
+        out = torch.empty((1, 4), dtype=torch.int32, device="cuda")
+        rc, T = self.extract_into(field, iso, out, stream)
+        if rc == _capi.E_CAPACITY:
+            out = torch.empty((3 * T + 16, 4), dtype=torch.int32, device="cuda")
+            rc, T = self.extract_into(field, iso, out, stream)
+        _capi.check(rc)
+        return out[: 3 * T], T
+
+    def active_cells(self):
+        n = C.c_uint64(0)
+        _capi.check(lib().bcmc_dense_active_cells(self._h, C.byref(n)))
+        return int(n.value)
+
+
 def extract_blocks_noalloc(blocks, dims, iso, out, stream=None):
     """Extraction over decoded blocks ([N_b, 64] CUDA float32) into a
     preallocated [cap, 4] int32 CUDA tensor without any device allocation

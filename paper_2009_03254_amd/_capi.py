@@ -82,6 +82,10 @@ SIGNATURES = {
     "bcmc_batch_tune": (_int, [_P, C.c_char_p, _P]),
     "bcmc_batch_get_info": (_int, [_P, _P]),
     "bcmc_batch_free": (None, [_P]),
+    "bcmc_dense_create": (_int, [_u32, _u32, _u32, _P]),
+    "bcmc_dense_extract": (_int, [_P, _P, _f32, _P, _u64, _P, _P]),
+    "bcmc_dense_active_cells": (_int, [_P, _P]),
+    "bcmc_dense_free": (None, [_P]),
     "bcmc_extract_blocks_noalloc": (_int, [_P, _u32, _u32, _u32, _f32, _P, _u64, _P, _P]),
     "bcmc_debug_ranges": (_int, [_P, _P]),
     "bcmc_debug_active": (_int, [_P, _P, _P, _P]),

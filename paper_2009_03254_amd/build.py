@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbcmc.so")
-SOURCES = ["tables.cpp", "zfp.hip", "extract.hip", "batch.hip", "capi.cpp", "batch_api.cpp"]
+SOURCES = ["tables.cpp", "zfp.hip", "extract.hip", "batch.hip", "dense.hip", "capi.cpp",
+           "batch_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

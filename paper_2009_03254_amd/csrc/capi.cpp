@@ -664,6 +664,98 @@ int bcmc_debug_cases(bcmc_volume *v, float iso, uint8_t *d_cases, void *hip_stre
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Dense baseline (Sec. 3.3.3): marching cubes over an uncompressed field.
+// ---------------------------------------------------------------------------
+struct bcmc_dense {
+    uint32_t nx = 0, ny = 0, nz = 0;
+    uint32_t *ids = nullptr;
+    uint8_t *cases = nullptr;
+    uint64_t *first = nullptr, *status = nullptr, *mc_table = nullptr;
+    void *ctr = nullptr;
+    uint64_t *h_ctr = nullptr;   // pinned copy of the counters
+};
+
+namespace {
+void dense_destroy(bcmc_dense *h) {
+    if (!h) return;
+    dev_free(h->ids);
+    dev_free(h->cases);
+    dev_free(h->first);
+    dev_free(h->status);
+    dev_free(h->mc_table);
+    if (h->ctr) (void)hipFree(h->ctr);
+    if (h->h_ctr) (void)hipHostFree(h->h_ctr);
+    delete h;
+}
+}  // namespace
+
+extern "C" int bcmc_dense_create(uint32_t nx, uint32_t ny, uint32_t nz, bcmc_dense **out) {
+    if (!out) return invalid("null output handle");
+    *out = nullptr;
+    if (nx < 2 || ny < 2 || nz < 2) return invalid("every dimension must be at least 2");
+    if ((uint64_t)nx * ny * nz >= (1ull << 32)) return invalid("at most 2^32 - 1 samples");
+    if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
+    bcmc_dense *h = new (std::nothrow) bcmc_dense();
+    if (!h) return BCMC_E_NOMEM;
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    const uint64_t cells = (uint64_t)(nx - 1) * (ny - 1) * (nz - 1);
+    int rc;
+    if ((rc = dev_alloc(&h->ids, cells)) || (rc = dev_alloc(&h->cases, cells)) ||
+        (rc = dev_alloc(&h->first, cells)) ||
+        (rc = dev_alloc(&h->status, dense_status_words(nx, ny, nz))) ||
+        (rc = dev_alloc(&h->mc_table, 256))) {
+        dense_destroy(h);
+        return rc;
+    }
+    if (hipMalloc(&h->ctr, dense_counter_bytes()) != hipSuccess ||
+        hipHostMalloc((void **)&h->h_ctr, dense_counter_bytes(), hipHostMallocDefault) != hipSuccess ||
+        hipMemcpy(h->mc_table, mc_table_host(), 256 * sizeof(uint64_t), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        dense_destroy(h);
+        set_error("dense baseline set-up failed");
+        return BCMC_E_NOMEM;
+    }
+    *out = h;
+    return BCMC_OK;
+}
+
+extern "C" int bcmc_dense_extract(bcmc_dense *h, const float *d_field, float iso, void *d_out,
+                                  uint64_t capacity_vertices, uint64_t *n_triangles,
+                                  void *hip_stream) {
+    if (!h || !d_field || !n_triangles) return invalid("null argument");
+    if (!d_out && capacity_vertices) return invalid("null output buffer with nonzero capacity");
+    if (iso != iso) return invalid("iso is NaN");
+    hipStream_t s = as_stream(hip_stream);
+    launch_dense(h->nx, h->ny, h->nz, d_field, iso, h->ids, h->cases, h->first, h->status, h->ctr,
+                 h->mc_table, d_out, capacity_vertices, s);
+    BCMC_HIP_TRY(hipGetLastError());
+    BCMC_HIP_TRY(hipMemcpyAsync(h->h_ctr, h->ctr, dense_counter_bytes(), hipMemcpyDeviceToHost, s));
+    BCMC_HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t n_verts = h->h_ctr[3];   // counters: n_active at word 2, n_verts at word 3
+    *n_triangles = n_verts / 3;
+    if (n_verts > capacity_vertices) {
+        set_error("vertex buffer too small: need " + std::to_string(n_verts) + " vertices");
+        return BCMC_E_CAPACITY;
+    }
+    return BCMC_OK;
+}
+
+extern "C" int bcmc_dense_active_cells(const bcmc_dense *h, uint64_t *n_active) {
+    if (!h || !n_active) return invalid("null argument");
+    *n_active = h->h_ctr[2];
+    return BCMC_OK;
+}
+
+extern "C" void bcmc_dense_free(bcmc_dense *h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    dense_destroy(h);
+}
+
+// ---------------------------------------------------------------------------
 // Extraction over caller-owned decoded blocks without any allocation: every
 // buffer the kernels need beyond the caller's input and output lives in one
 // file-scope device array.  Each GPU holds its own copy of the array (it is

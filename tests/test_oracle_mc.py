@@ -428,3 +428,35 @@ def test_q10_axis_plane_hand_worked(orc):
     assert set((code & 1023).tolist()) <= {0, 256, 512, 767, 1023}
     assert set(((code >> 10) & 1023).tolist()) <= {0, 256, 512, 767, 1023}
     assert {0, 1023} <= set((code & 1023).tolist())
+
+
+def test_dense_order_soup_is_the_block_soup_reordered(orc):
+    """The dense scan's soup holds the block-order soup's triangles exactly:
+    grouped per cell (global key of the cell) both give the same float32
+    vertices, cell by cell; the count is the brute force's, and the cells
+    come in global row-major order."""
+    for dims, seed in (((37, 29, 23), 6), ((20, 33, 17), 8)):
+        f = fields.turbulence(*dims, seed=seed, n_modes=32)
+        iso = float(fields.percentile_iso(f, 40))
+        v, vb = orc.mc_extract_dense(f, iso)
+        assert len(vb) == 3 * orc.brute_count(f, iso) > 0
+        B = orc.field_to_blocks(f)
+        r = orc.mc_extract(B, dims, iso, want=("cell_keys", "cases"))
+        v32, vb32 = orc.mc_extract_f32(B, dims, iso)
+        nt, _, _ = orc.mc_tables()
+        # the block soup's vertices per cell, keyed by global cell coordinates
+        nx, ny, nz = dims
+        nbx, nby = (nx + 3) // 4, (ny + 3) // 4
+        keys = r["cell_keys"].astype(np.int64)
+        bid, loc = keys // 64, keys % 64
+        gx = 4 * (bid % nbx) + loc % 4
+        gy = 4 * ((bid // nbx) % nby) + (loc // 4) % 4
+        gz = 4 * (bid // (nbx * nby)) + loc // 16
+        gkey = gx + nx * (gy + ny * gz)
+        nv = 3 * nt[r["cases"]]
+        starts = np.concatenate([[0], np.cumsum(nv)[:-1]])
+        order = np.argsort(gkey, kind="stable")
+        assert np.all(np.diff(gkey[order]) > 0)
+        idx = np.concatenate([np.arange(starts[i], starts[i] + nv[i]) for i in order])
+        assert np.array_equal(v.view(np.uint32), v32[idx].view(np.uint32))
+        assert np.array_equal(vb, vb32[idx])
