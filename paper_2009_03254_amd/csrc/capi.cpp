@@ -39,6 +39,7 @@ struct bcmc_volume {
     int have_extract = 0;
     float last_iso = 0.0f;
     float cull_iso = NAN;          // isovalue of the last cull (NaN: the flags are all zero)
+    uint32_t gen = 0;              // extract calls, as the cull stamps rounds with active blocks
 };
 
 namespace bcmc {
@@ -137,6 +138,8 @@ int alloc_common(bcmc_volume *v) {
     if ((rc = dev_alloc(&v->d.ranges, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.tile_ranges, cull_tiles(v->g)))) return rc;
     if ((rc = dev_alloc(&v->d.active, v->g.nb + 16))) return rc;
+    if ((rc = dev_alloc(&v->d.round_gen, block_rounds(v->g.nb)))) return rc;
+    BCMC_HIP_TRY(hipMemset(v->d.round_gen, 0, block_rounds(v->g.nb) * sizeof(uint32_t)));
     if ((rc = dev_alloc(&v->d.I_active, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_cnt, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_off, v->g.nb))) return rc;
@@ -161,6 +164,7 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.ranges);
     dev_free(v->d.tile_ranges);
     dev_free(v->d.active);
+    dev_free(v->d.round_gen);
     dev_free(v->d.I_active);
     dev_free(v->d.I_new);
     dev_free(v->d.I_slot);
@@ -421,9 +425,13 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
         return (marks >> i) & 1u ? hipEventRecord(v->ev[i], s) : hipSuccess;
     };
     BCMC_HIP_TRY(mark(0));
-    launch_cull(v->g, v->d, v->sl, iso, v->cull_iso, v->n_slots, v->identity, s);
+    if (++v->gen == 0) {   // the stamps would repeat: start over from all-zero
+        launch_fill_u32(v->d.round_gen, 0u, block_rounds(v->g.nb), s);
+        v->gen = 1;
+    }
+    launch_cull(v->g, v->d, v->sl, iso, v->cull_iso, v->n_slots, v->identity, v->gen, s);
     v->cull_iso = iso;
-    launch_compact_blocks(v->g, v->d, v->sl, v->identity, s);
+    launch_compact_blocks(v->g, v->d, v->sl, v->identity, v->gen, s);
     BCMC_HIP_TRY(mark(1));
     if (!v->identity) {
         if (v->calls_since_reset < 0x7FFFFFFFu) v->calls_since_reset++;
@@ -807,6 +815,7 @@ uint64_t carve_scratch(const Geom &g, const StatusLayout &sl, uintptr_t base, De
     d.ranges = reinterpret_cast<float2 *>(take(g.nb * sizeof(float2)));
     d.tile_ranges = reinterpret_cast<float2 *>(take(cull_tiles(g) * sizeof(float2)));
     d.active = take((g.nb + 16 + 3) / 4 * 4);
+    d.round_gen = reinterpret_cast<uint32_t *>(take(block_rounds(g.nb) * sizeof(uint32_t)));
     d.I_active = reinterpret_cast<uint32_t *>(take(g.nb * sizeof(uint32_t)));
     d.blk_cnt = reinterpret_cast<uint32_t *>(take(g.nb * sizeof(uint32_t)));
     d.blk_off = reinterpret_cast<uint64_t *>(take(g.nb * sizeof(uint64_t)));
@@ -843,6 +852,7 @@ extern "C" int bcmc_extract_blocks_noalloc(const float *d_blocks, uint32_t nx, u
     if ((rc = scratch_address(&base))) return rc;
     carve_scratch(g, sl, reinterpret_cast<uintptr_t>(base), d, &range_err);
     hipStream_t s = as_stream(hip_stream);
+    const uint32_t gen = 1;   // the round stamps are cleared below, every call
     // the previous call on this device left its own contents: clear what
     // must start at zero (counters, error word, flags), rewrite the table
     launch_fill_u32(reinterpret_cast<uint32_t *>(d.ctr), 0u, sizeof(Counters) / 4, s);
@@ -852,8 +862,9 @@ extern "C" int bcmc_extract_blocks_noalloc(const float *d_blocks, uint32_t nx, u
     launch_ranges_from_blocks(g, d_blocks, d.ranges, range_err, s);
     launch_tile_ranges(g, d.ranges, d.tile_ranges, s);
     launch_fill_u32(reinterpret_cast<uint32_t *>(d.active), 0u, (g.nb + 3) / 4, s);
-    launch_cull(g, d, sl, iso, NAN, 0, 1, s);
-    launch_compact_blocks(g, d, sl, 1, s);
+    launch_fill_u32(d.round_gen, 0u, block_rounds(g.nb), s);
+    launch_cull(g, d, sl, iso, NAN, 0, 1, gen, s);
+    launch_compact_blocks(g, d, sl, 1, gen, s);
     launch_mc_count(g, d, d_blocks, nullptr, 1, iso, 0, s);
     launch_mc_emit(g, d, d_blocks, nullptr, 1, iso, d_out, capacity_vertices, 0, s);
     BCMC_HIP_TRY(hipGetLastError());

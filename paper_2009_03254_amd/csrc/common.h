@@ -70,6 +70,7 @@ struct DevState {
     float2 *ranges = nullptr;       // per block (min, max) of decoded valid samples
     float2 *tile_ranges = nullptr;  // per cull tile: hull of its blocks' and halo's ranges
     uint8_t *active = nullptr;      // M_active
+    uint32_t *round_gen = nullptr;  // per 4096-block round: the last call that found an active block in it
     uint32_t *I_active = nullptr;   // ascending active block ids
     uint32_t *I_new = nullptr;      // ascending new block ids
     int32_t *I_slot = nullptr;      // per block: slot or -1
@@ -103,10 +104,13 @@ struct StatusLayout {
 
 // ---- launchers (extract.hip) -------------------------------------------
 // prev_iso: the previous cull's isovalue (NaN after the flags were cleared).
+// gen: a number that differs from every earlier call's on these buffers
+// (rounds of blocks whose round_gen equals it hold this call's active blocks).
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
-                 uint64_t n_slots_host, int identity_cache, hipStream_t s);
+                 uint64_t n_slots_host, int identity_cache, uint32_t gen, hipStream_t s);
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
-                           int identity_cache, hipStream_t s);
+                           int identity_cache, uint32_t gen, hipStream_t s);
+inline uint64_t block_rounds(uint64_t nb) { return (nb + BLK_TILE - 1) / BLK_TILE; }
 // age_cap: exceeds the age of every slot used since the cache was reset.
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
                       uint32_t age_cap, hipStream_t s);

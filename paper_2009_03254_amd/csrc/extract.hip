@@ -82,7 +82,8 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
                                              const int32_t *__restrict__ I_slot, int identity,
                                              uint8_t *__restrict__ active, Counters *ctr,
                                              uint64_t n_slots_host, uint64_t *status,
-                                             uint64_t status_words, uint64_t tile_mul) {
+                                             uint64_t status_words, uint64_t tile_mul,
+                                             uint32_t *__restrict__ round_gen, uint32_t gen) {
     const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
     const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
     if (gid == 0) {
@@ -182,6 +183,14 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
                         const uint64_t b = ((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx;
                         const bool fresh = act && !identity && I_slot[b] < 0;
                         active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u) | (fresh ? 4u : 0u);
+                        // mark the 4096-block rounds holding active blocks for the
+                        // compaction: each half-wave is 32 consecutive blocks of one
+                        // row, so its first and last active lanes name every round
+                        const uint64_t am = __ballot(act);
+                        const uint32_t half = (uint32_t)(am >> (lane() & 32));
+                        const int hl = lane() & 31;
+                        if (act && (hl == __builtin_ctz(half) || hl == 31 - __builtin_clz(half)))
+                            round_gen[b / BLK_TILE] = gen;
                     }
                     l3a = l3b;
                     h3a = h3b;
@@ -240,7 +249,9 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
                                                        uint32_t *__restrict__ I_active,
                                                        uint32_t *__restrict__ I_new, Counters *ctr,
                                                        uint32_t *__restrict__ part_cand,
-                                                       uint64_t *status, uint32_t m) {
+                                                       uint64_t *status, uint32_t m,
+                                                       const uint32_t *__restrict__ round_gen,
+                                                       uint32_t gen) {
     const uint64_t tile_blocks = (uint64_t)BLK_TILE * m;
     const uint64_t n_tiles = (g.nb + tile_blocks - 1) / tile_blocks;
     const uint32_t t = take_tile(&ctr->tile_ctr[TC_BLK]);
@@ -248,12 +259,18 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
     const uint64_t tbase = t * tile_blocks + 16u * threadIdx.x;
     uint32_t nact = 0, nnew = 0, cand = 0;
     uint64_t any[2] = {0ull, 0ull};   // rounds in which this thread saw an active block
+    // rounds whose round_gen is not this call's hold no active block: their
+    // flags are all zero and are not read
+    const uint32_t *rg = round_gen + (uint64_t)t * m;
+    const uint64_t n_rounds = (g.nb + BLK_TILE - 1) / BLK_TILE;
+    const uint32_t m_here = (uint32_t)min((uint64_t)m, n_rounds - (uint64_t)t * m);
     for (uint32_t r0 = 0; r0 < m; r0 += 4) {
         uint4 q[4];
 #pragma unroll
         for (int k = 0; k < 4; k++)
-            q[k] = r0 + k < m ? load_flags16(active, tbase + (uint64_t)BLK_TILE * (r0 + k), g.nb)
-                              : make_uint4(0u, 0u, 0u, 0u);
+            q[k] = r0 + k < m_here && rg[r0 + k] == gen
+                       ? load_flags16(active, tbase + (uint64_t)BLK_TILE * (r0 + k), g.nb)
+                       : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             uint32_t actb, newb;
@@ -293,7 +310,8 @@ __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *_
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const uint32_t r = r0 + k;
-            use[k] = r < m && (r >= COMPACT_MAX_ROUNDS || (((r < 64 ? wany0 : wany1) >> (r & 63)) & 1ull));
+            use[k] = r < m_here && rg[r] == gen &&
+                     (r >= COMPACT_MAX_ROUNDS || (((r < 64 ? wany0 : wany1) >> (r & 63)) & 1ull));
             q[k] = use[k] ? load_flags16(active, tbase + (uint64_t)BLK_TILE * r, g.nb)
                           : make_uint4(0u, 0u, 0u, 0u);
         }
@@ -1014,13 +1032,13 @@ static uint64_t coprime_mul(uint64_t n) {
 }
 
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
-                 uint64_t n_slots_host, int identity_cache, hipStream_t s) {
+                 uint64_t n_slots_host, int identity_cache, uint32_t gen, hipStream_t s) {
     static unsigned rgrid = 0;
     if (!rgrid) rgrid = resident_grid(k_cull, ~0ull >> 4);
     const uint64_t nt = cull_tiles(g);
     k_cull<<<(unsigned)std::min<uint64_t>(nt, rgrid), 256, 0, s>>>(
         g, d.ranges, iso, prev_iso, d.tile_ranges, d.I_slot, identity_cache, d.active, d.ctr, n_slots_host,
-        d.status, sl.total, coprime_mul(nt));
+        d.status, sl.total, coprime_mul(nt), d.round_gen, gen);
 }
 
 uint64_t cull_tiles(const Geom &g) {
@@ -1033,11 +1051,12 @@ void launch_tile_ranges(const Geom &g, const float2 *ranges, float2 *tile_ranges
 }
 
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
-                           int identity_cache, hipStream_t s) {
+                           int identity_cache, uint32_t gen, hipStream_t s) {
     const uint32_t m = compact_blocks_per_thread16(g.nb);
     const uint64_t tiles = (g.nb + (uint64_t)BLK_TILE * m - 1) / ((uint64_t)BLK_TILE * m);
     k_compact_blocks<<<(unsigned)tiles, 256, 0, s>>>(g, d.active, d.I_active, d.I_new, d.ctr,
-                                                     d.part_cand, d.status + sl.blk, m);
+                                                     d.part_cand, d.status + sl.blk, m, d.round_gen,
+                                                     gen);
 }
 
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,

@@ -395,6 +395,50 @@ __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t 
     const int end_bits = 64 * rate;
     int kend;
     const uint64_t found = staged_pass1<true>(st, rec, rate, kend);
+    const double s = ldexp(1.0, emax - 62);
+    if (kend >= 34) {
+        // ---- pass 2 when the stream ends by plane 34 (low rates): the
+        // visited planes kend..63 are at most 30 rows of a bit matrix, rebuilt
+        // in lockstep (row r = plane kend + r) and turned into coefficients by
+        // two 32x32 transposes.  Coefficient bits below kend are zero, so
+        // c = c' << kend with c' < 2^30, and the negabinary value is
+        // ((c' ^ (NB >> kend)) - (NB >> kend)) << kend, exact in 32 bits
+        // before the shift ----
+        uint32_t lo[32], hi[32];
+        int o = 1 + T::EBITS, nn = 0;
+        uint64_t below = 0;
+#pragma unroll
+        for (int r = 31; r >= 0; r--) {
+            const int kk = kend + r;
+            uint64_t x = 0;
+            if (kk <= T::P - 1) {
+                const uint32_t rw = rec[kk >> 1], rk = (kk & 1) ? (rw >> 16) : (rw & 0xFFFFu);
+                const int m = nn < end_bits - o ? nn : end_bits - o;
+                if (m > 0) x = peek_staged(st, o) & (~0ull >> (64 - m));
+                const int nn2 = nn + (int)(rk >> 8);
+                const uint64_t below2 = nn2 >= 64 ? ~0ull : ((1ull << nn2) - 1);
+                x |= found & below2 & ~below;
+                below = below2;
+                nn = nn2;
+                o += m + (int)(rk & 0xFFu);
+            }
+            lo[r] = (uint32_t)x;
+            hi[r] = (uint32_t)(x >> 32);
+        }
+        transpose32(lo);
+        transpose32(hi);
+        const uint32_t nbh = (uint32_t)(T::NB >> kend);
+        int64_t v[64];
+#pragma unroll
+        for (int r = 0; r < 32; r++) {
+            v[kOrder.idx[r]] = (int64_t)((uint64_t)(int64_t)(int32_t)((lo[r] ^ nbh) - nbh) << kend);
+            v[kOrder.idx[r + 32]] = (int64_t)((uint64_t)(int64_t)(int32_t)((hi[r] ^ nbh) - nbh) << kend);
+        }
+        inv_zyx(v);
+#pragma unroll
+        for (int i = 0; i < 64; i++) out[i] = (float)((double)v[i] * s);
+        return;
+    }
     // ---- pass 2: plane words in lockstep, each deposited into the
     // coefficients below n_{k+1} in groups of 8 ----
     uint64_t c[64];
@@ -426,7 +470,6 @@ __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t 
 #pragma unroll
     for (int r = 0; r < 64; r++) v[kOrder.idx[r]] = (int64_t)((c[r] ^ T::NB) - T::NB);
     inv_zyx(v);
-    const double s = ldexp(1.0, emax - 62);
 #pragma unroll
     for (int i = 0; i < 64; i++) out[i] = (float)((double)v[i] * s);
 }
