@@ -96,6 +96,9 @@ typedef struct {
     uint64_t n_slots;      /* cache slots after this call */
     uint64_t n_triangles;
     uint64_t calls;        /* extract calls on this handle */
+    uint64_t n_general;    /* new blocks of a low-rate double-precision stream
+                              whose bits reach below plane 39, decoded by the
+                              general decoder after the low-rate one */
     double hit_rate;       /* 1 - n_new / n_active (1 when nothing is active) */
     double alg_bytes;      /* 8*N_b + n_new*(8*rate+256) + 256*n_active + 24*T */
     double stage_ms[8];    /* for the profiled stages (HIP events on the

@@ -25,7 +25,8 @@ class Stats(C.Structure):
     _fields_ = [("n_blocks", C.c_uint64), ("n_active", C.c_uint64), ("n_new", C.c_uint64),
                 ("n_evicted", C.c_uint64), ("n_occupied", C.c_uint64),
                 ("n_candidates", C.c_uint64), ("n_slots", C.c_uint64),
-                ("n_triangles", C.c_uint64), ("calls", C.c_uint64), ("hit_rate", C.c_double),
+                ("n_triangles", C.c_uint64), ("calls", C.c_uint64), ("n_general", C.c_uint64),
+                ("hit_rate", C.c_double),
                 ("alg_bytes", C.c_double), ("stage_ms", C.c_double * 8)]
 
     def as_dict(self):

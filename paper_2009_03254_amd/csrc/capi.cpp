@@ -167,6 +167,7 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.round_gen);
     dev_free(v->d.I_active);
     dev_free(v->d.I_new);
+    dev_free(v->d.retry);
     dev_free(v->d.I_slot);
     dev_free(v->d.blk_cnt);
     dev_free(v->d.blk_off);
@@ -274,7 +275,8 @@ int bcmc_load_compressed(const void *stream, uint64_t nbytes, int stream_is_devi
     v->is_f64 = type == BCMC_F64;
     v->rate = rate;
     if ((rc = alloc_common(v)) || (rc = dev_alloc(&v->d.stream, g.nb * rate)) ||
-        (rc = dev_alloc(&v->d.I_new, g.nb)) || (rc = dev_alloc(&v->d.I_slot, g.nb))) {
+        (rc = dev_alloc(&v->d.I_new, g.nb)) || (rc = dev_alloc(&v->d.I_slot, g.nb)) ||
+        (v->is_f64 && rate <= LOW_RATE_MAX && (rc = dev_alloc(&v->d.retry, g.nb)))) {
         destroy(v);
         return rc;
     }
@@ -470,7 +472,7 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
         reset_cache_state(v, s);
         v->stats.n_active = c.n_act;
         v->stats.n_new = v->stats.n_evicted = v->stats.n_occupied = v->stats.n_triangles = 0;
-        v->stats.n_candidates = 0;
+        v->stats.n_candidates = v->stats.n_general = 0;
         v->stats.n_slots = v->n_slots;
         set_error("the active blocks (" + std::to_string(c.n_act) +
                   ") do not fit the cache cap of " + std::to_string(v->max_slots) + " slots");
@@ -485,6 +487,7 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     st.n_evicted = c.n_evicted;
     st.n_occupied = c.n_occ;
     st.n_candidates = c.n_cand;
+    st.n_general = v->identity ? 0 : c.tile_ctr[TC_RETRY];
     st.n_slots = v->n_slots;
     st.n_triangles = T;
     st.hit_rate = c.n_act ? 1.0 - (double)st.n_new / (double)c.n_act : 1.0;

@@ -48,7 +48,10 @@ struct Counters {
     unsigned int tile_ctr[12];       // dynamic work counters (tiles / batches)
 };
 enum { TC_BLK = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */,
-       TC_MCCOUNT = 7, TC_MCEMIT = 8 };
+       TC_MCCOUNT = 7, TC_MCEMIT = 8, TC_RETRY = 9 /* blocks the low-rate decoder handed back */ };
+// Double-precision streams up to this rate decode with the low-rate decoder
+// (and a general pass over the blocks it hands back).
+constexpr uint32_t LOW_RATE_MAX = 4;
 
 // Block compaction tiles hold BLK_TILE * m blocks (16 * m per thread), with m
 // the smallest making at most 1024 tiles: one look-back ticket per tile.
@@ -73,6 +76,7 @@ struct DevState {
     uint32_t *round_gen = nullptr;  // per 4096-block round: the last call that found an active block in it
     uint32_t *I_active = nullptr;   // ascending active block ids
     uint32_t *I_new = nullptr;      // ascending new block ids
+    uint32_t *retry = nullptr;      // low-rate f64 decode: indices into I_new handed back
     int32_t *I_slot = nullptr;      // per block: slot or -1
     // cache (max_slots entries)
     int32_t *S_block = nullptr;

@@ -108,11 +108,37 @@ __global__ __launch_bounds__(256) void k_ranges_from_blocks(Geom g, const float 
     }
 }
 
+// Set bits of m below the calling lane.
+__device__ __forceinline__ uint32_t mbcnt_lo_hi(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Store a decoded block into its slot, with its sign mask for this call's
+// isovalue (so the mask pass need not read the freshly decoded slot back).
+__device__ __forceinline__ void store_slot(const float *v, uint64_t s, float iso, float *__restrict__ slots,
+                                           uint64_t *__restrict__ masks, uint32_t *__restrict__ mask_iso) {
+    float4 *o = reinterpret_cast<float4 *>(slots + s * 64);
+    uint32_t mw[2] = {0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const float4 f = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+        o[q] = f;
+        mw[q >> 3] |= ((f.x < iso ? 1u : 0u) | (f.y < iso ? 2u : 0u) | (f.z < iso ? 4u : 0u) |
+                       (f.w < iso ? 8u : 0u)) << (4 * (q & 7));
+    }
+    masks[s] = (uint64_t)mw[1] << 32 | mw[0];
+    mask_iso[s] = __float_as_uint(iso);
+}
+
 // Alg. 1 AssignSlots fused with DecompressBlocks: new block I_new[i] takes the
 // i-th slot of the age-sorted available list, evicting its previous owner,
 // and is decoded straight into that slot.
-template <bool F64, bool STAGED>
-__global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
+// LOW (double precision, staged, low rates): the decode is
+// decode_block_staged_low, which holds the kernel to the registers of the
+// low-rate decoder; the blocks it hands back (their indices into I_new) are
+// listed in `retry` for k_decode_retry.
+template <bool F64, bool STAGED, bool LOW = false>
+__global__ __launch_bounds__(256, LOW ? 3 : 1) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
                                                       const uint32_t *__restrict__ sorted0,
                                                       const uint32_t *__restrict__ sorted1,
                                                       int32_t *S_block, int32_t *I_slot,
@@ -120,7 +146,8 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
                                                       int rate, float *__restrict__ slots,
                                                       uint64_t n_blocks, float iso,
                                                       uint64_t *__restrict__ masks,
-                                                      uint32_t *__restrict__ mask_iso) {
+                                                      uint32_t *__restrict__ mask_iso,
+                                                      uint32_t *__restrict__ retry = nullptr) {
     if (ctr->err) return;
     const uint64_t n_slots = ctr->n_slots;
     const uint64_t n_new = ctr->n_new;
@@ -153,27 +180,30 @@ __global__ __launch_bounds__(256) void k_assign_decode(Counters *ctr, const uint
             S_age[s] = 0;
         }
         float v[64];
+        bool done = true;
         if (staged) {
             stage_words(stream, rate, b, valid, st);
-            if (valid) decode_block_staged<F64>(st, rate, v);
+            if constexpr (LOW) {
+                if (valid) done = decode_block_staged_low(st, rate, v);
+            } else {
+                if (valid) decode_block_staged<F64>(st, rate, v);
+            }
             __builtin_amdgcn_wave_barrier();   // st is rewritten by the next round
         } else if (valid) {
             decode_block<F64>(stream + (uint64_t)b * rate, rate, v);
         }
-        if (!valid) continue;
-        // store the block, and its sign mask for this call's isovalue (so the
-        // mask pass need not read the freshly decoded slot back)
-        float4 *o = reinterpret_cast<float4 *>(slots + (uint64_t)s * 64);
-        uint32_t mw[2] = {0u, 0u};
-#pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const float4 f = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-            o[q] = f;
-            mw[q >> 3] |= ((f.x < iso ? 1u : 0u) | (f.y < iso ? 2u : 0u) | (f.z < iso ? 4u : 0u) |
-                           (f.w < iso ? 8u : 0u)) << (4 * (q & 7));
+        if (valid && done) store_slot(v, s, iso, slots, masks, mask_iso);
+        if constexpr (LOW) {   // one atomic per wave for the blocks handed back
+            const uint64_t back = __ballot(valid && !done);
+            if (back) {
+                const int first = (int)__builtin_ctzll(back);
+                uint32_t base = 0;
+                if (__lane_id() == (unsigned)first)
+                    base = atomicAdd(&ctr->tile_ctr[TC_RETRY], (uint32_t)__popcll(back));
+                base = __shfl(base, first, 64);
+                if (valid && !done) retry[base + mbcnt_lo_hi(back)] = (uint32_t)i;
+            }
         }
-        masks[s] = (uint64_t)mw[1] << 32 | mw[0];
-        mask_iso[s] = __float_as_uint(iso);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) evicted += __shfl_xor(evicted, d, 64);   // one atomic per wave
@@ -198,6 +228,28 @@ __global__ __launch_bounds__(256) void k_encode(Geom g, const void *__restrict__
             x[i] = F64 ? ((const double *)field)[idx] : (double)((const float *)field)[idx];
         }
         if (!encode_block<F64>(x, rate, stream + b * rate)) atomicOr(err, ERR_NONFINITE);
+    }
+}
+
+// The blocks the low-rate decoder handed back, decoded with the general
+// decoder from global memory into the slots the assignment gave them.
+__global__ __launch_bounds__(256) void k_decode_retry(const Counters *ctr, const uint32_t *__restrict__ I_new,
+                                                     const uint32_t *__restrict__ sorted0,
+                                                     const uint32_t *__restrict__ sorted1,
+                                                     const uint64_t *__restrict__ stream, int rate,
+                                                     float *__restrict__ slots, float iso,
+                                                     uint64_t *__restrict__ masks,
+                                                     uint32_t *__restrict__ mask_iso,
+                                                     const uint32_t *__restrict__ retry) {
+    if (ctr->err) return;
+    const uint32_t n = ctr->tile_ctr[TC_RETRY];
+    const uint32_t *sorted = (__popc(ctr->pass_mask) & 1) ? sorted1 : sorted0;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const uint32_t i = retry[j];
+        const uint32_t b = I_new[i], s = sorted[i];
+        float v[64];
+        decode_block<true>(stream + (uint64_t)b * rate, rate, v);
+        store_slot(v, s, iso, slots, masks, mask_iso);
     }
 }
 
@@ -234,6 +286,15 @@ void launch_ranges_from_blocks(const Geom &g, const float *blocks, float2 *range
 void launch_assign_decode(const DevState &d, int is_f64, uint32_t rate, uint64_t max_new, float iso,
                           hipStream_t s) {
     unsigned grid = grid_for(max_new, 2048);
+    const unsigned lds = stage_lds_bytes((int)rate, is_f64 != 0);
+    if (is_f64 && lds && rate <= LOW_RATE_MAX && d.retry) {
+        k_assign_decode<true, true, true><<<grid, 256, lds, s>>>(
+            d.ctr, d.I_new, d.sort_val[0], d.sort_val[1], d.S_block, d.I_slot, d.S_age, d.stream,
+            (int)rate, d.slots, max_new, iso, d.masks, d.mask_iso, d.retry);
+        k_decode_retry<<<64, 256, 0, s>>>(d.ctr, d.I_new, d.sort_val[0], d.sort_val[1], d.stream,
+                                          (int)rate, d.slots, iso, d.masks, d.mask_iso, d.retry);
+        return;
+    }
     BCMC_DECODE_LAUNCH(k_assign_decode, grid, rate, s, d.ctr, d.I_new, d.sort_val[0], d.sort_val[1],
                        d.S_block, d.I_slot, d.S_age, d.stream, (int)rate, d.slots, max_new, iso,
                        d.masks, d.mask_iso);

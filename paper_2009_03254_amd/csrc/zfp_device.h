@@ -92,6 +92,50 @@ __host__ __device__ __forceinline__ void inv_zyx(Int *v) {
     for (int i = 0; i < 16; i++) inv4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
 }
 
+// Value of the low w bits of x as a w-bit two's complement integer (1 <= w <= 31).
+__host__ __device__ __forceinline__ int32_t sext_bits(uint32_t x, int w) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sbfe((int)x, 0u, (unsigned)w);
+#else
+    return (int32_t)(x << (32 - w)) >> (32 - w);
+#endif
+}
+
+// The 64-bit inverse transform of coefficients that are all multiples of
+// 2^K (K >= WRAP32_KMIN), carried out on y = c / 2^(K - 6) in 32 bits.
+// Every value stays a multiple of 2^(K - 6) through the three passes (each
+// pass lowers the power of two dividing a value by at most 2, so the right
+// shifts are exact on both sides), hence the 64-bit computation, wrapping
+// modulo 2^64, is the 32-bit one modulo 2^(70 - K) = 2^width, scaled by
+// 2^(K - 6).  Additions, subtractions and left shifts commute with reducing
+// modulo 2^width <= 2^31; before each right shift the operand is reduced to
+// its signed width-bit value, which is then the 64-bit operand / 2^(K - 6).
+// The results are exact modulo 2^width (sext_bits gives the 64-bit value /
+// 2^(K - 6)).
+constexpr int WRAP32_KMIN = 39;
+__host__ __device__ __forceinline__ void inv4_wrap32(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d,
+                                                     int width) {
+    d = (uint32_t)sext_bits(d, width);
+    b += (uint32_t)((int32_t)d >> 1);
+    b = (uint32_t)sext_bits(b, width);
+    d -= (uint32_t)((int32_t)b >> 1);
+    b += d; d = (d << 1) - b;
+    c += a; a = (a << 1) - c;
+    b += c; c = (c << 1) - b;
+    d += a; a = (a << 1) - d;
+}
+__host__ __device__ __forceinline__ void inv_zyx_wrap32(uint32_t *v, int width) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) inv4_wrap32(v[i], v[i + 16], v[i + 32], v[i + 48], width);
+#pragma unroll
+    for (int z = 0; z < 4; z++)
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+            inv4_wrap32(v[x + 16 * z], v[x + 4 + 16 * z], v[x + 8 + 16 * z], v[x + 12 + 16 * z], width);
+#pragma unroll
+    for (int i = 0; i < 16; i++) inv4_wrap32(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3], width);
+}
+
 // ---- staging layout ---------------------------------------------------------
 // A wave's staging area holds word w of lane l's block at st[w * STAGE_STRIDE + l]
 // (see stage_words below).
@@ -282,6 +326,10 @@ __host__ __device__ __forceinline__ int ctz64(uint64_t x) {   // x != 0
 
 // Pass 1 (after a nonzero block header): returns the found set; kend is the
 // lowest plane visited, and the records of planes kend..P-1 are written.
+// The group tests form one serial chain (each starts where the previous one
+// ended), so the words under the read position are held in registers (words
+// wb and wb + 1) and fetched again only when the position moves to another
+// word: most steps then wait on no memory read.
 template <bool F64>
 __host__ __device__ __forceinline__ uint64_t staged_pass1(const uint64_t *st, uint32_t *rec, int rate,
                                                           int &kend) {
@@ -292,6 +340,8 @@ __host__ __device__ __forceinline__ uint64_t staged_pass1(const uint64_t *st, ui
     bool at_start = true;
     uint64_t found = 0;
     uint32_t pend = 0;   // record of the odd plane above, written with its even neighbour
+    int wb = 0;
+    uint64_t w0 = st[0], w1 = rate > 1 ? st[STAGE_STRIDE] : 0ull;
     while (k >= 0 && budget > 0) {
         if (at_start) {   // skip the bits of the n significant coefficients
             const int m = n < budget ? n : budget;
@@ -307,7 +357,14 @@ __host__ __device__ __forceinline__ uint64_t staged_pass1(const uint64_t *st, ui
             // to the next significant coefficient, which the run may not
             // pass: coefficient 63 (implied) and the budget (the run stops
             // where the bits end) bound it at lim
-            const uint64_t w = peek_staged(st, off);
+            const int wi = off >> 6;   // < rate: budget > 0
+            if (wi != wb) {
+                wb = wi;
+                w0 = st[wi * STAGE_STRIDE];
+                w1 = wi + 1 < rate ? st[(wi + 1) * STAGE_STRIDE] : 0ull;
+            }
+            const uint32_t sh = (uint32_t)off & 63u;
+            const uint64_t w = (w0 >> sh) | ((w1 << 1) << (63u - sh));
             const int lim = (63 - n < budget - 1) ? 63 - n : budget - 1;
             const int z = ctz64((w >> 1) | (1ull << lim));
             const bool g = (w & 1u) != 0;
@@ -382,6 +439,58 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
     for (int i = 0; i < 64; i++) out[i] = (float)v[i] * s;
 }
 
+// Pass 2 and the transform of a double-precision block whose stream ends by
+// plane WRAP32_KMIN (low rates): the visited planes kend..63 are at most 25
+// rows of a bit matrix, rebuilt in lockstep (row 6 + r = plane kend + r;
+// rows 0..5 zero) and turned into the coefficients' words u' << 6
+// (u' = u >> kend) by two 32x32 transposes; the transform then runs in 32
+// bits on c / 2^(kend - 6) (inv_zyx_wrap32, which equals the 64-bit
+// transform exactly).
+__host__ __device__ __forceinline__ void staged_f64_top_planes(const uint64_t *st, const uint32_t *rec,
+                                                               int rate, uint64_t found, int kend, int emax,
+                                                               float *out) {
+    using T = Prec<true>;
+    const int end_bits = 64 * rate;
+    uint32_t lo[32], hi[32];
+#pragma unroll
+    for (int r = 0; r < 6; r++) lo[r] = hi[r] = 0u;
+    int o = 1 + T::EBITS, nn = 0;
+    uint64_t below = 0;
+#pragma unroll
+    for (int r = 31; r >= 6; r--) {
+        const int kk = kend + r - 6;
+        uint64_t x = 0;
+        if (kk <= T::P - 1) {
+            const uint32_t rw = rec[kk >> 1], rk = (kk & 1) ? (rw >> 16) : (rw & 0xFFFFu);
+            const int m = nn < end_bits - o ? nn : end_bits - o;
+            if (m > 0) x = peek_staged(st, o) & (~0ull >> (64 - m));
+            const int nn2 = nn + (int)(rk >> 8);
+            const uint64_t below2 = nn2 >= 64 ? ~0ull : ((1ull << nn2) - 1);
+            x |= found & below2 & ~below;
+            below = below2;
+            nn = nn2;
+            o += m + (int)(rk & 0xFFu);
+        }
+        lo[r] = (uint32_t)x;
+        hi[r] = (uint32_t)(x >> 32);
+    }
+    transpose32(lo);
+    transpose32(hi);
+    // negabinary -> two's complement on the scaled words (mod 2^(70 - kend))
+    const uint32_t nb6 = (uint32_t)((T::NB >> kend) << 6);
+    uint32_t v[64];
+#pragma unroll
+    for (int r = 0; r < 32; r++) {
+        v[kOrder.idx[r]] = (lo[r] ^ nb6) - nb6;
+        v[kOrder.idx[r + 32]] = (hi[r] ^ nb6) - nb6;
+    }
+    const int width = 70 - kend;
+    inv_zyx_wrap32(v, width);
+    const double s6 = ldexp(1.0, kend - 6 + emax - 62);
+#pragma unroll
+    for (int i = 0; i < 64; i++) out[i] = (float)((double)sext_bits(v[i], width) * s6);
+}
+
 __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t *st, uint32_t *rec,
                                                                  int rate, float *out) {
     using T = Prec<true>;
@@ -396,47 +505,8 @@ __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t 
     int kend;
     const uint64_t found = staged_pass1<true>(st, rec, rate, kend);
     const double s = ldexp(1.0, emax - 62);
-    if (kend >= 34) {
-        // ---- pass 2 when the stream ends by plane 34 (low rates): the
-        // visited planes kend..63 are at most 30 rows of a bit matrix, rebuilt
-        // in lockstep (row r = plane kend + r) and turned into coefficients by
-        // two 32x32 transposes.  Coefficient bits below kend are zero, so
-        // c = c' << kend with c' < 2^30, and the negabinary value is
-        // ((c' ^ (NB >> kend)) - (NB >> kend)) << kend, exact in 32 bits
-        // before the shift ----
-        uint32_t lo[32], hi[32];
-        int o = 1 + T::EBITS, nn = 0;
-        uint64_t below = 0;
-#pragma unroll
-        for (int r = 31; r >= 0; r--) {
-            const int kk = kend + r;
-            uint64_t x = 0;
-            if (kk <= T::P - 1) {
-                const uint32_t rw = rec[kk >> 1], rk = (kk & 1) ? (rw >> 16) : (rw & 0xFFFFu);
-                const int m = nn < end_bits - o ? nn : end_bits - o;
-                if (m > 0) x = peek_staged(st, o) & (~0ull >> (64 - m));
-                const int nn2 = nn + (int)(rk >> 8);
-                const uint64_t below2 = nn2 >= 64 ? ~0ull : ((1ull << nn2) - 1);
-                x |= found & below2 & ~below;
-                below = below2;
-                nn = nn2;
-                o += m + (int)(rk & 0xFFu);
-            }
-            lo[r] = (uint32_t)x;
-            hi[r] = (uint32_t)(x >> 32);
-        }
-        transpose32(lo);
-        transpose32(hi);
-        const uint32_t nbh = (uint32_t)(T::NB >> kend);
-        int64_t v[64];
-#pragma unroll
-        for (int r = 0; r < 32; r++) {
-            v[kOrder.idx[r]] = (int64_t)((uint64_t)(int64_t)(int32_t)((lo[r] ^ nbh) - nbh) << kend);
-            v[kOrder.idx[r + 32]] = (int64_t)((uint64_t)(int64_t)(int32_t)((hi[r] ^ nbh) - nbh) << kend);
-        }
-        inv_zyx(v);
-#pragma unroll
-        for (int i = 0; i < 64; i++) out[i] = (float)((double)v[i] * s);
+    if (kend >= WRAP32_KMIN) {
+        staged_f64_top_planes(st, rec, rate, found, kend, emax, out);
         return;
     }
     // ---- pass 2: plane words in lockstep, each deposited into the
@@ -472,6 +542,28 @@ __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t 
     inv_zyx(v);
 #pragma unroll
     for (int i = 0; i < 64; i++) out[i] = (float)((double)v[i] * s);
+}
+
+// Low-rate double precision: the block when its stream ends by plane
+// WRAP32_KMIN (pass 1, then staged_f64_top_planes, the same values as
+// decode_block_staged_f64) and true; false, with out untouched, for a block
+// whose stream goes on below that plane (the caller decodes it with the
+// general decoder).
+__host__ __device__ __forceinline__ bool decode_block_staged_f64_low(const uint64_t *st, uint32_t *rec,
+                                                                    int rate, float *out) {
+    using T = Prec<true>;
+    const uint64_t head = st[0];
+    if (!(head & 1u)) {
+#pragma unroll
+        for (int i = 0; i < 64; i++) out[i] = 0.0f;
+        return true;
+    }
+    const int emax = (int)((head >> 1) & 0x7FFu) - T::BIAS;
+    int kend;
+    const uint64_t found = staged_pass1<true>(st, rec, rate, kend);
+    if (kend < WRAP32_KMIN) return false;
+    staged_f64_top_planes(st, rec, rate, found, kend, emax, out);
+    return true;
 }
 
 // Decode one block straight from the stream in global memory.
@@ -528,6 +620,12 @@ __device__ __forceinline__ void stage_words(const uint64_t *__restrict__ stream,
 // per-lane plane records of the two-pass decoder.
 __host__ __device__ inline unsigned stage_wave_words(int rate, bool f64) {
     return (unsigned)(STAGE_STRIDE * rate + (f64 ? RecLayout<true>::WORDS : RecLayout<false>::WORDS));
+}
+
+// Lane l's block from the staging area by decode_block_staged_f64_low.
+__device__ __forceinline__ bool decode_block_staged_low(uint64_t *st, int rate, float *out) {
+    uint32_t *rec = reinterpret_cast<uint32_t *>(st + STAGE_STRIDE * rate) + __lane_id() * RecLayout<true>::STRIDE;
+    return decode_block_staged_f64_low(st + __lane_id(), rec, rate, out);
 }
 
 // Decode lane l's block from the staging area (stage_wave_words(rate, F64)

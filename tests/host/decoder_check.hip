@@ -1,9 +1,11 @@
 // Host build of the library's block decoders (the device header compiled for
 // the CPU), checked value for value against the oracle's decoder on random
 // block bits at every rate: the plain plane-by-plane decoder for both
-// precisions, and the two-pass decoders of both precisions over an emulated
+// precisions, the two-pass decoders of both precisions over an emulated
 // LDS staging area (one lane's view; the row past the block's words holds
-// garbage, as the next row or the record area does on the GPU).
+// garbage, as the next row or the record area does on the GPU), and the
+// low-rate double-precision decoder (the blocks it takes; it must leave the
+// others untouched).
 // Exit status 0 iff every value matches bit for bit.
 #include "../../paper_2009_03254_amd/csrc/zfp_device.h"
 
@@ -17,7 +19,7 @@ extern "C" int oracle_zfp_decode_some(const uint64_t *stream, int is_f64, uint32
 
 int main() {
     std::mt19937_64 rng(12345);
-    long bad = 0, total = 0;
+    long bad = 0, total = 0, low_taken = 0, low_back = 0;
     const int rates[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 16, 24, 32};
     const double dens[] = {0.5, 0.2, 0.05, 0.01, 0.9, 0.7};
     for (int f64 = 0; f64 < 2; f64++)
@@ -62,6 +64,21 @@ int main() {
                         else bcmc::decode_block_staged_f32(st.data(), rec, rate, got.data() + (size_t)b * 64);
                     }
                     for (size_t i = 0; i < got.size(); i++) n2 += memcmp(&got[i], &ref[i], 4) != 0;
+                    if (f64) {   // the low-rate decoder: the blocks it takes, value for value
+                        for (int b = 0; b < nb; b++) {
+                            for (int w = 0; w < rate; w++) st[(size_t)w * bcmc::STAGE_STRIDE] = s[(size_t)b * rate + w];
+                            for (auto &r : rec) r = 0xDEADBEEFu;
+                            float *o = got.data() + (size_t)b * 64;
+                            for (int i = 0; i < 64; i++) o[i] = -1.0f;
+                            if (bcmc::decode_block_staged_f64_low(st.data(), rec, rate, o)) {
+                                low_taken++;
+                                for (int i = 0; i < 64; i++) n2 += memcmp(&o[i], &ref[(size_t)b * 64 + i], 4) != 0;
+                            } else {
+                                low_back++;
+                                for (int i = 0; i < 64; i++) n2 += o[i] != -1.0f;   // untouched
+                            }
+                        }
+                    }
                 }
                 total += nb;
                 if (n1 || n2)
@@ -69,6 +86,7 @@ int main() {
                            rate, p, n1, n2);
                 bad += n1 + n2;
             }
+    printf("low-rate decoder: %ld blocks decoded, %ld handed back\n", low_taken, low_back);
     printf("blocks %ld, mismatching values %ld\n", total, bad);
-    return bad != 0;
+    return bad != 0 || low_taken < 10000 || low_back < 10000;
 }

@@ -63,6 +63,9 @@ RANDOM_STREAMS = [
     (1, False, 0.5), (3, False, 0.2), (5, False, 0.05), (8, False, 0.5), (8, False, 0.02),
     (8, False, 0.9), (16, False, 0.3), (24, False, 0.1), (2, True, 0.5), (8, True, 0.05),
     (12, True, 0.3), (16, True, 0.3),
+    # double precision at low rates: the stream ends within the top planes,
+    # where pass 2 builds the planes by bit transposes
+    (1, True, 0.5), (3, True, 0.9), (4, True, 0.2), (4, True, 0.97),
 ]
 
 
@@ -84,6 +87,12 @@ def test_random_streams_decode_bitexact(bc, orc, rate, is64, density):
     iso = float(np.median(D))
     T = _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=False)
     assert T > 0
+    st = vol.stats()
+    if (rate, is64, density) == (4, True, 0.2):
+        # bits reaching below plane 39: the general decoder's second pass ran
+        assert 0 < st["n_general"] < st["n_new"], st
+    elif not is64 or rate > 4:
+        assert st["n_general"] == 0, st
     _, ids = vol.active()
     I_slot, _, _ = vol.cache_state()
     slots = vol.slot_data()
