@@ -122,8 +122,8 @@ void free_cache(bcmc_volume *v) {
 
 StatusLayout status_layout(const Geom &g, uint64_t max_slots) {
     StatusLayout s;
-    s.blk = 0;
-    s.slot = s.blk + (g.nb + BLK_TILE - 1) / BLK_TILE;
+    s.rnd = 0;
+    s.slot = s.rnd + block_rounds(g.nb) / 4096 + 1;
     s.mc = s.slot + (max_slots + SLOT_TILE - 1) / SLOT_TILE;
     s.scan = s.mc + (g.nb + SCAN_TILE - 1) / SCAN_TILE + 1;
     uint64_t rtiles = (max_slots + RADIX_TILE - 1) / RADIX_TILE;
@@ -137,6 +137,7 @@ int alloc_common(bcmc_volume *v) {
     int rc;
     if ((rc = dev_alloc(&v->d.ranges, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.tile_ranges, cull_tiles(v->g)))) return rc;
+    if ((rc = dev_alloc(&v->d.cull_list, 2 * cull_tiles(v->g)))) return rc;
     if ((rc = dev_alloc(&v->d.active, v->g.nb + 16))) return rc;
     if ((rc = dev_alloc(&v->d.round_gen, block_rounds(v->g.nb)))) return rc;
     BCMC_HIP_TRY(hipMemset(v->d.round_gen, 0, block_rounds(v->g.nb) * sizeof(uint32_t)));
@@ -144,6 +145,8 @@ int alloc_common(bcmc_volume *v) {
     if ((rc = dev_alloc(&v->d.blk_cnt, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.blk_off, v->g.nb))) return rc;
     if ((rc = dev_alloc(&v->d.part_cand, (v->g.nb + BLK_TILE - 1) / BLK_TILE))) return rc;
+    if ((rc = dev_alloc(&v->d.round_list, block_rounds(v->g.nb)))) return rc;
+    if ((rc = dev_alloc(&v->d.round_cnt, block_rounds(v->g.nb)))) return rc;
     if ((rc = dev_alloc(&v->d.part_wave, 4 * MC_MAX_GRID))) return rc;
     if ((rc = dev_alloc(&v->d.part_occw, 4 * MC_MAX_GRID))) return rc;
     if ((rc = dev_alloc(&v->d.ctr, 1))) return rc;
@@ -163,6 +166,7 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.stream);
     dev_free(v->d.ranges);
     dev_free(v->d.tile_ranges);
+    dev_free(v->d.cull_list);
     dev_free(v->d.active);
     dev_free(v->d.round_gen);
     dev_free(v->d.I_active);
@@ -172,6 +176,8 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.blk_cnt);
     dev_free(v->d.blk_off);
     dev_free(v->d.part_cand);
+    dev_free(v->d.round_list);
+    dev_free(v->d.round_cnt);
     dev_free(v->d.part_wave);
     dev_free(v->d.part_occw);
     dev_free(v->d.ctr);
@@ -433,7 +439,7 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     }
     launch_cull(v->g, v->d, v->sl, iso, v->cull_iso, v->n_slots, v->identity, v->gen, s);
     v->cull_iso = iso;
-    launch_compact_blocks(v->g, v->d, v->sl, v->identity, v->gen, s);
+    launch_compact_blocks(v->g, v->d, v->sl, v->gen, s);
     BCMC_HIP_TRY(mark(1));
     if (!v->identity) {
         if (v->calls_since_reset < 0x7FFFFFFFu) v->calls_since_reset++;
@@ -817,6 +823,7 @@ uint64_t carve_scratch(const Geom &g, const StatusLayout &sl, uintptr_t base, De
     d.mc_table = reinterpret_cast<uint64_t *>(take(256 * sizeof(uint64_t)));
     d.ranges = reinterpret_cast<float2 *>(take(g.nb * sizeof(float2)));
     d.tile_ranges = reinterpret_cast<float2 *>(take(cull_tiles(g) * sizeof(float2)));
+    d.cull_list = reinterpret_cast<uint32_t *>(take(2 * cull_tiles(g) * sizeof(uint32_t)));
     d.active = take((g.nb + 16 + 3) / 4 * 4);
     d.round_gen = reinterpret_cast<uint32_t *>(take(block_rounds(g.nb) * sizeof(uint32_t)));
     d.I_active = reinterpret_cast<uint32_t *>(take(g.nb * sizeof(uint32_t)));
@@ -824,6 +831,8 @@ uint64_t carve_scratch(const Geom &g, const StatusLayout &sl, uintptr_t base, De
     d.blk_off = reinterpret_cast<uint64_t *>(take(g.nb * sizeof(uint64_t)));
     d.masks = reinterpret_cast<uint64_t *>(take(g.nb * sizeof(uint64_t)));
     d.part_cand = reinterpret_cast<uint32_t *>(take((g.nb + BLK_TILE - 1) / BLK_TILE * sizeof(uint32_t)));
+    d.round_list = reinterpret_cast<uint32_t *>(take(block_rounds(g.nb) * sizeof(uint32_t)));
+    d.round_cnt = reinterpret_cast<uint64_t *>(take(block_rounds(g.nb) * sizeof(uint64_t)));
     d.part_wave = reinterpret_cast<uint64_t *>(take(4 * MC_MAX_GRID * sizeof(uint64_t)));
     d.part_occw = reinterpret_cast<uint32_t *>(take(4 * MC_MAX_GRID * sizeof(uint32_t)));
     d.status = reinterpret_cast<uint64_t *>(take(sl.total * sizeof(uint64_t)));
@@ -867,7 +876,7 @@ extern "C" int bcmc_extract_blocks_noalloc(const float *d_blocks, uint32_t nx, u
     launch_fill_u32(reinterpret_cast<uint32_t *>(d.active), 0u, (g.nb + 3) / 4, s);
     launch_fill_u32(d.round_gen, 0u, block_rounds(g.nb), s);
     launch_cull(g, d, sl, iso, NAN, 0, 1, gen, s);
-    launch_compact_blocks(g, d, sl, 1, gen, s);
+    launch_compact_blocks(g, d, sl, gen, s);
     launch_mc_count(g, d, d_blocks, nullptr, 1, iso, 0, s);
     launch_mc_emit(g, d, d_blocks, nullptr, 1, iso, d_out, capacity_vertices, 0, s);
     BCMC_HIP_TRY(hipGetLastError());

@@ -42,23 +42,19 @@ struct Counters {
     unsigned long long n_occ;        // active blocks that emit triangles
     unsigned long long n_cand;       // active blocks that may emit (staged by the count pass)
     unsigned long long total_verts;  // 3 * triangles
+    unsigned long long n_live_rounds;  // 4096-block rounds holding an active block
     unsigned int err;                // ERR_* bits
     unsigned int key_or, key_and;    // OR / AND of the sort keys of available slots
     unsigned int pass_mask;          // radix digits that vary (bit p = digit p)
-    unsigned int tile_ctr[12];       // dynamic work counters (tiles / batches)
+    unsigned int tile_ctr[16];       // dynamic work counters (tiles / batches)
 };
-enum { TC_BLK = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */,
-       TC_MCCOUNT = 7, TC_MCEMIT = 8, TC_RETRY = 9 /* blocks the low-rate decoder handed back */ };
+enum { TC_ROUNDS = 0, TC_SLOT = 1, TC_MC = 2, TC_SCAN0 = 3 /* 3..6 per radix pass */,
+       TC_MCCOUNT = 7, TC_MCEMIT = 8, TC_RETRY = 9 /* blocks the low-rate decoder handed back */,
+       TC_CULL_LIVE = 10, TC_CULL_STALE = 11 /* the cull's queued tiles */ };
 // Double-precision streams up to this rate decode with the low-rate decoder
 // (and a general pass over the blocks it hands back).
 constexpr uint32_t LOW_RATE_MAX = 4;
 
-// Block compaction tiles hold BLK_TILE * m blocks (16 * m per thread), with m
-// the smallest making at most 1024 tiles: one look-back ticket per tile.
-__host__ __device__ inline uint32_t compact_blocks_per_thread16(uint64_t nb) {
-    const uint64_t tiles = (nb + BLK_TILE - 1) / BLK_TILE;
-    return (uint32_t)((tiles + 1023) / 1024);
-}
 
 // Geometry of a volume in blocks.
 struct Geom {
@@ -72,6 +68,7 @@ struct DevState {
     uint64_t *stream = nullptr;     // fixed-rate ZFP words, block b at b*rate
     float2 *ranges = nullptr;       // per block (min, max) of decoded valid samples
     float2 *tile_ranges = nullptr;  // per cull tile: hull of its blocks' and halo's ranges
+    uint32_t *cull_list = nullptr;  // 2 x cull tiles: the call's live tiles, then its stale ones
     uint8_t *active = nullptr;      // M_active
     uint32_t *round_gen = nullptr;  // per 4096-block round: the last call that found an active block in it
     uint32_t *I_active = nullptr;   // ascending active block ids
@@ -93,7 +90,9 @@ struct DevState {
     // MC
     uint32_t *blk_cnt = nullptr;    // per active block vertex count
     uint64_t *blk_off = nullptr;    // per active block first vertex
-    uint32_t *part_cand = nullptr;  // per compaction tile: blocks that may emit
+    uint32_t *part_cand = nullptr;  // per live round: blocks that may emit
+    uint32_t *round_list = nullptr; // ascending live rounds of the call
+    uint64_t *round_cnt = nullptr;  // per live round: (active << 32 | new) blocks, then their offsets
     uint64_t *part_wave = nullptr;  // [4 * max MC grid] per-wave vertex totals of the count pass
     uint32_t *part_occw = nullptr;  // [4 * max MC grid] per-wave occupied blocks
     uint64_t *status = nullptr;     // look-back status words (all kernels)
@@ -103,7 +102,7 @@ struct DevState {
 
 // Offsets of each kernel's region inside DevState::status.
 struct StatusLayout {
-    uint64_t blk, slot, mc, scan, total;
+    uint64_t rnd, slot, mc, scan, total;
 };
 
 // ---- launchers (extract.hip) -------------------------------------------
@@ -112,8 +111,8 @@ struct StatusLayout {
 // (rounds of blocks whose round_gen equals it hold this call's active blocks).
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
                  uint64_t n_slots_host, int identity_cache, uint32_t gen, hipStream_t s);
-void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
-                           int identity_cache, uint32_t gen, hipStream_t s);
+void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl, uint32_t gen,
+                           hipStream_t s);
 inline uint64_t block_rounds(uint64_t nb) { return (nb + BLK_TILE - 1) / BLK_TILE; }
 // age_cap: exceeds the age of every slot used since the cache was reset.
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,

@@ -12,7 +12,6 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <numeric>
 
 #include "common.h"
 #include "mc_device.h"
@@ -71,21 +70,11 @@ __global__ __launch_bounds__(256) void k_tile_ranges(Geom g, const float2 *__res
                                               fmaxf(fmaxf(s_h[0].y, s_h[1].y), fmaxf(s_h[2].y, s_h[3].y)));
 }
 
-// Flags per block: bit 0 active, bit 1 may emit, bit 2 active without a
-// slot (new, Alg. 1 MarkNewBlocks; never set for an identity cache).
-// prev_iso: the isovalue of the previous cull (NaN: none since the flags
-// were cleared).  The flags are zero outside the tiles that call culled, so
-// a tile live then and dead now is cleared here, a live tile is rewritten
-// in full, and no other flag is touched.
-__global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
-                                             float prev_iso, const float2 *__restrict__ tile_ranges,
-                                             const int32_t *__restrict__ I_slot, int identity,
-                                             uint8_t *__restrict__ active, Counters *ctr,
-                                             uint64_t n_slots_host, uint64_t *status,
-                                             uint64_t status_words, uint64_t tile_mul,
-                                             uint32_t *__restrict__ round_gen, uint32_t gen) {
+// The per-call counters and the look-back status words of the call's scans
+// start at zero: cleared first (the cull's tile queue counts in the counters).
+__global__ __launch_bounds__(256) void k_call_reset(Counters *ctr, uint64_t n_slots_host, uint64_t *status,
+                                                   uint64_t status_words) {
     const uint64_t gid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    const uint64_t gsz = (uint64_t)gridDim.x * blockDim.x;
     if (gid == 0) {
         Counters c{};
         c.n_slots = n_slots_host;
@@ -94,129 +83,169 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
         c.key_and = ~0u;
         *ctr = c;
     }
-    for (uint64_t w = gid; w < status_words; w += gsz) status[w] = 0;
+    for (uint64_t w = gid; w < status_words; w += (uint64_t)gridDim.x * blockDim.x) status[w] = 0;
+}
 
+// Tile queue of the cull: the tiles whose hull straddles iso (live: culled
+// block by block) and those whose hull straddled the previous call's isovalue
+// only (stale: their flags are cleared), one tile per thread, appended with
+// one atomic per wave.  live: n_tiles entries, stale: the n_tiles after.
+__global__ __launch_bounds__(256) void k_cull_scan(const float2 *__restrict__ tile_ranges, uint64_t n_tiles,
+                                                  float iso, float prev_iso, uint32_t *__restrict__ list,
+                                                  Counters *ctr) {
+    const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    bool live = false, stale = false;
+    if (t < n_tiles) {
+        const float2 hull = tile_ranges[t];
+        live = hull.x < iso && iso <= hull.y;
+        stale = !live && hull.x < prev_iso && prev_iso <= hull.y;
+    }
+    const uint64_t lm = __ballot(live), sm = __ballot(stale);
+    uint32_t lb = 0, sb = 0;
+    if (lane() == 0) {
+        if (lm) lb = atomicAdd(&ctr->tile_ctr[TC_CULL_LIVE], (uint32_t)__popcll(lm));
+        if (sm) sb = atomicAdd(&ctr->tile_ctr[TC_CULL_STALE], (uint32_t)__popcll(sm));
+    }
+    lb = __shfl(lb, 0, 64);
+    sb = __shfl(sb, 0, 64);
+    if (live) list[lb + mbcnt(lm)] = (uint32_t)t;
+    if (stale) list[n_tiles + sb + mbcnt(sm)] = (uint32_t)t;
+}
+
+// Flags per block: bit 0 active, bit 1 may emit, bit 2 active without a
+// slot (new, Alg. 1 MarkNewBlocks; never set for an identity cache).
+// The flags are zero outside the tiles the previous call culled, so a tile
+// live then and dead now (stale) is cleared here, a live tile is rewritten
+// in full, and no other flag is touched.  Persistent: workgroup w takes
+// queue entries w, w + G, ... (stale tiles first), so that a surface's live
+// tiles spread evenly over the workgroups whatever their layout, with no
+// shared counter (same-address atomics serialise, ~14 ns each).
+__global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__ ranges, float iso,
+                                             const uint32_t *__restrict__ list, uint64_t n_tiles,
+                                             const int32_t *__restrict__ I_slot, int identity,
+                                             uint8_t *__restrict__ active, Counters *ctr,
+                                             uint32_t *__restrict__ round_gen, uint32_t gen) {
     constexpr int NL = CULL_TZ + 2, RX = CULL_TX + 2, RY = CULL_TY + 2, SLOTS = RX * RY;
     __shared__ float2 sh[NL][RY][RX];
-    __shared__ uint32_t live[256], stale[256];
-    __shared__ uint32_t n_live, n_stale;
     const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
-    const uint64_t n_tiles = (uint64_t)ntx * nty * ((g.nbz + CULL_TZ - 1) / CULL_TZ);
-    // The workgroup's tiles are (j * tile_mul) mod n_tiles for j = blockIdx.x
-    // + gridDim.x * i (tile_mul coprime with n_tiles: a permutation that
-    // spreads the runs of consecutive live tiles a surface makes over all
-    // workgroups); their hulls are read 256 at a time, and only the tiles
-    // whose hull straddles iso are culled block by block
-    const uint64_t G = gridDim.x;
-    for (uint64_t i0 = 0; blockIdx.x + G * i0 < n_tiles; i0 += 256) {
-        if (threadIdx.x == 0) n_live = n_stale = 0;
-        __syncthreads();
-        const uint64_t j = blockIdx.x + G * (i0 + threadIdx.x);
-        if (j < n_tiles) {
-            const uint64_t ti = (j * tile_mul) % n_tiles;
-            const float2 hull = tile_ranges[ti];
-            if (hull.x < iso && iso <= hull.y) live[atomicAdd(&n_live, 1u)] = (uint32_t)ti;
-            else if (hull.x < prev_iso && prev_iso <= hull.y) stale[atomicAdd(&n_stale, 1u)] = (uint32_t)ti;
-        }
-        __syncthreads();
-        for (uint32_t k = 0; k < n_stale; k++) {   // clear the tiles culled last time only
-            uint32_t t = stale[k];
-            const uint32_t tx = t % ntx;
-            t /= ntx;
-            const uint32_t ty = t % nty, tz = t / nty;
-            const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
-            const uint32_t bx = tx * CULL_TX + threadIdx.x % CULL_TX, by = ty * CULL_TY + threadIdx.x / CULL_TX;
+    const uint32_t n_live = ctr->tile_ctr[TC_CULL_LIVE], n_stale = ctr->tile_ctr[TC_CULL_STALE];
+    for (uint32_t q = blockIdx.x; q < n_stale + n_live; q += gridDim.x) {
+        const bool clear = q < n_stale;
+        uint32_t t = clear ? list[n_tiles + q] : list[q - n_stale];
+        const uint32_t tx = t % ntx;
+        t /= ntx;
+        const uint32_t ty = t % nty, tz = t / nty;
+        const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+        const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
+        const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
+        if (clear) {   // culled last time only
             if (bx < g.nbx && by < g.nby)
                 for (int z = z0; z < z1; z++) active[((uint64_t)z * g.nby + by) * g.nbx + bx] = 0;
+            continue;
         }
-        const uint32_t nl = n_live;
-        for (uint32_t k = 0; k < nl; k++) {
-            uint32_t t = live[k];
-            const uint32_t tx = t % ntx;
-            t /= ntx;
-            const uint32_t ty = t % nty, tz = t / nty;
-            const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
-#pragma unroll 4
-            for (int i = threadIdx.x; i < NL * SLOTS; i += 256) {
-                const int li = i / SLOTS, r = i - li * SLOTS;
-                const int hy = r / RX, hx = r - hy * RX;
-                const int zl = z0 - 1 + li;
-                const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
-                float2 v = make_float2(INFINITY, -INFINITY);
-                if (zl >= 0 && zl < (int)g.nbz && zl <= z1 && x >= 0 && x < (int)g.nbx && y >= 0 &&
-                    y < (int)g.nby)
-                    v = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
-                sh[li][hy][hx] = v;
-            }
-            __syncthreads();
-            const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
-            const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
-            if (bx < g.nbx && by < g.nby) {
-                // per layer: 3x3 min / max, 2x2 positive min / max, own range
-                float l3a = INFINITY, h3a = -INFINITY;                       // layer zl - 2
-                float l3b = INFINITY, h3b = -INFINITY, p2lb = INFINITY, p2hb = -INFINITY;
-                float2 ownb = make_float2(INFINITY, -INFINITY);             // layer zl - 1
-                for (int li = 0; li < NL; li++) {
-                    const int zl = z0 - 1 + li;
-                    if (zl > z1) break;
-                    float l3 = INFINITY, h3 = -INFINITY, p2l = INFINITY, p2h = -INFINITY;
+        // the box's ranges with their halo, all loads in flight together
+        constexpr int PER = (NL * SLOTS + 255) / 256;
+        float2 v[PER];
 #pragma unroll
-                    for (int dy = -1; dy <= 1; dy++)
+        for (int k = 0; k < PER; k++) {
+            const int i = (int)threadIdx.x + 256 * k;
+            const int li = i / SLOTS, r = i - li * SLOTS;
+            const int hy = r / RX, hx = r - hy * RX;
+            const int zl = z0 - 1 + li;
+            const int x = (int)(tx * CULL_TX) + hx - 1, y = (int)(ty * CULL_TY) + hy - 1;
+            v[k] = make_float2(INFINITY, -INFINITY);
+            if (i < NL * SLOTS && zl >= 0 && zl < (int)g.nbz && zl <= z1 && x >= 0 && x < (int)g.nbx &&
+                y >= 0 && y < (int)g.nby)
+                v[k] = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
+        }
 #pragma unroll
-                        for (int dx = -1; dx <= 1; dx++) {
-                            const float2 q = sh[li][ly + 1 + dy][lx + 1 + dx];
-                            l3 = fminf(l3, q.x);
-                            h3 = fmaxf(h3, q.y);
-                            if (dx >= 0 && dy >= 0) {
-                                p2l = fminf(p2l, q.x);
-                                p2h = fmaxf(p2h, q.y);
-                            }
+        for (int k = 0; k < PER; k++) {
+            const int i = (int)threadIdx.x + 256 * k;
+            if (i < NL * SLOTS) (&sh[0][0][0])[i] = v[k];
+        }
+        __syncthreads();
+        uint32_t act = 0;   // bit z - z0: block (bx, by, z) is active
+        if (bx < g.nbx && by < g.nby) {
+            // per layer: 3x3 min / max, 2x2 positive min / max, own range
+            float l3a = INFINITY, h3a = -INFINITY;                       // layer zl - 2
+            float l3b = INFINITY, h3b = -INFINITY, p2lb = INFINITY, p2hb = -INFINITY;
+            float2 ownb = make_float2(INFINITY, -INFINITY);             // layer zl - 1
+            uint32_t can = 0;
+#pragma unroll
+            for (int li = 0; li < NL; li++) {
+                float l3 = INFINITY, h3 = -INFINITY, p2l = INFINITY, p2h = -INFINITY;
+#pragma unroll
+                for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; dx++) {
+                        const float2 q2 = sh[li][ly + 1 + dy][lx + 1 + dx];
+                        l3 = fminf(l3, q2.x);
+                        h3 = fmaxf(h3, q2.y);
+                        if (dx >= 0 && dy >= 0) {
+                            p2l = fminf(p2l, q2.x);
+                            p2h = fmaxf(p2h, q2.y);
                         }
-                    const float2 own = sh[li][ly + 1][lx + 1];
-                    if (zl > z0) {   // layer zl - 1 has both z neighbours now
-                        const float LO = fminf(l3a, fminf(l3b, l3)), HI = fmaxf(h3a, fmaxf(h3b, h3));
-                        const float PLO = fminf(p2lb, p2l), PHI = fmaxf(p2hb, p2h);
-                        const bool act = (ownb.x < iso && iso <= HI) || (LO < iso && iso <= ownb.y);
-                        // "can emit": the hull of the 2x2x2 group headed by the block
-                        // contains iso (implies act, as that group contains the block)
-                        const bool can_emit = PLO < iso && iso <= PHI;
-                        const uint64_t b = ((uint64_t)(zl - 1) * g.nby + by) * g.nbx + bx;
-                        const bool fresh = act && !identity && I_slot[b] < 0;
-                        active[b] = (act ? 1u : 0u) | (can_emit ? 2u : 0u) | (fresh ? 4u : 0u);
-                        // mark the 4096-block rounds holding active blocks for the
-                        // compaction: each half-wave is 32 consecutive blocks of one
-                        // row, so its first and last active lanes name every round
-                        const uint64_t am = __ballot(act);
-                        const uint32_t half = (uint32_t)(am >> (lane() & 32));
-                        const int hl = lane() & 31;
-                        if (act && (hl == __builtin_ctz(half) || hl == 31 - __builtin_clz(half)))
-                            round_gen[b / BLK_TILE] = gen;
                     }
-                    l3a = l3b;
-                    h3a = h3b;
-                    l3b = l3;
-                    h3b = h3;
-                    p2lb = p2l;
-                    p2hb = p2h;
-                    ownb = own;
+                const float2 own = sh[li][ly + 1][lx + 1];
+                if (li >= 2 && z0 - 2 + li < z1) {   // layer z0 - 2 + li has both z neighbours now
+                    const float LO = fminf(l3a, fminf(l3b, l3)), HI = fmaxf(h3a, fmaxf(h3b, h3));
+                    const float PLO = fminf(p2lb, p2l), PHI = fmaxf(p2hb, p2h);
+                    // "can emit": the hull of the 2x2x2 group headed by the block
+                    // contains iso (implies act, as that group contains the block)
+                    if ((ownb.x < iso && iso <= HI) || (LO < iso && iso <= ownb.y)) act |= 1u << (li - 2);
+                    if (PLO < iso && iso <= PHI) can |= 1u << (li - 2);
                 }
+                l3a = l3b;
+                h3a = h3b;
+                l3b = l3;
+                h3b = h3;
+                p2lb = p2l;
+                p2hb = p2h;
+                ownb = own;
             }
-            __syncthreads();   // sh is restaged for the next live tile
+            // the slots of the active blocks (new: none), their loads in flight together
+            int32_t sl[CULL_TZ];
+#pragma unroll
+            for (int z = 0; z < CULL_TZ; z++) {
+                sl[z] = 0;
+                if (!identity && ((act >> z) & 1u))
+                    sl[z] = I_slot[((uint64_t)(z0 + z) * g.nby + by) * g.nbx + bx];
+            }
+#pragma unroll
+            for (int z = 0; z < CULL_TZ; z++) {
+                if (z0 + z >= z1) break;
+                const bool a = (act >> z) & 1u;
+                const uint64_t b = ((uint64_t)(z0 + z) * g.nby + by) * g.nbx + bx;
+                active[b] = (a ? 1u : 0u) | (((can >> z) & 1u) ? 2u : 0u) | (a && sl[z] < 0 ? 4u : 0u);
+            }
         }
-        __syncthreads();   // live / n_live are rewritten for the next chunk
+        // mark the 4096-block rounds holding active blocks for the
+        // compaction: each half-wave is 32 consecutive blocks of one row, so
+        // its first and last active lanes name every round
+#pragma unroll
+        for (int z = 0; z < CULL_TZ; z++) {
+            const bool a = (act >> z) & 1u;
+            const uint64_t am = __ballot(a);
+            const uint32_t half = (uint32_t)(am >> (lane() & 32));
+            const int hl = lane() & 31;
+            if (a && (hl == __builtin_ctz(half) || hl == 31 - __builtin_clz(half)))
+                round_gen[(((uint64_t)(z0 + z) * g.nby + by) * g.nbx + bx) / BLK_TILE] = gen;
+        }
+        __syncthreads();   // sh is restaged for the next live tile
     }
 }
 
 // I_active (StreamCompactIDs of M_active) and I_new (active blocks without a
-// slot, Alg. 1 MarkNewBlocks, flagged by the cull) in one look-back pass over
-// the blocks.  A tile is m rounds of 4096 consecutive blocks; in a round each
-// thread takes 16 consecutive flags (one 16-byte load, the workgroup's loads
-// contiguous).  The first pass counts, the look-back places the tile, the
-// second pass revisits the rounds holding an active block and places each
-// thread's blocks by a workgroup scan.  Counts are packed as
-// (active << 31 | new) so one status word carries both.
-constexpr int COMPACT_MAX_ROUNDS = 128;   // rounds tracked one by one (more: all revisited)
-
+// slot, Alg. 1 MarkNewBlocks, flagged by the cull).  The blocks are cut into
+// rounds of 4096 consecutive blocks, and the cull stamped every round holding
+// an active block with the call's gen (the other rounds' flags are all zero).
+// k_round_list lists the live rounds in ascending order; k_round_counts
+// counts each one's active and new blocks, k_round_scan turns the counts into
+// offsets, and k_compact_blocks writes each round's ids there.  A surface
+// makes runs of live rounds: taking them one per workgroup (rounds w, w + G,
+// ...) spreads a run over the chip, with no waiting between workgroups and no
+// shared counter.  In a round each thread takes 16 consecutive flags (one
+// 16-byte load).
 // Bit 0 of each byte of w, gathered into bits 0..3: the four bits land on
 // bits 21..24 of the product with no carries between them.
 __device__ __forceinline__ uint32_t byte_bits(uint32_t w) {
@@ -245,107 +274,126 @@ __device__ __forceinline__ uint4 load_flags16(const uint8_t *__restrict__ active
     return make_uint4(wd[0], wd[1], wd[2], wd[3]);
 }
 
+
+// The live rounds (round_gen == gen) in ascending order: 16 stamps per thread
+// (4096 per workgroup), a look-back over the workgroups; the last one writes
+// their number.
+__global__ __launch_bounds__(256) void k_round_list(const uint32_t *__restrict__ round_gen, uint64_t n_rounds,
+                                                   uint32_t gen, uint32_t *__restrict__ list, Counters *ctr,
+                                                   uint64_t *status) {
+    const uint64_t t = take_tile(&ctr->tile_ctr[TC_ROUNDS]);   // look-back order = start order
+    const uint64_t n_tiles = (n_rounds + 4095) / 4096;
+    const uint64_t r0 = t * 4096 + 16u * threadIdx.x;
+    uint32_t live = 0;   // bit j: round r0 + j
+    if (r0 + 16 <= n_rounds) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(round_gen + r0);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint4 q = p[k];
+            live |= ((q.x == gen ? 1u : 0u) | (q.y == gen ? 2u : 0u) | (q.z == gen ? 4u : 0u) |
+                     (q.w == gen ? 8u : 0u)) << (4 * k);
+        }
+    } else {
+        for (int j = 0; j < 16; j++)
+            if (r0 + j < n_rounds && round_gen[r0 + j] == gen) live |= 1u << j;
+    }
+    uint64_t total;
+    uint64_t o = tile_scan_lookback((uint64_t)__popc(live), status, t, &total);
+    for (uint32_t m = live; m; m &= m - 1) list[o++] = (uint32_t)(r0 + __builtin_ctz(m));
+    if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_live_rounds = total;
+}
+
+// Per live round: (active << 32 | new) blocks, and the blocks that may emit.
+__global__ __launch_bounds__(256) void k_round_counts(Geom g, const uint8_t *__restrict__ active,
+                                                     const uint32_t *__restrict__ round_list,
+                                                     uint64_t *__restrict__ round_cnt,
+                                                     uint32_t *__restrict__ part_cand, const Counters *ctr) {
+    __shared__ uint64_t s_part[4];
+    const uint64_t n_live = ctr->n_live_rounds;
+    for (uint64_t k = blockIdx.x; k < n_live; k += gridDim.x) {
+        const uint64_t base = (uint64_t)round_list[k] * BLK_TILE + 16u * threadIdx.x;
+        uint32_t actb, newb, cand = 0;
+        flag_bits(load_flags16(active, base, g.nb), actb, newb, cand);
+        // three counts of at most 4096 in 21-bit fields
+        uint64_t v = (uint64_t)__popc(actb) | ((uint64_t)__popc(newb) << 21) | ((uint64_t)cand << 42);
+        v = wave_sum(v);
+        if (lane() == 0) s_part[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint64_t t = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+            const uint64_t m21 = (1ull << 21) - 1;
+            round_cnt[k] = ((t & m21) << 32) | ((t >> 21) & m21);
+            part_cand[k] = (uint32_t)(t >> 42);
+        }
+        __syncthreads();   // s_part is rewritten by the next round
+    }
+}
+
+// Exclusive prefix of the live rounds' counts, in place; the totals are the
+// call's n_act and n_new.  One workgroup, 4096 rounds per step.
+__global__ __launch_bounds__(256) void k_round_scan(uint64_t *__restrict__ round_cnt, Counters *ctr) {
+    __shared__ uint64_t s_w[4];
+    const uint64_t n = ctr->n_live_rounds;
+    const int w = threadIdx.x >> 6;
+    uint64_t carry = 0;
+    for (uint64_t c0 = 0; c0 < n; c0 += 4096) {
+        const uint64_t i0 = c0 + 16u * threadIdx.x;
+        uint64_t v[16], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            v[j] = i0 + j < n ? round_cnt[i0 + j] : 0ull;
+            sum += v[j];
+        }
+        const uint64_t incl = wave_incl_scan(sum);
+        if (lane() == 63) s_w[w] = incl;
+        __syncthreads();
+        uint64_t o = carry + incl - sum, tot = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (i < w) o += s_w[i];
+            tot += s_w[i];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            if (i0 + j < n) round_cnt[i0 + j] = o;
+            o += v[j];
+        }
+        carry += tot;
+        __syncthreads();   // s_w is rewritten by the next step
+    }
+    if (threadIdx.x == 0) {
+        ctr->n_act = carry >> 32;
+        ctr->n_new = carry & 0xFFFFFFFFull;
+    }
+}
+
+// Each live round's active and new block ids, from its offsets on
+// (workgroup exclusive scan of the threads' counts).
 __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *__restrict__ active,
+                                                       const uint32_t *__restrict__ round_list,
+                                                       const uint64_t *__restrict__ round_off,
                                                        uint32_t *__restrict__ I_active,
-                                                       uint32_t *__restrict__ I_new, Counters *ctr,
-                                                       uint32_t *__restrict__ part_cand,
-                                                       uint64_t *status, uint32_t m,
-                                                       const uint32_t *__restrict__ round_gen,
-                                                       uint32_t gen) {
-    const uint64_t tile_blocks = (uint64_t)BLK_TILE * m;
-    const uint64_t n_tiles = (g.nb + tile_blocks - 1) / tile_blocks;
-    const uint32_t t = take_tile(&ctr->tile_ctr[TC_BLK]);
-    if (t >= n_tiles) return;
-    const uint64_t tbase = t * tile_blocks + 16u * threadIdx.x;
-    uint32_t nact = 0, nnew = 0, cand = 0;
-    uint64_t any[2] = {0ull, 0ull};   // rounds in which this thread saw an active block
-    // rounds whose round_gen is not this call's hold no active block: their
-    // flags are all zero and are not read
-    const uint32_t *rg = round_gen + (uint64_t)t * m;
-    const uint64_t n_rounds = (g.nb + BLK_TILE - 1) / BLK_TILE;
-    const uint32_t m_here = (uint32_t)min((uint64_t)m, n_rounds - (uint64_t)t * m);
-    for (uint32_t r0 = 0; r0 < m; r0 += 4) {
-        uint4 q[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-            q[k] = r0 + k < m_here && rg[r0 + k] == gen
-                       ? load_flags16(active, tbase + (uint64_t)BLK_TILE * (r0 + k), g.nb)
-                       : make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            uint32_t actb, newb;
-            flag_bits(q[k], actb, newb, cand);
-            nact += __popc(actb);
-            nnew += __popc(newb);
-            if (actb && r0 + k < COMPACT_MAX_ROUNDS) any[(r0 + k) >> 6] |= 1ull << ((r0 + k) & 63);
-        }
-    }
-    cand = wg_sum_u32(cand);
-    if (threadIdx.x == 0) part_cand[t] = cand;
-    // rounds holding an active block anywhere in the workgroup
-    __shared__ uint64_t s_any[4][2];
-    __shared__ uint64_t s_base;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        any[0] |= __shfl_xor(any[0], d, 64);
-        any[1] |= __shfl_xor(any[1], d, 64);
-    }
-    if (lane() == 0) {
-        s_any[threadIdx.x >> 6][0] = any[0];
-        s_any[threadIdx.x >> 6][1] = any[1];
-    }
-    uint64_t incl_end;
-    const uint64_t e = tile_scan_lookback(((uint64_t)nact << 31) | (uint64_t)nnew, status, t, &incl_end);
-    if (threadIdx.x == 0) s_base = e;   // thread 0's prefix is the tile's
-    __syncthreads();
-    uint64_t oa = s_base >> 31, on = s_base & 0x7FFFFFFFull;
-    const uint64_t wany0 = s_any[0][0] | s_any[1][0] | s_any[2][0] | s_any[3][0];
-    const uint64_t wany1 = s_any[0][1] | s_any[1][1] | s_any[2][1] | s_any[3][1];
-    // 4 rounds at a time: their loads in flight together, one pair of
-    // barriers for the 4 workgroup scans
-    __shared__ uint32_t s_w[4][4];   // [round of the group][wave]
-    for (uint32_t r0 = 0; r0 < m; r0 += 4) {
-        bool use[4];
-        uint4 q[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const uint32_t r = r0 + k;
-            use[k] = r < m_here && rg[r] == gen &&
-                     (r >= COMPACT_MAX_ROUNDS || (((r < 64 ? wany0 : wany1) >> (r & 63)) & 1ull));
-            q[k] = use[k] ? load_flags16(active, tbase + (uint64_t)BLK_TILE * r, g.nb)
-                          : make_uint4(0u, 0u, 0u, 0u);
-        }
-        if (!(use[0] || use[1] || use[2] || use[3])) continue;   // uniform: wany is
-        uint32_t actb[4], newb[4], packed[4], incl[4], unused = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            flag_bits(q[k], actb[k], newb[k], unused);
-            packed[k] = ((uint32_t)__popc(actb[k]) << 16) | (uint32_t)__popc(newb[k]);
-            incl[k] = wave_incl_scan(packed[k]);   // workgroup scans (each field < 2^16)
-            if (lane() == 63) s_w[k][threadIdx.x >> 6] = incl[k];
-        }
+                                                       uint32_t *__restrict__ I_new, const Counters *ctr) {
+    __shared__ uint32_t s_w[4];
+    const uint64_t n_live = ctr->n_live_rounds;
+    const int w = threadIdx.x >> 6;
+    for (uint64_t k = blockIdx.x; k < n_live; k += gridDim.x) {
+        const uint64_t base = (uint64_t)round_list[k] * BLK_TILE + 16u * threadIdx.x;
+        const uint64_t off = round_off[k];
+        uint32_t actb, newb, unused = 0;
+        flag_bits(load_flags16(active, base, g.nb), actb, newb, unused);
+        const uint32_t packed = ((uint32_t)__popc(actb) << 16) | (uint32_t)__popc(newb);
+        const uint32_t incl = wave_incl_scan(packed);   // fields < 2^13 each
+        if (lane() == 63) s_w[w] = incl;
         __syncthreads();
+        uint32_t ex = incl - packed;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            uint32_t woff = 0, tot = 0;
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                if (i < (int)(threadIdx.x >> 6)) woff += s_w[k][i];
-                tot += s_w[k][i];
-            }
-            const uint64_t base = tbase + (uint64_t)BLK_TILE * (r0 + k);
-            const uint32_t ex = woff + incl[k] - packed[k];
-            uint64_t pa = oa + (ex >> 16), pn = on + (ex & 0xFFFFu);
-            for (uint32_t mm = actb[k]; mm; mm &= mm - 1) I_active[pa++] = (uint32_t)(base + __builtin_ctz(mm));
-            for (uint32_t mm = newb[k]; mm; mm &= mm - 1) I_new[pn++] = (uint32_t)(base + __builtin_ctz(mm));
-            oa += tot >> 16;
-            on += tot & 0xFFFFu;
-        }
-        __syncthreads();
-    }
-    if (t == n_tiles - 1 && threadIdx.x == 0) {
-        ctr->n_act = incl_end >> 31;
-        ctr->n_new = incl_end & 0x7FFFFFFFull;
+        for (int i = 0; i < 4; i++)
+            if (i < w) ex += s_w[i];
+        uint64_t pa = (off >> 32) + (ex >> 16), pn = (off & 0xFFFFFFFFull) + (ex & 0xFFFFu);
+        for (uint32_t mm = actb; mm; mm &= mm - 1) I_active[pa++] = (uint32_t)(base + __builtin_ctz(mm));
+        for (uint32_t mm = newb; mm; mm &= mm - 1) I_new[pn++] = (uint32_t)(base + __builtin_ctz(mm));
+        __syncthreads();   // s_w is rewritten by the next round
     }
 }
 
@@ -803,8 +851,7 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
         before = s_base[0] + s_base[1] + s_base[2] + s_base[3];
         __syncthreads();
         if (first) {
-            const uint64_t ctile = (uint64_t)BLK_TILE * compact_blocks_per_thread16(g.nb);
-            const uint64_t n_ct = (g.nb + ctile - 1) / ctile;
+            const uint64_t n_ct = ctr->n_live_rounds;
             uint32_t cand = 0;
             for (uint64_t i = threadIdx.x; i < n_ct; i += blockDim.x) cand += part_cand[i];
             all = wave_sum(all);
@@ -1023,22 +1070,16 @@ static unsigned mc_grid(uint64_t max_blocks) {
     return (unsigned)((g + 7) / 8 * 8);   // whole XCD rounds
 }
 
-// A multiplier near 0.618 n, coprime with n: j -> (j * a) mod n permutes [0, n).
-static uint64_t coprime_mul(uint64_t n) {
-    if (n <= 2) return 1;
-    uint64_t a = (uint64_t)(0.6180339887 * (double)n) | 1u;
-    while (std::gcd(a, n) != 1) a += 2;
-    return a % n;
-}
-
 void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float iso, float prev_iso,
                  uint64_t n_slots_host, int identity_cache, uint32_t gen, hipStream_t s) {
     static unsigned rgrid = 0;
     if (!rgrid) rgrid = resident_grid(k_cull, ~0ull >> 4);
     const uint64_t nt = cull_tiles(g);
+    k_call_reset<<<grid_cap(sl.total, 64), 256, 0, s>>>(d.ctr, n_slots_host, d.status, sl.total);
+    k_cull_scan<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(d.tile_ranges, nt, iso, prev_iso, d.cull_list,
+                                                             d.ctr);
     k_cull<<<(unsigned)std::min<uint64_t>(nt, rgrid), 256, 0, s>>>(
-        g, d.ranges, iso, prev_iso, d.tile_ranges, d.I_slot, identity_cache, d.active, d.ctr, n_slots_host,
-        d.status, sl.total, coprime_mul(nt), d.round_gen, gen);
+        g, d.ranges, iso, d.cull_list, nt, d.I_slot, identity_cache, d.active, d.ctr, d.round_gen, gen);
 }
 
 uint64_t cull_tiles(const Geom &g) {
@@ -1050,13 +1091,19 @@ void launch_tile_ranges(const Geom &g, const float2 *ranges, float2 *tile_ranges
     k_tile_ranges<<<(unsigned)cull_tiles(g), 256, 0, s>>>(g, ranges, tile_ranges);
 }
 
-void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl,
-                           int identity_cache, uint32_t gen, hipStream_t s) {
-    const uint32_t m = compact_blocks_per_thread16(g.nb);
-    const uint64_t tiles = (g.nb + (uint64_t)BLK_TILE * m - 1) / ((uint64_t)BLK_TILE * m);
-    k_compact_blocks<<<(unsigned)tiles, 256, 0, s>>>(g, d.active, d.I_active, d.I_new, d.ctr,
-                                                     d.part_cand, d.status + sl.blk, m, d.round_gen,
-                                                     gen);
+void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl, uint32_t gen,
+                           hipStream_t s) {
+    static unsigned cgrid = 0, wgrid = 0;
+    if (!cgrid) cgrid = resident_grid(k_round_counts, ~0ull >> 4);
+    if (!wgrid) wgrid = resident_grid(k_compact_blocks, ~0ull >> 4);
+    const uint64_t n_rounds = block_rounds(g.nb);
+    k_round_list<<<(unsigned)((n_rounds + 4095) / 4096), 256, 0, s>>>(d.round_gen, n_rounds, gen, d.round_list,
+                                                                      d.ctr, d.status + sl.rnd);
+    k_round_counts<<<(unsigned)std::min<uint64_t>(n_rounds, cgrid), 256, 0, s>>>(
+        g, d.active, d.round_list, d.round_cnt, d.part_cand, d.ctr);
+    k_round_scan<<<1, 256, 0, s>>>(d.round_cnt, d.ctr);
+    k_compact_blocks<<<(unsigned)std::min<uint64_t>(n_rounds, wgrid), 256, 0, s>>>(
+        g, d.active, d.round_list, d.round_cnt, d.I_active, d.I_new, d.ctr);
 }
 
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
