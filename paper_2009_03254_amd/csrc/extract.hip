@@ -709,6 +709,8 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
                                               const Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
+    // every active block was decoded by this call, its mask with it
+    if (!identity && ctr->n_new == n_act) return;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_act;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t b = I_active[i];

@@ -138,7 +138,7 @@ __device__ __forceinline__ void store_slot(const float *v, uint64_t s, float iso
 // low-rate decoder; the blocks it hands back (their indices into I_new) are
 // listed in `retry` for k_decode_retry.
 template <bool F64, bool STAGED, bool LOW = false>
-__global__ __launch_bounds__(256, LOW ? 3 : 1) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
+__global__ __launch_bounds__(256, LOW ? 3 : (F64 ? 1 : 4)) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
                                                       const uint32_t *__restrict__ sorted0,
                                                       const uint32_t *__restrict__ sorted1,
                                                       int32_t *S_block, int32_t *I_slot,

@@ -374,6 +374,13 @@ __host__ __device__ __forceinline__ uint64_t staged_pass1(const uint64_t *st, ui
             found |= (uint64_t)g << (n + z);
             n += g ? z + 1 : 0;
             end = !g || n == 64 || budget == 0;
+            // after a find, a 0 as the next group test (mostly still inside
+            // w) ends the plane in this step
+            if (!end && adv < 64 && !((w >> adv) & 1u)) {
+                off++;
+                budget--;
+                end = true;
+            }
         }
         if (end) {
             const uint32_t r = (uint32_t)(off - gstart) | ((uint32_t)(n - nstart) << 8);
