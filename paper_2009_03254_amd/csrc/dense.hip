@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_dense_emit(DenseGeom g, const float *__
             const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
             const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
             const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
-            if (o < cap) stream_store(out, o, px, py, pz, b);
+            if (o < cap) store_record(out, o, px, py, pz, b);
         }
     }
 }

@@ -482,13 +482,15 @@ constexpr uint64_t edge_lut(bool tile_offset) {
 }
 constexpr uint64_t kEdgeGeom = edge_lut(false), kEdgeTile = edge_lut(true);
 
-// Vertex records are written once and not read back by the path: streaming
-// (non-temporal) stores keep them from evicting the staged slots from L2.
+// Vertex records are written once and not read back by the path:
+// non-temporal stores.  (Plain stores drain a bare streaming write faster on
+// gfx950, but in this kernel the two measured the same within the spread
+// that the output buffer's physical placement causes.)
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void stream_store(void *out, uint64_t o, uint64_t r) {
+__device__ __forceinline__ void store_record(void *out, uint64_t o, uint64_t r) {
     __builtin_nontemporal_store(r, reinterpret_cast<uint64_t *>(out) + o);
 }
-__device__ __forceinline__ void stream_store(void *out, uint64_t o, float x, float y, float z, uint32_t b) {
+__device__ __forceinline__ void store_record(void *out, uint64_t o, float x, float y, float z, uint32_t b) {
     u32x4_t v = {__float_as_uint(x), __float_as_uint(y), __float_as_uint(z), b};
     __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t *>(out) + o);
 }
@@ -586,7 +588,7 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
                 uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
                 qt = qt < 4194303u ? qt : 4194303u;
                 const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
-                if (o < cap) stream_store(out, o, r);
+                if (o < cap) store_record(out, o, r);
             } else {
                 // the edge's first corner plus t along its axis (adding 0 to the
                 // other two coordinates leaves them exact)
@@ -594,9 +596,9 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
                 const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
                 const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
                 if (FMT == VFMT_Q10) {
-                    if (o < cap) stream_store(out, o, (uint64_t)q10_code(px, py, pz) | ((uint64_t)b << 32));
+                    if (o < cap) store_record(out, o, (uint64_t)q10_code(px, py, pz) | ((uint64_t)b << 32));
                 } else {
-                    if (o < cap) stream_store(out, o, px, py, pz, b);
+                    if (o < cap) store_record(out, o, px, py, pz, b);
                 }
             }
         }
