@@ -687,7 +687,7 @@ struct bcmc_dense {
     uint32_t nx = 0, ny = 0, nz = 0;
     uint32_t *ids = nullptr;
     uint8_t *cases = nullptr;
-    uint64_t *first = nullptr, *status = nullptr, *mc_table = nullptr;
+    uint64_t *first = nullptr, *work = nullptr, *mc_table = nullptr;
     void *ctr = nullptr;
     uint64_t *h_ctr = nullptr;   // pinned copy of the counters
 };
@@ -698,7 +698,7 @@ void dense_destroy(bcmc_dense *h) {
     dev_free(h->ids);
     dev_free(h->cases);
     dev_free(h->first);
-    dev_free(h->status);
+    dev_free(h->work);
     dev_free(h->mc_table);
     if (h->ctr) (void)hipFree(h->ctr);
     if (h->h_ctr) (void)hipHostFree(h->h_ctr);
@@ -721,7 +721,7 @@ extern "C" int bcmc_dense_create(uint32_t nx, uint32_t ny, uint32_t nz, bcmc_den
     int rc;
     if ((rc = dev_alloc(&h->ids, cells)) || (rc = dev_alloc(&h->cases, cells)) ||
         (rc = dev_alloc(&h->first, cells)) ||
-        (rc = dev_alloc(&h->status, dense_status_words(nx, ny, nz))) ||
+        (rc = dev_alloc(&h->work, dense_work_words(nx, ny, nz))) ||
         (rc = dev_alloc(&h->mc_table, 256))) {
         dense_destroy(h);
         return rc;
@@ -746,7 +746,7 @@ extern "C" int bcmc_dense_extract(bcmc_dense *h, const float *d_field, float iso
     if (!d_out && capacity_vertices) return invalid("null output buffer with nonzero capacity");
     if (iso != iso) return invalid("iso is NaN");
     hipStream_t s = as_stream(hip_stream);
-    launch_dense(h->nx, h->ny, h->nz, d_field, iso, h->ids, h->cases, h->first, h->status, h->ctr,
+    launch_dense(h->nx, h->ny, h->nz, d_field, iso, h->ids, h->cases, h->first, h->work, h->ctr,
                  h->mc_table, d_out, capacity_vertices, s);
     BCMC_HIP_TRY(hipGetLastError());
     BCMC_HIP_TRY(hipMemcpyAsync(h->h_ctr, h->ctr, dense_counter_bytes(), hipMemcpyDeviceToHost, s));

@@ -142,10 +142,10 @@ void launch_copy_calibration(void *dst, const void *src, uint64_t n16, hipStream
 void launch_iota_i32(int32_t *p, uint64_t n, hipStream_t s);
 
 // ---- launchers (dense.hip): dense marching cubes baseline ---------------
-uint64_t dense_status_words(uint32_t nx, uint32_t ny, uint32_t nz);
+uint64_t dense_work_words(uint32_t nx, uint32_t ny, uint32_t nz);
 uint64_t dense_counter_bytes();
 void launch_dense(uint32_t nx, uint32_t ny, uint32_t nz, const float *field, float iso,
-                  uint32_t *ids, uint8_t *cases, uint64_t *first, uint64_t *status,
+                  uint32_t *ids, uint8_t *cases, uint64_t *first, uint64_t *work,
                   void *ctr_mem, const uint64_t *mc_table, void *out, uint64_t cap, hipStream_t s);
 
 // ---- launchers (zfp.hip) -----------------------------------------------

@@ -11,6 +11,13 @@
 // position + block id), computed with the same operations, so the soup is
 // the block path's soup with the cells in global row-major order (x fastest)
 // instead of block order.
+//
+// The two prefix sums run over tiles of 4096 cells: a pass classifies every
+// cell and counts each tile's cells with triangles and their vertices, one
+// workgroup scans the tile counts, and a pass over the stored cases writes
+// the compacted cells with their first vertex (the per-cell vertex counts
+// and the second prefix sum come with the first, so no pass of their own).
+// No same-address atomics: tiles are indexed by workgroup.
 #include <stdint.h>
 
 #include <algorithm>
@@ -24,16 +31,14 @@ namespace {
 constexpr int DENSE_SEG = 16;   // cells per thread: a segment of one row of cells
 
 struct DenseCtr {
-    unsigned int tile_cls, tile_cnt;   // tile tickets of the two scans
-    unsigned int err;
-    unsigned int pad;
+    unsigned int unused[4];
     unsigned long long n_active, n_verts;
 };
 
 // A row of cells is split into segments of DENSE_SEG cells; segment s covers
 // cells x in [16 k, min(16 k + 16, nx - 1)) of row r = s / segs_per_row
 // (r = y + (ny - 1) z), so the segments in order visit the cells in global
-// row-major order.
+// row-major order.  A tile is 256 segments.
 struct DenseGeom {
     uint32_t nx, ny, nz;
     uint32_t segs_per_row;
@@ -41,28 +46,35 @@ struct DenseGeom {
     uint32_t nbx, nby;    // blocks per row / per layer (for the block ids of the records)
 };
 
-// Pass 1: classify the cells of a tile (256 segments), and compact the ids
-// (index of the cell's lowest sample) and cases of those whose case is not
-// 0 or 255, in order, by a single-pass scan with decoupled look-back.
-__global__ __launch_bounds__(256) void k_dense_classify(DenseGeom g, const float *__restrict__ f,
-                                                       float iso, uint32_t *__restrict__ ids,
-                                                       uint8_t *__restrict__ cases, DenseCtr *ctr,
-                                                       uint64_t *status) {
-    const uint64_t n_tiles = (g.n_segs + 255) / 256;
-    const uint32_t t = take_tile(&ctr->tile_cls);
-    if (t >= n_tiles) return;
-    const uint64_t s = (uint64_t)t * 256 + threadIdx.x;
-    uint32_t cs[DENSE_SEG];
-    uint32_t act = 0, x0 = 0, ncell = 0;
-    uint64_t row_base = 0;
+// Segment s: first sample of its row, first cell x0, number of cells.
+__device__ __forceinline__ void dense_segment(const DenseGeom &g, uint64_t s, uint64_t &row_base, uint32_t &x0,
+                                              uint32_t &ncell) {
+    const uint32_t r = (uint32_t)(s / g.segs_per_row);
+    const uint32_t k = (uint32_t)(s - (uint64_t)r * g.segs_per_row);
+    const uint32_t y = r % (g.ny - 1), z = r / (g.ny - 1);
+    x0 = DENSE_SEG * k;
+    ncell = min((uint32_t)DENSE_SEG, g.nx - 1 - x0);
+    row_base = ((uint64_t)z * g.ny + y) * g.nx;
+}
+
+// Pass 1: the cases of the segment's cells (stored as the segment's 16
+// bytes), and the tile's count of cells whose case is not 0 or 255 and of
+// their vertices (3 per triangle), as (vertices << 32 | cells).
+__global__ __launch_bounds__(256) void k_dense_classify(DenseGeom g, const float *__restrict__ f, float iso,
+                                                       const uint64_t *__restrict__ mc_table,
+                                                       uint4 *__restrict__ seg_cases,
+                                                       uint64_t *__restrict__ tile_cnt) {
+    __shared__ uint8_t s_ntri[256];
+    __shared__ uint64_t s_w[4];
+    s_ntri[threadIdx.x] = (uint8_t)(mc_table[threadIdx.x] >> 60);
+    __syncthreads();
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t na = 0, nv = 0;
     if (s < g.n_segs) {
-        const uint32_t r = (uint32_t)(s / g.segs_per_row);
-        const uint32_t k = (uint32_t)(s - (uint64_t)r * g.segs_per_row);
-        const uint32_t y = r % (g.ny - 1), z = r / (g.ny - 1);
-        x0 = DENSE_SEG * k;
-        ncell = min((uint32_t)DENSE_SEG, g.nx - 1 - x0);
-        row_base = ((uint64_t)z * g.ny + y) * g.nx;
-        const uint64_t sx = 1, sy = g.nx, sz = (uint64_t)g.nx * g.ny;
+        uint64_t row_base;
+        uint32_t x0, ncell;
+        dense_segment(g, s, row_base, x0, ncell);
+        const uint64_t sy = g.nx, sz = (uint64_t)g.nx * g.ny;
         // the four sample rows of the segment, DENSE_SEG + 1 samples each
         float v[4][DENSE_SEG + 1];
 #pragma unroll
@@ -71,61 +83,130 @@ __global__ __launch_bounds__(256) void k_dense_classify(DenseGeom g, const float
 #pragma unroll
             for (int j = 0; j <= DENSE_SEG; j++) v[q][j] = j <= (int)ncell ? p[j] : 0.0f;
         }
-        (void)sx;
+        uint32_t cw[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int j = 0; j < DENSE_SEG; j++) {
             uint32_t c = 0;
 #pragma unroll
             for (int kk = 0; kk < 8; kk++)
                 c |= (v[((kk >> 1) & 1) | ((kk >> 2) << 1)][j + (kk & 1)] < iso ? 1u : 0u) << kk;
-            cs[j] = c;
-            if (j < (int)ncell && c != 0u && c != 255u) act |= 1u << j;
+            cw[j >> 2] |= c << (8 * (j & 3));
+            if (j < (int)ncell && c != 0u && c != 255u) {
+                na++;
+                nv += 3u * s_ntri[c];
+            }
+        }
+        seg_cases[s] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+    }
+    uint64_t x = wave_sum(((uint64_t)nv << 32) | na);
+    if (lane() == 0) s_w[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// Pass 2 (one workgroup): exclusive prefix of the tiles' counts, tile_off[2t]
+// = cells before tile t, tile_off[2t + 1] = vertices before it; the totals.
+__global__ __launch_bounds__(256) void k_dense_scan(const uint64_t *__restrict__ tile_cnt, uint64_t n_tiles,
+                                                   uint64_t *__restrict__ tile_off, DenseCtr *ctr) {
+    __shared__ uint64_t s_a[4], s_v[4];
+    const int w = threadIdx.x >> 6;
+    uint64_t ca = 0, cv = 0;   // carries
+    for (uint64_t c0 = 0; c0 < n_tiles; c0 += 4096) {
+        const uint64_t i0 = c0 + 16u * threadIdx.x;
+        uint64_t t[16], sa = 0, sv = 0;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            t[j] = i0 + j < n_tiles ? tile_cnt[i0 + j] : 0ull;
+            sa += t[j] & 0xFFFFFFFFull;
+            sv += t[j] >> 32;
+        }
+        const uint64_t ia = wave_incl_scan(sa), iv = wave_incl_scan(sv);
+        if (lane() == 63) {
+            s_a[w] = ia;
+            s_v[w] = iv;
+        }
+        __syncthreads();
+        uint64_t oa = ca + ia - sa, ov = cv + iv - sv, ta = 0, tv = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (i < w) {
+                oa += s_a[i];
+                ov += s_v[i];
+            }
+            ta += s_a[i];
+            tv += s_v[i];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            if (i0 + j < n_tiles) {
+                tile_off[2 * (i0 + j)] = oa;
+                tile_off[2 * (i0 + j) + 1] = ov;
+            }
+            oa += t[j] & 0xFFFFFFFFull;
+            ov += t[j] >> 32;
+        }
+        ca += ta;
+        cv += tv;
+        __syncthreads();   // s_a / s_v are rewritten by the next step
+    }
+    if (threadIdx.x == 0) {
+        ctr->n_active = ca;
+        ctr->n_verts = cv;
+    }
+}
+
+// Pass 3: the cells with triangles, in order: id (index of the cell's lowest
+// sample), case, first vertex (the tile's offsets plus a workgroup scan).
+__global__ __launch_bounds__(256) void k_dense_compact(DenseGeom g, const uint4 *__restrict__ seg_cases,
+                                                      const uint64_t *__restrict__ tile_off,
+                                                      const uint64_t *__restrict__ mc_table,
+                                                      uint32_t *__restrict__ ids, uint8_t *__restrict__ cases,
+                                                      uint64_t *__restrict__ first) {
+    __shared__ uint8_t s_ntri[256];
+    __shared__ uint32_t s_w[4];
+    s_ntri[threadIdx.x] = (uint8_t)(mc_table[threadIdx.x] >> 60);
+    __syncthreads();
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t cw[4] = {0u, 0u, 0u, 0u}, act = 0, x0 = 0, ncell = 0;
+    uint64_t row_base = 0;
+    uint32_t na = 0, nv = 0;
+    if (s < g.n_segs) {
+        dense_segment(g, s, row_base, x0, ncell);
+        const uint4 q = seg_cases[s];
+        cw[0] = q.x; cw[1] = q.y; cw[2] = q.z; cw[3] = q.w;
+#pragma unroll
+        for (int j = 0; j < DENSE_SEG; j++) {
+            const uint32_t c = (cw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            if (j < (int)ncell && c != 0u && c != 255u) {
+                act |= 1u << j;
+                na++;
+                nv += 3u * s_ntri[c];
+            }
         }
     }
-    uint64_t total;
-    const uint64_t base = tile_scan_lookback((uint64_t)__popc(act), status, t, &total);
-    uint64_t o = base;
+    // per thread na <= 16, nv <= 240; per workgroup na < 2^13, nv < 2^16
+    const uint32_t packed = na | (nv << 13);
+    const uint32_t incl = wave_incl_scan(packed);
+    if (lane() == 63) s_w[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t ex = incl - packed;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        if (i < (int)(threadIdx.x >> 6)) ex += s_w[i];
+    uint64_t o = tile_off[2 * (uint64_t)blockIdx.x] + (ex & 0x1FFFu);
+    uint64_t ov = tile_off[2 * (uint64_t)blockIdx.x + 1] + (ex >> 13);
     for (uint32_t m = act; m; m &= m - 1) {
         const int j = __builtin_ctz(m);
+        const uint32_t c = (cw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
         ids[o] = (uint32_t)(row_base + x0 + (uint32_t)j);
-        cases[o] = (uint8_t)cs[j];
+        cases[o] = (uint8_t)c;
+        first[o] = ov;
         o++;
+        ov += 3u * s_ntri[c];
     }
-    if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_active = total;
 }
 
-// Pass 2: the vertex count of every compacted cell (3 per triangle of its
-// case) and their exclusive prefix sum (decoupled look-back): each cell's
-// first vertex, and the total.
-__global__ __launch_bounds__(256) void k_dense_count(const uint8_t *__restrict__ cases,
-                                                    const uint64_t *__restrict__ mc_table,
-                                                    uint64_t *__restrict__ first, DenseCtr *ctr,
-                                                    uint64_t *status) {
-    __shared__ uint8_t s_ntri[256];
-    for (int i = threadIdx.x; i < 256; i += 256) s_ntri[i] = (uint8_t)(mc_table[i] >> 60);
-    __syncthreads();
-    const uint64_t n = ctr->n_active;
-    const uint64_t n_tiles = (n + 256 * DENSE_SEG - 1) / (256 * DENSE_SEG);
-    const uint32_t t = take_tile(&ctr->tile_cnt);
-    if (t >= n_tiles) return;
-    const uint64_t i0 = (uint64_t)t * 256 * DENSE_SEG + (uint64_t)threadIdx.x * DENSE_SEG;
-    uint32_t c[DENSE_SEG], sum = 0;
-#pragma unroll
-    for (int j = 0; j < DENSE_SEG; j++) {
-        c[j] = i0 + j < n ? 3u * s_ntri[cases[i0 + j]] : 0u;
-        sum += c[j];
-    }
-    uint64_t total;
-    uint64_t o = tile_scan_lookback(sum, status, t, &total);
-#pragma unroll
-    for (int j = 0; j < DENSE_SEG; j++) {
-        if (i0 + j < n) first[i0 + j] = o;
-        o += c[j];
-    }
-    if (t == n_tiles - 1 && threadIdx.x == 0) ctr->n_verts = total;
-}
-
-// Pass 3: one thread per compacted cell writes its triangles' vertices from
+// Pass 4: one thread per compacted cell writes its triangles' vertices from
 // its first vertex on (records past cap dropped).
 __global__ __launch_bounds__(256) void k_dense_emit(DenseGeom g, const float *__restrict__ f, float iso,
                                                    const uint32_t *__restrict__ ids,
@@ -168,29 +249,23 @@ __global__ __launch_bounds__(256) void k_dense_emit(DenseGeom g, const float *__
     }
 }
 
-__global__ void k_dense_reset(DenseCtr *ctr, uint64_t *status, uint64_t n_status) {
-    const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    if (i == 0) *ctr = DenseCtr{};
-    for (uint64_t w = i; w < n_status; w += (uint64_t)gridDim.x * blockDim.x) status[w] = 0;
-}
-
 }  // namespace
 
-// Look-back status words the two scans need (classification tiles, then
-// count tiles: at most one per 4096 cells).
-uint64_t dense_status_words(uint32_t nx, uint32_t ny, uint32_t nz) {
+// 64-bit words of work memory: the segments' cases (2 words each), the
+// tiles' counts (1) and offsets (2).
+uint64_t dense_work_words(uint32_t nx, uint32_t ny, uint32_t nz) {
     const uint64_t segs = (uint64_t)((nx - 2) / DENSE_SEG + 1) * (ny - 1) * (nz - 1);
-    const uint64_t cells = (uint64_t)(nx - 1) * (ny - 1) * (nz - 1);
-    return (segs + 255) / 256 + (cells + 256 * DENSE_SEG - 1) / (256 * DENSE_SEG) + 2;
+    const uint64_t tiles = (segs + 255) / 256;
+    return 2 * segs + 3 * tiles;
 }
 
 uint64_t dense_counter_bytes() { return sizeof(DenseCtr); }
 
-// ids, cases, first: per cell of the volume at most; status: see above;
+// ids, cases, first: per cell of the volume at most; work: see above;
 // ctr: dense_counter_bytes().  The counters' n_active and n_verts (u64 at
 // byte offsets 16 and 24) are valid when the stream reaches the end.
 void launch_dense(uint32_t nx, uint32_t ny, uint32_t nz, const float *field, float iso,
-                  uint32_t *ids, uint8_t *cases, uint64_t *first, uint64_t *status,
+                  uint32_t *ids, uint8_t *cases, uint64_t *first, uint64_t *work,
                   void *ctr_mem, const uint64_t *mc_table, void *out, uint64_t cap, hipStream_t s) {
     DenseGeom g;
     g.nx = nx;
@@ -201,13 +276,13 @@ void launch_dense(uint32_t nx, uint32_t ny, uint32_t nz, const float *field, flo
     g.nbx = (nx + 3) / 4;
     g.nby = (ny + 3) / 4;
     DenseCtr *ctr = reinterpret_cast<DenseCtr *>(ctr_mem);
-    const uint64_t n_status = dense_status_words(nx, ny, nz);
-    const uint64_t cls_tiles = (g.n_segs + 255) / 256;
-    k_dense_reset<<<256, 256, 0, s>>>(ctr, status, n_status);
-    k_dense_classify<<<(unsigned)cls_tiles, 256, 0, s>>>(g, field, iso, ids, cases, ctr, status);
+    const uint64_t tiles = (g.n_segs + 255) / 256;
+    uint4 *seg_cases = reinterpret_cast<uint4 *>(work);
+    uint64_t *tile_cnt = work + 2 * g.n_segs, *tile_off = tile_cnt + tiles;
+    k_dense_classify<<<(unsigned)tiles, 256, 0, s>>>(g, field, iso, mc_table, seg_cases, tile_cnt);
+    k_dense_scan<<<1, 256, 0, s>>>(tile_cnt, tiles, tile_off, ctr);
+    k_dense_compact<<<(unsigned)tiles, 256, 0, s>>>(g, seg_cases, tile_off, mc_table, ids, cases, first);
     const uint64_t cells = (uint64_t)(nx - 1) * (ny - 1) * (nz - 1);
-    const uint64_t cnt_tiles = (cells + 256 * DENSE_SEG - 1) / (256 * DENSE_SEG);
-    k_dense_count<<<(unsigned)cnt_tiles, 256, 0, s>>>(cases, mc_table, first, ctr, status + cls_tiles);
     k_dense_emit<<<(unsigned)std::min<uint64_t>((cells + 255) / 256, 8192), 256, 0, s>>>(
         g, field, iso, ids, cases, first, mc_table, out, cap, ctr);
 }
