@@ -830,8 +830,9 @@ def dense_bench(steps, warmup, n_random=100):
     res["random100"]["block_mean_ms"] = round(float(np.mean(ts)) * 1e3, 4)
     res["note"] = ("dense = classify every cell (with its vertex count) -> prefix sums over "
                    "4096-cell tiles -> compact (ids, cases, first vertices) -> emit, over the "
-                   "512 MiB uncompressed field; block = the compressed path (cull, cache, decode, block-wise MC) on the 128 MiB stream; "
-                   "host-timed calls with their count readback")
+                   "512 MiB uncompressed field; block = the compressed path (cull, cache, "
+                   "decode, block-wise MC) on the 128 MiB stream; host-timed calls with their "
+                   "count readback")
     dm.close()
     vol.close()
     del dense, out, flush_buf
