@@ -409,9 +409,12 @@ __global__ __launch_bounds__(256) void k_slot_pass(const uint8_t *__restrict__ a
                                                   uint32_t *__restrict__ part_and, Counters *ctr,
                                                   uint64_t *status) {
     const uint64_t n_tiles = (n_slots + SLOT_TILE - 1) / SLOT_TILE;
-    const uint32_t t = take_tile(&ctr->tile_ctr[TC_SLOT]);
-    if (t >= n_tiles) return;
+    // the list of available slots (look-back order = ticket order) is needed
+    // only when the call has new blocks; otherwise the tiles just age, in any
+    // order, without a shared ticket counter
     const bool need_list = ctr->n_new != 0;
+    const uint32_t t = need_list ? take_tile(&ctr->tile_ctr[TC_SLOT]) : blockIdx.x;
+    if (t >= n_tiles) return;
     constexpr int PER = SLOT_TILE / 256;   // consecutive slots per thread (16-byte loads)
     static_assert(PER % 4 == 0, "the vector path loads 4 slots at a time");
     const uint64_t base = (uint64_t)t * SLOT_TILE + threadIdx.x * PER;
