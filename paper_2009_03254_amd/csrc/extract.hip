@@ -8,7 +8,10 @@
 //   * single-pass scans with decoupled look-back (Merrill & Garland 2016):
 //     each tile publishes its aggregate, then its inclusive prefix, in a
 //     64-bit status word (2 flag bits + value); tiles are taken from an atomic
-//     counter in order, so a tile only ever waits on tiles already running.
+//     counter in order, so a tile only ever waits on tiles already running;
+//   * device-scope atomics on one address serialise (~14 ns each), so work
+//     without a look-back is spread statically (workgroup w takes items w,
+//     w + G, ...) and per-workgroup counts go to arrays, not one counter.
 #include <stdint.h>
 
 #include <algorithm>
@@ -24,9 +27,8 @@ namespace {
 // united with the range of one of its 26 neighbours, contains iso
 // (lo < iso <= hi).  With LO / HI the min / max over the 3x3x3 neighbourhood
 // that is:  (lo_b < iso <= HI)  or  (LO < iso <= hi_b).
-// Also resets the call's counters and clears the look-back status words.
 // ---------------------------------------------------------------------------
-// Tiled: a workgroup owns a CULL_TX x CULL_TY x CULL_TZ box of blocks.  The
+// Tiled: a workgroup culls a CULL_TX x CULL_TY x CULL_TZ box of blocks.  The
 // box's ranges with a one-block halo (+inf / -inf outside the volume) are
 // staged in LDS with all loads in flight at once; the 3x3 in-plane min / max
 // and the 2x2 positive-quadrant min / max are then combined across z in
