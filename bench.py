@@ -313,7 +313,8 @@ def batch_bench(steps, warmup):
         "n_blocks": n_blocks, "triangles": T,
         "schedule": {"stage_blocks": info["stage_blocks"], "grid": info["grid"],
                      "workgroups_per_cu": info["workgroups_per_cu"],
-                     "front_grid": info["front_grid"], "graph": info["graph"]},
+                     "front_grid": info["front_grid"], "scan_schedule": info["scan_schedule"],
+                     "graph": info["graph"]},
         "cold": {"batch_ms": round(cold_ms, 4),
                  "batch_gpu_ms": round(float(np.median(gpu_ms["cold"])), 4),
                  "phase_ms": [round(float(x), 4) for x in np.median(np.array(phases["cold"]), axis=0)],

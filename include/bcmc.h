@@ -256,6 +256,9 @@ typedef struct {
     uint32_t grid;            /* schedule: workgroups of the back kernel */
     uint32_t workgroups_per_cu;  /* of the back kernel */
     uint32_t front_grid;      /* schedule: workgroups of the front kernel */
+    uint32_t scan_schedule;   /* schedule: 0 = workgroup 0 scans the front kernel's
+                                 counts, then a grid barrier; 1 = every workgroup
+                                 sums the counts before its own */
     uint32_t decode_grid;     /* workgroups of the decode kernel */
     uint32_t ran_front_grid;  /* grids the last run's kernels were launched with, */
     uint32_t ran_decode_grid; /* as each kernel recorded them (0: that kernel */
@@ -290,12 +293,14 @@ BCMC_API int bcmc_batch_run(bcmc_batch *b, void *d_out, uint64_t capacity_vertic
 /* Set the schedule by hand: stage_blocks (4 or 8) blocks staged per round
  * trip, per_cu workgroups per CU of the back kernel and front_per_cu of the
  * front kernel, each clamped to what stays resident (bcmc_batch_get_info
- * reports the grids).  The next run captures its graph again.
+ * reports the grids), and scan_schedule (0 or 1, see bcmc_batch_info) for the
+ * offsets of the front kernel's lists.  The next run captures its graph again.
  * Errors: BCMC_E_INVALID. */
 BCMC_API int bcmc_batch_set_schedule(bcmc_batch *b, int stage_blocks, int per_cu,
-                                     int front_per_cu);
+                                     int front_per_cu, int scan_schedule);
 /* Autotune the schedule (blocks staged per round trip, workgroups per CU
- * of the back and the front kernel) by timing cold + warm runs of this batch; the best is kept and appended
+ * of the back and the front kernel, the front kernel's scan schedule) by
+ * timing cold + warm runs of this batch; the best is kept and appended
  * to cache_path (one JSON object per line, keyed by arch, scalar type and
  * batch shape; NULL: $BCMC_AUTOTUNE_CACHE, or nothing).  Batches created
  * later with a matching key start from the stored schedule.  Empties the

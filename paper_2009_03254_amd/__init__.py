@@ -437,9 +437,9 @@ class Batch:
     def set_graph(self, on=True):
         _capi.check(lib().bcmc_batch_set_graph(self._h, 1 if on else 0))
 
-    def set_schedule(self, stage_blocks, per_cu, front_per_cu):
+    def set_schedule(self, stage_blocks, per_cu, front_per_cu, scan=0):
         _capi.check(lib().bcmc_batch_set_schedule(self._h, int(stage_blocks), int(per_cu),
-                                                  int(front_per_cu)))
+                                                  int(front_per_cu), int(scan)))
 
     def tune(self, cache_path=None, stream=None):
         _capi.check(lib().bcmc_batch_tune(self._h, cache_path.encode() if cache_path else None,

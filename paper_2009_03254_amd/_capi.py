@@ -41,6 +41,7 @@ class BatchInfo(C.Structure):
                 ("n_pairs", C.c_uint64), ("n_vertices", C.c_uint64),
                 ("stage_blocks", C.c_uint32), ("grid", C.c_uint32),
                 ("workgroups_per_cu", C.c_uint32), ("front_grid", C.c_uint32),
+                ("scan_schedule", C.c_uint32),
                 ("decode_grid", C.c_uint32), ("ran_front_grid", C.c_uint32),
                 ("ran_decode_grid", C.c_uint32), ("ran_grid", C.c_uint32),
                 ("graph", C.c_int32),
@@ -79,7 +80,7 @@ SIGNATURES = {
     "bcmc_batch_reset": (_int, [_P, _P]),
     "bcmc_batch_set_graph": (_int, [_P, _int]),
     "bcmc_batch_run": (_int, [_P, _P, _u64, _P, _P]),
-    "bcmc_batch_set_schedule": (_int, [_P, _int, _int, _int]),
+    "bcmc_batch_set_schedule": (_int, [_P, _int, _int, _int, _int]),
     "bcmc_batch_tune": (_int, [_P, C.c_char_p, _P]),
     "bcmc_batch_get_info": (_int, [_P, _P]),
     "bcmc_batch_free": (None, [_P]),

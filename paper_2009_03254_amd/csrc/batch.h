@@ -51,6 +51,9 @@ struct BatchParams {
     uint64_t n_gblocks, n_jblocks, max_slots;
     uint32_t uniform_rate;       // the rate of every volume when they share one <= 16, else 0
     uint32_t max_vol_jobs;       // most jobs of one volume
+    uint32_t scan_sched;         // offsets of the front kernel's lists: 0 = workgroup 0 scans the
+                                 // counts, then a grid barrier; 1 = every workgroup sums the
+                                 // counts before its own (no barrier)
     int32_t *I_slot;             // [n_gblocks] slot of each global block or -1
     float *slots;                // [max_slots][64]
     uint8_t *need;               // [n_gblocks] 0 unused, 1 used and new, 2 used and resident

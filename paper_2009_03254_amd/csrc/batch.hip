@@ -177,6 +177,45 @@ __device__ uint64_t scan_partials(uint64_t *partial, uint32_t n, uint64_t *sh_w)
     return tot;
 }
 
+// Sum of part[0..n) over the workgroup (its loads spread over the threads,
+// 8 in flight each); with m > 0 also the sum of part[0..m) into *all.  Every
+// thread of the workgroup calls it and gets the sums.
+__device__ uint64_t sum_before(const uint64_t *part, uint32_t n, uint32_t m, uint64_t *sh_w, uint64_t *all) {
+    const uint32_t lim = n > m ? n : m;
+    uint64_t s = 0, t = 0;
+    for (uint32_t i0 = threadIdx.x; i0 < lim; i0 += 8u * BT) {
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t i = i0 + (uint32_t)j * BT;
+            v[j] = i < lim ? part[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t i = i0 + (uint32_t)j * BT;
+            if (i < n) s += v[j];
+            if (i < m) t += v[j];
+        }
+    }
+    s = wave_sum(s);
+    t = wave_sum(t);
+    const int w = threadIdx.x >> 6;
+    if (lane() == 0) sh_w[w] = s;
+    __syncthreads();
+    uint64_t S = 0;
+#pragma unroll
+    for (int k = 0; k < BT / 64; k++) S += sh_w[k];
+    __syncthreads();
+    if (lane() == 0) sh_w[w] = t;
+    __syncthreads();
+    uint64_t T = 0;
+#pragma unroll
+    for (int k = 0; k < BT / 64; k++) T += sh_w[k];
+    __syncthreads();
+    *all = T;
+    return S;
+}
+
 // Sign mask of a decoded block for one isovalue: bit i = (sample i < iso),
 // the inside test of the per-cell classification (Sec. 4.4).
 __device__ __forceinline__ uint64_t sign_mask(const float *v, float iso) {
@@ -320,11 +359,43 @@ __global__ __launch_bounds__(BT) void k_batch_front(BatchParams p) {
     if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 2);
 
-    // ---- phase 2: workgroup 0 scans the counts -----------------------------------
-    if (blockIdx.x == 0) {
-        uint64_t tn = scan_partials(p.part_new, gridDim.x, sh_w64);
-        uint64_t tl = scan_partials(p.part_list, gridDim.x * (BT / 64), sh_w64);
-        if (threadIdx.x == 0) {
+    // ---- phase 2: offsets of the workgroups' new blocks and the waves' pairs ----
+    // scan_sched 0: workgroup 0 scans both count arrays in place, then a grid
+    // barrier; 1: every workgroup sums the counts before its own (and
+    // workgroup 0 all of them for the totals), no barrier.  The autotuner
+    // picks one.
+    uint64_t new_off, list_off;
+    uint32_t wv_list;   // the wave's share of the flag words (index into part_list)
+    {
+        uint64_t slo, shi;
+        wv_list = wave_share(n_words, slo, shi);
+    }
+    if (p.scan_sched == 0) {
+        if (blockIdx.x == 0) {
+            uint64_t tn = scan_partials(p.part_new, gridDim.x, sh_w64);
+            uint64_t tl = scan_partials(p.part_list, gridDim.x * (BT / 64), sh_w64);
+            if (threadIdx.x == 0) {
+                const uint64_t n_slots0 = p.ctr->n_slots;
+                p.ctr->slot_base = n_slots0;
+                p.ctr->n_slots = n_slots0 + tn;
+                p.ctr->n_new = tn;
+                p.ctr->n_list = tl;
+            }
+        }
+        if (!grid_barrier(p.bar, &p.ctr->err)) return;
+        new_off = p.part_new[blockIdx.x];
+        list_off = p.part_list[wv_list];
+    } else {
+        const uint32_t nw = gridDim.x * (BT / 64);
+        const bool all = blockIdx.x == 0;
+        new_off = sum_before(p.part_new, blockIdx.x, all ? gridDim.x : 0u, sh_w64, &list_off);
+        const uint64_t tn = list_off;
+        // the waves before this workgroup's first wave, then its own earlier waves
+        const uint32_t wv0 = wv_list - (threadIdx.x >> 6);
+        uint64_t tl;
+        list_off = sum_before(p.part_list, wv0, all ? nw : 0u, sh_w64, &tl);
+        for (uint32_t k = wv0; k < wv_list; k++) list_off += p.part_list[k];
+        if (all && threadIdx.x == 0) {
             const uint64_t n_slots0 = p.ctr->n_slots;
             p.ctr->slot_base = n_slots0;
             p.ctr->n_slots = n_slots0 + tn;
@@ -332,7 +403,6 @@ __global__ __launch_bounds__(BT) void k_batch_front(BatchParams p) {
             p.ctr->n_list = tl;
         }
     }
-    if (!grid_barrier(p.bar, &p.ctr->err)) return;
     stamp(p, 3);
 
     // ---- phase 3: ordered scatter of both lists --------------------------------
@@ -345,14 +415,14 @@ __global__ __launch_bounds__(BT) void k_batch_front(BatchParams p) {
         for (uint64_t i = a; i < z; i++) c += p.need[i] == 1;
         uint32_t excl;
         wg_excl_scan(c, excl, sh_w);
-        uint64_t o = p.part_new[blockIdx.x] + excl;
+        uint64_t o = new_off + excl;
         for (uint64_t i = a; i < z; i++)
             if (p.need[i] == 1) p.new_list[o++] = (uint32_t)i;
 
         // L: each wave walks its share of the flag words again, 64 words per
         // step, placing the pairs by a wave scan of the per-word counts.
         const uint32_t wv = wave_share(n_words, lo, hi);
-        uint64_t base = p.part_list[wv];
+        uint64_t base = list_off;
         SegCursor cur;
         cur.reset();
         for (uint64_t i0 = lo; i0 < hi; i0 += 64) {

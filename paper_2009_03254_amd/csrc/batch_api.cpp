@@ -48,7 +48,7 @@ struct bcmc_batch {
     void *graph_out = nullptr;
     uint64_t graph_cap = 0;
     int graph_sb = 0;
-    unsigned graph_grid = 0, graph_front_grid = 0, graph_decode_grid = 0;
+    unsigned graph_grid = 0, graph_front_grid = 0, graph_decode_grid = 0, graph_scan = 0;
     int use_graph = 1, graph_failed = 0;
     float last_ms = 0.0f;
     unsigned long long *h_ts = nullptr;   // phase clock stamps of the last run
@@ -104,8 +104,8 @@ unsigned grid_for(bcmc_batch *b, int per_cu) {
 
 // Back kernel: `sb` blocks staged per round trip, `per_cu` workgroups per
 // CU; front kernel: `front_pc` workgroups per CU (both clamped to what stays
-// resident).
-int set_schedule(bcmc_batch *b, int sb, int per_cu, int front_pc) {
+// resident) and `scan` its scan schedule (BatchParams::scan_sched).
+int set_schedule(bcmc_batch *b, int sb, int per_cu, int front_pc, int scan) {
     int maxc = 0;
     if (batch_back_per_cu(sb, &maxc) != 0 || maxc < 1)
         return binvalid("the batched kernel cannot be made resident");
@@ -113,6 +113,7 @@ int set_schedule(bcmc_batch *b, int sb, int per_cu, int front_pc) {
     b->per_cu_max = maxc;
     b->grid = grid_for(b, std::min(std::max(per_cu, 1), maxc));
     b->front_grid = grid_for(b, std::min(std::max(front_pc, 1), b->front_pc_max));
+    b->p.scan_sched = scan ? 1u : 0u;
     return BCMC_OK;
 }
 
@@ -129,7 +130,7 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
         // any schedule dimension or the output changes
         if (!b->exec || b->graph_out != d_out || b->graph_cap != cap || b->graph_sb != b->sb ||
             b->graph_grid != b->grid || b->graph_front_grid != b->front_grid ||
-            b->graph_decode_grid != b->decode_grid) {
+            b->graph_decode_grid != b->decode_grid || b->graph_scan != b->p.scan_sched) {
             drop_graph(b);
             hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
@@ -150,6 +151,7 @@ int run_once(bcmc_batch *b, void *d_out, uint64_t cap, hipStream_t caller) {
                 b->graph_grid = b->grid;
                 b->graph_front_grid = b->front_grid;
                 b->graph_decode_grid = b->decode_grid;
+                b->graph_scan = b->p.scan_sched;
             }
         }
         if (b->exec) {
@@ -199,7 +201,8 @@ int reset_cache(bcmc_batch *b, hipStream_t s) {
 }
 
 // ---- schedule cache: one JSON object per line, keyed by arch and shape ----
-bool load_schedule(const char *path, const std::string &key, int *sb, int *per_cu, int *front_pc) {
+bool load_schedule(const char *path, const std::string &key, int *sb, int *per_cu, int *front_pc,
+                   int *scan) {
     if (!path || !*path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
@@ -210,8 +213,9 @@ bool load_schedule(const char *path, const std::string &key, int *sb, int *per_c
         const char *a = strstr(line, "\"sb\": ");
         const char *c = strstr(line, "\"per_cu\": ");
         const char *f = strstr(line, "\"front_per_cu\": ");
-        if (a && c && f && sscanf(a, "\"sb\": %d", sb) == 1 && sscanf(c, "\"per_cu\": %d", per_cu) == 1 &&
-            sscanf(f, "\"front_per_cu\": %d", front_pc) == 1)
+        const char *d = strstr(line, "\"scan\": ");
+        if (a && c && f && d && sscanf(a, "\"sb\": %d", sb) == 1 && sscanf(c, "\"per_cu\": %d", per_cu) == 1 &&
+            sscanf(f, "\"front_per_cu\": %d", front_pc) == 1 && sscanf(d, "\"scan\": %d", scan) == 1)
             found = true;
     }
     fclose(f);
@@ -219,7 +223,7 @@ bool load_schedule(const char *path, const std::string &key, int *sb, int *per_c
 }
 
 void save_schedule(const char *path, const std::string &key, int sb, int per_cu, int front_pc,
-                   double ms) {
+                   int scan, double ms) {
     if (!path || !*path) return;
     std::vector<std::string> keep;
     if (FILE *f = fopen(path, "r")) {
@@ -230,8 +234,8 @@ void save_schedule(const char *path, const std::string &key, int sb, int per_cu,
     }
     if (FILE *f = fopen(path, "w")) {
         for (auto &l : keep) fputs(l.c_str(), f);
-        fprintf(f, "{\"key\": \"%s\", \"sb\": %d, \"per_cu\": %d, \"front_per_cu\": %d, \"ms\": %.4f}\n",
-                key.c_str(), sb, per_cu, front_pc, ms);
+        fprintf(f, "{\"key\": \"%s\", \"sb\": %d, \"per_cu\": %d, \"front_per_cu\": %d, \"scan\": %d, "
+                   "\"ms\": %.4f}\n", key.c_str(), sb, per_cu, front_pc, scan, ms);
         fclose(f);
     }
 }
@@ -306,7 +310,7 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
     }
     b->front_pc_max = pcf;
     b->decode_grid = grid_for(b, pcd);
-    int rc = set_schedule(b, 8, 1 << 30, std::max(1, pcf / 2));
+    int rc = set_schedule(b, 8, 1 << 30, std::max(1, pcf / 2), 0);
     if (rc) {
         destroy_batch(b);
         return rc;
@@ -382,10 +386,10 @@ int bcmc_batch_create(bcmc_volume *const *vols, uint32_t n_vols, const uint32_t 
     snprintf(key, sizeof key, "gfx950|%s|jobs=%u|vols=%u|blocks~2^%d", f64 ? "f64" : "f32", n_jobs,
              n_vols, 64 - __builtin_clzll(jb));
     b->key = key;
-    int sb = 0, per_cu = 0, front_pc = 0;
-    if (load_schedule(getenv("BCMC_AUTOTUNE_CACHE"), b->key, &sb, &per_cu, &front_pc) &&
+    int sb = 0, per_cu = 0, front_pc = 0, scan = 0;
+    if (load_schedule(getenv("BCMC_AUTOTUNE_CACHE"), b->key, &sb, &per_cu, &front_pc, &scan) &&
         (sb == 4 || sb == 8))
-        (void)set_schedule(b, sb, per_cu, front_pc);
+        (void)set_schedule(b, sb, per_cu, front_pc, scan);
     *out = b;
     return BCMC_OK;
 }
@@ -426,11 +430,13 @@ int bcmc_batch_run(bcmc_batch *b, void *d_out, uint64_t capacity_vertices, uint6
     return BCMC_OK;
 }
 
-int bcmc_batch_set_schedule(bcmc_batch *b, int stage_blocks, int per_cu, int front_per_cu) {
+int bcmc_batch_set_schedule(bcmc_batch *b, int stage_blocks, int per_cu, int front_per_cu,
+                            int scan_schedule) {
     if (!b) return binvalid("null handle");
     if (stage_blocks != 4 && stage_blocks != 8) return binvalid("stage_blocks must be 4 or 8");
     if (per_cu < 1 || front_per_cu < 1) return binvalid("workgroups per CU must be >= 1");
-    return set_schedule(b, stage_blocks, per_cu, front_per_cu);
+    if (scan_schedule != 0 && scan_schedule != 1) return binvalid("scan_schedule must be 0 or 1");
+    return set_schedule(b, stage_blocks, per_cu, front_per_cu, scan_schedule);
 }
 
 int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
@@ -448,7 +454,7 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
         set_error("no memory for the tuning buffer");
         return BCMC_E_NOMEM;
     }
-    int best_sb = b->sb, best_pc = b->per_cu_max, best_fpc = b->front_pc_max;
+    int best_sb = b->sb, best_pc = b->per_cu_max, best_fpc = b->front_pc_max, best_scan = 0;
     double best = 1e30;
     // the front kernel's barriers cost more with more workgroups: half and
     // a quarter of what stays resident
@@ -461,8 +467,10 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
         std::sort(pcs.begin(), pcs.end());
         pcs.erase(std::unique(pcs.begin(), pcs.end()), pcs.end());
         for (int pc : pcs) {
-            for (int fpc : fpcs) {
-                if ((rc = set_schedule(b, sb, pc, fpc))) break;
+            // each front grid with both scan schedules
+            for (size_t fs = 0; fs < 2 * fpcs.size(); fs++) {
+                const int fpc = fpcs[fs / 2], scan = (int)(fs % 2);
+                if ((rc = set_schedule(b, sb, pc, fpc, scan))) break;
                 // median over 5 repetitions of a cold run (empty batch
                 // store) + a warm run; a first repetition warms up
                 std::vector<double> ts;
@@ -480,6 +488,7 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
                     best_sb = sb;
                     best_pc = pc;
                     best_fpc = fpc;
+                    best_scan = scan;
                 }
             }
             if (rc) break;
@@ -488,10 +497,10 @@ int bcmc_batch_tune(bcmc_batch *b, const char *cache_path, void *hip_stream) {
     }
     (void)hipFree(buf);
     if (rc) return rc;
-    rc = set_schedule(b, best_sb, best_pc, best_fpc);
+    rc = set_schedule(b, best_sb, best_pc, best_fpc, best_scan);
     if (rc) return rc;
     save_schedule(cache_path ? cache_path : getenv("BCMC_AUTOTUNE_CACHE"), b->key, best_sb, best_pc,
-                  best_fpc, best / 2.0);
+                  best_fpc, best_scan, best / 2.0);
     return reset_cache(b, s);
 }
 
@@ -510,6 +519,7 @@ int bcmc_batch_get_info(const bcmc_batch *b, bcmc_batch_info *out) {
     out->workgroups_per_cu = b->grid / (unsigned)std::max(b->cus, 1);
     out->front_grid = b->front_grid;
     out->decode_grid = b->decode_grid;
+    out->scan_schedule = b->p.scan_sched;
     out->ran_front_grid = b->h_ctr ? b->h_ctr->grid_front : 0;
     out->ran_decode_grid = b->h_ctr ? b->h_ctr->grid_decode : 0;
     out->ran_grid = b->h_ctr ? b->h_ctr->grid_back : 0;

@@ -182,9 +182,10 @@ def test_batch_checkerboard_with_turbulence(orc):
 
 def test_batch_schedule_change_recaptures_graph(orc):
     """Changing one schedule dimension at a time (the front kernel's grid
-    alone, then the back kernel's, then the staging) captures the graph
-    again: every kernel records the grid it ran with, which must be the grid
-    the schedule reports, and the output stays byte-identical."""
+    alone, its scan schedule alone, then the back kernel's grid, then the
+    staging) captures the graph again: every kernel records the grid it ran
+    with, which must be the grid the schedule reports, and the output stays
+    byte-identical."""
     torch_cuda()
     import paper_2009_03254_amd as bc
     dims_list = [(41, 37, 29), (30, 26, 45)]
@@ -196,15 +197,16 @@ def test_batch_schedule_change_recaptures_graph(orc):
     batch = bc.Batch(vols, jobs)
     batch.set_graph(True)
     seen = set()
-    for sb, pc, fpc in ((8, 4, 4), (8, 4, 1), (8, 4, 2), (8, 2, 2), (4, 2, 2), (4, 2, 1)):
-        batch.set_schedule(sb, pc, fpc)
+    for sb, pc, fpc, scan in ((8, 4, 4, 0), (8, 4, 1, 0), (8, 4, 1, 1), (8, 4, 2, 1), (8, 2, 2, 1),
+                              (4, 2, 2, 0), (4, 2, 1, 1)):
+        batch.set_schedule(sb, pc, fpc, scan)
         batch.reset()                   # cold: the decode kernel runs too
         _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)
         info = batch.info()
-        say(f"  schedule {sb},{pc},{fpc}: {info['front_grid']} {info['decode_grid']} {info['grid']}"
+        say(f"  schedule {sb},{pc},{fpc},{scan}: {info['front_grid']} {info['decode_grid']} {info['grid']}"
             f" ran {info['ran_front_grid']} {info['ran_decode_grid']} {info['ran_grid']}"
             f" graph={info['graph']}")
-        assert info["stage_blocks"] == sb
+        assert info["stage_blocks"] == sb and info["scan_schedule"] == scan
         assert info["ran_front_grid"] == info["front_grid"]
         assert info["ran_decode_grid"] == info["decode_grid"]
         assert info["ran_grid"] == info["grid"]
@@ -212,6 +214,8 @@ def test_batch_schedule_change_recaptures_graph(orc):
         _check(bc, orc, batch, vols, dims_list, decoded, jobs, plain)    # warm replay
         assert batch.info()["ran_front_grid"] == info["front_grid"]
     assert len(seen) >= 3
+    with pytest.raises(bc.BcmcError):
+        batch.set_schedule(8, 4, 4, 2)   # scan schedules are 0 and 1
     batch.close()
 
 
