@@ -256,8 +256,10 @@ __device__ __forceinline__ void stamp_last(const BatchParams &p, int k) {
     }
 }
 
-// Contiguous share [lo, hi) of n items for the calling wave, as
-// xcd_wave_range; returns the share's rank in item order.
+// Contiguous share [lo, hi) of n items for the calling wave: the workgroups
+// of one XCD (blockIdx % 8) take one contiguous eighth of the range, so that
+// blocks whose halos overlap are staged through the same L2; returns the
+// share's rank in item order.
 __device__ __forceinline__ uint32_t wave_share(uint64_t n, uint64_t &lo, uint64_t &hi) {
     const uint32_t G = gridDim.x, g = blockIdx.x;
     const uint32_t logical = (g % 8u) * (G / 8u) + g / 8u;
@@ -609,6 +611,7 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
     // ---- phase 6: each workgroup sums the per-wave totals before its first
     // wave and all of them (no grid barrier: the counts are a kernel earlier)
     for (int i = threadIdx.x; i < 256; i += BT) sh.tab[i] = p.mc_table[i];   // published by the barrier below
+    if (threadIdx.x < 16) sh.emit.edge[threadIdx.x] = edge_entry((int)threadIdx.x);
     const uint32_t W = gridDim.x * (BT / 64), wv0 = wv - (uint32_t)w;
     uint64_t before = 0, all = 0;
     for (uint32_t i0 = threadIdx.x; i0 < W; i0 += 8u * BT) {   // 8 loads in flight at a time

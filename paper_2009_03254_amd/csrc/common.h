@@ -93,7 +93,8 @@ struct DevState {
     uint32_t *part_cand = nullptr;  // per live round: blocks that may emit
     uint32_t *round_list = nullptr; // ascending live rounds of the call
     uint64_t *round_cnt = nullptr;  // per live round: (active << 32 | new) blocks, then their offsets
-    uint64_t *part_wave = nullptr;  // [4 * max MC grid] per-wave vertex totals of the count pass
+    uint64_t *chunk_off = nullptr;  // per 64-entry chunk of the active list: vertices, then first vertex
+                                    // in its XCD eighth; then the 8 eighths' totals
     uint32_t *part_occw = nullptr;  // [4 * max MC grid] per-wave occupied blocks
     uint64_t *status = nullptr;     // look-back status words (all kernels)
     Counters *ctr = nullptr;
@@ -114,6 +115,8 @@ void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl, uint32_t gen,
                            hipStream_t s);
 inline uint64_t block_rounds(uint64_t nb) { return (nb + BLK_TILE - 1) / BLK_TILE; }
+// Chunks of 64 active blocks (the count pass's and emission's unit of work).
+inline uint64_t mc_chunks(uint64_t nb) { return (nb + 63) / 64; }
 // age_cap: exceeds the age of every slot used since the cache was reset.
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
                       uint32_t age_cap, hipStream_t s);

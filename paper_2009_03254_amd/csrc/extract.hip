@@ -740,59 +740,158 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
 }
 
 // Count pass (Sec. 4.4): vertex count of every active block (0 unless it can
-// emit), one lane per block.  The cases of all 64 cells are evaluated at once
-// on the corner masks, and the triangle count per case by the bit-sliced
-// diagram of the marching-cubes table (mc_ntri_bits, generated at build time).
+// emit), one lane per block, over the 64-block chunks of xcd_chunks; each
+// chunk's total goes to chunk_off for k_chunk_scan.  The cases of all 64
+// cells are evaluated at once on the corner masks, and the triangle count per
+// case by the bit-sliced diagram of the marching-cubes table (mc_ntri_bits,
+// generated at build time).
 __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__restrict__ I_active,
                                                  const uint8_t *__restrict__ active,
                                                  const int32_t *__restrict__ I_slot, int identity,
                                                  const uint64_t *__restrict__ masks,
                                                  uint32_t *__restrict__ blk_cnt,
-                                                 uint64_t *__restrict__ part_wave,
+                                                 uint64_t *__restrict__ chunk_off,
                                                  uint32_t *__restrict__ part_occw, Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
-    uint64_t lo, hi;
-    const uint32_t wv = xcd_wave_range(n_act, lo, hi);
-    uint32_t wsum = 0, wocc = 0;
-    for (uint64_t i = lo + lane(); i < hi; i += 64) {
-        const uint32_t b = I_active[i];
+    const ChunkRange cr = xcd_chunks((n_act + 63) / 64);
+    uint32_t wocc = 0;
+    for (uint64_t c = cr.first; c < cr.end; c += cr.stride) {
+        const uint64_t i = c * 64 + lane();
         uint32_t cnt = 0;
-        if (active[b] & 2u) {
+        const uint32_t b = i < n_act ? I_active[i] : 0u;
+        if (i < n_act && (active[b] & 2u)) {
             uint32_t so[8], bx, by, bz;
             if (!octet(g, b, I_slot, identity, so, bx, by, bz)) {
                 atomicOr(&ctr->err, ERR_INTERNAL);
             } else {
-                uint64_t M[8], c[8];
+                uint64_t M[8], cm[8];
 #pragma unroll
                 for (int m = 0; m < 8; m++) M[m] = masks[so[m]];
-                corner_masks(M, c);
+                corner_masks(M, cm);
                 uint64_t n0, n1, n2;
-                mc_ntri_bits(c, n0, n1, n2);
+                mc_ntri_bits(cm, n0, n1, n2);
                 const uint64_t V = valid_cells(g, bx, by, bz);
                 const uint32_t tris = (uint32_t)__popcll(n0 & V) + 2u * (uint32_t)__popcll(n1 & V) +
                                       4u * (uint32_t)__popcll(n2 & V);
                 cnt = 3u * tris;
             }
         }
-        blk_cnt[i] = cnt;
-        wsum += cnt;
+        if (i < n_act) blk_cnt[i] = cnt;
+        const uint32_t tot = wave_sum(cnt);   // the chunk's vertices (k_chunk_scan turns them into offsets)
+        if (lane() == 0) chunk_off[c] = tot;
         wocc += cnt ? 1u : 0u;
     }
-    // per-wave totals in item order (the emission runs on the same grid, so
-    // its waves own the same shares)
-    wsum = wave_sum(wsum);
     wocc = wave_sum(wocc);
-    if (lane() == 0) {
-        part_wave[wv] = wsum;
-        part_occw[wv] = wocc;
+    if (lane() == 0) part_occw[blockIdx.x * MC_WAVES + (threadIdx.x >> 6)] = wocc;
+}
+
+// Sec. 4.4's prefix sum over the block counts, at the granularity of the
+// count pass's 64-block chunks.  Workgroup x < 8 scans the chunk totals of
+// XCD eighth x (the split of xcd_chunks) in place, exclusively, in rounds of
+// 16 K chunks (thread t holds chunks t + 1024 j, j < 16: coalesced loads; a
+// chunk holds at most 64 * 960 vertices, so a round's sums fit 32 bits), and
+// writes the eighth's total to xcd_tot[x] (the emission adds the totals of
+// the eighths before its own).  Workgroup 8 forms the call's occupied and
+// may-emit block counts.
+__global__ __launch_bounds__(1024) void k_chunk_scan(uint64_t *__restrict__ chunk_off,
+                                                    uint64_t *__restrict__ xcd_tot,
+                                                    const uint32_t *__restrict__ part_occw,
+                                                    uint32_t n_waves,
+                                                    const uint32_t *__restrict__ part_cand,
+                                                    Counters *ctr) {
+    constexpr int J = 16;
+    __shared__ uint32_t s_w[J * 16];   // per (j, wave): the wave's total, then its exclusive prefix
+    __shared__ uint32_t s_round;
+    __shared__ uint32_t s_occ[16], s_cand[16];
+    if (ctr->err) return;
+    const int t = threadIdx.x, w = t >> 6, l = lane();
+    if (blockIdx.x < 8) {
+        const uint64_t n = (ctr->n_act + 63) / 64, per = (n + 7) / 8;
+        uint64_t lo = blockIdx.x * per;
+        if (lo > n) lo = n;
+        const uint64_t hi = lo + per < n ? lo + per : n;
+        uint64_t carry = 0;
+        for (uint64_t base = lo; base < hi; base += J * 1024) {
+            uint32_t v[J], inc[J];
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+                const uint64_t i = base + 1024 * (uint64_t)j + t;
+                v[j] = i < hi ? (uint32_t)chunk_off[i] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < J; j++) inc[j] = wave_incl_scan(v[j]);
+            if (l == 63) {
+#pragma unroll
+                for (int j = 0; j < J; j++) s_w[16 * j + w] = inc[j];
+            }
+            __syncthreads();
+            if (w == 0) {   // exclusive scan of the 256 wave totals in chunk order (j, then wave)
+                uint32_t e[4], run = 0;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t x = s_w[4 * l + k];
+                    e[k] = run;
+                    run += x;
+                }
+                const uint32_t incl = wave_incl_scan(run);
+#pragma unroll
+                for (int k = 0; k < 4; k++) s_w[4 * l + k] = incl - run + e[k];
+                if (l == 63) s_round = incl;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+                const uint64_t i = base + 1024 * (uint64_t)j + t;
+                if (i < hi) chunk_off[i] = carry + s_w[16 * j + w] + (inc[j] - v[j]);
+            }
+            carry += s_round;
+            __syncthreads();   // s_w and s_round are rewritten next round
+        }
+        if (t == 0) xcd_tot[blockIdx.x] = carry;
+        return;
+    }
+    // 8 loads in flight per thread (a plain loop waits for each load)
+    uint32_t occ = 0, cand = 0;
+    for (uint32_t i0 = t; i0 < n_waves; i0 += 8 * 1024) {
+        uint32_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) x[j] = i0 + 1024u * j < n_waves ? part_occw[i0 + 1024u * j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; j++) occ += x[j];
+    }
+    const uint64_t n_ct = ctr->n_live_rounds;
+    for (uint64_t i0 = t; i0 < n_ct; i0 += 8 * 1024) {
+        uint32_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) x[j] = i0 + 1024u * j < n_ct ? part_cand[i0 + 1024u * j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; j++) cand += x[j];
+    }
+    occ = wave_sum(occ);
+    cand = wave_sum(cand);
+    if (l == 0) {
+        s_occ[w] = occ;
+        s_cand[w] = cand;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t o = 0, c = 0;
+        for (int k = 0; k < 16; k++) {
+            o += s_occ[k];
+            c += s_cand[k];
+        }
+        ctr->n_occ = o;
+        ctr->n_cand = c;
     }
 }
 
 
-// Emission pass (Sec. 4.5): restage the occupied blocks a few at a time, take
-// each block's in-block prefix of its per-cell triangle counts, list the
-// triangles of the staged blocks together and write them lane per vertex
+// Emission pass (Sec. 4.5), over the chunks of xcd_chunks (the count pass's
+// schedule), each from its scanned offset: the chunk's block offsets by a
+// wave scan of the counts, then the occupied blocks restaged a few at a time;
+// each block's in-block prefix of its per-cell triangle counts, the
+// triangles of the staged blocks listed together and written lane per vertex
 // from the first block's offset, in canonical order (block, cell, triangle,
 // vertex).
 template <int FMT>
@@ -803,85 +902,34 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
                                                 const uint32_t *__restrict__ blk_cnt,
                                                 uint64_t *__restrict__ blk_off,
                                                 void *__restrict__ out, uint64_t cap,
-                                                const uint32_t *__restrict__ part_cand,
-                                                const uint64_t *__restrict__ part_wave,
-                                                const uint32_t *__restrict__ part_occw,
+                                                const uint64_t *__restrict__ chunk_off,
+                                                const uint64_t *__restrict__ xcd_tot,
                                                 Counters *ctr) {
     __shared__ EmitSharedPlain sh;
-    __shared__ uint64_t s_base[MC_WAVES];
     if (ctr->err) return;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];   // the barriers below publish it
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
+    if (threadIdx.x < 16) sh.edge[threadIdx.x] = edge_entry((int)threadIdx.x);
+    __syncthreads();
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    uint64_t lo, hi;
-    const uint32_t wv = xcd_wave_range(n_act, lo, hi);
-    // Sec. 4.4's prefix sum over the block counts, without a pass of its
-    // own: the count pass left per-wave totals for the same shares, and each
-    // workgroup sums those before its waves; workgroup 0 also forms the
-    // call's totals
-    uint64_t before = 0;
-    {
-        const uint32_t W = gridDim.x * MC_WAVES, wv0 = wv - (uint32_t)w;
-        uint64_t all = 0;
-        uint32_t occ = 0;
-        const bool first = blockIdx.x == 0;
-        // 8 loads in flight per thread at a time (a plain loop waits for each
-        // load before the next: ~30 µs for the last workgroups)
-        const uint32_t lim = first ? W : wv0;
-        for (uint32_t i0 = threadIdx.x; i0 < lim; i0 += 8u * blockDim.x) {
-            uint64_t v[8];
-#pragma unroll
-            for (int j = 0; j < 8; j++) {
-                const uint32_t i = i0 + (uint32_t)j * blockDim.x;
-                v[j] = i < lim ? part_wave[i] : 0ull;
-            }
-#pragma unroll
-            for (int j = 0; j < 8; j++) {
-                const uint32_t i = i0 + (uint32_t)j * blockDim.x;
-                if (i < wv0) before += v[j];
-                all += v[j];
-            }
-            if (first) {
-                uint32_t o[8];
-#pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    const uint32_t i = i0 + (uint32_t)j * blockDim.x;
-                    o[j] = i < lim ? part_occw[i] : 0u;
-                }
-#pragma unroll
-                for (int j = 0; j < 8; j++) occ += o[j];
-            }
-        }
-        before = wave_sum(before);
-        if (lane() == 0) s_base[w] = before;
-        __syncthreads();
-        before = s_base[0] + s_base[1] + s_base[2] + s_base[3];
-        __syncthreads();
-        if (first) {
-            const uint64_t n_ct = ctr->n_live_rounds;
-            uint32_t cand = 0;
-            for (uint64_t i = threadIdx.x; i < n_ct; i += blockDim.x) cand += part_cand[i];
-            all = wave_sum(all);
-            if (lane() == 0) s_base[w] = all;
-            cand = wg_sum_u32(cand);
-            occ = wg_sum_u32(occ);   // its barriers also publish s_base
-            if (threadIdx.x == 0) {
-                ctr->n_cand = cand;
-                ctr->n_occ = occ;
-                ctr->total_verts = s_base[0] + s_base[1] + s_base[2] + s_base[3];
-            }
-        }
+    const ChunkRange cr = xcd_chunks((n_act + 63) / 64);
+    // the vertices of the XCD eighths before this workgroup's (the chunk
+    // offsets are local to their eighth); workgroup 0 forms the call's total
+    uint64_t xbase = 0, all = 0;
+    for (uint32_t x = 0; x < 8; x++) {
+        const uint64_t tx = xcd_tot[x];
+        xbase += x < blockIdx.x % 8u ? tx : 0ull;
+        all += tx;
     }
-    uint64_t base = before;   // the wave's first vertex (wave-uniform)
-    for (int k = 0; k < w; k++) base += part_wave[wv - (uint32_t)w + (uint32_t)k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->total_verts = all;
     const LaneGeom q = lane_geom();
-    for (uint64_t i0 = lo; i0 < hi; i0 += 64) {
-        const uint64_t idx = i0 + l;
-        const bool valid = idx < hi;
+    for (uint64_t c = cr.first; c < cr.end; c += cr.stride) {
+        const uint64_t base = xbase + chunk_off[c];   // the chunk's first vertex (wave-uniform)
+        const uint64_t idx = c * 64 + l;
+        const bool valid = idx < n_act;
         const uint32_t cnt = valid ? blk_cnt[idx] : 0u;
         const uint32_t incl = wave_incl_scan(cnt);
         const uint64_t off = base + (incl - cnt);
-        base += __shfl(incl, 63, 64);
         if (valid) blk_off[idx] = off;
         const uint32_t b = cnt ? I_active[idx] : 0u;
         const uint64_t boff = off;
@@ -1146,8 +1194,9 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
 }
 
 
-// The emission's grid; the count pass runs on the same one, so that both
-// give each wave the same share of the active blocks.
+// Grid of the count pass and the emission: as many workgroups as are
+// resident at once (their waves sweep the chunks of the active list as one
+// window), in whole XCD rounds.
 static unsigned emit_grid(const Geom &g, int fmt) {
     static unsigned grid[3] = {0, 0, 0};
     if (!grid[0]) grid[0] = resident_grid(k_mc_emit<VFMT_F32>, ~0ull >> 4);
@@ -1162,9 +1211,11 @@ void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const
     if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
     k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
         d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_iso, d.ctr);
-    k_mc_count<<<emit_grid(g, fmt), 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache,
-                                                   d.masks, d.blk_cnt, d.part_wave, d.part_occw,
-                                                   d.ctr);
+    const unsigned cgrid = emit_grid(g, fmt);
+    k_mc_count<<<cgrid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, d.masks,
+                                     d.blk_cnt, d.chunk_off, d.part_occw, d.ctr);
+    k_chunk_scan<<<9, 1024, 0, s>>>(d.chunk_off, d.chunk_off + mc_chunks(g.nb), d.part_occw,
+                                    cgrid * MC_WAVES, d.part_cand, d.ctr);
 }
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
@@ -1173,8 +1224,8 @@ void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const 
     const unsigned n = emit_grid(g, fmt);
 #define BCMC_EMIT(F)                                                                          \
     k_mc_emit<F><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table, iso, \
-                                   d.blk_cnt, d.blk_off, out, cap_verts, d.part_cand, d.part_wave,  \
-                                   d.part_occw, d.ctr)
+                                   d.blk_cnt, d.blk_off, out, cap_verts, d.chunk_off,              \
+                                   d.chunk_off + mc_chunks(g.nb), d.ctr)
     if (fmt == VFMT_EDGE8) BCMC_EMIT(VFMT_EDGE8);
     else if (fmt == VFMT_Q10) BCMC_EMIT(VFMT_Q10);
     else BCMC_EMIT(VFMT_F32);

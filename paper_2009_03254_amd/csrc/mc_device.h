@@ -408,22 +408,28 @@ __device__ __forceinline__ int tile_case(const Geom &g, uint32_t bx, uint32_t by
     return cs;
 }
 
-// Contiguous share [lo, hi) of n items for the calling wave.  Workgroups are
-// dispatched round-robin over the 8 XCDs (blockIdx % 8); the mapping gives
-// the workgroups of one XCD one contiguous eighth of the range, so blocks
-// whose halos overlap are staged through the same L2.  gridDim.x must be a
-// multiple of 8.
-// Returns the share's rank in item order.
-__device__ __forceinline__ uint32_t xcd_wave_range(uint64_t n, uint64_t &lo, uint64_t &hi) {
+// The chunks of 64 items a wave of a persistent grid takes.  Workgroups are
+// dispatched round-robin over the 8 XCDs (blockIdx % 8): the workgroups of one
+// XCD take one contiguous eighth of the chunks, so that blocks whose halos
+// overlap are staged through the same L2, and that XCD's waves take its
+// chunks in turn (wave r: chunks r, r + W, r + 2 W, ... of the eighth, W its
+// waves), so that they all work in one window that moves along the eighth:
+// a block's +y and +z neighbours are staged at about the same time as the
+// block, and the output is written in a few dense regions instead of one
+// stream per wave.  gridDim.x must be a multiple of 8.
+struct ChunkRange {
+    uint64_t first, end;
+    uint32_t stride;
+};
+__device__ __forceinline__ ChunkRange xcd_chunks(uint64_t n_chunks) {
     const uint32_t G = gridDim.x, g = blockIdx.x;
-    const uint32_t logical = (g % 8u) * (G / 8u) + g / 8u;
-    const uint64_t waves = (uint64_t)G * MC_WAVES;
-    const uint64_t wv = (uint64_t)logical * MC_WAVES + (threadIdx.x >> 6);
-    const uint64_t chunk = (n + waves - 1) / waves;
-    lo = wv * chunk;
-    if (lo > n) lo = n;
-    hi = lo + chunk < n ? lo + chunk : n;
-    return (uint32_t)wv;
+    const uint32_t per_xcd = (G / 8u) * MC_WAVES;                  // waves of one XCD
+    const uint32_t r = (g / 8u) * MC_WAVES + (threadIdx.x >> 6);  // this wave's rank there
+    const uint64_t per = (n_chunks + 7) / 8;
+    uint64_t lo = (uint64_t)(g % 8u) * per;
+    if (lo > n_chunks) lo = n_chunks;
+    const uint64_t hi = lo + per < n_chunks ? lo + per : n_chunks;
+    return {lo + r, hi, per_xcd};
 }
 
 // Corner masks of the 64 cells of a block from the sign masks of the block
@@ -465,22 +471,20 @@ __device__ __forceinline__ uint64_t valid_cells(const Geom &g, uint32_t bx, uint
 }
 
 // Per-edge lookup, 5 bits per edge id e (0..11), built from edge_geom's
-// convention: kEdgeGeom holds ox | oy << 1 | oz << 2 | axis << 3 (first
-// corner offset and axis), kEdgeTile the first corner's offset in the 5^3
-// tile index (ox + 5 oy + 25 oz).
-constexpr uint64_t edge_lut(bool tile_offset) {
+// convention: ox | oy << 1 | oz << 2 | axis << 3 (first corner offset and
+// axis).
+constexpr uint64_t edge_lut() {
     uint64_t r = 0;
     for (int e = 0; e < 12; e++) {
         const int axis = e >> 2, b0 = e & 1, b1 = (e >> 1) & 1;
         const int ox = axis == 0 ? 0 : b0;
         const int oy = axis == 1 ? 0 : (axis == 0 ? b0 : b1);
         const int oz = axis == 2 ? 0 : b1;
-        const int v = tile_offset ? ox + 5 * oy + 25 * oz : (ox | oy << 1 | oz << 2 | axis << 3);
-        r |= (uint64_t)v << (5 * e);
+        r |= (uint64_t)(ox | oy << 1 | oz << 2 | axis << 3) << (5 * e);
     }
     return r;
 }
-constexpr uint64_t kEdgeGeom = edge_lut(false), kEdgeTile = edge_lut(true);
+constexpr uint64_t kEdgeGeom = edge_lut();
 
 // Vertex records are written once and not read back by the path:
 // non-temporal stores.  (Plain stores drain a bare streaming write faster on
@@ -514,12 +518,34 @@ __host__ __device__ __forceinline__ uint32_t q10_code(float x, float y, float z)
     return q10_axis(x) | (q10_axis(y) << 10) | (q10_axis(z) << 20);
 }
 
+// Per-edge entry of the emission's LDS edge table: low word the first
+// corner's offset in the cell as bytes (x, y, z in bytes 0-2, each 0 or 1)
+// plus the tile step along the edge's axis (1, 5 or 25) in byte 3; high word
+// the axis as a unit vector of bytes.  Edges 12-15 are unused (zero).
+__host__ __device__ constexpr uint64_t edge_entry(int e) {
+    if (e >= 12) return 0;
+    const uint32_t d = (uint32_t)(kEdgeGeom >> (5 * e)) & 31u;   // ox | oy << 1 | oz << 2 | axis << 3
+    const uint32_t axis = d >> 3;
+    const uint32_t o = (d & 1u) | ((d >> 1) & 1u) << 8 | ((d >> 2) & 1u) << 16;
+    const uint32_t step = axis == 0 ? 1u : (axis == 1 ? 5u : 25u);
+    return (uint64_t)(o | step << 24) | (uint64_t)(1u << (8 * axis)) << 32;
+}
+// Tile index (x + 5 y + 25 z) of a point given as bytes x | y << 8 | z << 16.
+__device__ __forceinline__ uint32_t tile_index(uint32_t xyz) {
+    return __builtin_amdgcn_udot4(xyz, 0x00190501u, 0u, false);
+}
+// Tile index of the point one step along the axis whose step is in byte 3.
+__device__ __forceinline__ uint32_t tile_index_next(uint32_t xyz_step) {
+    return __builtin_amdgcn_udot4(xyz_step, 0x01190501u, 0u, false);
+}
+
 // Per-wave LDS of the emission: SB staged tiles, the triangle list of the
 // staged blocks and each staged block's id and isovalue.
 template <int SB>
 struct EmitSharedT {
+    uint64_t edge[16];                  // edge_entry(e), read per vertex
     float tiles[MC_WAVES][SB][128];
-    uint32_t tri[MC_WAVES][EMIT_TRIS];  // per triangle: cell | 3 edge ids << 6 | staged block << 18
+    uint32_t tri[MC_WAVES][EMIT_TRIS];  // per triangle: its list record (emit_batch)
     uint32_t blk[MC_WAVES][SB];         // block id of each staged block
     float iso[MC_WAVES][SB];            // its isovalue
 };
@@ -530,6 +556,7 @@ using EmitShared = EmitSharedT<MC_SB>;
 constexpr int EMIT_SB = MC_SB - 2;
 struct EmitSharedPlain {
     uint64_t tab[256];
+    uint64_t edge[16];
     float tiles[MC_WAVES][EMIT_SB][128];
     uint32_t tri[MC_WAVES][EMIT_TRIS];
     uint32_t blk[MC_WAVES][EMIT_SB];
@@ -562,24 +589,26 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
                                            int w, uint64_t base, void *__restrict__ out,
                                            uint64_t cap) {
     const int l = lane();
+    // the lane's cell as bytes x | y << 8 | z << 16
+    const uint32_t cell_xyz = (uint32_t)(l & 3) | (uint32_t)((l >> 2) & 3) << 8 | (uint32_t)(l >> 4) << 16;
     uint32_t run = 0;   // triangles listed
+    // List record of a triangle: the cell as bytes (bits 0-1, 8-9, 16-17),
+    // the staged block in bits 2-4, the 3 edge ids in bits 20-31 (as in the
+    // case table).
     auto flush = [&]() {
         wave_lds_sync();
         const int total = 3 * (int)run;
         for (int j = l; j < total; j += 64) {
             const int t = (j * 43691) >> 17;               // j / 3 for j < 3 * EMIT_TRIS
             const uint32_t rec = sh.tri[w][t];
-            const int c = (int)(rec & 63u);
-            const int e = (int)((rec >> (6 + 4 * (j - 3 * t))) & 15u);
-            const int k = (int)(rec >> 18);
+            const uint32_t e = (rec >> (20 + 4 * (j - 3 * t))) & 15u;
+            const uint32_t k = (rec >> 2) & 7u;
+            const uint64_t ent = sh.edge[e];
+            const uint32_t cxyz = rec & 0x030303u;         // the cell
+            const uint32_t p0 = cxyz + (uint32_t)ent;      // the edge's first corner | step << 24
             const float *tile = tiles[k];
-            const uint32_t d = (uint32_t)(kEdgeGeom >> (5 * e)) & 31u;
-            const int axis = (int)(d >> 3);
-            const int cx = c & 3, cy = (c >> 2) & 3, cz = c >> 4;
-            const int i0 = tix(cx, cy, cz) + (int)((kEdgeTile >> (5 * e)) & 31u);
-            const int i1 = i0 + (int)((0x190501u >> (8 * axis)) & 0xFFu);   // +1 / +5 / +25
-            const float a = tile[i0];
-            const float bv = tile[i1];
+            const float a = tile[tile_index(p0)];
+            const float bv = tile[tile_index_next(p0)];
             const float iso = sh.iso[w][k];
             const uint32_t b = sh.blk[w][k];
             const float tt = (iso - a) / (bv - a);
@@ -587,14 +616,27 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
             if (FMT == VFMT_EDGE8) {
                 uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
                 qt = qt < 4194303u ? qt : 4194303u;
+                const uint32_t c = __builtin_amdgcn_udot4(cxyz, 0x00100401u, 0u, false);   // x + 4 y + 16 z
                 const uint64_t r = (uint64_t)b | ((uint64_t)c << 32) | ((uint64_t)e << 38) | ((uint64_t)qt << 42);
                 if (o < cap) store_record(out, o, r);
             } else {
-                // the edge's first corner plus t along its axis (adding 0 to the
-                // other two coordinates leaves them exact)
-                const float px = (float)(cx + (int)(d & 1u)) + (axis == 0 ? tt : 0.0f);
-                const float py = (float)(cy + (int)((d >> 1) & 1u)) + (axis == 1 ? tt : 0.0f);
-                const float pz = (float)(cz + (int)((d >> 2) & 1u)) + (axis == 2 ? tt : 0.0f);
+                // the first corner plus t along the edge's axis: t * 1 + x
+                // rounds as x + t, and t * 0 + x is x exactly (for finite t)
+                const uint32_t u = (uint32_t)(ent >> 32);
+                const float x0 = (float)(p0 & 0xFFu), y0 = (float)((p0 >> 8) & 0xFFu),
+                            z0 = (float)((p0 >> 16) & 0xFFu);
+                const float ux = (float)(u & 0xFFu), uy = (float)((u >> 8) & 0xFFu),
+                            uz = (float)((u >> 16) & 0xFFu);
+                float px = __builtin_fmaf(tt, ux, x0);
+                float py = __builtin_fmaf(tt, uy, y0);
+                float pz = __builtin_fmaf(tt, uz, z0);
+                if (__builtin_expect(tt != tt, 0)) {
+                    // both differences overflowed (inf / inf): NaN on the
+                    // axis only, the other two coordinates stay the corner's
+                    px = ux != 0.0f ? x0 + tt : x0;
+                    py = uy != 0.0f ? y0 + tt : y0;
+                    pz = uz != 0.0f ? z0 + tt : z0;
+                }
                 if (FMT == VFMT_Q10) {
                     if (o < cap) store_record(out, o, (uint64_t)q10_code(px, py, pz) | ((uint64_t)b << 32));
                 } else {
@@ -621,9 +663,9 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
             sh.blk[w][k] = b;
             sh.iso[w][k] = iso;
         }
+        const uint32_t rec0 = cell_xyz | (uint32_t)k << 2;
         for (uint32_t t = 0; t < nt; t++)
-            sh.tri[w][run + incl - nt + t] =
-                (uint32_t)l | ((uint32_t)(tb >> (12 * t)) & 0xFFFu) << 6 | (uint32_t)k << 18;
+            sh.tri[w][run + incl - nt + t] = rec0 | (uint32_t)(tb >> (12 * t)) << 20;
         run += tot;
     }
     if (run) flush();
