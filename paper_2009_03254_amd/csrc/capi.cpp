@@ -147,7 +147,7 @@ int alloc_common(bcmc_volume *v) {
     if ((rc = dev_alloc(&v->d.part_cand, (v->g.nb + BLK_TILE - 1) / BLK_TILE))) return rc;
     if ((rc = dev_alloc(&v->d.round_list, block_rounds(v->g.nb)))) return rc;
     if ((rc = dev_alloc(&v->d.round_cnt, block_rounds(v->g.nb)))) return rc;
-    if ((rc = dev_alloc(&v->d.chunk_off, mc_chunks(v->g.nb) + 8))) return rc;
+    if ((rc = dev_alloc(&v->d.chunk_off, mc_chunk_slots(v->g.nb) + 8))) return rc;
     if ((rc = dev_alloc(&v->d.part_occw, 4 * MC_MAX_GRID))) return rc;
     if ((rc = dev_alloc(&v->d.ctr, 1))) return rc;
     if ((rc = dev_alloc(&v->d.mc_table, 256))) return rc;
@@ -833,7 +833,7 @@ uint64_t carve_scratch(const Geom &g, const StatusLayout &sl, uintptr_t base, De
     d.part_cand = reinterpret_cast<uint32_t *>(take((g.nb + BLK_TILE - 1) / BLK_TILE * sizeof(uint32_t)));
     d.round_list = reinterpret_cast<uint32_t *>(take(block_rounds(g.nb) * sizeof(uint32_t)));
     d.round_cnt = reinterpret_cast<uint64_t *>(take(block_rounds(g.nb) * sizeof(uint64_t)));
-    d.chunk_off = reinterpret_cast<uint64_t *>(take((mc_chunks(g.nb) + 8) * sizeof(uint64_t)));
+    d.chunk_off = reinterpret_cast<uint64_t *>(take((mc_chunk_slots(g.nb) + 8) * sizeof(uint64_t)));
     d.part_occw = reinterpret_cast<uint32_t *>(take(4 * MC_MAX_GRID * sizeof(uint32_t)));
     d.status = reinterpret_cast<uint64_t *>(take(sl.total * sizeof(uint64_t)));
     return off;

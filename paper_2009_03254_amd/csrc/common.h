@@ -115,8 +115,14 @@ void launch_cull(const Geom &g, const DevState &d, const StatusLayout &sl, float
 void launch_compact_blocks(const Geom &g, const DevState &d, const StatusLayout &sl, uint32_t gen,
                            hipStream_t s);
 inline uint64_t block_rounds(uint64_t nb) { return (nb + BLK_TILE - 1) / BLK_TILE; }
-// Chunks of 64 active blocks (the count pass's and emission's unit of work).
-inline uint64_t mc_chunks(uint64_t nb) { return (nb + 63) / 64; }
+// Chunk entries of the count pass's and emission's chunk totals: a call
+// with n_act active blocks on W waves has ceil(n_act / cs) chunks of
+// cs = min(64, ceil(n_act / W)) blocks (mc_chunk_size), at most
+// max(ceil(nb / 64), W); the 8 XCD totals follow them.
+inline uint64_t mc_chunk_slots(uint64_t nb) {
+    const uint64_t a = (nb + 63) / 64, b = 4ull * MC_MAX_GRID;
+    return a > b ? a : b;
+}
 // age_cap: exceeds the age of every slot used since the cache was reset.
 void launch_slot_pass(const DevState &d, const StatusLayout &sl, uint64_t n_slots_host,
                       uint32_t age_cap, hipStream_t s);

@@ -740,11 +740,11 @@ __global__ __launch_bounds__(256) void k_masks(const uint32_t *__restrict__ I_ac
 }
 
 // Count pass (Sec. 4.4): vertex count of every active block (0 unless it can
-// emit), one lane per block, over the 64-block chunks of xcd_chunks; each
-// chunk's total goes to chunk_off for k_chunk_scan.  The cases of all 64
-// cells are evaluated at once on the corner masks, and the triangle count per
-// case by the bit-sliced diagram of the marching-cubes table (mc_ntri_bits,
-// generated at build time).
+// emit), one lane per block, over the chunks of xcd_chunks (mc_chunk_size
+// blocks each); each chunk's total goes to chunk_off for k_chunk_scan.  The
+// cases of all 64 cells are evaluated at once on the corner masks, and the
+// triangle count per case by the bit-sliced diagram of the marching-cubes
+// table (mc_ntri_bits, generated at build time).
 __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__restrict__ I_active,
                                                  const uint8_t *__restrict__ active,
                                                  const int32_t *__restrict__ I_slot, int identity,
@@ -754,13 +754,15 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
                                                  uint32_t *__restrict__ part_occw, Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
-    const ChunkRange cr = xcd_chunks((n_act + 63) / 64);
+    const uint32_t cs = mc_chunk_size(n_act, gridDim.x * MC_WAVES);
+    const ChunkRange cr = xcd_chunks((n_act + cs - 1) / cs);
     uint32_t wocc = 0;
     for (uint64_t c = cr.first; c < cr.end; c += cr.stride) {
-        const uint64_t i = c * 64 + lane();
+        const uint64_t i = c * cs + lane();
+        const bool in = lane() < (int)cs && i < n_act;
         uint32_t cnt = 0;
-        const uint32_t b = i < n_act ? I_active[i] : 0u;
-        if (i < n_act && (active[b] & 2u)) {
+        const uint32_t b = in ? I_active[i] : 0u;
+        if (in && (active[b] & 2u)) {
             uint32_t so[8], bx, by, bz;
             if (!octet(g, b, I_slot, identity, so, bx, by, bz)) {
                 atomicOr(&ctr->err, ERR_INTERNAL);
@@ -777,7 +779,7 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
                 cnt = 3u * tris;
             }
         }
-        if (i < n_act) blk_cnt[i] = cnt;
+        if (in) blk_cnt[i] = cnt;
         const uint32_t tot = wave_sum(cnt);   // the chunk's vertices (k_chunk_scan turns them into offsets)
         if (lane() == 0) chunk_off[c] = tot;
         wocc += cnt ? 1u : 0u;
@@ -787,9 +789,9 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
 }
 
 // Sec. 4.4's prefix sum over the block counts, at the granularity of the
-// count pass's 64-block chunks.  Workgroup x < 8 scans the chunk totals of
-// XCD eighth x (the split of xcd_chunks) in place, exclusively, in rounds of
-// 16 K chunks (thread t holds chunks t + 1024 j, j < 16: coalesced loads; a
+// count pass's chunks (up to 64 blocks).  Workgroup x < 8 scans the chunk
+// totals of XCD eighth x (the split of xcd_chunks) in place, exclusively, in
+// rounds of 16 K chunks (thread t holds chunks t + 1024 j, j < 16: coalesced loads; a
 // chunk holds at most 64 * 960 vertices, so a round's sums fit 32 bits), and
 // writes the eighth's total to xcd_tot[x] (the emission adds the totals of
 // the eighths before its own).  Workgroup 8 forms the call's occupied and
@@ -807,7 +809,8 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(uint64_t *__restrict__ chun
     if (ctr->err) return;
     const int t = threadIdx.x, w = t >> 6, l = lane();
     if (blockIdx.x < 8) {
-        const uint64_t n = (ctr->n_act + 63) / 64, per = (n + 7) / 8;
+        const uint32_t cs = mc_chunk_size(ctr->n_act, n_waves);
+        const uint64_t n = (ctr->n_act + cs - 1) / cs, per = (n + 7) / 8;
         uint64_t lo = blockIdx.x * per;
         if (lo > n) lo = n;
         const uint64_t hi = lo + per < n ? lo + per : n;
@@ -912,7 +915,8 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
     __syncthreads();
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    const ChunkRange cr = xcd_chunks((n_act + 63) / 64);
+    const uint32_t cs = mc_chunk_size(n_act, gridDim.x * MC_WAVES);
+    const ChunkRange cr = xcd_chunks((n_act + cs - 1) / cs);
     // the vertices of the XCD eighths before this workgroup's (the chunk
     // offsets are local to their eighth); workgroup 0 forms the call's total
     uint64_t xbase = 0, all = 0;
@@ -925,8 +929,8 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
     const LaneGeom q = lane_geom();
     for (uint64_t c = cr.first; c < cr.end; c += cr.stride) {
         const uint64_t base = xbase + chunk_off[c];   // the chunk's first vertex (wave-uniform)
-        const uint64_t idx = c * 64 + l;
-        const bool valid = idx < n_act;
+        const uint64_t idx = c * cs + l;
+        const bool valid = l < (int)cs && idx < n_act;
         const uint32_t cnt = valid ? blk_cnt[idx] : 0u;
         const uint32_t incl = wave_incl_scan(cnt);
         const uint64_t off = base + (incl - cnt);
@@ -1214,7 +1218,7 @@ void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const
     const unsigned cgrid = emit_grid(g, fmt);
     k_mc_count<<<cgrid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, d.masks,
                                      d.blk_cnt, d.chunk_off, d.part_occw, d.ctr);
-    k_chunk_scan<<<9, 1024, 0, s>>>(d.chunk_off, d.chunk_off + mc_chunks(g.nb), d.part_occw,
+    k_chunk_scan<<<9, 1024, 0, s>>>(d.chunk_off, d.chunk_off + mc_chunk_slots(g.nb), d.part_occw,
                                     cgrid * MC_WAVES, d.part_cand, d.ctr);
 }
 
@@ -1225,7 +1229,7 @@ void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const 
 #define BCMC_EMIT(F)                                                                          \
     k_mc_emit<F><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table, iso, \
                                    d.blk_cnt, d.blk_off, out, cap_verts, d.chunk_off,              \
-                                   d.chunk_off + mc_chunks(g.nb), d.ctr)
+                                   d.chunk_off + mc_chunk_slots(g.nb), d.ctr)
     if (fmt == VFMT_EDGE8) BCMC_EMIT(VFMT_EDGE8);
     else if (fmt == VFMT_Q10) BCMC_EMIT(VFMT_Q10);
     else BCMC_EMIT(VFMT_F32);

@@ -408,7 +408,7 @@ __device__ __forceinline__ int tile_case(const Geom &g, uint32_t bx, uint32_t by
     return cs;
 }
 
-// The chunks of 64 items a wave of a persistent grid takes.  Workgroups are
+// The chunks of items (mc_chunk_size) a wave of a persistent grid takes.  Workgroups are
 // dispatched round-robin over the 8 XCDs (blockIdx % 8): the workgroups of one
 // XCD take one contiguous eighth of the chunks, so that blocks whose halos
 // overlap are staged through the same L2, and that XCD's waves take its
@@ -417,6 +417,13 @@ __device__ __forceinline__ int tile_case(const Geom &g, uint32_t bx, uint32_t by
 // a block's +y and +z neighbours are staged at about the same time as the
 // block, and the output is written in a few dense regions instead of one
 // stream per wave.  gridDim.x must be a multiple of 8.
+// Blocks per chunk for n active blocks on `waves` waves: 64 (one per lane)
+// once every wave has at least that many, fewer for small calls, so that
+// every wave still gets work.
+__host__ __device__ __forceinline__ uint32_t mc_chunk_size(uint64_t n, uint32_t waves) {
+    const uint64_t per = (n + waves - 1) / waves;
+    return per >= 64 ? 64u : (per < 1 ? 1u : (uint32_t)per);
+}
 struct ChunkRange {
     uint64_t first, end;
     uint32_t stride;
