@@ -751,10 +751,11 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
                                                  const uint64_t *__restrict__ masks,
                                                  uint32_t *__restrict__ blk_cnt,
                                                  uint64_t *__restrict__ chunk_off,
-                                                 uint32_t *__restrict__ part_occw, Counters *ctr) {
+                                                 uint32_t *__restrict__ part_occw, uint32_t emit_waves,
+                                                 Counters *ctr) {
     if (ctr->err) return;
     const uint64_t n_act = ctr->n_act;
-    const uint32_t cs = mc_chunk_size(n_act, gridDim.x * MC_WAVES);
+    const uint32_t cs = mc_chunk_size(n_act, emit_waves);   // the emission's chunks
     const ChunkRange cr = xcd_chunks((n_act + cs - 1) / cs);
     uint32_t wocc = 0;
     for (uint64_t c = cr.first; c < cr.end; c += cr.stride) {
@@ -799,7 +800,7 @@ __global__ __launch_bounds__(256) void k_mc_count(Geom g, const uint32_t *__rest
 __global__ __launch_bounds__(1024) void k_chunk_scan(uint64_t *__restrict__ chunk_off,
                                                     uint64_t *__restrict__ xcd_tot,
                                                     const uint32_t *__restrict__ part_occw,
-                                                    uint32_t n_waves,
+                                                    uint32_t n_waves, uint32_t emit_waves,
                                                     const uint32_t *__restrict__ part_cand,
                                                     Counters *ctr) {
     constexpr int J = 16;
@@ -809,7 +810,7 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(uint64_t *__restrict__ chun
     if (ctr->err) return;
     const int t = threadIdx.x, w = t >> 6, l = lane();
     if (blockIdx.x < 8) {
-        const uint32_t cs = mc_chunk_size(ctr->n_act, n_waves);
+        const uint32_t cs = mc_chunk_size(ctr->n_act, emit_waves);
         const uint64_t n = (ctr->n_act + cs - 1) / cs, per = (n + 7) / 8;
         uint64_t lo = blockIdx.x * per;
         if (lo > n) lo = n;
@@ -1198,9 +1199,9 @@ void launch_radix(const DevState &d, const StatusLayout &sl, uint64_t max_elems,
 }
 
 
-// Grid of the count pass and the emission: as many workgroups as are
-// resident at once (their waves sweep the chunks of the active list as one
-// window), in whole XCD rounds.
+// Grid of the emission: as many workgroups as are resident at once (their
+// waves sweep the chunks of the active list as one window), in whole XCD
+// rounds.  Its wave count also sets the chunk size (mc_chunk_size).
 static unsigned emit_grid(const Geom &g, int fmt) {
     static unsigned grid[3] = {0, 0, 0};
     if (!grid[0]) grid[0] = resident_grid(k_mc_emit<VFMT_F32>, ~0ull >> 4);
@@ -1215,11 +1216,15 @@ void launch_mc_count(const Geom &g, const DevState &d, const float *slots, const
     if (!mgrid) mgrid = resident_grid(k_masks, ~0ull >> 4);
     k_masks<<<std::min<unsigned>(mgrid, mc_grid(g.nb / 16 + 1)), 256, 0, s>>>(
         d.I_active, I_slot, identity_cache, slots, iso, d.masks, d.mask_iso, d.ctr);
-    const unsigned cgrid = emit_grid(g, fmt);
+    // the count pass takes the emission's chunks on a grid of its own (all
+    // of it resident)
+    static unsigned cres = 0;
+    if (!cres) cres = std::min<unsigned>(resident_grid(k_mc_count, ~0ull >> 4), MC_MAX_GRID);
+    const unsigned egrid = emit_grid(g, fmt), cgrid = std::min<unsigned>(cres, mc_grid(g.nb));
     k_mc_count<<<cgrid, 256, 0, s>>>(g, d.I_active, d.active, I_slot, identity_cache, d.masks,
-                                     d.blk_cnt, d.chunk_off, d.part_occw, d.ctr);
+                                     d.blk_cnt, d.chunk_off, d.part_occw, egrid * MC_WAVES, d.ctr);
     k_chunk_scan<<<9, 1024, 0, s>>>(d.chunk_off, d.chunk_off + mc_chunk_slots(g.nb), d.part_occw,
-                                    cgrid * MC_WAVES, d.part_cand, d.ctr);
+                                    cgrid * MC_WAVES, egrid * MC_WAVES, d.part_cand, d.ctr);
 }
 
 void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const int32_t *I_slot,
