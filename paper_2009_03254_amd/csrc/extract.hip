@@ -369,33 +369,50 @@ __global__ __launch_bounds__(256) void k_round_scan(uint64_t *__restrict__ round
     }
 }
 
-// Each live round's active and new block ids, from its offsets on
-// (workgroup exclusive scan of the threads' counts).
+// Each live round's active and new block ids, from its offsets on.  A wave
+// takes 1024 consecutive flags of the round (16 per lane, one 16-byte load),
+// puts them in LDS and writes the ids 64 blocks at a time: lane l takes block
+// 64 j + l, a ballot orders the wave's ids, and each store covers one
+// contiguous run of the lists.
 __global__ __launch_bounds__(256) void k_compact_blocks(Geom g, const uint8_t *__restrict__ active,
                                                        const uint32_t *__restrict__ round_list,
                                                        const uint64_t *__restrict__ round_off,
                                                        uint32_t *__restrict__ I_active,
                                                        uint32_t *__restrict__ I_new, const Counters *ctr) {
     __shared__ uint32_t s_w[4];
+    __shared__ uint4 s_fl[4][64];   // per wave: its 1024 flags in block order
     const uint64_t n_live = ctr->n_live_rounds;
-    const int w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6, l = lane();
     for (uint64_t k = blockIdx.x; k < n_live; k += gridDim.x) {
-        const uint64_t base = (uint64_t)round_list[k] * BLK_TILE + 16u * threadIdx.x;
+        const uint64_t wbase = (uint64_t)round_list[k] * BLK_TILE + 1024u * w;
         const uint64_t off = round_off[k];
+        const uint4 q = load_flags16(active, wbase + 16u * l, g.nb);
         uint32_t actb, newb, unused = 0;
-        flag_bits(load_flags16(active, base, g.nb), actb, newb, unused);
-        const uint32_t packed = ((uint32_t)__popc(actb) << 16) | (uint32_t)__popc(newb);
-        const uint32_t incl = wave_incl_scan(packed);   // fields < 2^13 each
-        if (lane() == 63) s_w[w] = incl;
+        flag_bits(q, actb, newb, unused);
+        const uint32_t tot = wave_sum(((uint32_t)__popc(actb) << 16) | (uint32_t)__popc(newb));   // < 2^11 each
+        if (l == 0) s_w[w] = tot;
+        s_fl[w][l] = q;
         __syncthreads();
-        uint32_t ex = incl - packed;
+        uint32_t ex = 0;
 #pragma unroll
         for (int i = 0; i < 4; i++)
             if (i < w) ex += s_w[i];
         uint64_t pa = (off >> 32) + (ex >> 16), pn = (off & 0xFFFFFFFFull) + (ex & 0xFFFFu);
-        for (uint32_t mm = actb; mm; mm &= mm - 1) I_active[pa++] = (uint32_t)(base + __builtin_ctz(mm));
-        for (uint32_t mm = newb; mm; mm &= mm - 1) I_new[pn++] = (uint32_t)(base + __builtin_ctz(mm));
-        __syncthreads();   // s_w is rewritten by the next round
+        if (tot) {
+            const uint8_t *fl = reinterpret_cast<const uint8_t *>(s_fl[w]);
+#pragma unroll 4
+            for (int j = 0; j < 16; j++) {
+                const uint32_t f = fl[64 * j + l];
+                const bool a = (f & 7u) != 0, nw = (f & 4u) != 0;   // any flag bit marks an active block
+                const uint64_t am = __ballot(a), nm = __ballot(nw);
+                const uint32_t blk = (uint32_t)(wbase + 64u * j + (uint32_t)l);
+                if (a) I_active[pa + mbcnt(am)] = blk;
+                if (nw) I_new[pn + mbcnt(nm)] = blk;
+                pa += (uint64_t)__popcll(am);
+                pn += (uint64_t)__popcll(nm);
+            }
+        }
+        __syncthreads();   // s_w and s_fl are rewritten by the next round
     }
 }
 
