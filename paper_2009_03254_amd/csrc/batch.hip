@@ -423,7 +423,7 @@ __global__ __launch_bounds__(BT) void k_batch_front(BatchParams p) {
 
         // L: each wave walks its share of the flag words again, 64 words per
         // step, placing the pairs by a wave scan of the per-word counts.
-        const uint32_t wv = wave_share(n_words, lo, hi);
+        wave_share(n_words, lo, hi);
         uint64_t base = list_off;
         SegCursor cur;
         cur.reset();

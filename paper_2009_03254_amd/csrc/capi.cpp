@@ -149,6 +149,7 @@ int alloc_common(bcmc_volume *v) {
     if ((rc = dev_alloc(&v->d.round_cnt, block_rounds(v->g.nb)))) return rc;
     if ((rc = dev_alloc(&v->d.chunk_off, mc_chunk_slots(v->g.nb) + 8))) return rc;
     if ((rc = dev_alloc(&v->d.part_occw, 4 * MC_MAX_GRID))) return rc;
+    if ((rc = dev_alloc(&v->d.part_giso, 4 * MC_MAX_GRID))) return rc;
     if ((rc = dev_alloc(&v->d.ctr, 1))) return rc;
     if ((rc = dev_alloc(&v->d.mc_table, 256))) return rc;
     if (mc_table_status() != 0) return invalid("marching cubes table generation failed");
@@ -180,6 +181,7 @@ void destroy(bcmc_volume *v) {
     dev_free(v->d.round_cnt);
     dev_free(v->d.chunk_off);
     dev_free(v->d.part_occw);
+    dev_free(v->d.part_giso);
     dev_free(v->d.ctr);
     dev_free(v->d.mc_table);
     if (v->h_ctr) (void)hipHostFree(v->h_ctr);
@@ -532,7 +534,7 @@ int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_t n_verts
     BCMC_HIP_TRY(hipMemsetAsync(d_diso, 0, sizeof(float), s));
     if (!n_verts) return BCMC_OK;
     BCMC_HIP_TRY(hipMemsetAsync(&v->d.ctr->err, 0, sizeof(unsigned int), s));
-    launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, d_dfield, d_diso, v->g.nb, s);
+    launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, n_verts, d_dfield, d_diso, v->vertex_format, s);
     BCMC_HIP_TRY(hipGetLastError());
     // the kernel compares each block's vertex count with the forward's
     BCMC_HIP_TRY(hipMemcpyAsync(&v->h_ctr->err, &v->d.ctr->err, sizeof(unsigned int),

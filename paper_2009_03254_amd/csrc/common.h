@@ -96,6 +96,7 @@ struct DevState {
     uint64_t *chunk_off = nullptr;  // per 64-entry chunk of the active list: vertices, then first vertex
                                     // in its XCD eighth; then the 8 eighths' totals
     uint32_t *part_occw = nullptr;  // [4 * max MC grid] per-wave occupied blocks
+    float *part_giso = nullptr;     // [4 * max MC grid] per-wave dL/diso of the backward
     uint64_t *status = nullptr;     // look-back status words (all kernels)
     Counters *ctr = nullptr;
     uint64_t *mc_table = nullptr;   // 256 packed cases
@@ -143,7 +144,7 @@ void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
                         const int32_t *I_slot, int identity_cache, float iso, uint8_t *cases,
                         uint64_t max_act, hipStream_t s);
 void launch_backward(const Geom &g, const DevState &d, const float *slots, float iso,
-                     const float *gV, float *dfield, float *diso, uint64_t max_act,
+                     const float *gV, uint64_t n_verts, float *dfield, float *diso, int fmt,
                      hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_age_slots(uint32_t *S_age, uint64_t n, uint32_t k, hipStream_t s);

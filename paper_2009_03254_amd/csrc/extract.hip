@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "mc_device.h"
@@ -916,7 +917,7 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(uint64_t *__restrict__ chun
 // from the first block's offset, in canonical order (block, cell, triangle,
 // vertex).
 template <int FMT>
-__global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
+__global__ __launch_bounds__(256, FMT == VFMT_GRAD ? 5 : 8) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
                                                 const int32_t *__restrict__ I_slot, int identity,
                                                 const float *__restrict__ slots,
                                                 const uint64_t *__restrict__ mc_table, float iso,
@@ -925,16 +926,31 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
                                                 void *__restrict__ out, uint64_t cap,
                                                 const uint64_t *__restrict__ chunk_off,
                                                 const uint64_t *__restrict__ xcd_tot,
-                                                Counters *ctr) {
-    __shared__ EmitSharedPlain sh;
+                                                uint32_t chunk_waves, Counters *ctr,
+                                                const float *__restrict__ gV = nullptr,
+                                                float *__restrict__ dfield = nullptr,
+                                                float *__restrict__ part_giso = nullptr) {
+    __shared__ std::conditional_t<FMT == VFMT_GRAD, EmitSharedGrad, EmitSharedPlain> sh;
     if (ctr->err) return;
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
     if (threadIdx.x < 16) sh.edge[threadIdx.x] = edge_entry((int)threadIdx.x);
+    if constexpr (FMT == VFMT_GRAD) {
+        for (int i = threadIdx.x; i < MC_WAVES * EMIT_SB * 128; i += blockDim.x) (&sh.acc[0][0][0])[i] = 0.0f;
+    }
     __syncthreads();
     const uint64_t n_act = ctr->n_act;
     const int w = threadIdx.x >> 6, l = lane();
-    const uint32_t cs = mc_chunk_size(n_act, gridDim.x * MC_WAVES);
+    const uint32_t cs = mc_chunk_size(n_act, chunk_waves);   // the count pass's chunks
     const ChunkRange cr = xcd_chunks((n_act + cs - 1) / cs);
+    GradCtx gc;
+    if constexpr (FMT == VFMT_GRAD) {
+        gc.gV = gV;
+        gc.dfield = dfield;
+        gc.err = &ctr->err;
+        gc.nbx = g.nbx;
+        gc.nbxy = g.nbx * g.nby;
+        gc.giso = 0.0f;
+    }
     // the vertices of the XCD eighths before this workgroup's (the chunk
     // offsets are local to their eighth); workgroup 0 forms the call's total
     uint64_t xbase = 0, all = 0;
@@ -986,8 +1002,33 @@ __global__ __launch_bounds__(256, 8) void k_mc_emit(Geom g, const uint32_t *__re
                 bz = bcast(lbz, jl[k]);
                 isok = iso;
             };
-            emit_batch<FMT>(nsb, info, sh.tiles[w], sh.tab, sh, w, ob, out, cap);
+            if constexpr (FMT == VFMT_GRAD) {
+#pragma unroll
+                for (int k = 0; k < EMIT_SB; k++) gc.expect[k] = bcast(cnt, jl[k]);
+            }
+            emit_batch<FMT>(nsb, info, sh.tiles[w], sh.tab, sh, w, ob, out, cap, &gc);
         }
+    }
+    if constexpr (FMT == VFMT_GRAD) {   // the wave's share of dL/diso (summed by k_sum_f32: no
+                                        // same-address atomics, a fixed order)
+        const float gi = wave_sum(gc.giso);
+        if (l == 0) part_giso[blockIdx.x * MC_WAVES + w] = gi;
+    }
+}
+
+// out = sum of p[0..n) in a fixed order (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_sum_f32(const float *__restrict__ p, uint32_t n,
+                                                 float *__restrict__ out) {
+    __shared__ float s_w[16];
+    float v = 0.0f;
+    for (uint32_t i = threadIdx.x; i < n; i += 1024) v += p[i];
+    v = wave_sum(v);
+    if (lane() == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int k = 0; k < 16; k++) t += s_w[k];
+        *out = t;
     }
 }
 
@@ -1019,68 +1060,6 @@ __global__ __launch_bounds__(256) void k_debug_cases(Geom g, const uint32_t *__r
         }
         cases[i * 64 + lane()] = (uint8_t)(cs < 0 ? 0 : cs);
     }
-}
-
-// Backward of the vertex positions through t = (iso - a)/(b - a), topology
-// fixed: for a vertex on an edge along axis e with dL/dv = gV,
-//   dL/dt = gV[e];  dL/da += dL/dt (t-1)/(b-a);  dL/db += dL/dt (-t)/(b-a);
-//   dL/diso += dL/dt / (b-a).
-// Recomputes the forward's per-block layout (same cells, same order) and
-// scatters into the block-layout field gradient.
-__global__ __launch_bounds__(256) void k_backward(Geom g, const uint32_t *__restrict__ I_active,
-                                                 const float *__restrict__ slots,
-                                                 const uint64_t *__restrict__ mc_table, float iso,
-                                                 const uint32_t *__restrict__ blk_cnt,
-                                                 const uint64_t *__restrict__ blk_off,
-                                                 const float *__restrict__ gV,
-                                                 float *__restrict__ dfield, float *diso,
-                                                 Counters *ctr) {
-    __shared__ McShared sh;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) sh.tab[i] = mc_table[i];
-    __syncthreads();
-    const uint64_t n_act = ctr->n_act;
-    const int w = threadIdx.x >> 6, l = lane();
-    const uint64_t waves = (uint64_t)gridDim.x * MC_WAVES;
-    const float *tile = sh.tile[w];
-    float giso = 0.0f;
-    for (uint64_t i = (uint64_t)blockIdx.x * MC_WAVES + w; i < n_act; i += waves) {
-        const uint32_t cnt = blk_cnt[i];
-        if (cnt == 0) continue;
-        const uint32_t b = I_active[i];
-        const uint64_t base = blk_off[i];
-        Halo h;
-        int total = block_layout(g, b, nullptr, 1, slots, iso, sh, w, h);
-        if ((uint32_t)total != cnt) {
-            // the field changed since the forward pass: its topology (and the
-            // gradient's vertex ranges) no longer hold; stay inside the
-            // forward's range and report
-            if (l == 0) atomicOr(&ctr->err, ERR_INTERNAL);
-            total = (uint32_t)total < cnt ? total : (int)cnt;
-        }
-        for (int j = l; j < total; j += 64) {
-            const int c = sh.map[w][j];
-            const int k = j - (int)sh.pref[w][c];
-            const int e = (int)((sh.tab[sh.cs[w][c]] >> (4 * k)) & 15u);
-            int ox, oy, oz, axis;
-            edge_geom(e, ox, oy, oz, axis);
-            const int x0 = (c & 3) + ox, y0 = ((c >> 2) & 3) + oy, z0 = (c >> 4) + oz;
-            const int x1 = x0 + (axis == 0), y1 = y0 + (axis == 1), z1 = z0 + (axis == 2);
-            const float a = tile[tix(x0, y0, z0)];
-            const float bv = tile[tix(x1, y1, z1)];
-            const float inv = 1.0f / (bv - a);
-            const float tt = (iso - a) * inv;
-            const float gt = gV[3 * (base + j) + axis];
-            // sample (x,y,z) of the 5^3 tile -> block id and local index
-            const uint32_t na = (h.bx + (x0 >> 2)) + g.nbx * ((h.by + (y0 >> 2)) + g.nby * (h.bz + (z0 >> 2)));
-            const uint32_t nb = (h.bx + (x1 >> 2)) + g.nbx * ((h.by + (y1 >> 2)) + g.nby * (h.bz + (z1 >> 2)));
-            atomicAdd(&dfield[(uint64_t)na * 64 + (x0 & 3) + 4 * (y0 & 3) + 16 * (z0 & 3)], gt * (tt - 1.0f) * inv);
-            atomicAdd(&dfield[(uint64_t)nb * 64 + (x1 & 3) + 4 * (y1 & 3) + 16 * (z1 & 3)], -gt * tt * inv);
-            giso += gt * inv;
-        }
-        wave_lds_sync();
-    }
-    giso = wave_sum(giso);
-    if (l == 0 && giso != 0.0f) atomicAdd(diso, giso);
 }
 
 // Plain streaming copy (16 B per lane per iteration): a known-size reference
@@ -1251,7 +1230,7 @@ void launch_mc_emit(const Geom &g, const DevState &d, const float *slots, const 
 #define BCMC_EMIT(F)                                                                          \
     k_mc_emit<F><<<n, 256, 0, s>>>(g, d.I_active, I_slot, identity_cache, slots, d.mc_table, iso, \
                                    d.blk_cnt, d.blk_off, out, cap_verts, d.chunk_off,              \
-                                   d.chunk_off + mc_chunk_slots(g.nb), d.ctr)
+                                   d.chunk_off + mc_chunk_slots(g.nb), n * MC_WAVES, d.ctr)
     if (fmt == VFMT_EDGE8) BCMC_EMIT(VFMT_EDGE8);
     else if (fmt == VFMT_Q10) BCMC_EMIT(VFMT_Q10);
     else BCMC_EMIT(VFMT_F32);
@@ -1282,11 +1261,24 @@ void launch_debug_cases(const Geom &g, const DevState &d, const float *slots,
                                                     slots, iso, cases, d.ctr);
 }
 
+// Backward of the vertex positions through t = (iso - a)/(b - a), topology
+// fixed: the emission's pass over the last extract's soup (same chunks and
+// offsets) in VFMT_GRAD mode, which for a vertex on an edge along axis e
+// with g = dL/dv[e] adds g (t - 1)/(b - a) to dL/da, -g t/(b - a) to dL/db
+// and g/(b - a) to dL/diso (float atomics into the field through per-block
+// LDS sums; dL/diso by per-wave partial sums).  fmt: the extract's vertex
+// format (its grid set the chunks).
 void launch_backward(const Geom &g, const DevState &d, const float *slots, float iso,
-                     const float *gV, float *dfield, float *diso, uint64_t max_act,
+                     const float *gV, uint64_t n_verts, float *dfield, float *diso, int fmt,
                      hipStream_t s) {
-    k_backward<<<mc_grid(max_act), 256, 0, s>>>(g, d.I_active, slots, d.mc_table, iso, d.blk_cnt,
-                                                 d.blk_off, gV, dfield, diso, d.ctr);
+    static unsigned grid = 0;
+    if (!grid) grid = resident_grid(k_mc_emit<VFMT_GRAD>, ~0ull >> 4);
+    const unsigned n = std::min<unsigned>(grid, mc_grid(g.nb));
+    k_mc_emit<VFMT_GRAD><<<n, 256, 0, s>>>(g, d.I_active, nullptr, 1, slots, d.mc_table, iso, d.blk_cnt,
+                                          d.blk_off, nullptr, n_verts, d.chunk_off,
+                                          d.chunk_off + mc_chunk_slots(g.nb),
+                                          emit_grid(g, fmt) * MC_WAVES, d.ctr, gV, dfield, d.part_giso);
+    k_sum_f32<<<1, 1024, 0, s>>>(d.part_giso, n * MC_WAVES, diso);
 }
 
 void launch_copy_calibration(void *dst, const void *src, uint64_t n16, hipStream_t s) {

@@ -257,35 +257,6 @@ __device__ __forceinline__ void edge_geom(int e, int &ox, int &oy, int &oz, int 
     oz = axis == 2 ? 0 : b1;
 }
 
-struct McShared {
-    uint64_t tab[256];
-    float tile[MC_WAVES][128];
-    uint32_t pref[MC_WAVES][64];
-    uint8_t cs[MC_WAVES][64];
-    uint8_t map[MC_WAVES][64 * 15];
-};
-
-// Stage block b, classify its cells and lay out its vertices in LDS:
-// pref = exclusive prefix of per-cell vertex counts, map[v] = cell of
-// vertex v.  Returns the block's vertex count (-1 on an internal error).
-__device__ __forceinline__ int block_layout(const Geom &g, uint32_t b, const int32_t *__restrict__ I_slot,
-                                            int identity, const float *__restrict__ slots, float iso,
-                                            McShared &sh, int w, Halo &h) {
-    const int l = lane();
-    halo_setup(g, b, I_slot, identity, h);
-    if (h.bad) return -1;
-    stage_tile(g, h, slots, sh.tile[w]);
-    wave_lds_sync();
-    const int cs = cell_case(g, h, sh.tile[w], iso);
-    const uint32_t nv = cs < 0 ? 0u : 3u * (uint32_t)(sh.tab[cs] >> 60);
-    const uint32_t incl = wave_incl_scan(nv);
-    sh.pref[w][l] = incl - nv;
-    sh.cs[w][l] = (uint8_t)(cs < 0 ? 0 : cs);
-    for (uint32_t k = 0; k < nv; k++) sh.map[w][incl - nv + k] = (uint8_t)l;
-    wave_lds_sync();
-    return (int)__shfl(incl, 63, 64);
-}
-
 // ---- batched staging ------------------------------------------------------
 // A wave takes 64 consecutive active blocks at a time (one per lane): each lane
 // resolves the cache slots of its block and the block's 7 positive neighbours
@@ -510,6 +481,10 @@ constexpr int EMIT_TRIS = 64 * 5;   // a wave's triangle list (one block's maxim
 
 // Output record formats of the emission.
 enum : int { VFMT_F32 = 0, VFMT_EDGE8 = 1, VFMT_Q10 = 2 };
+// Not an output format: the emission's pass over the soup of the last
+// extract, accumulating the gradient of a loss on the vertex positions
+// (GradCtx) instead of writing records.
+constexpr int VFMT_GRAD = 3;
 
 // Sec. 4.5's vertex: each block-relative coordinate (in [0, 4]) quantised to
 // 10 bits, q = trunc(x * (1023 / 4) + 1/2) (round to nearest, in float32,
@@ -561,6 +536,40 @@ using EmitShared = EmitSharedT<MC_SB>;
 // LDS (a per-lane lookup per block that global memory serves only after the
 // staged slots have evicted it from L1): its LDS then fits 8 workgroups per CU.
 constexpr int EMIT_SB = MC_SB - 2;
+
+// The backward's LDS: the plain emission's, and per staged block the
+// gradient accumulated at each of its 125 tile samples (added to the field
+// once per block instead of once per vertex and corner).
+struct EmitSharedGrad {
+    uint64_t tab[256];
+    uint64_t edge[16];
+    float tiles[MC_WAVES][EMIT_SB][128];
+    uint32_t tri[MC_WAVES][EMIT_TRIS];
+    uint32_t blk[MC_WAVES][EMIT_SB];
+    float iso[MC_WAVES][EMIT_SB];
+    float acc[MC_WAVES][EMIT_SB][128];
+};
+
+// The backward's side of emit_batch<VFMT_GRAD>: dL/dv per vertex (3 floats,
+// in the soup's order), the field's gradient in block layout, the staged
+// blocks' vertex counts of the forward (a block whose recomputed count
+// differs sets ERR_INTERNAL: the field changed), and the lane's share of
+// dL/diso.
+struct GradCtx {
+    const float *gV;
+    float *dfield;
+    unsigned int *err;
+    uint32_t nbx, nbxy;           // blocks per row and per layer
+    uint32_t expect[MC_SB];
+    float giso;
+};
+// Index in the block-layout field of the sample at tile position p (bytes
+// x | y << 8 | z << 16, 0..4 each) of the staged block b.
+__device__ __forceinline__ uint64_t tile_sample(const GradCtx &gc, uint32_t b, uint32_t p) {
+    const uint32_t x = p & 0xFFu, y = (p >> 8) & 0xFFu, z = (p >> 16) & 0xFFu;
+    const uint64_t blk = (uint64_t)b + (x >> 2) + (uint64_t)gc.nbx * (y >> 2) + (uint64_t)gc.nbxy * (z >> 2);
+    return blk * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3);
+}
 struct EmitSharedPlain {
     uint64_t tab[256];
     uint64_t edge[16];
@@ -594,11 +603,25 @@ template <int FMT, class Info, class SH>
 __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*tiles)[128],
                                            const uint64_t *__restrict__ mc_table, SH &sh,
                                            int w, uint64_t base, void *__restrict__ out,
-                                           uint64_t cap) {
+                                           uint64_t cap, GradCtx *gc = nullptr) {
     const int l = lane();
     // the lane's cell as bytes x | y << 8 | z << 16
     const uint32_t cell_xyz = (uint32_t)(l & 3) | (uint32_t)((l >> 2) & 3) << 8 | (uint32_t)(l >> 4) << 16;
     uint32_t run = 0;   // triangles listed
+    // backward: dL/dv of the lane's next vertex, loaded one pass ahead (the
+    // first pass's while the blocks are classified)
+    float gpre[3] = {0.0f, 0.0f, 0.0f};
+    auto gload = [&](uint64_t o) {
+        if constexpr (FMT == VFMT_GRAD) {
+            if (o < cap) {
+                const float *q = gc->gV + 3 * o;
+                gpre[0] = q[0];
+                gpre[1] = q[1];
+                gpre[2] = q[2];
+            }
+        }
+    };
+    gload(base + (uint64_t)l);
     // List record of a triangle: the cell as bytes (bits 0-1, 8-9, 16-17),
     // the staged block in bits 2-4, the 3 edge ids in bits 20-31 (as in the
     // case table).
@@ -606,6 +629,8 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
         wave_lds_sync();
         const int total = 3 * (int)run;
         for (int j = l; j < total; j += 64) {
+            const float gcur[3] = {gpre[0], gpre[1], gpre[2]};   // dL/dv of vertex base + j (backward)
+            if (j + 64 < total) gload(base + (uint64_t)(j + 64));
             const int t = (j * 43691) >> 17;               // j / 3 for j < 3 * EMIT_TRIS
             const uint32_t rec = sh.tri[w][t];
             const uint32_t e = (rec >> (20 + 4 * (j - 3 * t))) & 15u;
@@ -620,7 +645,23 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
             const uint32_t b = sh.blk[w][k];
             const float tt = (iso - a) / (bv - a);
             const uint64_t o = base + (uint64_t)j;
-            if (FMT == VFMT_EDGE8) {
+            if constexpr (FMT == VFMT_GRAD) {
+                // t = (iso - a) / (b - a): dt/da = (t - 1) / (b - a),
+                // dt/db = -t / (b - a), dt/diso = 1 / (b - a), times dL/dv
+                // along the edge's axis; the corners' shares go to the
+                // staged block's LDS accumulators
+                (void)b;
+                if (o < cap) {
+                    const uint32_t u = (uint32_t)(ent >> 32);
+                    const uint32_t axis = __builtin_amdgcn_udot4(u, 0x00020100u, 0u, false);
+                    const float gt = axis == 0 ? gcur[0] : (axis == 1 ? gcur[1] : gcur[2]);
+                    const float inv = 1.0f / (bv - a);
+                    const float t2 = (iso - a) * inv;
+                    atomicAdd(&sh.acc[w][k][tile_index(p0)], gt * (t2 - 1.0f) * inv);
+                    atomicAdd(&sh.acc[w][k][tile_index_next(p0)], -gt * t2 * inv);
+                    gc->giso += gt * inv;
+                }
+            } else if (FMT == VFMT_EDGE8) {
                 uint32_t qt = (uint32_t)(tt * 4194304.0f);   // t * 2^22 is exact
                 qt = qt < 4194303u ? qt : 4194303u;
                 const uint32_t c = __builtin_amdgcn_udot4(cxyz, 0x00100401u, 0u, false);   // x + 4 y + 16 z
@@ -653,6 +694,7 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
         }
         base += (uint64_t)total;
         run = 0;
+        gload(base + (uint64_t)l);   // for a further pass over the list
         wave_lds_sync();
     };
     for (int k = 0; k < nsb; k++) {
@@ -665,6 +707,7 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
         const uint32_t nt = (uint32_t)(tb >> 60);
         const uint32_t incl = wave_incl_scan(nt);
         const uint32_t tot = __shfl(incl, 63, 64);
+        if (FMT == VFMT_GRAD && 3 * tot != gc->expect[k] && l == 0) atomicOr(gc->err, ERR_INTERNAL);
         if (run + tot > (uint32_t)EMIT_TRIS) flush();
         if (l == 0) {
             sh.blk[w][k] = b;
@@ -677,6 +720,23 @@ __device__ __forceinline__ void emit_batch(int nsb, const Info &info, float (*ti
     }
     if (run) flush();
     else wave_lds_sync();   // the caller restages the tiles next
+    if constexpr (FMT == VFMT_GRAD) {
+        // each staged block's accumulated samples into the field (one
+        // atomic per touched sample), the accumulators back to zero
+        for (int k = 0; k < nsb; k++) {
+            const uint32_t b = sh.blk[w][k];
+            for (int i = l; i < 125; i += 64) {
+                const float v = sh.acc[w][k][i];
+                if (v != 0.0f) {
+                    const uint32_t z = (uint32_t)i / 25u, y = ((uint32_t)i - 25u * z) / 5u,
+                                   x = (uint32_t)i - 25u * z - 5u * y;
+                    atomicAdd(&gc->dfield[tile_sample(*gc, b, x | y << 8 | z << 16)], v);
+                    sh.acc[w][k][i] = 0.0f;
+                }
+            }
+        }
+        wave_lds_sync();
+    }
 }
 
 }  // namespace

@@ -80,32 +80,58 @@ __global__ __launch_bounds__(256) void k_decode_ranges(Geom g, const uint64_t *_
 __global__ __launch_bounds__(256) void k_ranges_from_blocks(Geom g, const float *__restrict__ blocks,
                                                            float2 *__restrict__ ranges,
                                                            unsigned int *err) {
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < g.nb;
-         b += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t bx, by, bz;
-        block_xyz(g, b, bx, by, bz);
-        uint32_t vx = min(4u, g.nx - 4 * bx), vy = min(4u, g.ny - 4 * by), vz = min(4u, g.nz - 4 * bz);
-        const float4 *src = reinterpret_cast<const float4 *>(blocks + b * 64);
-        float lo = INFINITY, hi = -INFINITY;
-        bool finite = true;
-#pragma unroll
+    // a wave takes 64 consecutive blocks at a time, lane l the l-th (its
+    // valid extent); the blocks' 16 KB are read 1 KB per load (in step q,
+    // lanes 16 m .. 16 m + 15 hold the 16 float4 of block 4 q + m) and
+    // reduced over each row of 16 lanes; the rows' results meet in LDS
+    __shared__ float2 s_r[4][64];
+    const int l = (int)__lane_id(), w = threadIdx.x >> 6;
+    const uint64_t waves = (uint64_t)gridDim.x * 4;
+    bool finite = true;
+    for (uint64_t b0 = (blockIdx.x * 4ull + w) * 64; b0 < g.nb; b0 += waves * 64) {
+        uint32_t ext = 0x040404u;   // the lane's block: valid samples per axis, as bytes
+        if (b0 + l < g.nb) {
+            uint32_t bx, by, bz;
+            block_xyz(g, b0 + l, bx, by, bz);
+            ext = min(4u, g.nx - 4 * bx) | min(4u, g.ny - 4 * by) << 8 | min(4u, g.nz - 4 * bz) << 16;
+        }
+        const int part = l & 15;   // float4 part: samples 4 part .. 4 part + 3 (y = part & 3, z = part >> 2)
+#pragma unroll 4
         for (int q = 0; q < 16; q++) {
-            float4 f = src[q];
-            float e[4] = {f.x, f.y, f.z, f.w};
+            const int m = l >> 4;
+            const uint64_t blk = b0 + 4 * q + m;
+            const uint32_t e = (uint32_t)__shfl((int)ext, 4 * q + m, 64);
+            float lo = INFINITY, hi = -INFINITY;
+            if (blk < g.nb) {
+                const float4 f = reinterpret_cast<const float4 *>(blocks + blk * 64)[part];
+                const float v[4] = {f.x, f.y, f.z, f.w};
+                const bool rowok = (uint32_t)(part & 3) < ((e >> 8) & 0xFFu) && (uint32_t)(part >> 2) < (e >> 16);
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                int i = 4 * q + j;
-                bool valid = (uint32_t)(i & 3) < vx && (uint32_t)((i >> 2) & 3) < vy && (uint32_t)(i >> 4) < vz;
-                if (valid) {
-                    lo = fminf(lo, e[j]);
-                    hi = fmaxf(hi, e[j]);
-                    finite = finite && isfinite(e[j]);
+                for (int j = 0; j < 4; j++) {
+                    if (rowok && (uint32_t)j < (e & 0xFFu)) {
+                        lo = fminf(lo, v[j]);
+                        hi = fmaxf(hi, v[j]);
+                        finite = finite && isfinite(v[j]);
+                    }
                 }
             }
+#pragma unroll
+            for (int d = 1; d < 16; d <<= 1) {
+                lo = fminf(lo, __shfl_xor(lo, d, 64));
+                hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+            }
+            if (part == 0) s_r[w][4 * q + m] = make_float2(lo, hi);
         }
-        ranges[b] = make_float2(lo, hi);
-        if (!finite) atomicOr(err, ERR_NONFINITE);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (b0 + l < g.nb) ranges[b0 + l] = s_r[w][l];
+        // s_r is rewritten next step
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    if (__ballot(!finite) && l == 0) atomicOr(err, ERR_NONFINITE);
 }
 
 // Set bits of m below the calling lane.
