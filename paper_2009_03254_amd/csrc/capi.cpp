@@ -38,6 +38,7 @@ struct bcmc_volume {
     hipEvent_t ev_done = nullptr;  // after the counters' readback (polled, not slept on)
     int have_extract = 0;
     float last_iso = 0.0f;
+    int last_format = BCMC_VERTEX_F32;   // the last extract's format (its grid set the chunks)
     float cull_iso = NAN;          // isovalue of the last cull (NaN: the flags are all zero)
     uint32_t gen = 0;              // extract calls, as the cull stamps rounds with active blocks
 };
@@ -515,6 +516,7 @@ int bcmc_extract(bcmc_volume *v, float iso, void *d_out, uint64_t capacity_verti
     }
     v->have_extract = 1;
     v->last_iso = iso;
+    v->last_format = v->vertex_format;
     if (c.total_verts > capacity_vertices) {
         set_error("vertex buffer too small: need " + std::to_string(c.total_verts) + " vertices");
         return BCMC_E_CAPACITY;
@@ -534,7 +536,7 @@ int bcmc_backward(bcmc_volume *v, float iso, const float *d_gV, uint64_t n_verts
     BCMC_HIP_TRY(hipMemsetAsync(d_diso, 0, sizeof(float), s));
     if (!n_verts) return BCMC_OK;
     BCMC_HIP_TRY(hipMemsetAsync(&v->d.ctr->err, 0, sizeof(unsigned int), s));
-    launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, n_verts, d_dfield, d_diso, v->vertex_format, s);
+    launch_backward(v->g, v->d, v->ext_blocks, iso, d_gV, n_verts, d_dfield, d_diso, v->last_format, s);
     BCMC_HIP_TRY(hipGetLastError());
     // the kernel compares each block's vertex count with the forward's
     BCMC_HIP_TRY(hipMemcpyAsync(&v->h_ctr->err, &v->d.ctr->err, sizeof(unsigned int),
