@@ -132,23 +132,30 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
     __shared__ float2 sh[NL][RY][RX];
     const uint32_t ntx = (g.nbx + CULL_TX - 1) / CULL_TX, nty = (g.nby + CULL_TY - 1) / CULL_TY;
     const uint32_t n_live = ctr->tile_ctr[TC_CULL_LIVE], n_stale = ctr->tile_ctr[TC_CULL_STALE];
-    for (uint32_t q = blockIdx.x; q < n_stale + n_live; q += gridDim.x) {
-        const bool clear = q < n_stale;
-        uint32_t t = clear ? list[n_tiles + q] : list[q - n_stale];
-        const uint32_t tx = t % ntx;
+    const uint32_t n_q = n_stale + n_live;
+    const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
+    auto tile_of = [&](uint32_t t, uint32_t &tx, uint32_t &ty, uint32_t &tz) {
+        tx = t % ntx;
         t /= ntx;
-        const uint32_t ty = t % nty, tz = t / nty;
+        ty = t % nty;
+        tz = t / nty;
+    };
+    uint32_t q = blockIdx.x;
+    for (; q < n_stale; q += gridDim.x) {   // culled last time only: flags cleared
+        uint32_t tx, ty, tz;
+        tile_of(list[n_tiles + q], tx, ty, tz);
         const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
-        const int lx = threadIdx.x % CULL_TX, ly = threadIdx.x / CULL_TX;
         const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
-        if (clear) {   // culled last time only
-            if (bx < g.nbx && by < g.nby)
-                for (int z = z0; z < z1; z++) active[((uint64_t)z * g.nby + by) * g.nbx + bx] = 0;
-            continue;
-        }
-        // the box's ranges with their halo, all loads in flight together
-        constexpr int PER = (NL * SLOTS + 255) / 256;
-        float2 v[PER];
+        if (bx < g.nbx && by < g.nby)
+            for (int z = z0; z < z1; z++) active[((uint64_t)z * g.nby + by) * g.nbx + bx] = 0;
+    }
+    // live tiles: a box's ranges with their halo, all loads in flight
+    // together; the next box's are loaded while this one is culled
+    constexpr int PER = (NL * SLOTS + 255) / 256;
+    auto load_box = [&](uint32_t qq, float2 (&v)[PER]) {
+        uint32_t tx, ty, tz;
+        tile_of(list[qq - n_stale], tx, ty, tz);
+        const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
 #pragma unroll
         for (int k = 0; k < PER; k++) {
             const int i = (int)threadIdx.x + 256 * k;
@@ -161,12 +168,21 @@ __global__ __launch_bounds__(256) void k_cull(Geom g, const float2 *__restrict__
                 y >= 0 && y < (int)g.nby)
                 v[k] = ranges[((uint64_t)zl * g.nby + (uint32_t)y) * g.nbx + (uint32_t)x];
         }
+    };
+    float2 v[PER];
+    if (q < n_q) load_box(q, v);
+    for (; q < n_q; q += gridDim.x) {
+        uint32_t tx, ty, tz;
+        tile_of(list[q - n_stale], tx, ty, tz);
+        const int z0 = (int)(tz * CULL_TZ), z1 = min(z0 + CULL_TZ, (int)g.nbz);
+        const uint32_t bx = tx * CULL_TX + lx, by = ty * CULL_TY + ly;
 #pragma unroll
         for (int k = 0; k < PER; k++) {
             const int i = (int)threadIdx.x + 256 * k;
             if (i < NL * SLOTS) (&sh[0][0][0])[i] = v[k];
         }
         __syncthreads();
+        if (q + gridDim.x < n_q) load_box(q + gridDim.x, v);
         uint32_t act = 0;   // bit z - z0: block (bx, by, z) is active
         if (bx < g.nbx && by < g.nby) {
             // per layer: 3x3 min / max, 2x2 positive min / max, own range
