@@ -178,3 +178,36 @@ def test_backward_rejects_changed_field(orc):
     with pytest.raises(RuntimeError):
         vol.backward(iso, gV)
     vol.close()
+
+
+@pytest.mark.parametrize("fmt", ["edge8", "q10"])
+def test_backward_after_8byte_extract(orc, fmt):
+    """The backward follows the soup of the extract before it whatever that
+    extract's record format: after an 8-byte-record extract it gives the same
+    gradients (up to float32 summation order) as after a 16-byte one, and the
+    oracle's."""
+    torch = torch_cuda()
+    import paper_2009_03254_amd as bcmc
+    n = 40
+    say(f"[backward] blobs 40^3 after a {fmt} extract")
+    f = fields.gaussian_blobs(n, 6, seed=31)
+    dims = (n, n, n)
+    B = orc.field_to_blocks(f)
+    iso = float(fields.percentile_iso(f, 60))
+    blocks = torch.from_numpy(B).cuda()
+    vol = bcmc.FieldVolume(blocks, dims)
+    verts, T = vol.extract(iso)
+    assert T > 1000
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    gV = torch.randn((3 * T, 3), generator=gen, dtype=torch.float32).cuda()
+    df16, di16 = (x.cpu().numpy().astype(np.float64) for x in vol.backward(iso, gV))
+    vol.set_vertex_format(fmt)
+    rec, T8 = vol.extract(iso)
+    assert T8 == T
+    df8, di8 = (x.cpu().numpy().astype(np.float64) for x in vol.backward(iso, gV))
+    vol.close()
+    assert np.linalg.norm(df8 - df16) <= 1e-5 * np.linalg.norm(df16)
+    assert float(di8) == pytest.approx(float(di16), rel=1e-5)
+    dfo, dio = orc.mc_backward(B, dims, iso, gV.cpu().numpy().astype(np.float64))
+    assert np.linalg.norm(df8 - dfo) <= 1e-4 * np.linalg.norm(dfo)
+    assert float(di8) == pytest.approx(dio, rel=1e-4)
