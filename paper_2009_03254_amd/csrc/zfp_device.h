@@ -55,15 +55,18 @@ __device__ __forceinline__ void fwd4(Int &a, Int &b, Int &c, Int &d) {
     d = (Int)((U)d + (U)b) >> 1; b = (Int)((U)b - (U)d);
     d = (Int)((U)d + (U)(b >> 1)); b = (Int)((U)b - (U)(d >> 1));
 }
-// Inverse: the same steps undone in reverse order.
+// Inverse: the same steps undone in reverse order.  Each of the last four
+// steps, x += y then y = 2 y - x, is the butterfly (x, y) -> (x + y, y - x)
+// (2 y - (x + y) = y - x, also modulo 2^P): two operations instead of three.
 template <typename Int>
 __host__ __device__ __forceinline__ void inv4(Int &a, Int &b, Int &c, Int &d) {
     using U = typename std::make_unsigned<Int>::type;
     b = (Int)((U)b + (U)(d >> 1)); d = (Int)((U)d - (U)(b >> 1));
-    b = (Int)((U)b + (U)d); d = (Int)(((U)d << 1) - (U)b);
-    c = (Int)((U)c + (U)a); a = (Int)(((U)a << 1) - (U)c);
-    b = (Int)((U)b + (U)c); c = (Int)(((U)c << 1) - (U)b);
-    d = (Int)((U)d + (U)a); a = (Int)(((U)a << 1) - (U)d);
+    U x;
+    x = (U)b; b = (Int)(x + (U)d); d = (Int)((U)d - x);
+    x = (U)c; c = (Int)(x + (U)a); a = (Int)((U)a - x);
+    x = (U)b; b = (Int)(x + (U)c); c = (Int)((U)c - x);
+    x = (U)d; d = (Int)(x + (U)a); a = (Int)((U)a - x);
 }
 
 template <typename Int>
@@ -92,49 +95,19 @@ __host__ __device__ __forceinline__ void inv_zyx(Int *v) {
     for (int i = 0; i < 16; i++) inv4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
 }
 
-// Value of the low w bits of x as a w-bit two's complement integer (1 <= w <= 31).
-__host__ __device__ __forceinline__ int32_t sext_bits(uint32_t x, int w) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_sbfe((int)x, 0u, (unsigned)w);
-#else
-    return (int32_t)(x << (32 - w)) >> (32 - w);
-#endif
-}
-
-// The 64-bit inverse transform of coefficients that are all multiples of
-// 2^K (K >= WRAP32_KMIN), carried out on y = c / 2^(K - 6) in 32 bits.
-// Every value stays a multiple of 2^(K - 6) through the three passes (each
-// pass lowers the power of two dividing a value by at most 2, so the right
-// shifts are exact on both sides), hence the 64-bit computation, wrapping
-// modulo 2^64, is the 32-bit one modulo 2^(70 - K) = 2^width, scaled by
-// 2^(K - 6).  Additions, subtractions and left shifts commute with reducing
-// modulo 2^width <= 2^31; before each right shift the operand is reduced to
-// its signed width-bit value, which is then the 64-bit operand / 2^(K - 6).
-// The results are exact modulo 2^width (sext_bits gives the 64-bit value /
-// 2^(K - 6)).
+// Lowest plane at which a double-precision block's stream may end for the
+// 32-bit transform of its coefficients' high words (staged_f64_top_planes).
+// The coefficients are then multiples of 2^K, K >= WRAP32_KMIN.  Each inverse
+// lifting pass lowers the power of two dividing a value by at most 2 (a
+// right shift of d, then one of the new b), so every operand of a right
+// shift is a multiple of 2^(K - 5) >= 2^34 and every value a multiple of
+// 2^(K - 6) >= 2^33.  With the low 32-bit words all zero, additions,
+// subtractions and left shifts (wrapping modulo 2^64) act on the high words
+// alone (wrapping modulo 2^32), and a right shift moves a zero out of the
+// high word: the 64-bit transform is the 32-bit one on the high words, times
+// 2^32.  So is the negabinary conversion (u ^ NB) - NB, the low words of
+// u ^ NB and NB being equal.  (K >= 38 would do.)
 constexpr int WRAP32_KMIN = 39;
-__host__ __device__ __forceinline__ void inv4_wrap32(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d,
-                                                     int width) {
-    d = (uint32_t)sext_bits(d, width);
-    b += (uint32_t)((int32_t)d >> 1);
-    b = (uint32_t)sext_bits(b, width);
-    d -= (uint32_t)((int32_t)b >> 1);
-    b += d; d = (d << 1) - b;
-    c += a; a = (a << 1) - c;
-    b += c; c = (c << 1) - b;
-    d += a; a = (a << 1) - d;
-}
-__host__ __device__ __forceinline__ void inv_zyx_wrap32(uint32_t *v, int width) {
-#pragma unroll
-    for (int i = 0; i < 16; i++) inv4_wrap32(v[i], v[i + 16], v[i + 32], v[i + 48], width);
-#pragma unroll
-    for (int z = 0; z < 4; z++)
-#pragma unroll
-        for (int x = 0; x < 4; x++)
-            inv4_wrap32(v[x + 16 * z], v[x + 4 + 16 * z], v[x + 8 + 16 * z], v[x + 12 + 16 * z], width);
-#pragma unroll
-    for (int i = 0; i < 16; i++) inv4_wrap32(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3], width);
-}
 
 // ---- staging layout ---------------------------------------------------------
 // A wave's staging area holds word w of lane l's block at st[w * STAGE_STRIDE + l]
@@ -447,12 +420,15 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
 }
 
 // Pass 2 and the transform of a double-precision block whose stream ends by
-// plane WRAP32_KMIN (low rates): the visited planes kend..63 are at most 25
-// rows of a bit matrix, rebuilt in lockstep (row 6 + r = plane kend + r;
-// rows 0..5 zero) and turned into the coefficients' words u' << 6
-// (u' = u >> kend) by two 32x32 transposes; the transform then runs in 32
-// bits on c / 2^(kend - 6) (inv_zyx_wrap32, which equals the 64-bit
-// transform exactly).
+// plane WRAP32_KMIN (low rates), on the coefficients' high 32-bit words: the
+// visited planes kend..63 are the rows kend - 32..31 of a bit matrix (row r =
+// plane 32 + r; the rows below are zero), rebuilt in lockstep and turned into
+// the high words by two 32x32 transposes; then negabinary conversion and the
+// inverse transform in 32 bits (exact, see WRAP32_KMIN).  The 64-bit value
+// is the high word times 2^32, and the double value of the decoded sample
+// h * 2^32 * 2^(emax - 62) = h * 2^(emax - 30), |h| < 2^31: for -96 <= emax
+// <= 96 that is float(h) * 2^(emax - 30) in single precision, rounded once
+// and never subnormal, else it is formed in double as the plain decoder does.
 __host__ __device__ __forceinline__ void staged_f64_top_planes(const uint64_t *st, const uint32_t *rec,
                                                                int rate, uint64_t found, int kend, int emax,
                                                                float *out) {
@@ -460,14 +436,14 @@ __host__ __device__ __forceinline__ void staged_f64_top_planes(const uint64_t *s
     const int end_bits = 64 * rate;
     uint32_t lo[32], hi[32];
 #pragma unroll
-    for (int r = 0; r < 6; r++) lo[r] = hi[r] = 0u;
+    for (int r = 0; r < WRAP32_KMIN - 32; r++) lo[r] = hi[r] = 0u;
     int o = 1 + T::EBITS, nn = 0;
     uint64_t below = 0;
 #pragma unroll
-    for (int r = 31; r >= 6; r--) {
-        const int kk = kend + r - 6;
+    for (int r = 31; r >= WRAP32_KMIN - 32; r--) {
+        const int kk = 32 + r;
         uint64_t x = 0;
-        if (kk <= T::P - 1) {
+        if (kk >= kend) {
             const uint32_t rw = rec[kk >> 1], rk = (kk & 1) ? (rw >> 16) : (rw & 0xFFFFu);
             const int m = nn < end_bits - o ? nn : end_bits - o;
             if (m > 0) x = peek_staged(st, o) & (~0ull >> (64 - m));
@@ -483,19 +459,23 @@ __host__ __device__ __forceinline__ void staged_f64_top_planes(const uint64_t *s
     }
     transpose32(lo);
     transpose32(hi);
-    // negabinary -> two's complement on the scaled words (mod 2^(70 - kend))
-    const uint32_t nb6 = (uint32_t)((T::NB >> kend) << 6);
-    uint32_t v[64];
+    constexpr uint32_t NB_HI = (uint32_t)(T::NB >> 32);
+    int32_t v[64];
 #pragma unroll
     for (int r = 0; r < 32; r++) {
-        v[kOrder.idx[r]] = (lo[r] ^ nb6) - nb6;
-        v[kOrder.idx[r + 32]] = (hi[r] ^ nb6) - nb6;
+        v[kOrder.idx[r]] = (int32_t)((lo[r] ^ NB_HI) - NB_HI);
+        v[kOrder.idx[r + 32]] = (int32_t)((hi[r] ^ NB_HI) - NB_HI);
     }
-    const int width = 70 - kend;
-    inv_zyx_wrap32(v, width);
-    const double s6 = ldexp(1.0, kend - 6 + emax - 62);
+    inv_zyx(v);
+    if (emax >= -96 && emax <= 96) {
+        const float s = ldexpf(1.0f, emax - 30);
 #pragma unroll
-    for (int i = 0; i < 64; i++) out[i] = (float)((double)sext_bits(v[i], width) * s6);
+        for (int i = 0; i < 64; i++) out[i] = (float)v[i] * s;
+    } else {
+        const double s = ldexp(1.0, emax - 62);
+#pragma unroll
+        for (int i = 0; i < 64; i++) out[i] = (float)((double)v[i] * 4294967296.0 * s);
+    }
 }
 
 __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t *st, uint32_t *rec,

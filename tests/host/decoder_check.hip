@@ -22,6 +22,8 @@ int main() {
     long bad = 0, total = 0, low_taken = 0, low_back = 0;
     const int rates[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 16, 24, 32};
     const double dens[] = {0.5, 0.2, 0.05, 0.01, 0.9, 0.7};
+    const int ext64[] = {-1000, -300, -127, -126, -121, -110, -97, -96, 96, 97, 126, 127, 300, 900};
+    const int ext32[] = {-126, -110, -100, -97, -96, 96, 97, 100, 127};
     for (int f64 = 0; f64 < 2; f64++)
         for (int rate : rates)
             for (double p : dens) {
@@ -35,9 +37,13 @@ int main() {
                         for (int i = 0; i < 64; i++) v |= (uint64_t)B(rng) << i;
                         s[(size_t)b * rate + w] = v;
                     }
-                    // nonzero flag and an exponent that keeps every value finite
+                    // nonzero flag and an exponent near 0; every 11th block one near
+                    // the ends of the range (values beyond single precision, either
+                    // way, and both sides of the single-precision scale's range)
                     uint64_t &w0 = s[(size_t)b * rate];
-                    const uint64_t e = (uint64_t)(bias - 20 + (int)(rng() % 41));
+                    int eo = -20 + (int)(rng() % 41);
+                    if (b % 11 == 5) eo = f64 ? ext64[rng() % 14] : ext32[rng() % 9];
+                    const uint64_t e = (uint64_t)(bias + eo);
                     w0 = (w0 & ~((1ull << (eb + 1)) - 1)) | 1ull | (e << 1);
                     if (b % 97 == 0) w0 &= ~1ull;   // some all-zero blocks
                 }
