@@ -158,17 +158,51 @@ struct BitReader {
     }
 };
 
+// Bytes of the 8-byte value hi:lo picked by the selector bytes of sel (each
+// 0..7, byte 0 = the lowest of lo): one v_perm_b32.
+__host__ __device__ __forceinline__ uint32_t byte_perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_perm(hi, lo, sel);
+#else
+    const uint64_t v = (uint64_t)hi << 32 | lo;
+    uint32_t r = 0;
+    for (int i = 0; i < 4; i++) r |= (uint32_t)(v >> (8 * ((sel >> (8 * i)) & 7u)) & 0xFFu) << (8 * i);
+    return r;
+#endif
+}
+// The bits of a where m is set, of b elsewhere: one v_bfi_b32 (the compiler
+// does not form it from this expression here).
+__host__ __device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(a), "v"(b));
+    return r;
+#else
+    return (m & a) | (~m & b);
+#endif
+}
+
 // One stage of an in-place 32x32 bit-matrix transpose (bit i of a[k] is
 // element (k, i)): within every 2J x 2J block the two off-diagonal J x J
-// blocks trade places.  M selects the bits i with (i & J) == 0.
+// blocks trade places.  M selects the bits i with (i & J) == 0.  Two
+// instructions per pair of words at J = 16 and 8 (byte permutes), four
+// below (a shift and a bit-field select per word).
 template <int J, uint32_t M>
 __host__ __device__ __forceinline__ void transpose_stage(uint32_t *a) {
 #pragma unroll
     for (int k = 0; k < 32; k++) {
         if (k & J) continue;
         const uint32_t x = a[k], y = a[k + J];
-        a[k] = (x & M) | ((y << J) & ~M);       // bit-field inserts: one shift and
-        a[k + J] = ((x >> J) & M) | (y & ~M);   // one v_bfi_b32 per word
+        if constexpr (J == 16) {
+            a[k] = byte_perm(y, x, 0x05040100u);       // low halves of x, y
+            a[k + J] = byte_perm(y, x, 0x07060302u);   // high halves
+        } else if constexpr (J == 8) {
+            a[k] = byte_perm(y, x, 0x06020400u);       // bytes x0 y0 x2 y2
+            a[k + J] = byte_perm(y, x, 0x07030501u);   // bytes x1 y1 x3 y3
+        } else {
+            a[k] = bit_select(M, x, y << J);
+            a[k + J] = bit_select(M, x >> J, y);
+        }
     }
 }
 __host__ __device__ __forceinline__ void transpose32(uint32_t *a) {
