@@ -406,15 +406,14 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
                                                                  int rate, float *out) {
     using T = Prec<false>;
     const uint64_t head = st[0];
-    if (!(head & 1u)) {
-#pragma unroll
-        for (int i = 0; i < 64; i++) out[i] = 0.0f;
-        return;
-    }
-    const int emax = (int)((head >> 1) & 0xFFu) - T::BIAS;
+    // an all-zero block takes the same path with no plane visited (see
+    // decode_block_staged_f64_low)
+    const bool zero = !(head & 1u);
+    const int emax = zero ? 0 : (int)((head >> 1) & 0xFFu) - T::BIAS;
     const int end_bits = 64 * rate;
-    int kend;
-    const uint64_t found = staged_pass1<false>(st, rec, rate, kend);
+    int kend = T::P;
+    uint64_t found = 0;
+    if (!zero) found = staged_pass1<false>(st, rec, rate, kend);
     // ---- pass 2: plane words, in lockstep ----
     uint32_t R[16];
 #pragma unroll
@@ -463,6 +462,9 @@ __host__ __device__ __forceinline__ void decode_block_staged_f32(const uint64_t 
 // h * 2^32 * 2^(emax - 62) = h * 2^(emax - 30), |h| < 2^31: for -96 <= emax
 // <= 96 that is float(h) * 2^(emax - 30) in single precision, rounded once
 // and never subnormal, else it is formed in double as the plain decoder does.
+// SINGLE_ONLY: the caller guarantees -96 <= emax <= 96 (no double-precision
+// branch, whose results the compiler would merge with register copies).
+template <bool SINGLE_ONLY = false>
 __host__ __device__ __forceinline__ void staged_f64_top_planes(const uint64_t *st, const uint32_t *rec,
                                                                int rate, uint64_t found, int kend, int emax,
                                                                float *out) {
@@ -501,7 +503,7 @@ __host__ __device__ __forceinline__ void staged_f64_top_planes(const uint64_t *s
         v[kOrder.idx[r + 32]] = (int32_t)((hi[r] ^ NB_HI) - NB_HI);
     }
     inv_zyx(v);
-    if (emax >= -96 && emax <= 96) {
+    if (SINGLE_ONLY || (emax >= -96 && emax <= 96)) {
         const float s = ldexpf(1.0f, emax - 30);
 #pragma unroll
         for (int i = 0; i < 64; i++) out[i] = (float)v[i] * s;
@@ -566,24 +568,25 @@ __host__ __device__ __forceinline__ void decode_block_staged_f64(const uint64_t 
 }
 
 // Low-rate double precision: the block when its stream ends by plane
-// WRAP32_KMIN (pass 1, then staged_f64_top_planes, the same values as
-// decode_block_staged_f64) and true; false, with out untouched, for a block
-// whose stream goes on below that plane (the caller decodes it with the
-// general decoder).
+// WRAP32_KMIN and |emax| <= 96 (pass 1, then staged_f64_top_planes, the same
+// values as decode_block_staged_f64) and true; false, with out untouched, for
+// a block whose stream goes on below that plane or whose exponent is outside
+// that range (the caller decodes it with the general decoder).
 __host__ __device__ __forceinline__ bool decode_block_staged_f64_low(const uint64_t *st, uint32_t *rec,
                                                                     int rate, float *out) {
     using T = Prec<true>;
     const uint64_t head = st[0];
-    if (!(head & 1u)) {
-#pragma unroll
-        for (int i = 0; i < 64; i++) out[i] = 0.0f;
-        return true;
-    }
-    const int emax = (int)((head >> 1) & 0x7FFu) - T::BIAS;
-    int kend;
-    const uint64_t found = staged_pass1<true>(st, rec, rate, kend);
+    // An all-zero block takes the same path with no plane visited (every
+    // coefficient 0, any scale): one path that writes `out`, so that the
+    // compiler does not merge the results of several with register copies.
+    const bool zero = !(head & 1u);
+    const int emax = zero ? 0 : (int)((head >> 1) & 0x7FFu) - T::BIAS;
+    if (emax < -96 || emax > 96) return false;   // values formed in double: the general decoder's
+    int kend = T::P;
+    uint64_t found = 0;
+    if (!zero) found = staged_pass1<true>(st, rec, rate, kend);
     if (kend < WRAP32_KMIN) return false;
-    staged_f64_top_planes(st, rec, rate, found, kend, emax, out);
+    staged_f64_top_planes<true>(st, rec, rate, found, kend, emax, out);
     return true;
 }
 
