@@ -161,10 +161,11 @@ __device__ __forceinline__ void store_slot(const float *v, uint64_t s, float iso
 // and is decoded straight into that slot.
 // LOW (double precision, staged, low rates): the decode is
 // decode_block_staged_low, which holds the kernel to the registers of the
-// low-rate decoder; the blocks it hands back (their indices into I_new) are
-// listed in `retry` for k_decode_retry.
+// low-rate decoder (4 waves per SIMD; 5 spills registers and is slower); the
+// blocks it hands back (their indices into I_new) are listed in `retry` for
+// k_decode_retry.
 template <bool F64, bool STAGED, bool LOW = false>
-__global__ __launch_bounds__(256, LOW ? 3 : (F64 ? 1 : 4)) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
+__global__ __launch_bounds__(256, LOW ? 4 : (F64 ? 1 : 4)) void k_assign_decode(Counters *ctr, const uint32_t *__restrict__ I_new,
                                                       const uint32_t *__restrict__ sorted0,
                                                       const uint32_t *__restrict__ sorted1,
                                                       int32_t *S_block, int32_t *I_slot,
