@@ -991,6 +991,7 @@ __global__ __launch_bounds__(256, FMT == VFMT_GRAD ? 5 : 8) void k_mc_emit(Geom 
         octet(g, b, I_slot, identity, so, lbx, lby, lbz);
         uint64_t todo = __ballot(cnt != 0);
         while (todo) {
+            const uint64_t left = todo;
             int jl[EMIT_SB], nsb = 0;
 #pragma unroll
             for (int k = 0; k < EMIT_SB; k++) {
@@ -1001,7 +1002,8 @@ __global__ __launch_bounds__(256, FMT == VFMT_GRAD ? 5 : 8) void k_mc_emit(Geom 
                     nsb++;
                 }
             }
-            stage_batch_n<EMIT_SB>(q, slots, so, jl, sh.tiles[w]);
+            // the triangle list area is empty between batches (emit_batch flushes)
+            stage_batch_tab<EMIT_SB>(q, slots, so, left & ~todo, nsb, sh.tri[w], sh.tiles[w]);
             wave_lds_sync();
             // the staged blocks are consecutive occupied blocks: their vertex
             // ranges follow each other from the first one's offset, so their

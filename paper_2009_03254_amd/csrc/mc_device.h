@@ -360,6 +360,39 @@ __device__ __forceinline__ void stage_batch_n(const LaneGeom &q, const float *__
     }
 }
 
+// stage_batch_n with the batch's slots passed through LDS: the lanes of the
+// batch (bits of `batch`, in lane order the blocks k < nsb; the rest repeat
+// block 0) write their 8 slots to tab[8 k + m], and every lane reads the two
+// it needs (its own sample's block, its halo sample's neighbour), where
+// stage_batch_n takes 8 lane reads and a chain of selects per block.  `tab`
+// holds 8 * SB words of the wave's LDS that nothing else uses meanwhile.
+template <int SB>
+__device__ __forceinline__ void stage_batch_tab(const LaneGeom &q, const float *__restrict__ slots,
+                                                const uint32_t so[8], uint64_t batch, int nsb,
+                                                uint32_t *tab, float (*tiles)[128]) {
+    const int l = lane();
+    if ((batch >> l) & 1u) {
+        uint4 *p = reinterpret_cast<uint4 *>(tab + 8 * mbcnt(batch));
+        p[0] = make_uint4(so[0], so[1], so[2], so[3]);
+        p[1] = make_uint4(so[4], so[5], so[6], so[7]);
+    }
+    wave_lds_sync();
+    float ov[SB], hv[SB];
+#pragma unroll
+    for (int k = 0; k < SB; k++) {
+        const int kk = k < nsb ? k : 0;
+        const uint32_t s_own = tab[8 * kk];
+        const uint32_t s_h = tab[8 * kk + q.halo_m];
+        ov[k] = slots[(uint64_t)s_own * 64 + l];
+        hv[k] = slots[(uint64_t)s_h * 64 + q.halo_l];
+    }
+#pragma unroll
+    for (int k = 0; k < SB; k++) {
+        tiles[k][q.own_t] = ov[k];
+        if (l < 61) tiles[k][q.halo_t] = hv[k];
+    }
+}
+
 __device__ __forceinline__ void stage_batch(const LaneGeom &q, const float *__restrict__ slots,
                                             const uint32_t so[8], const int *jl,
                                             float (*tiles)[128]) {
