@@ -673,6 +673,7 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
         octet(vol.g, b, p.I_slot + vol.gbase, 0, so, lbx, lby, lbz);
         uint64_t todo = __ballot(c != 0);
         while (todo) {
+            const uint64_t left = todo;
             int jl[SB], nsb = 0;
 #pragma unroll
             for (int k = 0; k < SB; k++) {
@@ -683,7 +684,9 @@ __global__ __launch_bounds__(BT) void k_batch_back(BatchParams p) {
                     nsb++;
                 }
             }
-            stage_batch_n<SB>(q, p.slots, so, jl, sh.emit.tiles[w]);
+            // the triangle list area is empty between batches (emit_batch flushes)
+            static_assert(8 * SB <= EMIT_TRIS, "slot table fits the triangle list");
+            stage_batch_tab<SB>(q, p.slots, so, left & ~todo, nsb, sh.emit.tri[w], sh.emit.tiles[w]);
             wave_lds_sync();
             // consecutive entries of L with triangles: adjacent vertex ranges
             const uint64_t ob = ((uint64_t)bcast((uint32_t)(off >> 32), jl[0]) << 32) |

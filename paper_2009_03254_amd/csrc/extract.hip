@@ -1003,6 +1003,7 @@ __global__ __launch_bounds__(256, FMT == VFMT_GRAD ? 5 : 8) void k_mc_emit(Geom 
                 }
             }
             // the triangle list area is empty between batches (emit_batch flushes)
+            static_assert(8 * EMIT_SB <= EMIT_TRIS, "slot table fits the triangle list");
             stage_batch_tab<EMIT_SB>(q, slots, so, left & ~todo, nsb, sh.tri[w], sh.tiles[w]);
             wave_lds_sync();
             // the staged blocks are consecutive occupied blocks: their vertex

@@ -365,16 +365,19 @@ __device__ __forceinline__ void stage_batch_n(const LaneGeom &q, const float *__
 // block 0) write their 8 slots to tab[8 k + m], and every lane reads the two
 // it needs (its own sample's block, its halo sample's neighbour), where
 // stage_batch_n takes 8 lane reads and a chain of selects per block.  `tab`
-// holds 8 * SB words of the wave's LDS that nothing else uses meanwhile.
+// holds 8 * SB words (8-byte aligned) of the wave's LDS that nothing else
+// uses meanwhile.
 template <int SB>
 __device__ __forceinline__ void stage_batch_tab(const LaneGeom &q, const float *__restrict__ slots,
                                                 const uint32_t so[8], uint64_t batch, int nsb,
                                                 uint32_t *tab, float (*tiles)[128]) {
     const int l = lane();
-    if ((batch >> l) & 1u) {
-        uint4 *p = reinterpret_cast<uint4 *>(tab + 8 * mbcnt(batch));
-        p[0] = make_uint4(so[0], so[1], so[2], so[3]);
-        p[1] = make_uint4(so[4], so[5], so[6], so[7]);
+    if ((batch >> l) & 1u) {   // 8-byte stores: `tab` is 8-byte aligned
+        uint2 *p = reinterpret_cast<uint2 *>(tab + 8 * mbcnt(batch));
+        p[0] = make_uint2(so[0], so[1]);
+        p[1] = make_uint2(so[2], so[3]);
+        p[2] = make_uint2(so[4], so[5]);
+        p[3] = make_uint2(so[6], so[7]);
     }
     wave_lds_sync();
     float ov[SB], hv[SB];
