@@ -332,41 +332,15 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
 }
 
-// Stage up to SB blocks (lanes jl[k] of the batch) into tiles[k].  Every
-// slot is loaded unconditionally (unused k repeat block jl[0]) so all 2*SB
-// loads of a lane are in flight before the first LDS write.
-template <int SB>
-__device__ __forceinline__ void stage_batch_n(const LaneGeom &q, const float *__restrict__ slots,
-                                              const uint32_t so[8], const int *jl,
-                                              float (*tiles)[128]) {
-    const int l = lane();
-    float ov[SB], hv[SB];
-#pragma unroll
-    for (int k = 0; k < SB; k++) {
-        uint32_t s_own = bcast(so[0], jl[k]);
-        uint32_t s_h = s_own;
-#pragma unroll
-        for (int m = 1; m < 8; m++) {
-            uint32_t sm = bcast(so[m], jl[k]);
-            s_h = (q.halo_m == m) ? sm : s_h;
-        }
-        ov[k] = slots[(uint64_t)s_own * 64 + l];
-        hv[k] = slots[(uint64_t)s_h * 64 + q.halo_l];
-    }
-#pragma unroll
-    for (int k = 0; k < SB; k++) {
-        tiles[k][q.own_t] = ov[k];
-        if (l < 61) tiles[k][q.halo_t] = hv[k];
-    }
-}
-
-// stage_batch_n with the batch's slots passed through LDS: the lanes of the
-// batch (bits of `batch`, in lane order the blocks k < nsb; the rest repeat
-// block 0) write their 8 slots to tab[8 k + m], and every lane reads the two
-// it needs (its own sample's block, its halo sample's neighbour), where
-// stage_batch_n takes 8 lane reads and a chain of selects per block.  `tab`
-// holds 8 * SB words (8-byte aligned) of the wave's LDS that nothing else
-// uses meanwhile.
+// Stage up to SB blocks (the lanes of `batch`, in lane order blocks
+// k < nsb; the rest repeat block 0) into tiles[k].  Their slots pass through
+// LDS: each lane of the batch writes its block's 8 slots (the block and its 7
+// positive neighbours) to tab[8 k + m], and every lane reads the two it needs,
+// its own sample's block and its halo sample's neighbour (per block, 8 lane
+// reads and a chain of selects, each select needing a copy, cost more).  Every
+// slot is loaded unconditionally, so that all 2 SB loads of a lane are in
+// flight before the first tile write.  `tab` holds 8 SB words (8-byte
+// aligned) of the wave's LDS that nothing else uses meanwhile.
 template <int SB>
 __device__ __forceinline__ void stage_batch_tab(const LaneGeom &q, const float *__restrict__ slots,
                                                 const uint32_t so[8], uint64_t batch, int nsb,
@@ -394,12 +368,6 @@ __device__ __forceinline__ void stage_batch_tab(const LaneGeom &q, const float *
         tiles[k][q.own_t] = ov[k];
         if (l < 61) tiles[k][q.halo_t] = hv[k];
     }
-}
-
-__device__ __forceinline__ void stage_batch(const LaneGeom &q, const float *__restrict__ slots,
-                                            const uint32_t so[8], const int *jl,
-                                            float (*tiles)[128]) {
-    stage_batch_n<MC_SB>(q, slots, so, jl, tiles);
 }
 
 // Case of the lane's cell in block (bx,by,bz) staged in `tile`, -1 outside.
