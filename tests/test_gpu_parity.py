@@ -101,6 +101,34 @@ def test_random_streams_decode_bitexact(bc, orc, rate, is64, density):
     vol.close()
 
 
+@pytest.mark.parametrize("rate,density", [(2, 0.5), (4, 0.2)])
+def test_random_streams_wide_exponents(bc, orc, rate, density):
+    """Double precision at low rates, block exponents up to +-120 (values
+    still finite in single precision): the low-rate decoder takes the blocks
+    with |emax| <= 96 and hands the others to the general decoder, which
+    forms their values in double; both give the oracle's values bit for bit,
+    through decode_all and through an extraction's cache fill."""
+    dims = (64, 48, 40)
+    say(f"[random stream, wide exponents] rate={rate} density={density}")
+    s = fields.random_block_stream(dims, rate, True, density, seed=300 + rate, exp_spread=120,
+                                   zero_every=11)
+    vol = bc.Volume(s, dims, "f64", rate)
+    dec = vol.decode_all().cpu().numpy()
+    D = orc.zfp_decode(s, dims, rate, True)
+    assert np.array_equal(dec.view(np.uint32), D.view(np.uint32))
+    iso = float(np.median(D))
+    T = _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=False)
+    assert T > 0
+    st = vol.stats()
+    assert 0 < st["n_general"] < st["n_new"], st
+    _, ids = vol.active()
+    I_slot, _, _ = vol.cache_state()
+    slots = vol.slot_data()
+    assert (I_slot[ids] >= 0).all()
+    assert np.array_equal(slots[I_slot[ids]].view(np.uint32), D[ids].view(np.uint32))
+    vol.close()
+
+
 def _extract_and_compare(bc, orc, vol, D, dims, iso, check_cells=True):
     import torch
     r = orc.mc_extract(D, dims, iso, want=("verts", "vblock", "cell_keys", "cases"))
