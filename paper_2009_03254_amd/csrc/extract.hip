@@ -933,7 +933,7 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(uint64_t *__restrict__ chun
 // from the first block's offset, in canonical order (block, cell, triangle,
 // vertex).
 template <int FMT>
-__global__ __launch_bounds__(256, FMT == VFMT_GRAD ? 5 : 8) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
+__global__ __launch_bounds__(256, FMT == VFMT_GRAD ? 5 : 7) void k_mc_emit(Geom g, const uint32_t *__restrict__ I_active,
                                                 const int32_t *__restrict__ I_slot, int identity,
                                                 const float *__restrict__ slots,
                                                 const uint64_t *__restrict__ mc_table, float iso,

@@ -538,7 +538,8 @@ struct EmitSharedT {
 using EmitShared = EmitSharedT<MC_SB>;
 // The plain emission stages two blocks fewer and keeps the triangle table in
 // LDS (a per-lane lookup per block that global memory serves only after the
-// staged slots have evicted it from L1): its LDS then fits 8 workgroups per CU.
+// staged slots have evicted it from L1): its LDS then fits 8 workgroups per CU
+// (its registers hold it to 7, where it needs no scratch).
 constexpr int EMIT_SB = MC_SB - 2;
 
 // The backward's LDS: the plain emission's, and per staged block the
